@@ -1,0 +1,214 @@
+"""FP64 oracle of ALS and N-GMRES for CP decomposition (test infrastructure only).
+
+Follows Section 2 of the paper step by step:
+
+* the one-step process M(u) is one ALS sweep (Section 2.3: nonlinear block
+  Gauss-Seidel on G^(n) = 0, n = 1..N, each mode solved with the factors of
+  the earlier modes already updated), followed by the normalisation and
+  reordering of the rank-one terms;
+* one N-GMRES iteration (Section 2.1, Steps I-III and the algorithm box
+  "N-GMRES optimization algorithm"): Step I u_bar = M(u_i); Step II the
+  accelerated iterate u_hat = u_bar + sum_j alpha_j (u_bar - u_j) over the
+  window, with alpha from the regularised normal equations of the linearised
+  gradient; Step III a Moré–Thuente line search on f(u_bar + beta (u_hat -
+  u_bar)), restart when the direction is not a descent direction, window of
+  the last w iterates (Section 2.1 remarks; Section 2.4 parameters).
+
+Readings of points the paper leaves open (shared with the GPU library):
+* stopping rule: ||g||_2 / ||T||_F <= tol at the current (normalised) iterate,
+  or max_iter iterations;
+* restart when g(u_bar)^T d >= 0 (equality counts as non-descent): skip the
+  line search, take u_{i+1} = u_bar, and the window restarts from u_{i+1};
+* the accelerated iterate u_hat is normalised before d = u_hat - u_bar is
+  formed; line-search trial points are not normalised; the accepted iterate
+  is normalised and its gradient transformed (not recomputed);
+* delta = eps * max diag(P^T P) with eps = 1e-12; if every p_j is zero,
+  alpha = 0 (u_hat = u_bar);
+* if the line search stops without a strong-Wolfe point, the evaluated trial
+  with the lowest objective is taken when it is below f(u_bar), else beta = 0.
+"""
+from __future__ import annotations
+
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg
+
+from . import cp
+from .linesearch import more_thuente
+
+__all__ = ["CPProblem", "step2_accelerate", "ngmres", "als", "IterRecord"]
+
+
+class CPProblem:
+    """f, g and the ALS sweep for a dense or COO data tensor and a rank R."""
+
+    def __init__(self, tensor, R):
+        self.t = tensor
+        self.R = int(R)
+        self.dims = tuple(tensor.dims)
+        self.N = len(self.dims)
+        self.norm_t = float(np.sqrt(tensor.norm2))
+        self.nfg = 0
+
+    def factors(self, u):
+        return cp.split_u(u, self.dims, self.R)
+
+    def f_and_g(self, u):
+        """Objective (Optimization Problem I) and gradient (Section 2.3)."""
+        self.nfg += 1
+        A = self.factors(u)
+        Ms = [self.t.mttkrp(A, n) for n in range(self.N)]
+        G = cp.gradient_from_mttkrps(A, Ms)
+        return self.t.objective(A, Ms), cp.join_u(G)
+
+    def normalise(self, u, g=None):
+        A = self.factors(u)
+        newA, scales, perm = cp.normalise(A)
+        u2 = cp.join_u(newA)
+        if g is None:
+            return u2, None
+        G = cp.split_u(g, self.dims, self.R)
+        return u2, cp.join_u(cp.transform_gradient(G, scales, perm))
+
+    def als_sweep(self, u, normalise=True):
+        """One ALS iteration M(u): solve G^(n) = 0 for A^(n), n = 1..N, in order."""
+        A = [a.copy() for a in self.factors(u)]
+        flags = []
+        for n in range(self.N):
+            M = self.t.mttkrp(A, n)
+            A[n], flag = cp.mode_solve(M, cp.gamma_bar(A, n))
+            flags.append(flag)
+        u2 = cp.join_u(A)
+        if normalise:
+            u2, _ = self.normalise(u2)
+        return u2, flags
+
+
+def step2_accelerate(U, Gw, u_bar, g_bar, eps=1e-12):
+    """N-GMRES Step II: u_hat = u_bar + sum_j alpha_j (u_bar - u_j).
+
+    U, Gw: window iterates and their gradients (m x L).  alpha minimises the
+    linearised residual ||g_bar + P alpha||_2 with p_j = g_bar - g_j, via the
+    normal equations (P^T P + delta I) alpha = -P^T g_bar, delta = eps * max
+    diag(P^T P) (Section 2.1 Step II and fifth remark; Section 2.4).
+    """
+    U = np.atleast_2d(np.asarray(U, dtype=np.float64))
+    Gw = np.atleast_2d(np.asarray(Gw, dtype=np.float64))
+    P = g_bar[None, :] - Gw                      # rows are p_j
+    B = P @ P.T
+    dmax = float(np.max(np.diag(B))) if B.size else 0.0
+    if dmax <= 0.0:
+        alpha = np.zeros(U.shape[0])
+    else:
+        rhs = -(P @ g_bar)
+        c = scipy.linalg.cho_factor(B + eps * dmax * np.eye(B.shape[0]), lower=True)
+        alpha = scipy.linalg.cho_solve(c, rhs)
+    u_hat = u_bar + np.sum(alpha[:, None] * (u_bar[None, :] - U), axis=0)
+    return u_hat, alpha
+
+
+@dataclass
+class IterRecord:
+    it: int
+    f: float
+    rho: float
+    beta: float = float("nan")
+    restart: bool = False
+    nfev: int = 0
+    ls_status: str = ""
+    m: int = 0
+
+
+@dataclass
+class Result:
+    u: np.ndarray
+    f: float
+    g: np.ndarray
+    rho: float
+    iters: int
+    converged: bool
+    trace: list = field(default_factory=list)
+    nfg: int = 0
+
+
+def _rho(problem, g):
+    return float(np.linalg.norm(g)) / problem.norm_t
+
+
+def ngmres(problem, u0, tol, max_iter=1000, w=20, eps=1e-12, ls=None,
+           normalise_accel=True):
+    """Algorithm "N-GMRES optimization algorithm" with the window grown from 1 to w."""
+    ls = dict(stp=1.0, ftol=1e-4, gtol=1e-2, maxfev=20, xtol=1e-15,
+              stpmin=1e-15, stpmax=1e15) | (ls or {})
+    u, _ = problem.normalise(np.asarray(u0, dtype=np.float64))
+    f, g = problem.f_and_g(u)
+    window = deque([(u, g)])
+    trace = []
+    it = 0
+    while True:
+        rho = _rho(problem, g)
+        rec = IterRecord(it=it, f=f, rho=rho, m=len(window))
+        trace.append(rec)
+        if rho <= tol or it >= max_iter:
+            break
+        # Step I
+        u_bar, _ = problem.als_sweep(u)
+        f_bar, g_bar = problem.f_and_g(u_bar)
+        # Step II
+        U = np.array([p[0] for p in window])
+        Gw = np.array([p[1] for p in window])
+        u_hat, _ = step2_accelerate(U, Gw, u_bar, g_bar, eps)
+        if normalise_accel:
+            u_hat, _ = problem.normalise(u_hat)
+        d = u_hat - u_bar
+        slope = float(g_bar @ d)
+        if not (slope < 0.0):
+            # restart: no line search, window back to one iterate
+            rec.restart = True
+            u_new, f_new, g_new = u_bar, f_bar, g_bar
+            window.clear()
+        else:
+            # Step III
+            def phi(beta):
+                fb, gb = problem.f_and_g(u_bar + beta * d)
+                return fb, float(gb @ d), gb
+            res = more_thuente(phi, f_bar, slope, **ls)
+            rec.nfev, rec.ls_status = res.nfev, res.status
+            if res.status == "converged":
+                beta, f_new, g_new = res.stp, res.f, res.payload
+            else:
+                best = min(res.trials, key=lambda t: t[1])
+                if best[1] < f_bar:
+                    beta, f_new, g_new = best[0], best[1], best[3]
+                else:
+                    beta, f_new, g_new = 0.0, f_bar, g_bar
+            rec.beta = beta
+            u_new = u_bar + beta * d if beta != 0.0 else u_bar
+        u, g = problem.normalise(u_new, g_new)
+        f = f_new
+        window.append((u, g))
+        while len(window) > w:
+            window.popleft()
+        it += 1
+    return Result(u=u, f=f, g=g, rho=trace[-1].rho, iters=it,
+                  converged=trace[-1].rho <= tol, trace=trace, nfg=problem.nfg)
+
+
+def als(problem, u0, tol, max_iter=1000):
+    """Stand-alone ALS: u_{i+1} = M(u_i), stopped on the same gradient criterion."""
+    u, _ = problem.normalise(np.asarray(u0, dtype=np.float64))
+    f, g = problem.f_and_g(u)
+    trace = []
+    it = 0
+    while True:
+        rho = _rho(problem, g)
+        trace.append(IterRecord(it=it, f=f, rho=rho))
+        if rho <= tol or it >= max_iter:
+            break
+        u, _ = problem.als_sweep(u)
+        f, g = problem.f_and_g(u)
+        it += 1
+    return Result(u=u, f=f, g=g, rho=trace[-1].rho, iters=it,
+                  converged=trace[-1].rho <= tol, trace=trace, nfg=problem.nfg)
