@@ -1,0 +1,268 @@
+/*
+ * cpng.h -- C ABI of the MI355X (gfx950) library for canonical rank-R tensor
+ * decomposition by ALS accelerated with nonlinear GMRES (N-GMRES).
+ *
+ * The operations follow the paper "A Nonlinear GMRES Optimization Algorithm
+ * for Canonical Tensor Decomposition" (H. De Sterck):
+ *   - the problem: minimise f = 1/2 ||T - [[A^(1),...,A^(N)]]||_F^2 over the
+ *     factor matrices (Section 1, Optimization Problem I);
+ *   - the gradient G^(n) = -T_(n) Phibar^(n) + A^(n) Gammabar^(n), its MTTKRP
+ *     term T_(n) Phibar^(n) and the Hadamard products of Grams Gammabar^(n)
+ *     (Section 2.3);
+ *   - ALS as the one-step process (Section 2.3, nonlinear block Gauss-Seidel)
+ *     with the normalisation and reordering of the rank-one terms;
+ *   - the three-step N-GMRES iteration (Section 2.1, Steps I-III and the
+ *     algorithm box), with the window, restart and delta regularisation of the
+ *     Section 2.1 remarks and the Section 2.4 parameters.
+ *
+ * Conventions
+ *   - Every function returns an int status: CP_OK (0), a negative error code,
+ *     or a positive informational code.  Nothing throws across the ABI.  The
+ *     message of the last failure on a handle is cp_last_error(h).
+ *   - Array arguments are DEVICE pointers owned by the caller unless stated
+ *     otherwise.  Work is enqueued on the given HIP stream (stream-ordered);
+ *     functions that must read a scalar back (line search, convergence test)
+ *     synchronise that stream and say so.
+ *   - The library owns only its handle workspace (grown on demand with
+ *     hipMalloc from host calls; never inside a kernel) and the prepared
+ *     structures that cp_tensor_prepare attaches to a tensor.
+ *   - One handle per host thread / stream.  For fixed inputs, device and
+ *     precision mode, results are bitwise reproducible: no kernel uses
+ *     floating-point atomics and every reduction has a fixed order.
+ *
+ * Layouts
+ *   - Dense tensor: C order over (I_1..I_N), last index fastest.
+ *   - Sparse tensor: coordinate format, structure of arrays: coords is an
+ *     order x nnz int32 array (row n holds the zero-based mode-n index of every
+ *     nonzero), values has nnz entries; no repeated coordinates.
+ *   - Factor A^(n): I_n x R, row-major, float64.  The iterate u is the
+ *     concatenation of A^(1)..A^(N) (length L = R * sum_n I_n); a gradient g
+ *     has the same layout.
+ */
+#ifndef CPNG_H
+#define CPNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CP_MAX_ORDER 8
+
+/* ---- status codes ---------------------------------------------------- */
+#define CP_OK            0
+#define CP_EINVAL       -1   /* bad argument (shape, rank, mode, null pointer, dtype/precision mix) */
+#define CP_ENOMEM       -2   /* device or pinned allocation failed */
+#define CP_EDEVICE      -3   /* a HIP runtime call or kernel launch failed */
+#define CP_ESINGULAR    -4   /* a Gammabar^(n) could not be factorised even after the shift */
+#define CP_EDUPLICATE   -5   /* sparse tensor has repeated coordinates */
+#define CP_ENOTFINITE   -6   /* objective or gradient became NaN/Inf */
+#define CP_MAXITER       1   /* cp_decompose: max_iter reached before the tolerance */
+#define CP_LS_FALLBACK   2   /* ngmres_step: line search ended without a strong-Wolfe point */
+
+typedef enum { CP_F32 = 0, CP_F64 = 1 } cp_dtype;
+
+/* Arithmetic of the MTTKRP bulk (every small solve stays float64):
+ *   CP_PREC_FP64            float64 products and sums (tensor float64, or float32 widened)
+ *   CP_PREC_FP32            float32 tensor and factor copies, float32 products and
+ *                           per-workgroup sums, float64 across workgroups
+ *   CP_PREC_BF16X3          dense only: tensor and Khatri-Rao rows split x = hi + lo
+ *                           (both bfloat16); hi*hi + hi*lo + lo*hi on MFMA with
+ *                           float32 accumulation; float64 across workgroups
+ *   CP_PREC_FP32IN_FP64ACC  float32 tensor widened to float64, float64 factors,
+ *                           products and sums (the same kernels as CP_PREC_FP64) */
+typedef enum {
+  CP_PREC_FP64 = 0, CP_PREC_FP32 = 1, CP_PREC_BF16X3 = 2, CP_PREC_FP32IN_FP64ACC = 3
+} cp_precision;
+
+typedef struct cp_handle cp_handle;
+typedef struct cp_ngmres_state cp_ngmres_state;
+
+/* Data tensor descriptor.  The caller fills order..coords; prepared and
+ * norm_sq are written by cp_tensor_prepare. */
+typedef struct cp_tensor {
+  int32_t order;                  /* N, 1 <= N <= CP_MAX_ORDER (2 or more for decompositions) */
+  int64_t dims[CP_MAX_ORDER];     /* I_1..I_N, each >= 1 */
+  int32_t sparse;                 /* 0 = dense, 1 = coordinate format */
+  int32_t dtype;                  /* cp_dtype of values */
+  const void* values;             /* device; dense: prod(dims) values; sparse: nnz values */
+  int64_t nnz;                    /* sparse only (0 allowed) */
+  const int32_t* coords;          /* device, sparse only: order x nnz */
+  void* prepared;                 /* library-owned, from cp_tensor_prepare */
+  double norm_sq;                 /* ||T||_F^2, from cp_tensor_prepare */
+} cp_tensor;
+
+/* Options of cp_decompose / cp_ngmres_create.  cp_options_default fills the
+ * paper's parameters (Section 2.4): window w = 20, eps = 1e-12, line search
+ * ftol = 1e-4, gtol = 1e-2, first step 1, at most 20 evaluations. */
+typedef struct cp_iter_info {
+  int32_t it;          /* iteration index i (state before the iteration) */
+  double f;            /* objective at u_i */
+  double rho;          /* ||g(u_i)||_2 / ||T||_F */
+  double beta;         /* accepted line-search step (NaN if no line search ran) */
+  int32_t restart;     /* 1 if this iteration restarted the window */
+  int32_t nfev;        /* objective/gradient evaluations of the line search */
+  int32_t ls_status;   /* 0 converged, 1 maxfev, 2 xtol, 3 stpmax, 4 stpmin, 5 rounding, -1 none */
+  int32_t m;           /* window size used by Step II */
+  int32_t precision;   /* cp_precision of the bulk MTTKRPs in this iteration */
+} cp_iter_info;
+
+#define CP_METHOD_NGMRES 0
+#define CP_METHOD_ALS    1
+
+typedef struct cp_options {
+  int32_t method;           /* CP_METHOD_NGMRES (default) or CP_METHOD_ALS */
+  int32_t window;           /* w, >= 1 (20) */
+  double eps;               /* delta = eps * max diag(P^T P) (1e-12) */
+  double ls_ftol;           /* sufficient-decrease constant (1e-4) */
+  double ls_gtol;           /* curvature constant (1e-2) */
+  double ls_stp0;           /* first trial step (1.0) */
+  int32_t ls_maxfev;        /* evaluations per line search (20) */
+  double ls_xtol;           /* relative interval width stop (1e-15) */
+  double ls_stpmin;         /* (1e-15) */
+  double ls_stpmax;         /* (1e15) */
+  int32_t max_iter;         /* (1000) */
+  int32_t precision;        /* bulk cp_precision for the first phase (CP_PREC_FP64) */
+  int32_t final_precision;  /* precision after the switch (CP_PREC_FP64) */
+  double switch_rho;        /* switch to final_precision (and restart the window) once
+                               rho <= switch_rho; 0 = never switch (0) */
+  int32_t normalize_accel;  /* normalise the accelerated iterate (1) */
+  cp_iter_info* trace;      /* host, nullable: per-iteration records */
+  int32_t trace_cap;        /* capacity of trace */
+} cp_options;
+
+typedef struct cp_report {
+  int32_t iters;            /* iterations performed */
+  int32_t converged;        /* 1 if rho <= tol */
+  double f;                 /* final objective */
+  double rho;               /* final ||g||_2 / ||T||_F (float64 gradient of the final iterate) */
+  int32_t n_fg;             /* objective/gradient evaluations */
+  int32_t n_restarts;
+  int32_t n_ls_fallback;
+  int32_t switch_iter;      /* iteration at which the precision switched (-1 none) */
+  int32_t n_trace;          /* records written to options.trace */
+  double seconds;           /* host wall time of the call */
+} cp_report;
+
+/* ---- handle ---------------------------------------------------------- */
+
+/* Create a handle on HIP device `device`.  workspace_bytes is an initial
+ * reservation (0 = grow on demand).  Errors: CP_EINVAL (device), CP_ENOMEM. */
+int cp_create(int device, size_t workspace_bytes, cp_handle** h);
+/* Destroy a handle and free its workspace (synchronises the device). */
+int cp_destroy(cp_handle* h);
+/* Message of the last failing call on h (static storage of the handle). */
+const char* cp_last_error(const cp_handle* h);
+void cp_options_default(cp_options* opt);
+
+/* ---- tensors ----------------------------------------------------------- */
+
+/* Validate the descriptor, compute ||T||_F^2 (float64, fixed-order
+ * reduction) and, for sparse tensors, build per-mode copies of the
+ * nonzeros stably sorted by that mode's index plus segment pointers, after
+ * checking coordinate bounds and duplicates.  Synchronises the stream.
+ * Errors: CP_EINVAL (shape, coordinate out of range), CP_EDUPLICATE, CP_ENOMEM. */
+int cp_tensor_prepare(cp_handle* h, cp_tensor* T, hipStream_t stream);
+/* Free what cp_tensor_prepare attached (synchronises the device). */
+int cp_tensor_release(cp_handle* h, cp_tensor* T);
+
+/* ---- hot-path building blocks ---------------------------------------- */
+
+/* MTTKRP (Section 2.3, the product T_(n) Phibar^(n) of the gradient):
+ *   M_out(i, r) = sum over all index tuples with i_mode = i of
+ *                 T(i_1..i_N) * prod_{k != mode} A^(k)(i_k, r)
+ * mode is zero-based; u holds the factors (float64, layout above); M_out is
+ * I_mode x R float64 row-major.  Dense tensors need no preparation; sparse
+ * ones must be prepared.  p selects the bulk arithmetic (cp_precision).
+ * Errors: CP_EINVAL (R < 1, mode out of range, precision not valid for the
+ * tensor: FP32/BF16X3 need a float32 tensor, BF16X3 needs a dense one). */
+int cp_mttkrp(cp_handle* h, const cp_tensor* T, const double* u, int32_t R, int32_t mode,
+              int32_t p, double* M_out, hipStream_t stream);
+
+/* Grams and their Hadamard products (Section 2.3): S^(k) = A^(k)^T A^(k)
+ * for all k (S_out: N x R x R), Gammabar^(n) = Hadamard product of S^(k)
+ * over k != n (gamma_bar_out: N x R x R, nullable), Gamma = Hadamard product
+ * of all S^(k) (gamma_out: R x R, nullable).  All float64. */
+int cp_gram(cp_handle* h, int32_t order, const int64_t* dims, const double* u, int32_t R,
+            double* S_out, double* gamma_bar_out, double* gamma_out, hipStream_t stream);
+
+/* Normalise and reorder the rank-one terms in place (Section 2.3, last
+ * paragraph): each factor column scaled to norm lambda_r^(1/N) with lambda_r
+ * the product of the column norms, terms sorted by decreasing lambda_r
+ * (stable; zero terms become zero and sort last).  If g_inout is non-null it
+ * is mapped to the gradient at the new point (column r of G^(n) divided by
+ * that column's scale, then permuted). */
+int cp_normalize(cp_handle* h, int32_t order, const int64_t* dims, double* u_inout, int32_t R,
+                 double* g_inout, hipStream_t stream);
+
+/* One ALS iteration M(u) in place (Section 2.3): for n = 1..N in order,
+ * A^(n) <- M^(n) (Gammabar^(n))^-1 by Cholesky, the later modes seeing the
+ * updated earlier ones; then, if normalize != 0, cp_normalize.  A
+ * Gammabar^(n) that is not positive definite is retried with a shift of
+ * 1e-14 tr/R and then solved by a pseudo-inverse (cyclic Jacobi eigen-
+ * decomposition), as the float64 reference does. */
+int cp_als_sweep(cp_handle* h, const cp_tensor* T, double* u_inout, int32_t R, int32_t p,
+                 int32_t normalize, hipStream_t stream);
+
+/* Objective and gradient at u (Optimization Problem I; Section 2.3):
+ *   f = 1/2 ||T||^2 - <A^(N), M^(N)> + 1/2 sum_{r,s} Gamma(r,s)
+ *   G^(n) = -M^(n) + A^(n) Gammabar^(n)           for every n
+ * f_out: device, 1 double; g_out: device, L doubles (nullable: f only still
+ * runs every MTTKRP it needs).  T must be prepared (for ||T||^2). */
+int cp_objective_grad(cp_handle* h, const cp_tensor* T, const double* u, int32_t R, int32_t p,
+                      double* f_out, double* g_out, hipStream_t stream);
+
+/* N-GMRES Step II (Section 2.1, accelerated iterate and normal equations):
+ *   p_j = g_bar - G_j, (P^T P + delta I) alpha = -P^T g_bar,
+ *   delta = eps * max_j (P^T P)_jj,  u_hat = u_bar + sum_j alpha_j (u_bar - U_j)
+ * U, G: m x L row-major (window iterates and gradients), 1 <= m <= 64.
+ * If every p_j is zero, alpha = 0.  alpha_out: device m doubles, nullable. */
+int ngmres_accelerate(cp_handle* h, int64_t L, int32_t m, const double* U, const double* G,
+                      const double* u_bar, const double* g_bar, double eps, double* u_hat_out,
+                      double* alpha_out, hipStream_t stream);
+
+/* ---- the method -------------------------------------------------------- */
+
+/* Create an N-GMRES (or ALS) state on a prepared tensor: copies u0 (device,
+ * L doubles), normalises it, evaluates f and g and starts the window.
+ * Keeps the window (w iterates and w gradients) on the device. */
+int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_options* opt,
+                     const double* u0, hipStream_t stream, cp_ngmres_state** st);
+/* One iteration (Steps I-III of the algorithm box for N-GMRES; u <- M(u) for
+ * ALS).  Synchronises the stream (scalar readbacks).  info_out: host,
+ * nullable, describes the iteration just taken.  Returns CP_OK, CP_LS_FALLBACK
+ * or an error. */
+int ngmres_step(cp_handle* h, cp_ngmres_state* st, cp_iter_info* info_out);
+/* Current iterate, gradient (device, nullable) and f, rho (host, nullable). */
+int cp_ngmres_get(cp_handle* h, cp_ngmres_state* st, double* u_out, double* g_out,
+                  double* f_out, double* rho_out);
+int cp_ngmres_destroy(cp_handle* h, cp_ngmres_state* st);
+
+/* Decompose a prepared tensor: iterate until rho = ||g||_2/||T||_F <= tol or
+ * max_iter.  u_inout (device, L doubles): initial guess in, result out.
+ * opt nullable (defaults).  rep_out: host, nullable.  Returns CP_OK,
+ * CP_MAXITER or an error. */
+int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const cp_options* opt,
+                 double* u_inout, cp_report* rep_out, hipStream_t stream);
+
+/* ---- kernel timing ------------------------------------------------------ */
+
+/* Kernel ids for cp_profile_read. */
+#define CP_KERNEL_DENSE_MTTKRP  0   /* main dense MTTKRP kernel (any precision) */
+#define CP_KERNEL_SPARSE_MTTKRP 1   /* main sparse segmented-reduction kernel */
+
+/* Enable (1) or disable (0) HIP-event timing of the main MTTKRP kernels on
+ * the stream each is launched on; enabling clears the counters. */
+int cp_profile(cp_handle* h, int32_t enable);
+/* Synchronise the recorded events and return, for kernel id `kernel`, the
+ * number of timed launches and their summed duration in milliseconds
+ * (host pointers). */
+int cp_profile_read(cp_handle* h, int32_t kernel, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPNG_H */

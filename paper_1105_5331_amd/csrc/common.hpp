@@ -1,0 +1,152 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "cpng.h"
+
+namespace cpng {
+
+// A device buffer owned by the handle, grown on demand from host code.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct Status {
+  int code = CP_OK;
+  std::string msg;
+};
+
+}  // namespace cpng
+
+struct cp_handle {
+  int device = 0;
+  std::string err;
+  // Workspace slices, each grown on demand (host calls only).
+  cpng::DevBuf part;     // MTTKRP per-workgroup partials
+  cpng::DevBuf stage;    // float32 copies of the factors
+  cpng::DevBuf mbuf;     // MTTKRP outputs used internally (N x maxI x R doubles)
+  cpng::DevBuf small;    // Grams, Gammabar, Gamma, scales, perms, alpha, scalars
+  cpng::DevBuf red;      // reduction partials
+  cpng::DevBuf carry;    // sparse segment carries
+  cpng::DevBuf tmpu;     // scratch iterate-sized vectors
+  double* pinned = nullptr;   // host pinned readback area (64 doubles)
+  int* flags = nullptr;       // device status word (ALS solve fallbacks)
+  // optional event timing of the main MTTKRP kernels
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[2];
+  int64_t prof_launches[2] = {0, 0};
+  double prof_ms[2] = {0.0, 0.0};
+};
+
+namespace cpng {
+
+// Sets h->err and returns code.
+int fail(cp_handle* h, int code, const char* fmt, ...);
+
+// Ensure `b` holds at least `bytes`; synchronises `stream` before freeing an
+// old allocation that may still be in use.
+int ensure(cp_handle* h, DevBuf& b, size_t bytes, hipStream_t stream);
+
+#define CP_HIP(h, call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::cpng::fail((h), CP_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CP_LAUNCH_CHECK(h)                                                           \
+  do {                                                                               \
+    hipError_t e_ = hipGetLastError();                                               \
+    if (e_ != hipSuccess)                                                            \
+      return ::cpng::fail((h), CP_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+#define CP_TRY(x)            \
+  do {                       \
+    int s_ = (x);            \
+    if (s_ < 0) return s_;   \
+  } while (0)
+
+// Shape helpers.
+struct Shape {
+  int N = 0;
+  int64_t dims[CP_MAX_ORDER] = {};
+  int64_t off[CP_MAX_ORDER + 1] = {};   // factor offsets in u, in rows (multiply by R)
+  int64_t total() const {
+    int64_t t = 1;
+    for (int k = 0; k < N; ++k) t *= dims[k];
+    return t;
+  }
+  int64_t sum_dims() const { return off[N]; }
+  int64_t max_dim() const {
+    int64_t m = 0;
+    for (int k = 0; k < N; ++k) m = dims[k] > m ? dims[k] : m;
+    return m;
+  }
+};
+
+int make_shape(cp_handle* h, int order, const int64_t* dims, Shape* s);
+
+// Event timing around a main kernel launch (no-op unless h->prof).
+struct KernelTimer {
+  cp_handle* h;
+  int id;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  KernelTimer(cp_handle* h_, int id_, hipStream_t st_);
+  ~KernelTimer();
+};
+
+// Library-owned per-mode sorted copies of a sparse tensor.
+struct SparseMode {
+  int32_t* coords = nullptr;   // (N-1) x nnz: the other modes' indices, sorted by this mode
+  void* values = nullptr;      // nnz values sorted by this mode
+  int64_t* seg = nullptr;      // I_n + 1 segment pointers
+};
+struct SparsePrepared {
+  int N = 0;
+  int64_t nnz = 0;
+  int dtype = CP_F32;
+  SparseMode mode[CP_MAX_ORDER];
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+int dense_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
+                 int mode, int prec, double* M, hipStream_t st);
+int sparse_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
+                  int mode, int prec, double* M, hipStream_t st);
+int sparse_prepare(cp_handle* h, cp_tensor* T, const Shape& s, hipStream_t st);
+int sparse_release(cp_handle* h, cp_tensor* T);
+int stage_factors_f32(cp_handle* h, const double* u, int64_t L, float** out, hipStream_t st);
+
+// small kernels
+int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, double* Gbar,
+             double* Gam, hipStream_t st);
+int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStream_t st);
+int mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int R, double* A,
+               hipStream_t st);
+int grad_epilogue(cp_handle* h, const double* M, const double* A, const double* Gbar, int64_t I,
+                  int R, double* G, hipStream_t st);
+// out[0] = sum x*y (fixed-order two-stage reduction), device result
+int dot(cp_handle* h, const double* x, const double* y, int64_t n, double* out, hipStream_t st);
+int sumsq_tensor(cp_handle* h, const void* v, int dtype, int64_t n, double* out, hipStream_t st);
+// f = 0.5*normsq - dotAM + 0.5*sum(Gamma)
+int objective_combine(cp_handle* h, double normsq, const double* dotAM, const double* Gam, int R,
+                      double* f, hipStream_t st);
+int axpy_to(cp_handle* h, const double* x, double a, const double* d, double* y, int64_t n,
+            hipStream_t st);   // y = x + a*d
+int sub_to(cp_handle* h, const double* a, const double* b, double* y, int64_t n,
+           hipStream_t st);    // y = a - b
+int step2(cp_handle* h, int64_t L, int m, const double* const* U, const double* const* G,
+          const double* ubar, const double* gbar, double eps, double* uhat, double* alpha,
+          hipStream_t st);
+
+}  // namespace cpng

@@ -1,0 +1,773 @@
+// Host side of the C ABI: argument checks, the objective/gradient and ALS
+// sweep built from the device kernels, the N-GMRES iteration (Section 2.1,
+// Steps I-III) with its Moré–Thuente line search, and cp_decompose.
+//
+// Everything iterate-sized stays on the device.  Per N-GMRES iteration the
+// host reads back: rho at the top (1 double), the slope g(u_bar)^T d after
+// Step II (1 double), and (f, phi') for every line-search trial (2 doubles).
+#include "common.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+using namespace cpng;
+
+struct cp_ngmres_state {
+  const cp_tensor* T = nullptr;
+  Shape s;
+  int R = 0;
+  int64_t L = 0;
+  cp_options opt{};
+  hipStream_t st = nullptr;
+  int prec = CP_PREC_FP64;
+  bool switched = false;
+  int it = 0;
+  double f = 0.0, rho = 0.0, normT = 0.0;
+  int n_fg = 0, n_restarts = 0, n_fallback = 0, switch_iter = -1;
+  // device buffers
+  double* mem = nullptr;
+  double *u, *g, *ubar, *gbar, *uhat, *d, *ut, *gt, *gbest, *scal;  // scal: 8 doubles
+  double *winU, *winG;
+  int wcap = 0, wcount = 0, whead = 0;   // ring buffer: slot (whead + j) % wcap, j oldest first
+};
+
+namespace {
+
+bool is_f64_acc(int p) { return p == CP_PREC_FP64 || p == CP_PREC_FP32IN_FP64ACC; }
+
+int check_prec(cp_handle* h, const cp_tensor* T, int p) {
+  if (p < 0 || p > 3) return fail(h, CP_EINVAL, "unknown precision %d", p);
+  if ((p == CP_PREC_FP32 || p == CP_PREC_BF16X3) && T->dtype != CP_F32)
+    return fail(h, CP_EINVAL, "precision %d needs a float32 tensor", p);
+  if (p == CP_PREC_BF16X3 && T->sparse)
+    return fail(h, CP_EINVAL, "BF16X3 applies to dense tensors only");
+  return CP_OK;
+}
+
+int check_tensor(cp_handle* h, const cp_tensor* T, Shape* s) {
+  if (!T) return fail(h, CP_EINVAL, "null tensor");
+  CP_TRY(make_shape(h, T->order, T->dims, s));
+  if (T->dtype != CP_F32 && T->dtype != CP_F64) return fail(h, CP_EINVAL, "bad dtype %d", T->dtype);
+  if (!T->sparse && !T->values) return fail(h, CP_EINVAL, "dense tensor without values");
+  if (!T->sparse && s->total() > (int64_t(1) << 40))
+    return fail(h, CP_EINVAL, "dense tensor too large");
+  return CP_OK;
+}
+
+int check_rank(cp_handle* h, int R) {
+  if (R < 1 || R > 64) return fail(h, CP_EINVAL, "rank %d outside 1..64", R);
+  return CP_OK;
+}
+
+int mttkrp_any(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R, int mode,
+               int prec, double* M, hipStream_t st) {
+  if (T->sparse) return sparse_mttkrp(h, T, s, u, R, mode, prec, M, st);
+  return dense_mttkrp(h, T, s, u, R, mode, prec, M, st);
+}
+
+// Internal buffers: M for every mode (sum_dims x R), S/Gbar/Gam, scalars.
+struct Scratch {
+  double* M;      // N blocks, mode n at off[n]*R
+  double* S;      // N R R
+  double* Gbar;   // N R R
+  double* Gam;    // R R
+  double* dot;    // 4 doubles
+};
+
+int scratch(cp_handle* h, const Shape& s, int R, hipStream_t st, Scratch* sc) {
+  const size_t L = (size_t)s.sum_dims() * R;
+  const size_t need = L + (size_t)(2 * s.N * R * R + R * R + 8);
+  CP_TRY(ensure(h, h->mbuf, sizeof(double) * need, st));
+  double* b = static_cast<double*>(h->mbuf.ptr);
+  sc->M = b;
+  sc->S = b + L;
+  sc->Gbar = sc->S + s.N * R * R;
+  sc->Gam = sc->Gbar + s.N * R * R;
+  sc->dot = sc->Gam + R * R;
+  return CP_OK;
+}
+
+int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
+                        int prec, double* f_out, double* g_out, hipStream_t st) {
+  Scratch sc;
+  CP_TRY(scratch(h, s, R, st, &sc));
+  CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, sc.Gam, st));
+  for (int n = 0; n < s.N; ++n) {
+    double* Mn = sc.M + s.off[n] * R;
+    CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
+    if (g_out)
+      CP_TRY(grad_epilogue(h, Mn, u + s.off[n] * R, sc.Gbar + n * R * R, s.dims[n], R,
+                           g_out + s.off[n] * R, st));
+  }
+  if (f_out) {
+    const int n = s.N - 1;
+    CP_TRY(dot(h, u + s.off[n] * R, sc.M + s.off[n] * R, s.dims[n] * R, sc.dot, st));
+    CP_TRY(objective_combine(h, T->norm_sq, sc.dot, sc.Gam, R, f_out, st));
+  }
+  return CP_OK;
+}
+
+int als_sweep_impl(cp_handle* h, const cp_tensor* T, const Shape& s, double* u, int R, int prec,
+                   int normalize_after, hipStream_t st) {
+  Scratch sc;
+  CP_TRY(scratch(h, s, R, st, &sc));
+  for (int n = 0; n < s.N; ++n) {
+    CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, nullptr, st));
+    double* Mn = sc.M + s.off[n] * R;
+    CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
+    CP_TRY(mode_solve(h, Mn, sc.Gbar + n * R * R, s.dims[n], R, u + s.off[n] * R, st));
+  }
+  if (normalize_after) CP_TRY(normalize(h, s, u, R, nullptr, st));
+  return CP_OK;
+}
+
+// Blocking readback of n doubles from device memory.
+int readback(cp_handle* h, const double* src, int n, double* dst, hipStream_t st) {
+  CP_HIP(h, hipMemcpyAsync(h->pinned, src, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  CP_HIP(h, hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i) dst[i] = h->pinned[i];
+  return CP_OK;
+}
+
+// ---- Moré–Thuente line search (host control, device evaluations) ----------
+// The method of More & Thuente (ACM TOMS 20(3), 1994): strong-Wolfe search
+// with an interval of uncertainty, the auxiliary function psi in the first
+// stage and safeguarded cubic/quadratic/secant trial steps (four cases).
+struct MTState {
+  double stx, fx, gx, sty, fy, gy;
+  bool brackt;
+};
+
+double cubic_min(double a, double fa, double da, double b, double fb, double db) {
+  const double theta = 3.0 * (fa - fb) / (b - a) + da + db;
+  const double sc = std::max({std::fabs(theta), std::fabs(da), std::fabs(db)});
+  double gamma = sc * std::sqrt((theta / sc) * (theta / sc) - (da / sc) * (db / sc));
+  if (b < a) gamma = -gamma;
+  const double p = (gamma - da) + theta;
+  const double q = ((gamma - da) + gamma) + db;
+  return a + (p / q) * (b - a);
+}
+
+// One trial-step update; returns the new trial step.
+double mt_step(MTState& m, double stp, double fp, double dp, double stmin, double stmax) {
+  const double sgnd = dp * std::copysign(1.0, m.gx);
+  double stpf;
+  if (fp > m.fx) {                                   // case 1
+    const double stpc = cubic_min(m.stx, m.fx, m.gx, stp, fp, dp);
+    const double stpq = m.stx + ((m.gx / ((m.fx - fp) / (stp - m.stx) + m.gx)) / 2.0) * (stp - m.stx);
+    stpf = std::fabs(stpc - m.stx) < std::fabs(stpq - m.stx) ? stpc : stpc + (stpq - stpc) / 2.0;
+    m.brackt = true;
+  } else if (sgnd < 0.0) {                           // case 2
+    const double stpc = cubic_min(stp, fp, dp, m.stx, m.fx, m.gx);
+    const double stpq = stp + (dp / (dp - m.gx)) * (m.stx - stp);
+    stpf = std::fabs(stpc - stp) > std::fabs(stpq - stp) ? stpc : stpq;
+    m.brackt = true;
+  } else if (std::fabs(dp) < std::fabs(m.gx)) {      // case 3
+    const double theta = 3.0 * (m.fx - fp) / (stp - m.stx) + m.gx + dp;
+    const double sc = std::max({std::fabs(theta), std::fabs(m.gx), std::fabs(dp)});
+    double gamma = sc * std::sqrt(std::max(0.0, (theta / sc) * (theta / sc) - (m.gx / sc) * (dp / sc)));
+    if (stp > m.stx) gamma = -gamma;
+    const double p = (gamma - dp) + theta;
+    const double q = (gamma + (m.gx - dp)) + gamma;
+    const double r = p / q;
+    double stpc;
+    if (r < 0.0 && gamma != 0.0) stpc = stp + r * (m.stx - stp);
+    else if (stp > m.stx) stpc = stmax;
+    else stpc = stmin;
+    const double stpq = stp + (dp / (dp - m.gx)) * (m.stx - stp);
+    if (m.brackt) {
+      stpf = std::fabs(stpc - stp) < std::fabs(stpq - stp) ? stpc : stpq;
+      const double lim = stp + 0.66 * (m.sty - stp);
+      stpf = stp > m.stx ? std::min(lim, stpf) : std::max(lim, stpf);
+    } else {
+      stpf = std::fabs(stpc - stp) > std::fabs(stpq - stp) ? stpc : stpq;
+      stpf = std::max(stmin, std::min(stmax, stpf));
+    }
+  } else {                                           // case 4
+    if (m.brackt) stpf = cubic_min(stp, fp, dp, m.sty, m.fy, m.gy);
+    else stpf = stp > m.stx ? stmax : stmin;
+  }
+  if (fp > m.fx) {
+    m.sty = stp; m.fy = fp; m.gy = dp;
+  } else {
+    if (sgnd < 0.0) { m.sty = m.stx; m.fy = m.fx; m.gy = m.gx; }
+    m.stx = stp; m.fx = fp; m.gx = dp;
+  }
+  return stpf;
+}
+
+enum { LS_CONVERGED = 0, LS_MAXFEV = 1, LS_XTOL = 2, LS_STPMAX = 3, LS_STPMIN = 4, LS_ROUNDING = 5 };
+
+// Evaluate phi(beta) = f(ubar + beta d), phi'(beta) = g(ubar + beta d)^T d.
+int ls_eval(cp_handle* h, cp_ngmres_state* S, double beta, double* f, double* dphi) {
+  CP_TRY(axpy_to(h, S->ubar, beta, S->d, S->ut, S->L, S->st));
+  CP_TRY(objective_grad_impl(h, S->T, S->s, S->ut, S->R, S->prec, S->scal, S->gt, S->st));
+  S->n_fg++;
+  CP_TRY(dot(h, S->gt, S->d, S->L, S->scal + 1, S->st));
+  double v[2];
+  CP_TRY(readback(h, S->scal, 2, v, S->st));
+  *f = v[0];
+  *dphi = v[1];
+  if (!std::isfinite(v[0]) || !std::isfinite(v[1]))
+    return fail(h, CP_ENOTFINITE, "objective or slope not finite in the line search");
+  return CP_OK;
+}
+
+// Runs the search from (f0, g0 < 0).  On return *beta, *f_acc hold the accepted
+// step and objective and S->gt (converged) or S->gbest (fallback) its gradient.
+int more_thuente(cp_handle* h, cp_ngmres_state* S, double f0, double g0, double* beta,
+                 double* f_acc, const double** g_acc, int* nfev_out, int* status_out) {
+  const cp_options& o = S->opt;
+  const double ftol = o.ls_ftol, gtol = o.ls_gtol, xtol = o.ls_xtol;
+  const double stpmin = o.ls_stpmin, stpmax = o.ls_stpmax;
+  double stp = o.ls_stp0;
+  MTState m{0.0, f0, g0, 0.0, f0, g0, false};
+  int stage = 1;
+  const double gtest = ftol * g0;
+  double width = stpmax - stpmin, width1 = 2.0 * width;
+  double stmin = 0.0, stmax = stp + 4.0 * stp;
+  double best_f = INFINITY, best_stp = 0.0;
+  int nfev = 0;
+  for (;;) {
+    double f, g;
+    CP_TRY(ls_eval(h, S, stp, &f, &g));
+    ++nfev;
+    if (f < best_f) {
+      best_f = f;
+      best_stp = stp;
+      CP_HIP(h, hipMemcpyAsync(S->gbest, S->gt, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+    }
+    const double ftest = f0 + stp * gtest;
+    if (stage == 1 && f <= ftest && g >= 0.0) stage = 2;
+    int status = -1;
+    if (f <= ftest && std::fabs(g) <= gtol * (-g0)) status = LS_CONVERGED;
+    else if (stp == stpmin && (f > ftest || g >= gtest)) status = LS_STPMIN;
+    else if (stp == stpmax && f <= ftest && g <= gtest) status = LS_STPMAX;
+    else if (m.brackt && stmax - stmin <= xtol * stmax) status = LS_XTOL;
+    else if (m.brackt && (stp <= stmin || stp >= stmax)) status = LS_ROUNDING;
+    else if (nfev >= o.ls_maxfev) status = LS_MAXFEV;
+    if (status >= 0) {
+      *nfev_out = nfev;
+      *status_out = status;
+      if (status == LS_CONVERGED) {
+        *beta = stp;
+        *f_acc = f;
+        *g_acc = S->gt;
+      } else if (best_f < f0) {
+        *beta = best_stp;
+        *f_acc = best_f;
+        *g_acc = S->gbest;
+      } else {
+        *beta = 0.0;
+        *f_acc = f0;
+        *g_acc = nullptr;
+      }
+      return CP_OK;
+    }
+    if (stage == 1 && f <= m.fx && f > ftest) {
+      MTState mm{m.stx, m.fx - m.stx * gtest, m.gx - gtest, m.sty, m.fy - m.sty * gtest,
+                 m.gy - gtest, m.brackt};
+      stp = mt_step(mm, stp, f - stp * gtest, g - gtest, stmin, stmax);
+      m.stx = mm.stx; m.sty = mm.sty; m.brackt = mm.brackt;
+      m.fx = mm.fx + mm.stx * gtest;
+      m.fy = mm.fy + mm.sty * gtest;
+      m.gx = mm.gx + gtest;
+      m.gy = mm.gy + gtest;
+    } else {
+      stp = mt_step(m, stp, f, g, stmin, stmax);
+    }
+    if (m.brackt) {
+      if (std::fabs(m.sty - m.stx) >= 0.66 * width1) stp = m.stx + 0.5 * (m.sty - m.stx);
+      width1 = width;
+      width = std::fabs(m.sty - m.stx);
+      stmin = std::min(m.stx, m.sty);
+      stmax = std::max(m.stx, m.sty);
+    } else {
+      stmin = stp + 1.1 * (stp - m.stx);
+      stmax = stp + 4.0 * (stp - m.stx);
+    }
+    stp = std::min(std::max(stp, stpmin), stpmax);
+    if (m.brackt && (stp <= stmin || stp >= stmax || stmax - stmin <= xtol * stmax)) stp = m.stx;
+  }
+}
+
+double* win_u(cp_ngmres_state* S, int j) { return S->winU + (size_t)((S->whead + j) % S->wcap) * S->L; }
+double* win_g(cp_ngmres_state* S, int j) { return S->winG + (size_t)((S->whead + j) % S->wcap) * S->L; }
+
+int window_push(cp_handle* h, cp_ngmres_state* S) {
+  if (S->wcount == S->wcap) {   // drop the oldest
+    S->whead = (S->whead + 1) % S->wcap;
+    S->wcount--;
+  }
+  const int j = S->wcount;
+  CP_HIP(h, hipMemcpyAsync(win_u(S, j), S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+  CP_HIP(h, hipMemcpyAsync(win_g(S, j), S->g, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+  S->wcount++;
+  return CP_OK;
+}
+
+int eval_current(cp_handle* h, cp_ngmres_state* S) {
+  CP_TRY(objective_grad_impl(h, S->T, S->s, S->u, S->R, S->prec, S->scal, S->g, S->st));
+  S->n_fg++;
+  CP_TRY(dot(h, S->g, S->g, S->L, S->scal + 1, S->st));
+  double v[2];
+  CP_TRY(readback(h, S->scal, 2, v, S->st));
+  S->f = v[0];
+  S->rho = std::sqrt(std::max(0.0, v[1])) / S->normT;
+  if (!std::isfinite(S->f) || !std::isfinite(S->rho))
+    return fail(h, CP_ENOTFINITE, "objective or gradient not finite");
+  return CP_OK;
+}
+
+}  // namespace
+
+// ============================== C ABI =====================================
+extern "C" {
+
+void cp_options_default(cp_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->method = CP_METHOD_NGMRES;
+  o->window = 20;
+  o->eps = 1e-12;
+  o->ls_ftol = 1e-4;
+  o->ls_gtol = 1e-2;
+  o->ls_stp0 = 1.0;
+  o->ls_maxfev = 20;
+  o->ls_xtol = 1e-15;
+  o->ls_stpmin = 1e-15;
+  o->ls_stpmax = 1e15;
+  o->max_iter = 1000;
+  o->precision = CP_PREC_FP64;
+  o->final_precision = CP_PREC_FP64;
+  o->switch_rho = 0.0;
+  o->normalize_accel = 1;
+  o->trace = nullptr;
+  o->trace_cap = 0;
+}
+
+int cp_create(int device, size_t workspace_bytes, cp_handle** out) {
+  if (!out) return CP_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CP_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return CP_EDEVICE;
+  auto* h = new (std::nothrow) cp_handle();
+  if (!h) return CP_ENOMEM;
+  h->device = device;
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->pinned), 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&h->flags), 16 * sizeof(int)) != hipSuccess) {
+    delete h;
+    return CP_ENOMEM;
+  }
+  (void)hipMemset(h->flags, 0, 16 * sizeof(int));
+  if (workspace_bytes > 0 && ensure(h, h->part, workspace_bytes, nullptr) != CP_OK) {
+    cp_destroy(h);
+    return CP_ENOMEM;
+  }
+  *out = h;
+  return CP_OK;
+}
+
+int cp_destroy(cp_handle* h) {
+  if (!h) return CP_OK;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&h->part, &h->stage, &h->mbuf, &h->small, &h->red, &h->carry, &h->tmpu};
+  for (DevBuf* b : bufs)
+    if (b->ptr) (void)hipFree(b->ptr);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->flags) (void)hipFree(h->flags);
+  for (auto& v : h->ev_pending)
+    for (auto& pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  delete h;
+  return CP_OK;
+}
+
+int cp_profile(cp_handle* h, int32_t enable) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  CP_HIP(h, hipDeviceSynchronize());
+  for (auto& v : h->ev_pending) {
+    for (auto& pr : v) {
+      h->ev_pool.push_back(pr.first);
+      h->ev_pool.push_back(pr.second);
+    }
+    v.clear();
+  }
+  for (int k = 0; k < 2; ++k) {
+    h->prof_launches[k] = 0;
+    h->prof_ms[k] = 0.0;
+  }
+  h->prof = enable != 0;
+  return CP_OK;
+}
+
+int cp_profile_read(cp_handle* h, int32_t kernel, int64_t* launches, double* total_ms) {
+  if (!h || kernel < 0 || kernel > 1 || !launches || !total_ms) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  auto& v = h->ev_pending[kernel];
+  for (auto& pr : v) {
+    float ms = 0.f;
+    CP_HIP(h, hipEventSynchronize(pr.second));
+    CP_HIP(h, hipEventElapsedTime(&ms, pr.first, pr.second));
+    h->prof_ms[kernel] += ms;
+    h->prof_launches[kernel]++;
+    h->ev_pool.push_back(pr.first);
+    h->ev_pool.push_back(pr.second);
+  }
+  v.clear();
+  *launches = h->prof_launches[kernel];
+  *total_ms = h->prof_ms[kernel];
+  return CP_OK;
+}
+
+const char* cp_last_error(const cp_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+int cp_tensor_prepare(cp_handle* h, cp_tensor* T, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  Shape s;
+  CP_TRY(check_tensor(h, T, &s));
+  if (T->prepared) CP_TRY(cp_tensor_release(h, T));
+  const int64_t n = T->sparse ? T->nnz : s.total();
+  CP_TRY(ensure(h, h->small, 4096, st));
+  double* d = static_cast<double*>(h->small.ptr);
+  if (n > 0) {
+    CP_TRY(sumsq_tensor(h, T->values, T->dtype, n, d, st));
+    double v;
+    CP_TRY(readback(h, d, 1, &v, st));
+    T->norm_sq = v;
+  } else {
+    T->norm_sq = 0.0;
+  }
+  if (T->sparse) CP_TRY(sparse_prepare(h, T, s, st));
+  return CP_OK;
+}
+
+int cp_tensor_release(cp_handle* h, cp_tensor* T) {
+  if (!h || !T) return CP_EINVAL;
+  if (T->sparse) return sparse_release(h, T);
+  T->prepared = nullptr;
+  return CP_OK;
+}
+
+int cp_mttkrp(cp_handle* h, const cp_tensor* T, const double* u, int32_t R, int32_t mode,
+              int32_t p, double* M_out, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  Shape s;
+  CP_TRY(check_tensor(h, T, &s));
+  if (R < 1) return fail(h, CP_EINVAL, "rank %d < 1", R);
+  if (mode < 0 || mode >= s.N) return fail(h, CP_EINVAL, "mode %d outside 0..%d", mode, s.N - 1);
+  if (!u || !M_out) return fail(h, CP_EINVAL, "null factor or output pointer");
+  CP_TRY(check_prec(h, T, p));
+  if (T->sparse && R > 64) return fail(h, CP_EINVAL, "sparse MTTKRP supports R <= 64");
+  return mttkrp_any(h, T, s, u, R, mode, p, M_out, st);
+}
+
+int cp_gram(cp_handle* h, int32_t order, const int64_t* dims, const double* u, int32_t R,
+            double* S_out, double* gamma_bar_out, double* gamma_out, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  if (!dims || !u || !S_out) return fail(h, CP_EINVAL, "null argument");
+  Shape s;
+  CP_TRY(make_shape(h, order, dims, &s));
+  CP_TRY(check_rank(h, R));
+  return gram_all(h, s, u, R, S_out, gamma_bar_out, gamma_out, st);
+}
+
+int cp_normalize(cp_handle* h, int32_t order, const int64_t* dims, double* u, int32_t R, double* g,
+                 hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  if (!dims || !u) return fail(h, CP_EINVAL, "null argument");
+  Shape s;
+  CP_TRY(make_shape(h, order, dims, &s));
+  CP_TRY(check_rank(h, R));
+  return normalize(h, s, u, R, g, st);
+}
+
+int cp_als_sweep(cp_handle* h, const cp_tensor* T, double* u, int32_t R, int32_t p,
+                 int32_t normalize_after, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  Shape s;
+  CP_TRY(check_tensor(h, T, &s));
+  CP_TRY(check_rank(h, R));
+  CP_TRY(check_prec(h, T, p));
+  if (!u) return fail(h, CP_EINVAL, "null iterate");
+  return als_sweep_impl(h, T, s, u, R, p, normalize_after, st);
+}
+
+int cp_objective_grad(cp_handle* h, const cp_tensor* T, const double* u, int32_t R, int32_t p,
+                      double* f_out, double* g_out, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  Shape s;
+  CP_TRY(check_tensor(h, T, &s));
+  CP_TRY(check_rank(h, R));
+  CP_TRY(check_prec(h, T, p));
+  if (!u || !f_out) return fail(h, CP_EINVAL, "null iterate or objective pointer");
+  if (T->sparse && !T->prepared) return fail(h, CP_EINVAL, "sparse tensor is not prepared");
+  return objective_grad_impl(h, T, s, u, R, p, f_out, g_out, st);
+}
+
+int ngmres_accelerate(cp_handle* h, int64_t L, int32_t m, const double* U, const double* G,
+                      const double* u_bar, const double* g_bar, double eps, double* u_hat_out,
+                      double* alpha_out, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  if (L < 1 || m < 1 || m > 64) return fail(h, CP_EINVAL, "need L >= 1 and 1 <= m <= 64");
+  if (!U || !G || !u_bar || !g_bar || !u_hat_out) return fail(h, CP_EINVAL, "null argument");
+  if (!(eps >= 0.0)) return fail(h, CP_EINVAL, "eps must be >= 0");
+  const double* Up[64];
+  const double* Gp[64];
+  for (int j = 0; j < m; ++j) {
+    Up[j] = U + (size_t)j * L;
+    Gp[j] = G + (size_t)j * L;
+  }
+  double* alpha = alpha_out;
+  if (!alpha) {
+    CP_TRY(ensure(h, h->small, 64 * 1024, st));
+    alpha = static_cast<double*>(h->small.ptr) + 4096;
+  }
+  return step2(h, L, m, Up, Gp, u_bar, g_bar, eps, u_hat_out, alpha, st);
+}
+
+int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_options* opt,
+                     const double* u0, hipStream_t st, cp_ngmres_state** out) {
+  if (!h || !out) return CP_EINVAL;
+  *out = nullptr;
+  CP_HIP(h, hipSetDevice(h->device));
+  Shape s;
+  CP_TRY(check_tensor(h, T, &s));
+  CP_TRY(check_rank(h, R));
+  if (!u0) return fail(h, CP_EINVAL, "null initial guess");
+  if (T->sparse && !T->prepared) return fail(h, CP_EINVAL, "sparse tensor is not prepared");
+  if (!(T->norm_sq > 0.0)) return fail(h, CP_EINVAL, "tensor not prepared or zero (||T|| = 0)");
+  cp_options o;
+  if (opt) o = *opt;
+  else cp_options_default(&o);
+  if (o.window < 1 || o.window > 64) return fail(h, CP_EINVAL, "window must be in 1..64");
+  if (o.ls_maxfev < 1 || !(o.ls_stp0 > 0.0)) return fail(h, CP_EINVAL, "bad line-search options");
+  CP_TRY(check_prec(h, T, o.precision));
+  CP_TRY(check_prec(h, T, o.final_precision));
+  auto* S = new (std::nothrow) cp_ngmres_state();
+  if (!S) return fail(h, CP_ENOMEM, "host allocation failed");
+  S->T = T;
+  S->s = s;
+  S->R = R;
+  S->L = s.sum_dims() * R;
+  S->opt = o;
+  S->st = st;
+  S->prec = o.precision;
+  S->normT = std::sqrt(T->norm_sq);
+  S->wcap = o.method == CP_METHOD_ALS ? 1 : o.window;
+  const size_t nvec = 9 + 2 * (size_t)S->wcap;
+  if (hipMalloc(&S->mem, sizeof(double) * (nvec * S->L + 80)) != hipSuccess) {
+    delete S;
+    return fail(h, CP_ENOMEM, "state allocation failed");
+  }
+  double* p = S->mem;
+  S->u = p; p += S->L;
+  S->g = p; p += S->L;
+  S->ubar = p; p += S->L;
+  S->gbar = p; p += S->L;
+  S->uhat = p; p += S->L;
+  S->d = p; p += S->L;
+  S->ut = p; p += S->L;
+  S->gt = p; p += S->L;
+  S->gbest = p; p += S->L;
+  S->winU = p; p += (size_t)S->wcap * S->L;
+  S->winG = p; p += (size_t)S->wcap * S->L;
+  S->scal = p;
+  int rc = CP_OK;
+  if (hipMemcpyAsync(S->u, u0, sizeof(double) * S->L, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    rc = fail(h, CP_EDEVICE, "copy of the initial guess failed");
+  if (rc == CP_OK) rc = normalize(h, s, S->u, R, nullptr, st);
+  if (rc == CP_OK) rc = eval_current(h, S);
+  if (rc == CP_OK) rc = window_push(h, S);
+  if (rc < 0) {
+    cp_ngmres_destroy(h, S);
+    return rc;
+  }
+  *out = S;
+  return CP_OK;
+}
+
+int cp_ngmres_destroy(cp_handle* h, cp_ngmres_state* S) {
+  if (!S) return CP_OK;
+  if (h) (void)hipSetDevice(h->device);
+  if (S->st) (void)hipStreamSynchronize(S->st);
+  if (S->mem) (void)hipFree(S->mem);
+  delete S;
+  return CP_OK;
+}
+
+int cp_ngmres_get(cp_handle* h, cp_ngmres_state* S, double* u_out, double* g_out, double* f_out,
+                  double* rho_out) {
+  if (!h || !S) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  if (u_out)
+    CP_HIP(h, hipMemcpyAsync(u_out, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+  if (g_out)
+    CP_HIP(h, hipMemcpyAsync(g_out, S->g, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+  if (f_out) *f_out = S->f;
+  if (rho_out) *rho_out = S->rho;
+  return CP_OK;
+}
+
+int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
+  if (!h || !S) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  cp_iter_info rec{};
+  rec.it = S->it;
+  rec.f = S->f;
+  rec.rho = S->rho;
+  rec.beta = NAN;
+  rec.ls_status = -1;
+  rec.m = S->wcount;
+  rec.precision = S->prec;
+  int rc = CP_OK;
+  const int L = 0;
+  (void)L;
+  if (S->opt.method == CP_METHOD_ALS) {
+    CP_TRY(als_sweep_impl(h, S->T, S->s, S->u, S->R, S->prec, 1, S->st));
+    CP_TRY(eval_current(h, S));
+  } else {
+    // Step I: u_bar = M(u_i); f, g at u_bar
+    CP_HIP(h, hipMemcpyAsync(S->ubar, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+    CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st));
+    CP_TRY(objective_grad_impl(h, S->T, S->s, S->ubar, S->R, S->prec, S->scal, S->gbar, S->st));
+    S->n_fg++;
+    double fbar;
+    CP_TRY(readback(h, S->scal, 1, &fbar, S->st));
+    // Step II over the window
+    const double* Up[64];
+    const double* Gp[64];
+    for (int j = 0; j < S->wcount; ++j) {
+      Up[j] = win_u(S, j);
+      Gp[j] = win_g(S, j);
+    }
+    CP_TRY(step2(h, S->L, S->wcount, Up, Gp, S->ubar, S->gbar, S->opt.eps, S->uhat,
+                 S->scal + 8, S->st));
+    if (S->opt.normalize_accel) CP_TRY(normalize(h, S->s, S->uhat, S->R, nullptr, S->st));
+    CP_TRY(sub_to(h, S->uhat, S->ubar, S->d, S->L, S->st));
+    CP_TRY(dot(h, S->gbar, S->d, S->L, S->scal + 2, S->st));
+    double slope;
+    CP_TRY(readback(h, S->scal + 2, 1, &slope, S->st));
+    const double* gnew = S->gbar;
+    double fnew = fbar;
+    double beta = 0.0;
+    if (!(slope < 0.0)) {
+      // restart: u_{i+1} = u_bar, window back to one iterate
+      rec.restart = 1;
+      S->n_restarts++;
+      S->wcount = 0;
+      S->whead = 0;
+    } else {
+      int nfev = 0, status = 0;
+      const double* gacc = nullptr;
+      CP_TRY(more_thuente(h, S, fbar, slope, &beta, &fnew, &gacc, &nfev, &status));
+      rec.nfev = nfev;
+      rec.ls_status = status;
+      rec.beta = beta;
+      if (status != LS_CONVERGED) {
+        S->n_fallback++;
+        rc = CP_LS_FALLBACK;
+      }
+      if (gacc) gnew = gacc;
+      else { beta = 0.0; fnew = fbar; gnew = S->gbar; }
+    }
+    if (beta != 0.0) CP_TRY(axpy_to(h, S->ubar, beta, S->d, S->u, S->L, S->st));
+    else CP_HIP(h, hipMemcpyAsync(S->u, S->ubar, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+    CP_HIP(h, hipMemcpyAsync(S->g, gnew, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+    CP_TRY(normalize(h, S->s, S->u, S->R, S->g, S->st));
+    S->f = fnew;
+    CP_TRY(dot(h, S->g, S->g, S->L, S->scal + 3, S->st));
+    double gg;
+    CP_TRY(readback(h, S->scal + 3, 1, &gg, S->st));
+    S->rho = std::sqrt(std::max(0.0, gg)) / S->normT;
+    if (!std::isfinite(S->f) || !std::isfinite(S->rho))
+      return fail(h, CP_ENOTFINITE, "objective or gradient not finite");
+    CP_TRY(window_push(h, S));
+  }
+  S->it++;
+  if (info) *info = rec;
+  return rc;
+}
+
+int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const cp_options* opt,
+                 double* u_inout, cp_report* rep, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  cp_options o;
+  if (opt) o = *opt;
+  else cp_options_default(&o);
+  if (!u_inout) return fail(h, CP_EINVAL, "null iterate");
+  if (!(tol >= 0.0)) return fail(h, CP_EINVAL, "tol must be >= 0");
+  cp_ngmres_state* S = nullptr;
+  CP_TRY(cp_ngmres_create(h, T, R, &o, u_inout, st, &S));
+  int rc = CP_OK;
+  int ntr = 0;
+  for (;;) {
+    // Precision schedule: once rho is small enough (or would stop the run),
+    // move the bulk to the final precision, re-evaluate and restart the window.
+    if (!S->switched && S->prec != o.final_precision &&
+        ((o.switch_rho > 0.0 && S->rho <= o.switch_rho) ||
+         (S->rho <= tol && !is_f64_acc(S->prec) && is_f64_acc(o.final_precision)))) {
+      S->prec = o.final_precision;
+      S->switched = true;
+      S->switch_iter = S->it;
+      rc = eval_current(h, S);
+      if (rc < 0) break;
+      S->wcount = 0;
+      S->whead = 0;
+      rc = window_push(h, S);
+      if (rc < 0) break;
+    }
+    if (S->rho <= tol || S->it >= o.max_iter) {
+      if (o.trace && ntr < o.trace_cap) {
+        cp_iter_info r{};
+        r.it = S->it; r.f = S->f; r.rho = S->rho; r.beta = NAN; r.ls_status = -1;
+        r.m = S->wcount; r.precision = S->prec;
+        o.trace[ntr++] = r;
+      }
+      break;
+    }
+    cp_iter_info info{};
+    rc = ngmres_step(h, S, &info);
+    if (rc < 0) break;
+    if (o.trace && ntr < o.trace_cap) o.trace[ntr++] = info;
+  }
+  if (rc >= 0) {
+    CP_HIP(h, hipMemcpyAsync(u_inout, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, st));
+    CP_HIP(h, hipStreamSynchronize(st));
+  }
+  if (rep) {
+    rep->iters = S->it;
+    rep->converged = S->rho <= tol;
+    rep->f = S->f;
+    rep->rho = S->rho;
+    rep->n_fg = S->n_fg;
+    rep->n_restarts = S->n_restarts;
+    rep->n_ls_fallback = S->n_fallback;
+    rep->switch_iter = S->switch_iter;
+    rep->n_trace = ntr;
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  const bool conv = S->rho <= tol;
+  cp_ngmres_destroy(h, S);
+  if (rc < 0) return rc;
+  return conv ? CP_OK : CP_MAXITER;
+}
+
+}  // extern "C"

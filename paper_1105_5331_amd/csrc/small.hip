@@ -1,0 +1,788 @@
+// Small float64 kernels around the MTTKRP: Grams and their Hadamard
+// products, normalisation/reordering, the ALS mode solve (Cholesky with the
+// shift and pseudo-inverse fallbacks), the gradient epilogue, fixed-order
+// reductions, and N-GMRES Step II.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+
+namespace cpng {
+
+int fail(cp_handle* h, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h) h->err = buf;
+  return code;
+}
+
+int ensure(cp_handle* h, DevBuf& b, size_t bytes, hipStream_t stream) {
+  if (bytes <= b.bytes) return CP_OK;
+  size_t want = std::max(bytes, b.bytes + b.bytes / 2);
+  want = (want + 4095) & ~size_t(4095);
+  if (b.ptr) {
+    CP_HIP(h, hipStreamSynchronize(stream));
+    CP_HIP(h, hipFree(b.ptr));
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  if (hipMalloc(&b.ptr, want) != hipSuccess) {
+    b.ptr = nullptr;
+    return fail(h, CP_ENOMEM, "device allocation of %zu bytes failed", want);
+  }
+  b.bytes = want;
+  return CP_OK;
+}
+
+static hipEvent_t pool_event(cp_handle* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+KernelTimer::KernelTimer(cp_handle* h_, int id_, hipStream_t st_) : h(h_), id(id_), st(st_) {
+  if (!h->prof) return;
+  a = pool_event(h);
+  b = pool_event(h);
+  if (a) (void)hipEventRecord(a, st);
+}
+
+KernelTimer::~KernelTimer() {
+  if (!a || !b) return;
+  (void)hipEventRecord(b, st);
+  h->ev_pending[id].emplace_back(a, b);
+  if (h->ev_pending[id].size() >= 512) {   // fold old pairs to bound the pool
+    for (auto& pr : h->ev_pending[id]) {
+      float ms = 0.f;
+      (void)hipEventSynchronize(pr.second);
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        h->prof_ms[id] += ms;
+        h->prof_launches[id]++;
+      }
+      h->ev_pool.push_back(pr.first);
+      h->ev_pool.push_back(pr.second);
+    }
+    h->ev_pending[id].clear();
+  }
+}
+
+int make_shape(cp_handle* h, int order, const int64_t* dims, Shape* s) {
+  if (order < 1 || order > CP_MAX_ORDER)
+    return fail(h, CP_EINVAL, "order %d outside 1..%d", order, CP_MAX_ORDER);
+  s->N = order;
+  s->off[0] = 0;
+  for (int k = 0; k < order; ++k) {
+    if (dims[k] < 1) return fail(h, CP_EINVAL, "dims[%d] = %lld < 1", k, (long long)dims[k]);
+    s->dims[k] = dims[k];
+    s->off[k + 1] = s->off[k] + dims[k];
+  }
+  return CP_OK;
+}
+
+namespace {
+
+constexpr int kRowsPerChunk = 256;
+constexpr int kMaxR = 64;
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+struct ModeTable {
+  int N, R;
+  int64_t dims[CP_MAX_ORDER];
+  int64_t off[CP_MAX_ORDER + 1];     // row offsets
+  int64_t coff[CP_MAX_ORDER + 1];    // chunk offsets (kRowsPerChunk rows per chunk)
+};
+
+ModeTable table(const Shape& s, int R) {
+  ModeTable t{};
+  t.N = s.N;
+  t.R = R;
+  t.coff[0] = 0;
+  for (int k = 0; k < s.N; ++k) {
+    t.dims[k] = s.dims[k];
+    t.off[k] = s.off[k];
+    t.coff[k + 1] = t.coff[k] + (s.dims[k] + kRowsPerChunk - 1) / kRowsPerChunk;
+  }
+  t.off[s.N] = s.off[s.N];
+  return t;
+}
+
+// ---- Grams -----------------------------------------------------------------
+// part[(chunk) * R * R + r * R + q] = sum_{rows in chunk} A(i, r) A(i, q); the
+// chunk index runs over every mode's chunks (blockIdx.x).
+__global__ void gram_partial_kernel(const double* __restrict__ u, ModeTable t,
+                                    double* __restrict__ part) {
+  __shared__ double rows[32][kMaxR];
+  const int R = t.R;
+  const int64_t ch = blockIdx.x;
+  int k = 0;
+  while (ch >= t.coff[k + 1]) ++k;
+  const int64_t i_begin = (ch - t.coff[k]) * kRowsPerChunk;
+  const int64_t i_end = min<int64_t>(t.dims[k], i_begin + kRowsPerChunk);
+  const double* A = u + t.off[k] * R;
+  double acc[16];
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int64_t i0 = i_begin; i0 < i_end; i0 += 32) {
+    const int nr = (int)min<int64_t>(32, i_end - i0);
+    for (int e = threadIdx.x; e < 32 * R; e += blockDim.x) {
+      const int ii = e / R, r = e - (e / R) * R;
+      rows[ii][r] = ii < nr ? A[(i0 + ii) * R + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int pr = threadIdx.x + q * blockDim.x;
+      if (pr < R * R) {
+        const int r = pr / R, c = pr - (pr / R) * R;
+        double s = acc[q];
+        for (int ii = 0; ii < nr; ++ii) s = fma(rows[ii][r], rows[ii][c], s);
+        acc[q] = s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int pr = threadIdx.x + q * blockDim.x;
+    if (pr < R * R) part[ch * R * R + pr] = acc[q];
+  }
+}
+
+// S^(k) = sum of that mode's chunk partials (chunk order); Gammabar^(n) and
+// Gamma as products over k in increasing order.
+__global__ void gram_final_kernel(const double* __restrict__ part, ModeTable t,
+                                  double* __restrict__ S, double* __restrict__ Gbar,
+                                  double* __restrict__ Gam) {
+  const int R = t.R;
+  for (int pr = threadIdx.x; pr < R * R; pr += blockDim.x) {
+    double sk[CP_MAX_ORDER];
+    for (int k = 0; k < t.N; ++k) {
+      double s = 0.0;
+      for (int64_t ch = t.coff[k]; ch < t.coff[k + 1]; ++ch) s += part[ch * R * R + pr];
+      sk[k] = s;
+      if (S) S[(int64_t)k * R * R + pr] = s;
+    }
+    if (Gbar) {
+      for (int n = 0; n < t.N; ++n) {
+        double gb = 1.0;
+        for (int k = 0; k < t.N; ++k)
+          if (k != n) gb *= sk[k];
+        Gbar[(int64_t)n * R * R + pr] = gb;
+      }
+    }
+    if (Gam) {
+      double g = 1.0;
+      for (int k = 0; k < t.N; ++k) g *= sk[k];
+      Gam[pr] = g;
+    }
+  }
+}
+
+// ---- normalisation ------------------------------------------------------------
+__global__ void colsq_partial_kernel(const double* __restrict__ u, ModeTable t,
+                                     double* __restrict__ part) {
+  const int R = t.R;
+  const int64_t ch = blockIdx.x;
+  int k = 0;
+  while (ch >= t.coff[k + 1]) ++k;
+  const int64_t i_begin = (ch - t.coff[k]) * kRowsPerChunk;
+  const int64_t i_end = min<int64_t>(t.dims[k], i_begin + kRowsPerChunk);
+  const double* A = u + t.off[k] * R;
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    double s = 0.0;
+    for (int64_t i = i_begin; i < i_end; ++i) s = fma(A[i * R + r], A[i * R + r], s);
+    part[ch * R + r] = s;
+  }
+}
+
+// One block: nu, lambda, scales (N x R) and the stable descending order.
+__global__ void norm_plan_kernel(const double* __restrict__ part, ModeTable t,
+                                 double* __restrict__ scales, int* __restrict__ perm) {
+  __shared__ double lam[kMaxR];
+  __shared__ double nu[CP_MAX_ORDER][kMaxR];
+  const int R = t.R;
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    double l = 1.0;
+    for (int k = 0; k < t.N; ++k) {
+      double s = 0.0;
+      for (int64_t ch = t.coff[k]; ch < t.coff[k + 1]; ++ch) s += part[ch * R + r];
+      nu[k][r] = sqrt(s);
+      l *= nu[k][r];
+    }
+    lam[r] = l;
+    const double root = pow(l, 1.0 / (double)t.N);
+    for (int k = 0; k < t.N; ++k) scales[k * R + r] = l > 0.0 ? root / nu[k][r] : 0.0;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    int pos = 0;
+    for (int q = 0; q < R; ++q)
+      if (lam[q] > lam[r] || (lam[q] == lam[r] && q < r)) ++pos;
+    perm[pos] = r;   // perm[new position] = old term index
+  }
+}
+
+// dst row j-th column = scale[k][perm[j]] * src[row][perm[j]] (u), or
+// src / scale for a gradient (scale 0 -> undivided).
+__global__ void norm_apply_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                  ModeTable t, const double* __restrict__ scales,
+                                  const int* __restrict__ perm, int gradient) {
+  const int R = t.R;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= t.off[t.N] * R) return;
+  const int64_t row = e / R;
+  const int j = (int)(e - row * R);
+  int k = 0;
+  while (row >= t.off[k + 1]) ++k;
+  const int r = perm[j];
+  const double s = scales[k * R + r];
+  const double x = src[row * R + r];
+  dst[e] = gradient ? (s != 0.0 ? x / s : x) : s * x;
+}
+
+// ---- ALS mode solve -----------------------------------------------------------
+// One block factorises Gammabar (R x R): Cholesky; if a pivot is not positive,
+// Cholesky of Gammabar + 1e-14 tr/R I; if that fails too, the pseudo-inverse
+// from a cyclic Jacobi eigendecomposition (eigenvalues below R eps max|w|
+// dropped).  out: kind (0 chol, 1 shifted chol, 2 pinv) in *kind, the lower
+// factor L or the pseudo-inverse P in F (R x R).
+__device__ bool chol_lds(double* a, int R, double* piv_ok) {
+  // right-looking Cholesky on a[R][R] in LDS, lower triangle
+  for (int j = 0; j < R; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = a[j * R + j];
+      *piv_ok = (d > 0.0 && isfinite(d)) ? 1.0 : 0.0;
+      a[j * R + j] = d > 0.0 ? sqrt(d) : d;
+    }
+    __syncthreads();
+    if (*piv_ok == 0.0) return false;
+    const double djj = a[j * R + j];
+    for (int i = j + 1 + threadIdx.x; i < R; i += blockDim.x) a[i * R + j] /= djj;
+    __syncthreads();
+    const int n = R - j - 1;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = j + 1 + e / n, c = j + 1 + e % n;
+      if (c <= i) a[i * R + c] -= a[i * R + j] * a[c * R + j];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+__global__ void factor_kernel(const double* __restrict__ G, int R, double* __restrict__ F,
+                              int* __restrict__ kind, int* __restrict__ flags) {
+  __shared__ double a[kMaxR * kMaxR];
+  __shared__ double v[kMaxR * kMaxR];
+  __shared__ double ok;
+  __shared__ double shift;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) a[e] = G[e];
+  __syncthreads();
+  int k = 0;
+  bool good = chol_lds(a, R, &ok);
+  if (!good) {
+    if (threadIdx.x == 0) {
+      double tr = 0.0;
+      for (int i = 0; i < R; ++i) tr += G[i * R + i];
+      shift = 1e-14 * tr / R;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * R; e += blockDim.x)
+      a[e] = G[e] + ((e / R) == (e % R) ? shift : 0.0);
+    __syncthreads();
+    k = 1;
+    good = chol_lds(a, R, &ok);
+  }
+  if (good) {
+    for (int e = threadIdx.x; e < R * R; e += blockDim.x)
+      F[e] = ((e % R) <= (e / R)) ? a[e] : 0.0;
+    if (threadIdx.x == 0) {
+      *kind = k;
+      if (k > *flags) *flags = k;   // single-block kernel: plain store, stream-ordered
+    }
+    return;
+  }
+  // cyclic Jacobi: a <- G, v <- I; rotate until off-diagonal mass is negligible
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    a[e] = G[e];
+    v[e] = ((e / R) == (e % R)) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  __shared__ double cs[2];
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    __shared__ double off;
+    if (threadIdx.x == 0) {
+      double o = 0.0, d = 0.0;
+      for (int i = 0; i < R; ++i)
+        for (int j = 0; j < R; ++j) (i == j ? d : o) += a[i * R + j] * a[i * R + j];
+      off = (o <= 1e-30 * d || o == 0.0) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (off != 0.0) break;
+    for (int p = 0; p < R - 1; ++p) {
+      for (int q = p + 1; q < R; ++q) {
+        if (threadIdx.x == 0) {
+          const double apq = a[p * R + q];
+          double c = 1.0, s = 0.0;
+          if (apq != 0.0) {
+            const double tau = (a[q * R + q] - a[p * R + p]) / (2.0 * apq);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+          cs[0] = c;
+          cs[1] = s;
+        }
+        __syncthreads();
+        const double c = cs[0], s = cs[1];
+        if (s != 0.0) {
+          // columns p, q
+          for (int i = threadIdx.x; i < R; i += blockDim.x) {
+            const double aip = a[i * R + p], aiq = a[i * R + q];
+            a[i * R + p] = c * aip - s * aiq;
+            a[i * R + q] = s * aip + c * aiq;
+            const double vip = v[i * R + p], viq = v[i * R + q];
+            v[i * R + p] = c * vip - s * viq;
+            v[i * R + q] = s * vip + c * viq;
+          }
+          __syncthreads();
+          // rows p, q
+          for (int i = threadIdx.x; i < R; i += blockDim.x) {
+            const double api = a[p * R + i], aqi = a[q * R + i];
+            a[p * R + i] = c * api - s * aqi;
+            a[q * R + i] = s * api + c * aqi;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  __shared__ double wmax;
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < R; ++i) m = fmax(m, fabs(a[i * R + i]));
+    wmax = m;
+  }
+  __syncthreads();
+  const double tol = R * 2.220446049250313e-16 * fmax(wmax, 1e-300);
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    const int i = e / R, j = e % R;
+    double s = 0.0;
+    for (int q = 0; q < R; ++q) {
+      const double w = a[q * R + q];
+      if (fabs(w) > tol) s += v[i * R + q] * v[j * R + q] / w;
+    }
+    F[e] = s;
+  }
+  if (threadIdx.x == 0) {
+    *kind = 2;
+    if (2 > *flags) *flags = 2;
+  }
+}
+
+// A(i,:) = M(i,:) Gammabar^-1 using the factor from factor_kernel.  One
+// thread per row, its vector in LDS.
+__global__ __launch_bounds__(64) void solve_rows_kernel(const double* __restrict__ M,
+                                                        const double* __restrict__ F,
+                                                        const int* __restrict__ kind, int64_t I,
+                                                        int R, double* __restrict__ A) {
+  __shared__ double f[kMaxR * kMaxR];
+  __shared__ double x[kMaxR * 64];   // x[r * 64 + lane]: conflict-free per r
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) f[e] = F[e];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (i >= I) return;
+  double* y = x + threadIdx.x;
+#define Y(r) y[(r) * 64]
+  const double* m = M + i * R;
+  if (*kind == 2) {
+    for (int c = 0; c < R; ++c) {
+      double s = 0.0;
+      for (int q = 0; q < R; ++q) s = fma(m[q], f[q * R + c], s);
+      A[i * R + c] = s;
+    }
+    return;
+  }
+  // forward: L y = m
+  for (int r = 0; r < R; ++r) {
+    double s = m[r];
+    for (int q = 0; q < r; ++q) s -= f[r * R + q] * Y(q);
+    Y(r) = s / f[r * R + r];
+  }
+  // backward: L^T x = y
+  for (int r = R - 1; r >= 0; --r) {
+    double s = Y(r);
+    for (int q = r + 1; q < R; ++q) s -= f[q * R + r] * Y(q);
+    Y(r) = s / f[r * R + r];
+  }
+  for (int r = 0; r < R; ++r) A[i * R + r] = Y(r);
+#undef Y
+}
+
+// G(i, r) = -M(i, r) + sum_s A(i, s) Gbar(s, r)
+__global__ void grad_epilogue_kernel(const double* __restrict__ M, const double* __restrict__ A,
+                                     const double* __restrict__ Gbar, int64_t I, int R,
+                                     double* __restrict__ G) {
+  __shared__ double gb[kMaxR * kMaxR];
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) gb[e] = Gbar[e];
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= I * R) return;
+  const int64_t i = e / R;
+  const int r = (int)(e - i * R);
+  double s = 0.0;
+  for (int q = 0; q < R; ++q) s = fma(A[i * R + q], gb[q * R + r], s);
+  G[e] = s - M[e];
+}
+
+// ---- fixed-order reductions ----------------------------------------------------
+constexpr int kRedBlocks = 512;
+
+__device__ double block_sum(double v) {
+  __shared__ double sh[256];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename X, typename Y>
+__global__ void dot_partial_kernel(const X* __restrict__ x, const Y* __restrict__ y, int64_t n,
+                                   int64_t per, double* __restrict__ part) {
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = min<int64_t>(n, b0 + per);
+  double s = 0.0;
+  for (int64_t e = b0 + threadIdx.x; e < b1; e += blockDim.x)
+    s = fma((double)x[e], (double)y[e], s);
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void sum_final_kernel(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+  s = block_sum(s);
+  if (threadIdx.x == 0) *out = s;
+}
+
+template <typename X, typename Y>
+int dot_impl(cp_handle* h, const X* x, const Y* y, int64_t n, double* out, hipStream_t st) {
+  const int64_t per = std::max<int64_t>(256, ((n + kRedBlocks - 1) / kRedBlocks + 255) / 256 * 256);
+  const int nb = (int)std::max<int64_t>(1, (n + per - 1) / per);
+  CP_TRY(ensure(h, h->red, sizeof(double) * kRedBlocks, st));
+  double* part = static_cast<double*>(h->red.ptr);
+  hipLaunchKernelGGL((dot_partial_kernel<X, Y>), dim3(nb), dim3(256), 0, st, x, y, n, per, part);
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(256), 0, st, part, nb, out);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+__global__ void objective_kernel(double normsq, const double* __restrict__ dotAM,
+                                 const double* __restrict__ Gam, int R, double* __restrict__ f) {
+  double s = 0.0;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) s += Gam[e];
+  s = block_sum(s);
+  if (threadIdx.x == 0) *f = 0.5 * normsq - *dotAM + 0.5 * s;
+}
+
+__global__ void axpy_kernel(const double* __restrict__ x, double a, const double* __restrict__ d,
+                            double* __restrict__ y, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = fma(a, d[e], x[e]);
+}
+
+__global__ void sub_kernel(const double* __restrict__ a, const double* __restrict__ b,
+                           double* __restrict__ y, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = a[e] - b[e];
+}
+
+// ---- N-GMRES Step II ----------------------------------------------------------
+constexpr int kMaxWin = 64;
+constexpr int kStepTile = 64;
+struct WinPtrs {
+  const double* u[kMaxWin];
+  const double* g[kMaxWin];
+};
+
+// Pair sums over a contiguous range of positions: for j <= k < m,
+// B(j,k) = sum p_j p_k and rhs(j) = sum p_j gbar, with p_j = gbar - g_j.
+// Partial slot layout: [pairs m(m+1)/2 in (j,k) row order][m rhs].
+__global__ void step2_partial_kernel(WinPtrs w, int m, const double* __restrict__ gbar,
+                                     int64_t L, int64_t per, double* __restrict__ part) {
+  __shared__ double P[kMaxWin + 1][kStepTile];
+  const int npairs = m * (m + 1) / 2;
+  const int nval = npairs + m;
+  double acc[9];
+  int pj[9], pk[9];
+  for (int q = 0; q < 9; ++q) {
+    acc[q] = 0.0;
+    const int v = threadIdx.x + q * blockDim.x;
+    int j = 0, k = 0;
+    if (v < npairs) {
+      // invert v = (pairs of rows before j) + (k - j)
+      int rem = v;
+      while (rem >= m - j) {
+        rem -= m - j;
+        ++j;
+      }
+      k = j + rem;
+    } else if (v < nval) {
+      j = v - npairs;
+      k = m;   // the gbar row
+    }
+    pj[q] = j;
+    pk[q] = k;
+  }
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = min<int64_t>(L, b0 + per);
+  for (int64_t x0 = b0; x0 < b1; x0 += kStepTile) {
+    const int nx = (int)min<int64_t>(kStepTile, b1 - x0);
+    for (int e = threadIdx.x; e < (m + 1) * kStepTile; e += blockDim.x) {
+      const int j = e / kStepTile, xx = e % kStepTile;
+      double val = 0.0;
+      if (xx < nx) {
+        const double gb = gbar[x0 + xx];
+        val = j < m ? gb - w.g[j][x0 + xx] : gb;
+      }
+      P[j][xx] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int v = threadIdx.x + q * blockDim.x;
+      if (v < nval) {
+        const int j = pj[q], k = pk[q];
+        double s = acc[q];
+        for (int xx = 0; xx < nx; ++xx) s = fma(P[j][xx], P[k][xx], s);
+        acc[q] = s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int v = threadIdx.x + q * blockDim.x;
+    if (v < nval) part[(int64_t)blockIdx.x * nval + v] = acc[q];
+  }
+}
+
+// One block: reduce partial slots in order, regularise, Cholesky-solve.
+__global__ void step2_solve_kernel(const double* __restrict__ part, int nb, int m, double eps,
+                                   double* __restrict__ alpha_out, int* __restrict__ flags) {
+  __shared__ double B[kMaxWin * kMaxWin];
+  __shared__ double rhs[kMaxWin];
+  __shared__ double ok;
+  __shared__ double dmax;
+  const int npairs = m * (m + 1) / 2;
+  const int nval = npairs + m;
+  for (int v = threadIdx.x; v < nval; v += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * nval + v];
+    if (v < npairs) {
+      int j = 0, rem = v;
+      while (rem >= m - j) {
+        rem -= m - j;
+        ++j;
+      }
+      const int k = j + rem;
+      B[j * m + k] = s;
+      B[k * m + j] = s;
+    } else {
+      rhs[v - npairs] = -s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d = 0.0;
+    for (int j = 0; j < m; ++j) d = fmax(d, B[j * m + j]);
+    dmax = d;
+  }
+  __syncthreads();
+  if (!(dmax > 0.0)) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) alpha_out[j] = 0.0;
+    return;
+  }
+  const double delta = eps * dmax;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) B[j * m + j] += delta;
+  __syncthreads();
+  if (!chol_lds(B, m, &ok)) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) alpha_out[j] = 0.0;
+    if (threadIdx.x == 0) *flags = *flags | 4;
+    return;
+  }
+  if (threadIdx.x == 0) {
+    double y[kMaxWin];
+    for (int r = 0; r < m; ++r) {
+      double s = rhs[r];
+      for (int q = 0; q < r; ++q) s -= B[r * m + q] * y[q];
+      y[r] = s / B[r * m + r];
+    }
+    for (int r = m - 1; r >= 0; --r) {
+      double s = y[r];
+      for (int q = r + 1; q < m; ++q) s -= B[q * m + r] * y[q];
+      y[r] = s / B[r * m + r];
+    }
+    for (int r = 0; r < m; ++r) alpha_out[r] = y[r];
+  }
+}
+
+__global__ void step2_combine_kernel(WinPtrs w, int m, const double* __restrict__ ubar,
+                                     const double* __restrict__ alpha, int64_t L,
+                                     double* __restrict__ uhat) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= L) return;
+  const double ub = ubar[x];
+  double s = 0.0;
+  for (int j = 0; j < m; ++j) s = fma(alpha[j], ub - w.u[j][x], s);
+  uhat[x] = ub + s;
+}
+
+}  // namespace
+
+// ---- host wrappers -----------------------------------------------------------------
+static size_t small_layout(int N, int R) {
+  // S, Gbar (N R R each), Gam (R R), scales (N R), perm (R ints), kind, alpha(64)
+  return sizeof(double) * (size_t)(2 * N * R * R + R * R + N * R + kMaxWin + 8) +
+         sizeof(int) * (size_t)(R + 8);
+}
+
+int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, double* Gbar,
+             double* Gam, hipStream_t st) {
+  if (R > kMaxR) return fail(h, CP_EINVAL, "rank %d above the supported %d", R, kMaxR);
+  ModeTable t = table(s, R);
+  const int64_t nch = t.coff[s.N];
+  CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)(nch * R * R), st));
+  double* part = static_cast<double*>(h->red.ptr);
+  hipLaunchKernelGGL(gram_partial_kernel, dim3((unsigned)nch), dim3(256), 0, st, u, t, part);
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(gram_final_kernel, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStream_t st) {
+  if (R > kMaxR) return fail(h, CP_EINVAL, "rank %d above the supported %d", R, kMaxR);
+  ModeTable t = table(s, R);
+  const int64_t nch = t.coff[s.N];
+  const int64_t L = s.sum_dims() * R;
+  CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)(nch * R), st));
+  CP_TRY(ensure(h, h->tmpu, sizeof(double) * (size_t)L, st));
+  CP_TRY(ensure(h, h->small, small_layout(s.N, R) + 4096, st));
+  double* part = static_cast<double*>(h->red.ptr);
+  double* scales = static_cast<double*>(h->small.ptr);
+  int* perm = reinterpret_cast<int*>(scales + s.N * R);
+  double* tmp = static_cast<double*>(h->tmpu.ptr);
+  hipLaunchKernelGGL(colsq_partial_kernel, dim3((unsigned)nch), dim3(64), 0, st, u, t, part);
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(norm_plan_kernel, dim3(1), dim3(64), 0, st, part, t, scales, perm);
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(norm_apply_kernel, dim3(nblk(L, 256)), dim3(256), 0, st, u, tmp, t, scales,
+                     perm, 0);
+  CP_LAUNCH_CHECK(h);
+  CP_HIP(h, hipMemcpyAsync(u, tmp, sizeof(double) * L, hipMemcpyDeviceToDevice, st));
+  if (g) {
+    hipLaunchKernelGGL(norm_apply_kernel, dim3(nblk(L, 256)), dim3(256), 0, st, g, tmp, t, scales,
+                       perm, 1);
+    CP_LAUNCH_CHECK(h);
+    CP_HIP(h, hipMemcpyAsync(g, tmp, sizeof(double) * L, hipMemcpyDeviceToDevice, st));
+  }
+  return CP_OK;
+}
+
+int mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int R, double* A,
+               hipStream_t st) {
+  if (R > kMaxR) return fail(h, CP_EINVAL, "rank %d above the supported %d", R, kMaxR);
+  CP_TRY(ensure(h, h->small, small_layout(CP_MAX_ORDER, R) + sizeof(double) * R * R + 4096, st));
+  double* F = static_cast<double*>(h->small.ptr) + small_layout(CP_MAX_ORDER, R) / sizeof(double);
+  int* kind = reinterpret_cast<int*>(F + R * R);
+  hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(256), 0, st, Gbar, R, F, kind, h->flags);
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(solve_rows_kernel, dim3(nblk(I, 64)), dim3(64), 0, st, M, F, kind, I, R, A);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int grad_epilogue(cp_handle* h, const double* M, const double* A, const double* Gbar, int64_t I,
+                  int R, double* G, hipStream_t st) {
+  if (I * R == 0) return CP_OK;
+  hipLaunchKernelGGL(grad_epilogue_kernel, dim3(nblk(I * R, 256)), dim3(256), 0, st, M, A, Gbar,
+                     I, R, G);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int dot(cp_handle* h, const double* x, const double* y, int64_t n, double* out, hipStream_t st) {
+  return dot_impl<double, double>(h, x, y, n, out, st);
+}
+
+int sumsq_tensor(cp_handle* h, const void* v, int dtype, int64_t n, double* out, hipStream_t st) {
+  if (dtype == CP_F32)
+    return dot_impl<float, float>(h, static_cast<const float*>(v), static_cast<const float*>(v), n,
+                                  out, st);
+  return dot_impl<double, double>(h, static_cast<const double*>(v), static_cast<const double*>(v),
+                                  n, out, st);
+}
+
+int objective_combine(cp_handle* h, double normsq, const double* dotAM, const double* Gam, int R,
+                      double* f, hipStream_t st) {
+  hipLaunchKernelGGL(objective_kernel, dim3(1), dim3(256), 0, st, normsq, dotAM, Gam, R, f);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int axpy_to(cp_handle* h, const double* x, double a, const double* d, double* y, int64_t n,
+            hipStream_t st) {
+  if (n == 0) return CP_OK;
+  hipLaunchKernelGGL(axpy_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, x, a, d, y, n);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int sub_to(cp_handle* h, const double* a, const double* b, double* y, int64_t n, hipStream_t st) {
+  if (n == 0) return CP_OK;
+  hipLaunchKernelGGL(sub_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, a, b, y, n);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int step2(cp_handle* h, int64_t L, int m, const double* const* U, const double* const* G,
+          const double* ubar, const double* gbar, double eps, double* uhat, double* alpha,
+          hipStream_t st) {
+  if (m < 1 || m > kMaxWin) return fail(h, CP_EINVAL, "window size %d outside 1..%d", m, kMaxWin);
+  WinPtrs w{};
+  for (int j = 0; j < m; ++j) {
+    w.u[j] = U[j];
+    w.g[j] = G[j];
+  }
+  const int nval = m * (m + 1) / 2 + m;
+  const int64_t per = std::max<int64_t>(kStepTile, ((L + 255) / 256 + kStepTile - 1) / kStepTile * kStepTile);
+  const int nb = (int)std::max<int64_t>(1, (L + per - 1) / per);
+  CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)nb * nval, st));
+  double* part = static_cast<double*>(h->red.ptr);
+  hipLaunchKernelGGL(step2_partial_kernel, dim3(nb), dim3(256), 0, st, w, m, gbar, L, per, part);
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(step2_solve_kernel, dim3(1), dim3(256), 0, st, part, nb, m, eps, alpha,
+                     h->flags);
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(step2_combine_kernel, dim3(nblk(L, 256)), dim3(256), 0, st, w, m, ubar, alpha,
+                     L, uhat);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+}  // namespace cpng

@@ -1,0 +1,80 @@
+"""The C ABI library loads and exports every function include/cpng.h declares,
+and the ctypes mirrors of its structs have the C layout (no GPU needed)."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cpng.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ["cp_mttkrp", "cp_gram", "cp_als_sweep", "cp_objective_grad", "ngmres_step",
+                     "cp_decompose", "ngmres_accelerate", "cp_tensor_prepare", "cp_normalize"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_function():
+    from paper_1105_5331_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        pytest.skip("libcpng.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(_native.LIB_PATH)
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    _native.lib()   # signatures bind
+
+
+def test_struct_layouts_match_c():
+    from paper_1105_5331_amd import _native as nat
+    gxx = shutil.which("g++")
+    if gxx is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("no host compiler / HIP headers")
+    src = r'''
+#include <cstdio>
+#include <cstddef>
+#include "cpng.h"
+#define P(T, f) printf("%s.%s %zu\n", #T, #f, offsetof(T, f));
+int main() {
+  printf("cp_tensor %zu\n", sizeof(cp_tensor));
+  printf("cp_options %zu\n", sizeof(cp_options));
+  printf("cp_iter_info %zu\n", sizeof(cp_iter_info));
+  printf("cp_report %zu\n", sizeof(cp_report));
+  P(cp_tensor, values) P(cp_tensor, nnz) P(cp_tensor, norm_sq)
+  P(cp_options, trace) P(cp_options, trace_cap) P(cp_options, switch_rho)
+  P(cp_iter_info, beta) P(cp_iter_info, precision)
+  P(cp_report, seconds) P(cp_report, n_trace)
+  return 0;
+}
+'''
+    tmp = os.path.join(ROOT, "_work")
+    os.makedirs(tmp, exist_ok=True)
+    cpp = os.path.join(tmp, "abi_layout.cpp")
+    exe = os.path.join(tmp, "abi_layout")
+    open(cpp, "w").write(src)
+    r = subprocess.run([gxx, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                        "-I" + os.path.join(ROOT, "include"), cpp, "-o", exe],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("could not compile the layout probe: " + r.stderr[:200])
+    out = subprocess.run([exe], capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.split() for line in out if line.strip())
+    S = {"cp_tensor": nat.cp_tensor, "cp_options": nat.cp_options,
+         "cp_iter_info": nat.cp_iter_info, "cp_report": nat.cp_report}
+    for k, v in got.items():
+        if "." in k:
+            s, f = k.split(".")
+            assert getattr(S[s], f).offset == int(v), k
+        else:
+            assert ctypes.sizeof(S[k]) == int(v), k

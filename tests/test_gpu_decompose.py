@@ -1,0 +1,155 @@
+"""GPU parity of the whole method (ALS, N-GMRES, line search, precision
+schedule) against the FP64 oracle, through cp_decompose in the C ABI.
+
+Trajectories are compared iterate by iterate from the same initial guess
+until the first discrete divergence (restart flag, window size or number of
+line-search evaluations differ); up to there the float64 paths differ only by
+summation order, so f and rho agree to the stated tolerances below.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import cp as ocp
+from oracle.ngmres import CPProblem, als, ngmres
+from workloads import initial_guess, test_problem_1, test_problem_2
+
+pytestmark = pytest.mark.gpu
+
+# Per-iterate tolerances on a shared trajectory (float64 on both sides):
+F_TOL = 1e-10     # |f_gpu - f_oracle| / (1/2 ||T||^2)
+RHO_REL = 1e-6    # |rho_gpu - rho_oracle| / rho_oracle (+ 1e-13 absolute)
+
+
+@pytest.fixture(scope="module")
+def h():
+    import paper_1105_5331_amd as cpng
+    with cpng.Handle(0) as handle:
+        yield handle
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _compare(trace, ref_trace, half, what):
+    n = 0
+    for a, b in zip(trace, ref_trace):
+        assert abs(a["f"] - b.f) <= F_TOL * half, f"{what} it {b.it}: f {a['f']} vs {b.f}"
+        assert abs(a["rho"] - b.rho) <= RHO_REL * b.rho + 1e-13, \
+            f"{what} it {b.it}: rho {a['rho']} vs {b.rho}"
+        n += 1
+        if a["restart"] != b.restart or a["m"] != b.m or a["nfev"] != b.nfev:
+            break
+        if b.nfev:
+            assert abs(a["beta"] - b.beta) <= 1e-6 * max(1.0, abs(b.beta)), \
+                f"{what} it {b.it}: beta {a['beta']} vs {b.beta}"
+    return n
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_ngmres_trajectory_small_dense_fp64(h, seed):
+    """Dense 20x20x20, R = 3, c = 0.5, l1 = l2 = 1 (Table 1 row 1), FP64."""
+    import paper_1105_5331_amd as cpng
+    dims, R, tol = (20, 20, 20), 3, 1e-8
+    print(f"case ngmres trajectory seed={seed}", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=seed)
+    u0 = initial_guess(dims, R, seed=seed + 10000)
+    ref = ngmres(CPProblem(ocp.DenseTensor(p.T), R), u0, tol=tol, max_iter=300)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u = _dev(u0)
+    out = cpng.cp_decompose(h, Tg, R, tol, u, trace_cap=400, max_iter=300)
+    half = 0.5 * np.sum(p.T ** 2)
+    n = _compare(out["trace"], ref.trace, half, f"seed {seed}")
+    assert n >= min(len(ref.trace), 5)
+    assert out["converged"] and ref.converged
+    hg = np.sqrt(2 * ocp.objective_direct(p.T, ocp.split_u(u.cpu().numpy(), dims, R))) / np.sqrt(2 * half)
+    ho = np.sqrt(2 * ocp.objective_direct(p.T, ocp.split_u(ref.u, dims, R))) / np.sqrt(2 * half)
+    assert abs(hg - ho) <= 1e-10
+
+
+def test_als_trajectory_dense_fp64(h):
+    import paper_1105_5331_amd as cpng
+    dims, R = (15, 12, 10), 3
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=7)
+    u0 = initial_guess(dims, R, seed=10007)
+    ref = als(CPProblem(ocp.DenseTensor(p.T), R), u0, tol=1e-8, max_iter=200)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    out = cpng.cp_decompose(h, Tg, R, 1e-8, _dev(u0), trace_cap=300, max_iter=200, method="als")
+    half = 0.5 * np.sum(p.T ** 2)
+    n = _compare(out["trace"], ref.trace, half, "als")
+    assert n == len(ref.trace) == len(out["trace"])
+
+
+def test_ngmres_trajectory_sparse_laplacian(h):
+    import paper_1105_5331_amd as cpng
+    sp = test_problem_2(2, 4)
+    R = 3
+    u0 = initial_guess(sp.dims, R, seed=10021)
+    t = ocp.CooTensor(sp.dims, sp.coords, sp.values)
+    ref = ngmres(CPProblem(t, R), u0, tol=1e-7, max_iter=150)
+    Tg = cpng.Tensor(sp.dims, _dev(sp.values), coords=_dev(sp.coords))
+    cpng.cp_tensor_prepare(h, Tg)
+    out = cpng.cp_decompose(h, Tg, R, 1e-7, _dev(u0), trace_cap=200, max_iter=150)
+    n = _compare(out["trace"], ref.trace, 0.5 * t.norm2, "laplacian")
+    assert n >= 3
+
+
+def test_step_by_step_state_api(h):
+    """cp_ngmres_create / ngmres_step / cp_ngmres_get follow the oracle's first steps."""
+    import paper_1105_5331_amd as cpng
+    dims, R = (12, 10, 11), 2
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=8)
+    u0 = initial_guess(dims, R, seed=10008)
+    ref = ngmres(CPProblem(ocp.DenseTensor(p.T), R), u0, tol=0.0, max_iter=4)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    st = cpng.NGMRESState(h, Tg, R, _dev(u0))
+    half = 0.5 * np.sum(p.T ** 2)
+    for k in range(4):
+        info = st.step()
+        assert abs(info["f"] - ref.trace[k].f) <= F_TOL * half
+    u, g, f, rho = st.get()
+    assert abs(f - ref.trace[4].f) <= F_TOL * half
+    assert abs(rho - ref.trace[4].rho) <= RHO_REL * ref.trace[4].rho + 1e-13
+    st.close()
+
+
+@pytest.mark.parametrize("bulk", ["fp32", "bf16x3"])
+def test_mixed_precision_reaches_fp64_certified_tolerance(h, bulk):
+    """Reduced-precision bulk, then FP64 accumulation: the final rho is certified
+    with a float64 gradient and the final h equals the FP64 run's h."""
+    import paper_1105_5331_amd as cpng
+    dims, R, tol = (30, 30, 30), 4, 1e-8
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=9, dtype=np.float32)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u0 = initial_guess(dims, R, seed=10009)
+    u_mixed = _dev(u0)
+    out = cpng.cp_decompose(h, Tg, R, tol, u_mixed, max_iter=400, precision=bulk,
+                            final_precision="fp32in_fp64acc", switch_rho=1e-5)
+    assert out["converged"] and out["switch_iter"] >= 0
+    u64 = _dev(u0)
+    ref = cpng.cp_decompose(h, Tg, R, tol, u64, max_iter=400)
+    assert ref["converged"]
+    T64 = p.T.astype(np.float64)
+    nt = np.sqrt(np.sum(T64 ** 2))
+    hm = np.sqrt(2 * ocp.objective_direct(T64, ocp.split_u(u_mixed.cpu().numpy(), dims, R))) / nt
+    hf = np.sqrt(2 * ocp.objective_direct(T64, ocp.split_u(u64.cpu().numpy(), dims, R))) / nt
+    assert abs(hm - hf) <= 1e-10
+    # certify rho of the returned iterate with the oracle
+    A = ocp.split_u(u_mixed.cpu().numpy(), dims, R)
+    g = ocp.join_u(ocp.gradient_from_mttkrps(A, [ocp.mttkrp(T64, A, n) for n in range(3)]))
+    assert np.linalg.norm(g) / nt <= tol * 1.01
+
+
+def test_decompose_rejects_zero_tensor(h):
+    import paper_1105_5331_amd as cpng
+    dims = (3, 4, 5)
+    Tg = cpng.Tensor(dims, torch.zeros(60, dtype=torch.float64, device="cuda"))
+    cpng.cp_tensor_prepare(h, Tg)
+    with pytest.raises(cpng.CpError):
+        cpng.cp_decompose(h, Tg, 2, 1e-8, _dev(np.ones(24)))

@@ -1,0 +1,315 @@
+"""GPU parity of the hot-path building blocks against the FP64 oracle.
+
+Every call goes through the C ABI (libcpng.so) via the ctypes binding; the
+expected values come only from ``oracle``.  Inputs are seeded and synthetic
+(``workloads``), at sizes that span several workgroup tiles with ragged tails.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import cp as ocp
+from oracle.ngmres import step2_accelerate
+from workloads import random_coo, test_problem_1, test_problem_2
+
+from helpers import TOL, abs_mttkrp, abs_mttkrp_coo, assert_close_to_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    import paper_1105_5331_amd as cpng
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    with cpng.Handle(0) as handle:
+        yield handle
+
+
+def _cpng():
+    import paper_1105_5331_amd as cpng
+    return cpng
+
+
+def _dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _factors(dims, R, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    return [scale * rng.standard_normal((I, R)) for I in dims]
+
+
+DENSE_SHAPES = [(3, 4, 5), (20, 20, 20), (33, 17, 45), (7, 9, 5, 11), (70, 3, 130),
+                (2, 3, 2, 3, 2), (2, 2, 3, 2, 2, 3, 2, 2), (1, 65, 1, 3), (129, 2, 67)]
+
+
+@pytest.mark.parametrize("dims", DENSE_SHAPES)
+@pytest.mark.parametrize("R", [1, 3, 10, 17, 33])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp32in_fp64acc"])
+def test_dense_mttkrp_parity(h, dims, R, prec):
+    cpng = _cpng()
+    print(f"case dense mttkrp dims={dims} R={R} prec={prec}", flush=True)
+    rng = np.random.default_rng(abs(hash((dims, R))) % 2**32)
+    T64 = rng.standard_normal(dims)
+    if prec == "fp64":
+        T = T64
+        Tt = _dev(T)
+    else:
+        T = T64.astype(np.float32)
+        Tt = _dev(T)
+    A = _factors(dims, R, 5)
+    u = _dev(ocp.join_u(A))
+    Tg = cpng.Tensor(dims, Tt.reshape(-1))
+    for n in range(len(dims)):
+        M = cpng.cp_mttkrp(h, Tg, u, R, n, prec).cpu().numpy()
+        ref = ocp.mttkrp(T.astype(np.float64), A, n)
+        bound = abs_mttkrp(T.astype(np.float64), A, n)
+        assert_close_to_bound(M, ref, bound, TOL[prec], f"mode {n}")
+        if prec == "bf16x3":
+            assert np.linalg.norm(M - ref) <= 1e-3 * max(np.linalg.norm(ref), 1e-300)
+
+
+def test_dense_mttkrp_bitwise_repeatable(h):
+    cpng = _cpng()
+    dims, R = (40, 50, 60), 16
+    T = np.random.default_rng(1).standard_normal(dims).astype(np.float32)
+    u = _dev(ocp.join_u(_factors(dims, R, 2)))
+    Tg = cpng.Tensor(dims, _dev(T).reshape(-1))
+    for prec in ("fp32", "bf16x3", "fp64"):
+        for n in range(3):
+            a = cpng.cp_mttkrp(h, Tg, u, R, n, prec).cpu().numpy()
+            b = cpng.cp_mttkrp(h, Tg, u, R, n, prec).cpu().numpy()
+            assert np.array_equal(a, b)
+
+
+def test_mttkrp_argument_errors(h):
+    cpng = _cpng()
+    dims, R = (4, 5, 6), 3
+    T64 = _dev(np.ones(dims))
+    Tg = cpng.Tensor(dims, T64.reshape(-1))
+    u = _dev(np.ones(15 * R))
+    with pytest.raises(cpng.CpError) as e:
+        cpng.cp_mttkrp(h, Tg, u, R, 3, "fp64")
+    assert e.value.code == -1
+    with pytest.raises(cpng.CpError):
+        cpng.cp_mttkrp(h, Tg, u, R, 0, "fp32")     # fp32 needs a float32 tensor
+    with pytest.raises(cpng.CpError):
+        cpng.cp_mttkrp(h, Tg, u, 0, 0, "fp64")
+
+
+@pytest.mark.parametrize("dims,R", [((5, 300, 7), 4), ((20, 20, 20, 3), 33), ((1, 1, 2), 1)])
+def test_gram_parity(h, dims, R):
+    cpng = _cpng()
+    A = _factors(dims, R, 7)
+    S, Gb, G = cpng.cp_gram(h, dims, _dev(ocp.join_u(A)), R)
+    S, Gb, G = S.cpu().numpy(), Gb.cpu().numpy(), G.cpu().numpy()
+    for k in range(len(dims)):
+        ref = A[k].T @ A[k]
+        np.testing.assert_allclose(S[k], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+        refb = ocp.gamma_bar(A, k)
+        np.testing.assert_allclose(Gb[k], refb, rtol=1e-11, atol=1e-12 * np.abs(refb).max())
+    refg = ocp.gamma(A)
+    np.testing.assert_allclose(G, refg, rtol=1e-11, atol=1e-12 * np.abs(refg).max())
+
+
+@pytest.mark.parametrize("dims,R", [((6, 7, 8), 5), ((30, 4, 9, 3), 12), ((3, 2), 1)])
+def test_normalize_parity(h, dims, R):
+    cpng = _cpng()
+    A = _factors(dims, R, 8)
+    A[0][:, R // 2] *= 30.0
+    G = _factors(dims, R, 9)
+    u, g = _dev(ocp.join_u(A)), _dev(ocp.join_u(G))
+    cpng.cp_normalize(h, dims, u, R, g)
+    B, scales, perm = ocp.normalise(A)
+    Gt = ocp.transform_gradient(G, scales, perm)
+    np.testing.assert_allclose(u.cpu().numpy(), ocp.join_u(B), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(g.cpu().numpy(), ocp.join_u(Gt), rtol=1e-12, atol=1e-14)
+
+
+def test_normalize_zero_term(h):
+    cpng = _cpng()
+    dims, R = (3, 4), 3
+    A = _factors(dims, R, 10)
+    A[1][:, 0] = 0.0
+    u = _dev(ocp.join_u(A))
+    cpng.cp_normalize(h, dims, u, R)
+    B, _, perm = ocp.normalise(A)
+    assert perm[-1] == 0
+    np.testing.assert_allclose(u.cpu().numpy(), ocp.join_u(B), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("dims,R,c", [((20, 20, 20), 3, 0.5), ((13, 30, 8, 5), 6, 0.9),
+                                      ((70, 9, 66), 10, 0.3)])
+def test_objective_grad_parity(h, dims, R, c):
+    cpng = _cpng()
+    p = test_problem_1(dims, R, c, 1, 1, seed=3)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    half = 0.5 * np.sum(p.T ** 2)
+    assert abs(Tg.norm_sq - 2 * half) <= 1e-12 * 2 * half
+    A = _factors(dims, R, 11, scale=0.5)
+    f, g = cpng.cp_objective_grad(h, Tg, _dev(ocp.join_u(A)), R, "fp64")
+    fo = ocp.objective_direct(p.T, A)
+    go = ocp.join_u(ocp.gradient_from_mttkrps(A, [ocp.mttkrp(p.T, A, n) for n in range(len(dims))]))
+    assert abs(f.item() - fo) <= 1e-12 * half
+    assert np.linalg.norm(g.cpu().numpy() - go) <= 1e-12 * np.sqrt(2 * half)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-4)])
+def test_objective_grad_reduced_precision(h, prec, tol):
+    """Per-iterate tolerance of the reduced-precision bulk (same input u):
+    |df| / (1/2 ||T||^2) and ||dg|| / ||T|| against the FP64 oracle."""
+    cpng = _cpng()
+    dims, R = (40, 36, 44), 8
+    p = test_problem_1(dims, R, 0.9, 1, 1, seed=4, dtype=np.float32)
+    T64 = p.T.astype(np.float64)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    A = _factors(dims, R, 12, scale=0.5)
+    f, g = cpng.cp_objective_grad(h, Tg, _dev(ocp.join_u(A)), R, prec)
+    half = 0.5 * np.sum(T64 ** 2)
+    fo = ocp.objective_direct(T64, A)
+    go = ocp.join_u(ocp.gradient_from_mttkrps(A, [ocp.mttkrp(T64, A, n) for n in range(3)]))
+    assert abs(f.item() - fo) / half <= tol
+    assert np.linalg.norm(g.cpu().numpy() - go) / np.sqrt(2 * half) <= tol
+
+
+@pytest.mark.parametrize("dims,R,c", [((20, 20, 20), 3, 0.5), ((9, 14, 6, 11), 5, 0.9)])
+def test_als_sweep_parity(h, dims, R, c):
+    cpng = _cpng()
+    from oracle.ngmres import CPProblem
+    p = test_problem_1(dims, R, c, 1, 1, seed=5)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    A = _factors(dims, R, 13)
+    u = _dev(ocp.join_u(A))
+    cpng.cp_als_sweep(h, Tg, u, R, "fp64", normalize=True)
+    prob = CPProblem(ocp.DenseTensor(p.T), R)
+    ref, flags = prob.als_sweep(ocp.join_u(A))
+    assert flags == [0] * len(dims)
+    np.testing.assert_allclose(u.cpu().numpy(), ref, rtol=1e-9, atol=1e-11)
+
+
+def test_als_sweep_singular_gammabar_fallback(h):
+    """Two identical terms make every Gammabar singular: both sides take the
+    same fallback (shifted Cholesky or pseudo-inverse)."""
+    cpng = _cpng()
+    from oracle.ngmres import CPProblem
+    dims, R = (6, 5, 4), 2
+    A = _factors(dims, 1, 14)
+    A = [np.hstack([a, a]) for a in A]
+    T = np.random.default_rng(15).standard_normal(dims)
+    Tg = cpng.Tensor(dims, _dev(T).reshape(-1))
+    u = _dev(ocp.join_u(A))
+    cpng.cp_als_sweep(h, Tg, u, R, "fp64", normalize=False)
+    prob = CPProblem(ocp.DenseTensor(T), R)
+    ref, flags = prob.als_sweep(ocp.join_u(A), normalise=False)
+    assert max(flags) >= 1
+    got = u.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-6 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("L,m", [(1, 1), (1000, 5), (40000, 20), (333, 64)])
+def test_ngmres_accelerate_parity(h, L, m):
+    cpng = _cpng()
+    rng = np.random.default_rng(L + m)
+    U = rng.standard_normal((m, L))
+    G = rng.standard_normal((m, L))
+    ub = rng.standard_normal(L)
+    gb = rng.standard_normal(L)
+    uh, alpha = cpng.ngmres_accelerate(h, _dev(U), _dev(G), _dev(ub), _dev(gb), 1e-12)
+    ref_u, ref_a = step2_accelerate(U, G, ub, gb, 1e-12)
+    np.testing.assert_allclose(alpha.cpu().numpy(), ref_a, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(uh.cpu().numpy(), ref_u, rtol=1e-8, atol=1e-10)
+
+
+def test_ngmres_accelerate_zero_differences(h):
+    cpng = _cpng()
+    L = 50
+    g = np.ones(L)
+    uh, alpha = cpng.ngmres_accelerate(h, _dev(np.zeros((2, L))), _dev(np.stack([g, g])),
+                                       _dev(np.arange(L, dtype=float)), _dev(g))
+    assert np.all(alpha.cpu().numpy() == 0.0)
+    np.testing.assert_array_equal(uh.cpu().numpy(), np.arange(L, dtype=float))
+
+
+# ------------------------------------------------------------------ sparse ---
+
+def _sparse(cpng, sp, dtype):
+    vals = _dev(sp.values.astype(dtype))
+    return cpng.Tensor(sp.dims, vals, coords=_dev(sp.coords))
+
+
+SPARSE_CASES = [
+    ("tp2_d2_s4", lambda: test_problem_2(2, 4)),
+    ("tp2_d3_s3", lambda: test_problem_2(3, 3)),
+    ("rand_small", lambda: random_coo((7, 8, 9), 100, seed=1)),
+    ("rand_ragged", lambda: random_coo((300, 40, 50), 9000, seed=2, skew=1.2)),
+    ("rand_4way", lambda: random_coo((17, 23, 5, 31), 4000, seed=3)),
+    ("long_rows", lambda: random_coo((3, 200, 200), 20000, seed=4)),
+]
+
+
+@pytest.mark.parametrize("name,make", SPARSE_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("R", [1, 5, 16, 40])
+def test_sparse_mttkrp_parity(h, name, make, prec, R):
+    cpng = _cpng()
+    print(f"case sparse mttkrp {name} R={R} prec={prec}", flush=True)
+    sp = make()
+    dtype = np.float64 if prec == "fp64" else np.float32
+    vals = sp.values.astype(dtype).astype(np.float64)
+    Tg = _sparse(cpng, sp, dtype)
+    cpng.cp_tensor_prepare(h, Tg)
+    A = _factors(sp.dims, R, 21)
+    u = _dev(ocp.join_u(A))
+    for n in range(len(sp.dims)):
+        M = cpng.cp_mttkrp(h, Tg, u, R, n, prec).cpu().numpy()
+        ref = ocp.mttkrp_coo(sp.dims, sp.coords, vals, A, n)
+        bound = abs_mttkrp_coo(sp.dims, sp.coords, vals, A, n)
+        assert_close_to_bound(M, ref, bound, TOL[prec], f"{name} mode {n}")
+    cpng.cp_tensor_release(h, Tg)
+
+
+def test_sparse_empty_and_errors(h):
+    cpng = _cpng()
+    dims = (4, 5, 6)
+    T = cpng.Tensor(dims, torch.zeros(0, dtype=torch.float64, device="cuda"),
+                    coords=torch.zeros((3, 0), dtype=torch.int32, device="cuda"))
+    cpng.cp_tensor_prepare(h, T)
+    M = cpng.cp_mttkrp(h, T, _dev(np.ones(15 * 2)), 2, 1, "fp64").cpu().numpy()
+    assert np.all(M == 0)
+    # duplicate coordinates are rejected
+    coords = np.array([[0, 1, 0], [2, 2, 2], [3, 3, 3]], dtype=np.int32)
+    Td = cpng.Tensor(dims, _dev(np.ones(3)), coords=_dev(coords))
+    with pytest.raises(cpng.CpError) as e:
+        cpng.cp_tensor_prepare(h, Td)
+    assert e.value.code == -5
+    # out-of-range coordinate is rejected
+    coords = np.array([[0, 4], [0, 0], [0, 0]], dtype=np.int32)
+    Tb = cpng.Tensor(dims, _dev(np.ones(2)), coords=_dev(coords))
+    with pytest.raises(cpng.CpError) as e:
+        cpng.cp_tensor_prepare(h, Tb)
+    assert e.value.code == -1
+
+
+def test_sparse_objective_grad_parity(h):
+    cpng = _cpng()
+    sp = random_coo((30, 20, 25), 3000, seed=9, skew=0.8)
+    R = 4
+    Tg = _sparse(cpng, sp, np.float64)
+    cpng.cp_tensor_prepare(h, Tg)
+    A = _factors(sp.dims, R, 22, scale=0.7)
+    f, g = cpng.cp_objective_grad(h, Tg, _dev(ocp.join_u(A)), R, "fp64")
+    t = ocp.CooTensor(sp.dims, sp.coords, sp.values)
+    Ms = [t.mttkrp(A, n) for n in range(3)]
+    fo = t.objective(A, Ms)
+    go = ocp.join_u(ocp.gradient_from_mttkrps(A, Ms))
+    half = 0.5 * t.norm2
+    assert abs(f.item() - fo) <= 1e-12 * half
+    assert np.linalg.norm(g.cpu().numpy() - go) <= 1e-12 * np.sqrt(t.norm2)
