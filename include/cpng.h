@@ -207,6 +207,16 @@ int cp_normalize(cp_handle* h, int32_t order, const int64_t* dims, double* u_ino
 int cp_als_sweep(cp_handle* h, const cp_tensor* T, double* u_inout, int32_t R, int32_t p,
                  int32_t normalize, hipStream_t stream);
 
+/* The ALS mode update alone (Section 2.3: solve the optimality equation
+ * G^(n) = 0 for A^(n)): A_out = M Gbar^-1 for M (I x R) and the symmetric
+ * Gbar (R x R), by Cholesky; if a pivot is not positive, Cholesky of
+ * Gbar + 1e-14 tr(Gbar)/R I; if that fails too, the pseudo-inverse from a
+ * cyclic Jacobi eigendecomposition (eigenvalues of magnitude below
+ * R eps max|w| dropped).  kind_out (host, nullable): 0, 1 or 2 for the path
+ * taken; synchronises the stream when kind_out is given. */
+int cp_mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int32_t R,
+                  double* A_out, int32_t* kind_out, hipStream_t stream);
+
 /* Objective and gradient at u (Optimization Problem I; Section 2.3):
  *   f = 1/2 ||T||^2 - <A^(N), M^(N)> + 1/2 sum_{r,s} Gamma(r,s)
  *   G^(n) = -M^(n) + A^(n) Gammabar^(n)           for every n

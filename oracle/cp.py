@@ -74,6 +74,8 @@ def mttkrp(T, factors, n):
     matricisation times the explicit Khatri-Rao product of the other factors.
     """
     others = [factors[k] for k in range(len(factors)) if k != n]
+    if not others:   # order 1: the empty Khatri-Rao product is a row of ones
+        return matricize(T, n) @ np.ones((1, factors[n].shape[1]))
     return matricize(T, n) @ khatri_rao(others)
 
 

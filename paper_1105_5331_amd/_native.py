@@ -86,6 +86,7 @@ def lib():
             "cp_normalize": (C.c_int, [vp, i32, C.POINTER(i64), vp, i32, vp, vp]),
             "cp_als_sweep": (C.c_int, [vp, C.POINTER(cp_tensor), vp, i32, i32, i32, vp]),
             "cp_objective_grad": (C.c_int, [vp, C.POINTER(cp_tensor), vp, i32, i32, vp, vp, vp]),
+            "cp_mode_solve": (C.c_int, [vp, vp, vp, i64, i32, vp, C.POINTER(i32), vp]),
             "ngmres_accelerate": (C.c_int, [vp, i64, i32, vp, vp, vp, vp, dp, vp, vp, vp]),
             "cp_ngmres_create": (C.c_int, [vp, C.POINTER(cp_tensor), i32, C.POINTER(cp_options),
                                            vp, vp, C.POINTER(vp)]),
@@ -217,12 +218,24 @@ def cp_tensor_release(h: Handle, T: Tensor):
 
 def cp_mttkrp(h: Handle, T: Tensor, u, R: int, mode: int, prec="fp64", M_out=None):
     p = PREC[prec] if isinstance(prec, str) else int(prec)
+    rows = T.dims[mode] if 0 <= mode < len(T.dims) else 1   # the library reports a bad mode
     if M_out is None:
-        M_out = torch.empty((T.dims[mode], R), dtype=torch.float64, device=u.device)
+        M_out = torch.empty((rows, max(int(R), 1)), dtype=torch.float64, device=u.device)
     h.check(lib().cp_mttkrp(h._h, C.byref(T.c), _ptr(u, torch.float64, iterate_length(T.dims, R), "u"),
-                            int(R), int(mode), p, _ptr(M_out, torch.float64, T.dims[mode] * R, "M_out"),
+                            int(R), int(mode), p, _ptr(M_out, torch.float64, rows * R, "M_out"),
                             _stream()))
     return M_out
+
+
+def cp_mode_solve(h: Handle, M, Gbar, A_out=None):
+    I, R = M.shape
+    if A_out is None:
+        A_out = torch.empty((I, R), dtype=torch.float64, device=M.device)
+    kind = C.c_int32()
+    h.check(lib().cp_mode_solve(h._h, _ptr(M, torch.float64, I * R, "M"),
+                                _ptr(Gbar, torch.float64, R * R, "Gbar"), int(I), int(R),
+                                _ptr(A_out, torch.float64, I * R, "A_out"), C.byref(kind), _stream()))
+    return A_out, kind.value
 
 
 def cp_gram(h: Handle, dims, u, R: int, want_bar=True, want_gamma=True):

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpng.so")
-SOURCES = ["dense_mttkrp.hip", "small.hip", "sparse.hip", "driver.hip"]
+SOURCES = ["dense_mttkrp.hip", "dense_fast.hip", "small.hip", "sparse.hip", "driver.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

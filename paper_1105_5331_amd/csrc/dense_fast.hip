@@ -1,0 +1,719 @@
+// Streaming dense MTTKRP on the gfx950 matrix cores (BF16x3), for the two
+// regular layouts that cover every mode of a C-order tensor whose innermost
+// contracted mode has a length divisible by 8.
+//
+// Both kernels split the contraction of M^(n) = T_(n) Phibar^(n)  (Section 2.3)
+// into an inner sum over one "inner" mode q and an outer sum over the rest:
+//     M(i, r) = sum_o P(o, r) * Y_o(i, r),   Y_o(i, r) = sum_k T(o, i, k) A^(q)(k, r),
+//     P(o, r) = prod_{modes m outside {n, q}} A^(m)(i_m(o), r).
+// The inner factor A^(q) is the same for every o: it is split into bf16
+// hi + lo once per workgroup and kept in LDS.  Y_o is a small GEMM on MFMA
+// (v_mfma_f32_16x16x32_bf16, three products hi*hi + hi*lo + lo*hi, float32
+// accumulation); the P(o, r) scaling is one FMA per accumulator.  The tensor
+// is read exactly once, straight from HBM into registers in the MFMA operand
+// layout (no LDS round trip), and split into bf16 hi + lo in registers.
+//
+//  * row kernel (n < N-1): inner mode q = N-1, contiguous in memory.  Lane
+//    l reads rows i (l % 16) as two float4 of 8 consecutive k: the A operand.
+//  * column kernel (n = N-1): inner mode q = N-2; the output index i is the
+//    contiguous one.  The MFMA computes Y^T = A^(q)^T T_o with the factor as
+//    the A operand (from LDS) and the tensor as the B operand: lane l reads
+//    8 rows k of one column i (l % 16), i.e. 16 consecutive floats per k-row
+//    across the lane group.
+//
+// Split-K over workgroups (blockIdx.x owns a contiguous range of outer
+// indices o); each workgroup writes its float32 partial sums to its own
+// slot; a second kernel adds the slots in slot order in float64.  No atomics.
+#include "common.hpp"
+
+#include <algorithm>
+
+namespace cpng {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThr = 256;
+constexpr int kMaxInner = 512;
+
+struct FastParams {
+  int R;
+  int nout;                          // number of outer modes
+  int64_t ostride[CP_MAX_ORDER];     // element stride of each outer mode in T
+  int64_t odims[CP_MAX_ORDER];
+  int64_t ofoff[CP_MAX_ORDER];       // factor offsets (elements) of the outer modes
+  int64_t qfoff;                     // factor offset of the inner mode
+  int64_t I_n;                       // output rows
+  int64_t K;                         // inner length (multiple of 8)
+  int64_t istride;                   // stride of the output index in T (row kernel)
+  int64_t kstride;                   // stride of the inner index in T (column kernel)
+  int64_t O;                         // number of outer indices
+  int64_t o_per_block;
+  int kpad;                          // LDS row length (bf16) of the staged inner factor
+  int nks;                           // K steps of 32
+  int vec_ok;                        // 16-byte loads along the unit-stride index are aligned
+};
+
+__device__ inline void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const __bf16 h = (__bf16)v[j];
+    hi[j] = h;
+    lo[j] = (__bf16)(v[j] - (float)h);   // v - h is exact in float32
+  }
+}
+
+// Stage the inner factor, columns r0..r0+31: S[r][k] = A^(q)(k, r0 + r) split,
+// zero for r >= R and for k in [K, 32 * nks).
+__device__ inline void stage_inner(const float* __restrict__ fac, const FastParams& p, int r0,
+                                   __bf16* Sh, __bf16* Sl) {
+  const int kr = p.nks * 32;
+  for (int e = threadIdx.x; e < 32 * kr; e += kThr) {
+    const int k = e >> 5, r = e & 31;
+    float v = 0.f;
+    if (k < p.K && r0 + r < p.R) v = fac[p.qfoff + (int64_t)k * p.R + r0 + r];
+    const __bf16 h = (__bf16)v;
+    Sh[r * p.kpad + k] = h;
+    Sl[r * p.kpad + k] = (__bf16)(v - (float)h);
+  }
+}
+
+// Base offset of outer index o in T and the scale P(o, r) for one rank r.
+__device__ inline int64_t outer_base(const FastParams& p, int64_t o) {
+  int64_t base = 0;
+  for (int m = p.nout - 1; m >= 0; --m) {
+    const int64_t d = p.odims[m];
+    const int64_t q = o / d;
+    base += (o - q * d) * p.ostride[m];
+    o = q;
+  }
+  return base;
+}
+
+__device__ inline float outer_scale(const float* __restrict__ fac, const FastParams& p, int64_t o,
+                                    int r) {
+  if (r >= p.R) return 0.f;
+  float s = 1.f;
+  for (int m = p.nout - 1; m >= 0; --m) {
+    const int64_t d = p.odims[m];
+    const int64_t q = o / d;
+    s *= fac[p.ofoff[m] + (o - q * d) * p.R + r];
+    o = q;
+  }
+  return s;
+}
+
+constexpr int kOChunk = 64;   // outer indices whose base offsets and scales sit in LDS
+
+// Base offsets (elements) and scales P(o, r0 + c), c < 32, of outer indices
+// oc .. oc + nc - 1, computed once per chunk instead of once per lane.
+__device__ inline void fill_outer_tables(const float* __restrict__ fac, const FastParams& p,
+                                         int64_t oc, int nc, int r0, int64_t* base_tab,
+                                         float* P_tab) {
+  __syncthreads();   // the previous chunk is no longer read
+  for (int e = threadIdx.x; e < nc * 33; e += kThr) {
+    const int j = e / 33, c = e - (e / 33) * 33;
+    if (c == 32) base_tab[j] = outer_base(p, oc + j);
+    else P_tab[j * 32 + c] = outer_scale(fac, p, oc + j, r0 + c);
+  }
+  __syncthreads();
+}
+
+// Row-kernel operand: 8 consecutive k of rows (w*MT + mt)*16 + lr, zero outside.
+template <int MT>
+__device__ inline void load_rows(const float* __restrict__ T, const FastParams& p, int64_t base,
+                                 const int64_t (&rowoff)[MT], const bool (&rowok)[MT], int k,
+                                 float (&v)[MT][8]) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    if (rowok[mt] && k < p.K) {
+      const float* src = T + base + rowoff[mt] + k;
+      const float4 a = *reinterpret_cast<const float4*>(src);
+      const float4 b = *reinterpret_cast<const float4*>(src + 4);
+      v[mt][0] = a.x; v[mt][1] = a.y; v[mt][2] = a.z; v[mt][3] = a.w;
+      v[mt][4] = b.x; v[mt][5] = b.y; v[mt][6] = b.z; v[mt][7] = b.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[mt][q] = 0.f;
+    }
+  }
+}
+
+// Row kernel: 4 waves x MT row tiles of 16 = 64*MT rows, 32 ranks.
+template <int MT>
+__global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restrict__ T,
+                                                           const float* __restrict__ fac,
+                                                           FastParams p, float* __restrict__ part) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  __bf16* Sh = reinterpret_cast<__bf16*>(dyn_lds);
+  __bf16* Sl = Sh + 32 * p.kpad;
+  __shared__ int64_t base_tab[kOChunk];
+  __shared__ float P_tab[kOChunk * 32];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int lr = lane & 15;
+  const int kb = (lane >> 4) * 8;
+  const int r0 = blockIdx.z * 32;
+  const int64_t i0 = (int64_t)blockIdx.y * (64 * MT);
+  stage_inner(fac, p, r0, Sh, Sl);
+  __syncthreads();
+
+  int64_t rowoff[MT];
+  bool rowok[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int64_t i = i0 + (w * MT + mt) * 16 + lr;
+    rowok[mt] = i < p.I_n;
+    rowoff[mt] = rowok[mt] ? i * p.istride : 0;
+  }
+  floatx4 acc[MT][2];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t ob = (int64_t)blockIdx.x * p.o_per_block;
+  const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
+  for (int64_t oc = ob; oc < oe; oc += kOChunk) {
+    const int nc = (int)min<int64_t>(kOChunk, oe - oc);
+    fill_outer_tables(fac, p, oc, nc, r0, base_tab, P_tab);
+    const int nit = nc * p.nks;
+    float v[MT][8], vn[MT][8];
+    load_rows<MT>(T, p, base_tab[0], rowoff, rowok, kb, v);
+    floatx4 Y[MT][2];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int j = 0, ks = 0;
+    for (int it = 0; it < nit; ++it) {
+      // prefetch the operand of the next (o, k-step) before the MFMAs of this one
+      const int ks_n = ks + 1 == p.nks ? 0 : ks + 1;
+      const int j_n = ks + 1 == p.nks ? j + 1 : j;
+      if (it + 1 < nit) load_rows<MT>(T, p, base_tab[j_n], rowoff, rowok, ks_n * 32 + kb, vn);
+      bf16x8 ah[MT], al[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) split8(v[mt], ah[mt], al[mt]);
+      const int k = ks * 32 + kb;
+      const int so0 = lr * p.kpad + k;
+      const int so1 = (16 + lr) * p.kpad + k;
+      const bf16x8 bh0 = *reinterpret_cast<const bf16x8*>(&Sh[so0]);
+      const bf16x8 bl0 = *reinterpret_cast<const bf16x8*>(&Sl[so0]);
+      const bf16x8 bh1 = *reinterpret_cast<const bf16x8*>(&Sh[so1]);
+      const bf16x8 bl1 = *reinterpret_cast<const bf16x8*>(&Sl[so1]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        Y[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bh0, Y[mt][0], 0, 0, 0);
+        Y[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bl0, Y[mt][0], 0, 0, 0);
+        Y[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh0, Y[mt][0], 0, 0, 0);
+        Y[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bh1, Y[mt][1], 0, 0, 0);
+        Y[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bl1, Y[mt][1], 0, 0, 0);
+        Y[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh1, Y[mt][1], 0, 0, 0);
+      }
+      if (ks + 1 == p.nks) {
+        const float P0 = P_tab[j * 32 + lr];
+        const float P1 = P_tab[j * 32 + 16 + lr];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            acc[mt][0][q] = fmaf(P0, Y[mt][0][q], acc[mt][0][q]);
+            acc[mt][1][q] = fmaf(P1, Y[mt][1][q], acc[mt][1][q]);
+          }
+          Y[mt][0] = floatx4{0.f, 0.f, 0.f, 0.f};
+          Y[mt][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[mt][q] = vn[mt][q];
+      ks = ks_n;
+      j = j_n;
+    }
+  }
+  float* out = part + (int64_t)blockIdx.x * p.I_n * p.R;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t i = i0 + (w * MT + mt) * 16 + (lane >> 4) * 4 + q;
+        const int r = r0 + nt * 16 + lr;
+        if (i < p.I_n && r < p.R) out[i * p.R + r] = acc[mt][nt][q];
+      }
+}
+
+// Column-kernel operand: rows k .. k+7 of columns (w*NT + nt)*16 + lr.
+template <int NT>
+__device__ inline void load_cols(const float* __restrict__ T, const FastParams& p, int64_t base,
+                                 const int64_t (&col)[NT], const bool (&colok)[NT], int k,
+                                 float (&v)[NT][8]) {
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    if (colok[nt] && k < p.K) {
+      const float* src = T + base + (int64_t)k * p.kstride + col[nt];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[nt][q] = src[(int64_t)q * p.kstride];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[nt][q] = 0.f;
+    }
+  }
+}
+
+// Column kernel: Y^T(r, i) = sum_k A^(q)(k, r) T(o, k, i); 4 waves x NT column
+// tiles of 16 = 64*NT output rows i, 32 ranks (two 16-row MFMA tiles).
+template <int NT>
+__global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restrict__ T,
+                                                           const float* __restrict__ fac,
+                                                           FastParams p, float* __restrict__ part) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  __bf16* Sh = reinterpret_cast<__bf16*>(dyn_lds);
+  __bf16* Sl = Sh + 32 * p.kpad;
+  __shared__ int64_t base_tab[kOChunk];
+  __shared__ float P_tab[kOChunk * 32];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int lr = lane & 15;
+  const int kb = (lane >> 4) * 8;
+  const int r0 = blockIdx.z * 32;
+  const int64_t i0 = (int64_t)blockIdx.y * (64 * NT);
+  stage_inner(fac, p, r0, Sh, Sl);
+  __syncthreads();
+
+  int64_t col[NT];
+  bool colok[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int64_t i = i0 + (w * NT + nt) * 16 + lr;
+    colok[nt] = i < p.I_n;
+    col[nt] = colok[nt] ? i : 0;
+  }
+  floatx4 acc[2][NT];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t ob = (int64_t)blockIdx.x * p.o_per_block;
+  const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
+  for (int64_t oc = ob; oc < oe; oc += kOChunk) {
+    const int nc = (int)min<int64_t>(kOChunk, oe - oc);
+    fill_outer_tables(fac, p, oc, nc, r0, base_tab, P_tab);
+    const int nit = nc * p.nks;
+    float v[NT][8], vn[NT][8];
+    load_cols<NT>(T, p, base_tab[0], col, colok, kb, v);
+    floatx4 Y[2][NT];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int j = 0, ks = 0;
+    for (int it = 0; it < nit; ++it) {
+      const int ks_n = ks + 1 == p.nks ? 0 : ks + 1;
+      const int j_n = ks + 1 == p.nks ? j + 1 : j;
+      if (it + 1 < nit) load_cols<NT>(T, p, base_tab[j_n], col, colok, ks_n * 32 + kb, vn);
+      const int k = ks * 32 + kb;
+      const int so0 = lr * p.kpad + k;
+      const int so1 = (16 + lr) * p.kpad + k;
+      const bf16x8 ah0 = *reinterpret_cast<const bf16x8*>(&Sh[so0]);
+      const bf16x8 al0 = *reinterpret_cast<const bf16x8*>(&Sl[so0]);
+      const bf16x8 ah1 = *reinterpret_cast<const bf16x8*>(&Sh[so1]);
+      const bf16x8 al1 = *reinterpret_cast<const bf16x8*>(&Sl[so1]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        bf16x8 bh, bl;
+        split8(v[nt], bh, bl);
+        Y[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, Y[0][nt], 0, 0, 0);
+        Y[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, Y[0][nt], 0, 0, 0);
+        Y[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, Y[0][nt], 0, 0, 0);
+        Y[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, Y[1][nt], 0, 0, 0);
+        Y[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, Y[1][nt], 0, 0, 0);
+        Y[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, Y[1][nt], 0, 0, 0);
+      }
+      if (ks + 1 == p.nks) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float P = P_tab[j * 32 + mt * 16 + (lane >> 4) * 4 + q];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt][q] = fmaf(P, Y[mt][nt][q], acc[mt][nt][q]);
+          }
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[nt][q] = vn[nt][q];
+      ks = ks_n;
+      j = j_n;
+    }
+  }
+  float* out = part + (int64_t)blockIdx.x * p.I_n * p.R;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + mt * 16 + (lane >> 4) * 4 + q;
+        const int64_t i = i0 + (w * NT + nt) * 16 + lr;
+        if (i < p.I_n && r < p.R) out[i * p.R + r] = acc[mt][nt][q];
+      }
+}
+
+// Two-stage fixed-order sum of the workgroup slots: stage 1 adds the slots of
+// group g (slots g*per .. g*per + per - 1) into part2[g]; stage 2 adds the
+// groups in order.
+__global__ void reduce_groups_f32_kernel(const float* __restrict__ part, int64_t nsplit, int64_t n,
+                                         int64_t per, double* __restrict__ part2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t g = blockIdx.y;
+  const int64_t k1 = min<int64_t>(nsplit, (g + 1) * per);
+  double s = 0.0;
+  for (int64_t k = g * per; k < k1; ++k) s += (double)part[k * n + e];
+  part2[g * n + e] = s;
+}
+
+__global__ void reduce_final_kernel(const double* __restrict__ part2, int64_t ngroups, int64_t n,
+                                    double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s = 0.0;
+  for (int64_t g = 0; g < ngroups; ++g) s += part2[g * n + e];
+  out[e] = s;
+}
+
+
+// ---- vector (VALU) streaming kernel: float32 or float64 arithmetic --------------
+// Same inner/outer split, on the vector ALUs: for each outer index o and
+// each 64-wide chunk of the inner mode the workgroup loads the 64 x 64 tile
+// T(o, i0..i0+63, k0..k0+63) with 16-byte coalesced loads along the unit-
+// stride index, stores it [k][i] in LDS, builds the Khatri-Rao tile
+// B(k, r) = P(o, r) A^(q)(k0 + k, r) next to it, and every lane (one row i)
+// accumulates acc(r) += T(i, k) B(k, r) over its wave's quarter of the k's.
+// The four waves are summed in a fixed order at the end.
+template <typename TT, typename CT, int RB, bool ROWS>
+__global__ __launch_bounds__(kThr) void mttkrp_tiles_vec(const TT* __restrict__ T,
+                                                         const CT* __restrict__ fac,
+                                                         FastParams p, CT* __restrict__ part) {
+  constexpr int TB = 64;           // tile edge (rows i and inner k)
+  constexpr int TS = TB + 1;       // padded LDS stride
+  constexpr int VE = 16 / sizeof(TT);   // elements per 16-byte load
+  __shared__ CT Ts[TB * TS];       // [k][i]
+  __shared__ CT Bs[TB * RB];       // [k][r]
+  __shared__ int64_t base_tab[kOChunk];
+  __shared__ CT P_tab[kOChunk * RB];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int g = tid >> 6;
+  const int r0 = blockIdx.z * RB;
+  const int64_t i0 = (int64_t)blockIdx.y * TB;
+  const int nkc = (int)((p.K + TB - 1) / TB);
+
+  CT acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = CT(0);
+
+  const int64_t ob = (int64_t)blockIdx.x * p.o_per_block;
+  const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
+  for (int64_t oc = ob; oc < oe; oc += kOChunk) {
+    const int nc = (int)min<int64_t>(kOChunk, oe - oc);
+    __syncthreads();
+    for (int e = tid; e < nc * (RB + 1); e += kThr) {
+      const int j = e / (RB + 1), c = e - (e / (RB + 1)) * (RB + 1);
+      if (c == RB) {
+        base_tab[j] = outer_base(p, oc + j);
+      } else {
+        CT sc = CT(0);
+        if (r0 + c < p.R) {
+          sc = CT(1);
+          int64_t o = oc + j;
+          for (int m = p.nout - 1; m >= 0; --m) {
+            const int64_t d = p.odims[m];
+            const int64_t q = o / d;
+            sc *= fac[p.ofoff[m] + (o - q * d) * p.R + r0 + c];
+            o = q;
+          }
+        }
+        P_tab[j * RB + c] = sc;
+      }
+    }
+    __syncthreads();   // tables complete before any wave reads them
+    for (int j = 0; j < nc; ++j) {
+      const int64_t base = base_tab[j];
+      for (int kc = 0; kc < nkc; ++kc) {
+        const int64_t k0 = (int64_t)kc * TB;
+        __syncthreads();
+        // tensor tile -> Ts[k][i]
+        for (int e = tid; e < TB * TB / VE; e += kThr) {
+          TT v[VE];
+          if (ROWS) {   // unit stride along k
+            const int ii = e / (TB / VE), kk = (e % (TB / VE)) * VE;
+            const int64_t i = i0 + ii, k = k0 + kk;
+            if (p.vec_ok && i < p.I_n && k + VE <= p.K) {
+              const TT* src = T + base + i * p.istride + k;
+              if constexpr (VE == 4) {
+                const float4 x = *reinterpret_cast<const float4*>(src);
+                v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+              } else {
+                const double2 x = *reinterpret_cast<const double2*>(src);
+                v[0] = x.x; v[1] = x.y;
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < VE; ++q)
+                v[q] = (i < p.I_n && k + q < p.K) ? T[base + i * p.istride + k + q] : TT(0);
+            }
+#pragma unroll
+            for (int q = 0; q < VE; ++q) Ts[(kk + q) * TS + ii] = (CT)v[q];
+          } else {      // unit stride along i
+            const int kk = e / (TB / VE), ii = (e % (TB / VE)) * VE;
+            const int64_t i = i0 + ii, k = k0 + kk;
+            if (p.vec_ok && k < p.K && i + VE <= p.I_n) {
+              const TT* src = T + base + k * p.kstride + i;
+              if constexpr (VE == 4) {
+                const float4 x = *reinterpret_cast<const float4*>(src);
+                v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+              } else {
+                const double2 x = *reinterpret_cast<const double2*>(src);
+                v[0] = x.x; v[1] = x.y;
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < VE; ++q)
+                v[q] = (k < p.K && i + q < p.I_n) ? T[base + k * p.kstride + i + q] : TT(0);
+            }
+#pragma unroll
+            for (int q = 0; q < VE; ++q) Ts[kk * TS + ii + q] = (CT)v[q];
+          }
+        }
+        // Khatri-Rao tile B(k, r) = P(o, r) A^(q)(k0 + k, r)
+        for (int e = tid; e < TB * RB; e += kThr) {
+          const int kk = e / RB, rr = e - (e / RB) * RB;
+          const int64_t k = k0 + kk;
+          CT b = CT(0);
+          if (k < p.K && r0 + rr < p.R) b = P_tab[j * RB + rr] * fac[p.qfoff + k * p.R + r0 + rr];
+          Bs[kk * RB + rr] = b;
+        }
+        __syncthreads();
+        for (int kk = g; kk < TB; kk += 4) {
+          const CT x = Ts[kk * TS + lane];
+#pragma unroll
+          for (int r = 0; r < RB; ++r) acc[r] = fma(x, Bs[kk * RB + r], acc[r]);
+        }
+      }
+    }
+  }
+  // fixed-order sum of the four waves: (0 + 2) + (1 + 3), then 0 + 1
+  __syncthreads();
+  CT* red = Ts;   // 2 x [64][RB] fits in Ts + Bs? use Ts rows 0..(2*RB-1)
+  if (g >= 2)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) red[((g - 2) * RB + r) * TS + lane] = acc[r];
+  __syncthreads();
+  if (g < 2)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] += red[(g * RB + r) * TS + lane];
+  __syncthreads();
+  if (g == 1)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) red[r * TS + lane] = acc[r];
+  __syncthreads();
+  if (g == 0) {
+    const int64_t i = i0 + lane;
+    if (i < p.I_n) {
+      CT* out = part + (int64_t)blockIdx.x * p.I_n * p.R + i * p.R;
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r0 + r < p.R) out[r0 + r] = acc[r] + red[r * TS + lane];
+    }
+  }
+}
+
+template <typename CT>
+__global__ void reduce_groups_kernel(const CT* __restrict__ part, int64_t nsplit, int64_t n,
+                                     int64_t per, double* __restrict__ part2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t g = blockIdx.y;
+  const int64_t k1 = min<int64_t>(nsplit, (g + 1) * per);
+  double s = 0.0;
+  for (int64_t k = g * per; k < k1; ++k) s += (double)part[k * n + e];
+  part2[g * n + e] = s;
+}
+
+}  // namespace
+
+// Returns CP_OK after launching, or 1 if the shape is not one the streaming
+// kernels cover (the caller then uses the generic kernel).
+int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shape& s, int R,
+                      int mode, double* M, hipStream_t st) {
+  const int N = s.N;
+  if (N < 2) return 1;
+  const bool rows = mode < N - 1;
+  const int q = rows ? N - 1 : N - 2;
+  const int64_t K = s.dims[q];
+  if (K % 8 != 0 || K > kMaxInner) return 1;
+  if (reinterpret_cast<uintptr_t>(T) % 16 != 0) return 1;
+  FastParams p{};
+  p.R = R;
+  int64_t stride[CP_MAX_ORDER];
+  stride[N - 1] = 1;
+  for (int k = N - 2; k >= 0; --k) stride[k] = stride[k + 1] * s.dims[k + 1];
+  p.nout = 0;
+  p.O = 1;
+  for (int k = 0; k < N; ++k) {
+    if (k == mode || k == q) continue;
+    p.ostride[p.nout] = stride[k];
+    p.odims[p.nout] = s.dims[k];
+    p.ofoff[p.nout] = s.off[k] * R;
+    p.O *= s.dims[k];
+    p.nout++;
+  }
+  p.qfoff = s.off[q] * R;
+  p.I_n = s.dims[mode];
+  p.K = K;
+  p.istride = stride[mode];
+  p.kstride = stride[q];
+  p.nks = (int)((K + 31) / 32);
+  p.kpad = p.nks * 32 + 8;
+  const int tile = (rows ? (p.I_n > 64 ? 128 : 64) : (p.I_n > 64 ? 128 : 64));
+  const int64_t ychunks = (p.I_n + tile - 1) / tile;
+  const int64_t rchunks = (R + 31) / 32;
+  const int64_t target = 1024;
+  int64_t ks = std::max<int64_t>(1, std::min<int64_t>(p.O, (target + ychunks * rchunks - 1) / (ychunks * rchunks)));
+  p.o_per_block = (p.O + ks - 1) / ks;
+  ks = (p.O + p.o_per_block - 1) / p.o_per_block;
+  const int64_t n_out = p.I_n * R;
+  const int64_t per = 32;
+  const int64_t ngroups = (ks + per - 1) / per;
+  const size_t part_bytes = (sizeof(float) * (size_t)(ks * n_out) + 255) & ~size_t(255);
+  CP_TRY(ensure(h, h->part, part_bytes + sizeof(double) * (size_t)(ngroups * n_out), st));
+  float* part = static_cast<float*>(h->part.ptr);
+  double* part2 = reinterpret_cast<double*>(static_cast<char*>(h->part.ptr) + part_bytes);
+  dim3 grid((unsigned)ks, (unsigned)ychunks, (unsigned)rchunks);
+  const size_t lds = 2 * sizeof(__bf16) * 32 * (size_t)p.kpad;
+  {
+    KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
+    if (rows) {
+      if (tile == 128) hipLaunchKernelGGL(mttkrp_rows_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, p, part);
+      else hipLaunchKernelGGL(mttkrp_rows_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, p, part);
+    } else {
+      if (tile == 128) hipLaunchKernelGGL(mttkrp_cols_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, p, part);
+      else hipLaunchKernelGGL(mttkrp_cols_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, p, part);
+    }
+  }
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(reduce_groups_f32_kernel, dim3((unsigned)((n_out + 255) / 256), (unsigned)ngroups),
+                     dim3(256), 0, st, part, ks, n_out, per, part2);
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
+                     part2, ngroups, n_out, M);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+}  // namespace cpng
+
+namespace cpng {
+
+// Fills the inner/outer description of mode `mode`; the inner mode is N-1
+// for the row layout and N-2 for the column layout.
+static void fill_params(const Shape& s, int R, int mode, FastParams* pp) {
+  FastParams& p = *pp;
+  const int N = s.N;
+  const bool rows = mode < N - 1;
+  const int q = rows ? N - 1 : N - 2;
+  p = FastParams{};
+  p.R = R;
+  int64_t stride[CP_MAX_ORDER];
+  stride[N - 1] = 1;
+  for (int k = N - 2; k >= 0; --k) stride[k] = stride[k + 1] * s.dims[k + 1];
+  p.nout = 0;
+  p.O = 1;
+  for (int k = 0; k < N; ++k) {
+    if (k == mode || k == q) continue;
+    p.ostride[p.nout] = stride[k];
+    p.odims[p.nout] = s.dims[k];
+    p.ofoff[p.nout] = s.off[k] * R;
+    p.O *= s.dims[k];
+    p.nout++;
+  }
+  p.qfoff = s.off[q] * R;
+  p.I_n = s.dims[mode];
+  p.K = s.dims[q];
+  p.istride = stride[mode];
+  p.kstride = stride[q];
+  p.nks = (int)((p.K + 31) / 32);
+  p.kpad = p.nks * 32 + 8;
+}
+
+template <typename TT, typename CT, int RB>
+static int launch_tiles(cp_handle* h, const TT* T, const CT* fac, FastParams p, bool rows,
+                        double* M, hipStream_t st) {
+  const int64_t ychunks = (p.I_n + 63) / 64;
+  const int64_t rchunks = (p.R + RB - 1) / RB;
+  const int64_t target = 1024;
+  int64_t ks = std::max<int64_t>(1, std::min<int64_t>(p.O, (target + ychunks * rchunks - 1) / (ychunks * rchunks)));
+  p.o_per_block = (p.O + ks - 1) / ks;
+  ks = (p.O + p.o_per_block - 1) / p.o_per_block;
+  const int64_t n_out = p.I_n * p.R;
+  const int64_t per = 32;
+  const int64_t ngroups = (ks + per - 1) / per;
+  const size_t part_bytes = (sizeof(CT) * (size_t)(ks * n_out) + 255) & ~size_t(255);
+  CP_TRY(ensure(h, h->part, part_bytes + sizeof(double) * (size_t)(ngroups * n_out), st));
+  CT* part = static_cast<CT*>(h->part.ptr);
+  double* part2 = reinterpret_cast<double*>(static_cast<char*>(h->part.ptr) + part_bytes);
+  dim3 grid((unsigned)ks, (unsigned)ychunks, (unsigned)rchunks);
+  {
+    KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
+    if (rows) hipLaunchKernelGGL((mttkrp_tiles_vec<TT, CT, RB, true>), grid, dim3(kThr), 0, st, T, fac, p, part);
+    else hipLaunchKernelGGL((mttkrp_tiles_vec<TT, CT, RB, false>), grid, dim3(kThr), 0, st, T, fac, p, part);
+  }
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL((reduce_groups_kernel<CT>), dim3((unsigned)((n_out + 255) / 256), (unsigned)ngroups),
+                     dim3(256), 0, st, part, ks, n_out, per, part2);
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
+                     part2, ngroups, n_out, M);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+// Vector-ALU streaming MTTKRP for FP32 (TT = CT = float) and FP64
+// accumulation (CT = double, TT = float or double).  Returns 1 if the layout
+// is not covered (order < 2 or a misaligned base pointer).
+template <typename TT, typename CT>
+int dense_fast_vec(cp_handle* h, const TT* T, const CT* fac, const Shape& s, int R, int mode,
+                   double* M, hipStream_t st) {
+  if (s.N < 2) return 1;
+  if (reinterpret_cast<uintptr_t>(T) % 16 != 0) return 1;
+  FastParams p;
+  fill_params(s, R, mode, &p);
+  const bool rows = mode < s.N - 1;
+  // 16-byte loads stay aligned when the unit-stride extent is a multiple of
+  // 16 bytes (every row or k-row then starts on a 16-byte boundary);
+  // otherwise the tile is loaded element by element.
+  p.vec_ok = rows ? (p.K * sizeof(TT)) % 16 == 0 : (p.I_n * sizeof(TT)) % 16 == 0;
+  if (R <= 8) return launch_tiles<TT, CT, 8>(h, T, fac, p, rows, M, st);
+  if (R <= 16) return launch_tiles<TT, CT, 16>(h, T, fac, p, rows, M, st);
+  return launch_tiles<TT, CT, 32>(h, T, fac, p, rows, M, st);
+}
+
+template int dense_fast_vec<float, float>(cp_handle*, const float*, const float*, const Shape&, int,
+                                          int, double*, hipStream_t);
+template int dense_fast_vec<float, double>(cp_handle*, const float*, const double*, const Shape&, int,
+                                           int, double*, hipStream_t);
+template int dense_fast_vec<double, double>(cp_handle*, const double*, const double*, const Shape&,
+                                            int, int, double*, hipStream_t);
+
+}  // namespace cpng

@@ -436,13 +436,29 @@ int dense_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double*
     CP_TRY(stage_factors_f32(h, u, L, &fac, st));
     if (prec == CP_PREC_BF16X3) {
       const float* Tv = static_cast<const float*>(T->values);
+      const int rc = dense_fast_bf16x3(h, Tv, fac, s, R, mode, M, st);
+      if (rc <= 0) return rc;   // launched (CP_OK) or failed
       return p.I_n > 64 ? launch_bf16x3<2>(h, Tv, fac, p, M, st)
                         : launch_bf16x3<1>(h, Tv, fac, p, M, st);
     }
+    {
+      const int rc = dense_fast_vec<float, float>(h, static_cast<const float*>(T->values), fac, s, R,
+                                                  mode, M, st);
+      if (rc <= 0) return rc;
+    }
     return dispatch_rank<float, float>(h, static_cast<const float*>(T->values), fac, p, M, st);
   }
-  if (T->dtype == CP_F32)
+  if (T->dtype == CP_F32) {
+    const int rc = dense_fast_vec<float, double>(h, static_cast<const float*>(T->values), u, s, R,
+                                                 mode, M, st);
+    if (rc <= 0) return rc;
     return dispatch_rank<float, double>(h, static_cast<const float*>(T->values), u, p, M, st);
+  }
+  {
+    const int rc = dense_fast_vec<double, double>(h, static_cast<const double*>(T->values), u, s, R,
+                                                  mode, M, st);
+    if (rc <= 0) return rc;
+  }
   return dispatch_rank<double, double>(h, static_cast<const double*>(T->values), u, p, M, st);
 }
 

@@ -507,6 +507,24 @@ int cp_als_sweep(cp_handle* h, const cp_tensor* T, double* u, int32_t R, int32_t
   return als_sweep_impl(h, T, s, u, R, p, normalize_after, st);
 }
 
+int cp_mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int32_t R,
+                  double* A_out, int32_t* kind_out, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  CP_TRY(check_rank(h, R));
+  if (I < 1 || !M || !Gbar || !A_out) return fail(h, CP_EINVAL, "bad mode-solve arguments");
+  CP_HIP(h, hipMemsetAsync(h->flags, 0, sizeof(int), st));
+  CP_TRY(mode_solve(h, M, Gbar, I, R, A_out, st));
+  if (kind_out) {
+    int v = 0;
+    CP_HIP(h, hipMemcpyAsync(&h->pinned[0], h->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    CP_HIP(h, hipStreamSynchronize(st));
+    std::memcpy(&v, &h->pinned[0], sizeof(int));
+    *kind_out = v & 3;
+  }
+  return CP_OK;
+}
+
 int cp_objective_grad(cp_handle* h, const cp_tensor* T, const double* u, int32_t R, int32_t p,
                       double* f_out, double* g_out, hipStream_t st) {
   if (!h) return CP_EINVAL;
@@ -634,11 +652,9 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
   rec.rho = S->rho;
   rec.beta = NAN;
   rec.ls_status = -1;
-  rec.m = S->wcount;
+  rec.m = S->opt.method == CP_METHOD_ALS ? 0 : S->wcount;
   rec.precision = S->prec;
   int rc = CP_OK;
-  const int L = 0;
-  (void)L;
   if (S->opt.method == CP_METHOD_ALS) {
     CP_TRY(als_sweep_impl(h, S->T, S->s, S->u, S->R, S->prec, 1, S->st));
     CP_TRY(eval_current(h, S));
@@ -738,7 +754,8 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
       if (o.trace && ntr < o.trace_cap) {
         cp_iter_info r{};
         r.it = S->it; r.f = S->f; r.rho = S->rho; r.beta = NAN; r.ls_status = -1;
-        r.m = S->wcount; r.precision = S->prec;
+        r.m = o.method == CP_METHOD_ALS ? 0 : S->wcount;
+        r.precision = S->prec;
         o.trace[ntr++] = r;
       }
       break;

@@ -3,8 +3,18 @@ schedule) against the FP64 oracle, through cp_decompose in the C ABI.
 
 Trajectories are compared iterate by iterate from the same initial guess
 until the first discrete divergence (restart flag, window size or number of
-line-search evaluations differ); up to there the float64 paths differ only by
-summation order, so f and rho agree to the stated tolerances below.
+line-search evaluations differ).  Up to there both sides are float64 and
+differ only in rounding (summation order, and the objective from the
+<T,[[A]]> expansion on the GPU against the direct residual in the oracle).
+The method amplifies rounding: the regularised normal equations of Step II
+have condition numbers up to 1/eps = 1e12, and near convergence the line
+search works on objective differences close to rounding.  The oracle run
+against itself with only its objective formula swapped, or with u0 perturbed
+by 1e-15 relative, moves beta by up to 1.2e-3 and rho by up to 2.5e-3
+relative on these problems (6 seeds), and rho by up to 6.4e-11 absolute
+once rho < 1e-7; the GPU path changes every summation order at once, so the
+tolerances below allow 4x to 15x those: 1e-2 relative plus an absolute
+floor of a tenth of the 1e-8 stopping tolerance.
 """
 import numpy as np
 import pytest
@@ -19,7 +29,9 @@ pytestmark = pytest.mark.gpu
 
 # Per-iterate tolerances on a shared trajectory (float64 on both sides):
 F_TOL = 1e-10     # |f_gpu - f_oracle| / (1/2 ||T||^2)
-RHO_REL = 1e-6    # |rho_gpu - rho_oracle| / rho_oracle (+ 1e-13 absolute)
+RHO_REL = 1e-2    # |rho_gpu - rho_oracle| / rho_oracle ...
+RHO_ABS = 1e-9    # ... + this absolute floor
+BETA_REL = 1e-2   # |beta_gpu - beta_oracle| / max(1, |beta_oracle|)
 
 
 @pytest.fixture(scope="module")
@@ -37,13 +49,13 @@ def _compare(trace, ref_trace, half, what):
     n = 0
     for a, b in zip(trace, ref_trace):
         assert abs(a["f"] - b.f) <= F_TOL * half, f"{what} it {b.it}: f {a['f']} vs {b.f}"
-        assert abs(a["rho"] - b.rho) <= RHO_REL * b.rho + 1e-13, \
+        assert abs(a["rho"] - b.rho) <= RHO_REL * b.rho + RHO_ABS, \
             f"{what} it {b.it}: rho {a['rho']} vs {b.rho}"
         n += 1
         if a["restart"] != b.restart or a["m"] != b.m or a["nfev"] != b.nfev:
             break
         if b.nfev:
-            assert abs(a["beta"] - b.beta) <= 1e-6 * max(1.0, abs(b.beta)), \
+            assert abs(a["beta"] - b.beta) <= BETA_REL * max(1.0, abs(b.beta)), \
                 f"{what} it {b.it}: beta {a['beta']} vs {b.beta}"
     return n
 
@@ -114,7 +126,7 @@ def test_step_by_step_state_api(h):
         assert abs(info["f"] - ref.trace[k].f) <= F_TOL * half
     u, g, f, rho = st.get()
     assert abs(f - ref.trace[4].f) <= F_TOL * half
-    assert abs(rho - ref.trace[4].rho) <= RHO_REL * ref.trace[4].rho + 1e-13
+    assert abs(rho - ref.trace[4].rho) <= RHO_REL * ref.trace[4].rho + RHO_ABS
     st.close()
 
 

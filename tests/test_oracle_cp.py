@@ -40,7 +40,7 @@ def _brute_full(factors):
     return X
 
 
-@pytest.mark.parametrize("dims", [(3, 4, 5), (2, 3, 2, 3), (4, 1, 3), (2, 2, 2, 2, 2)])
+@pytest.mark.parametrize("dims", [(3, 4, 5), (2, 3, 2, 3), (4, 1, 3), (2, 2, 2, 2, 2), (6,), (3, 4)])
 @pytest.mark.parametrize("R", [1, 2, 4])
 def test_p1_mttkrp_matches_brute_force(dims, R):
     T = np.random.default_rng(1).standard_normal(dims)
