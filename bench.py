@@ -93,6 +93,92 @@ def time_to_grad(h, cpng, torch, seed=0):
     return out
 
 
+def sparse_mttkrp(h, cpng, torch, nnz_draw=20_000_000, R=16, reps=10):
+    """Config: sparse 20000^3 COO, uniform random coordinates (duplicates
+    removed), values from a rank-16 canonical tensor plus 1%+1% noise,
+    float32, fit rank 16; per-mode segmented-reduction MTTKRP."""
+    from workloads import sparse_random_cp
+    dims = (20000, 20000, 20000)
+    t0 = time.perf_counter()
+    sp = sparse_random_cp(dims, nnz_draw, 16, seed=0, dtype=np.float32)
+    log(f"sparse tensor generated in {time.perf_counter() - t0:.1f} s, nnz {sp.values.size}")
+    Tg = cpng.Tensor(dims, torch.from_numpy(sp.values).cuda(),
+                     coords=torch.from_numpy(sp.coords).cuda())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cpng.cp_tensor_prepare(h, Tg)
+    prep = time.perf_counter() - t0
+    u = torch.rand(sum(dims) * R, dtype=torch.float64, device="cuda")
+    nnz = sp.values.size
+    per_mode = []
+    for n in range(3):
+        for _ in range(2):
+            cpng.cp_mttkrp(h, Tg, u, R, n, "fp32")
+        torch.cuda.synchronize()
+        cpng.cp_profile(h, True)
+        for _ in range(reps):
+            cpng.cp_mttkrp(h, Tg, u, R, n, "fp32")
+        torch.cuda.synchronize()
+        nl, ms = cpng.cp_profile_read(h, cpng.CP_KERNEL_SPARSE_MTTKRP)
+        cpng.cp_profile(h, False)
+        us = ms / nl * 1e3
+        # sorted copy read once (other two coordinates + value), segment
+        # pointers, the two other factors (float32) and the output (float64)
+        alg = nnz * 12 + (dims[n] + 1) * 8 + 2 * dims[0] * R * 4 + dims[n] * R * 8
+        per_mode.append({"mode": n, "kernel_us": round(us, 1),
+                         "GBs": round(alg / (us * 1e-6) / 1e9, 1),
+                         "frac": round(alg / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)})
+        log(f"sparse mode {n}: {per_mode[-1]}")
+    cpng.cp_tensor_release(h, Tg)
+    return {"nnz": int(nnz), "rank": R, "prepare_s": round(prep, 3), "modes": per_mode}
+
+
+def serving(cpng, torch, n=48, rate=None, slots_list=(4, 1), seed=7, max_iter=500):
+    """Poisson stream of decomposition requests (dense 3-/4-way float32, mode
+    sizes U{16..160}, R U{2..24}, congruence U[0, 0.9], noise 1%+1%,
+    tol 1e-8) through the continuous-batching server; p50/p99 latency from
+    submission to result, solves/s, for several slot counts."""
+    from workloads import initial_guess, serving_stream, test_problem_1_torch
+    reqs = serving_stream(n, rate_per_s=rate or 1e9, seed=seed)
+    data = []
+    for r in reqs:
+        T = test_problem_1_torch(r.dims, r.R, r.c, 1, 1, seed=r.seed)
+        u0 = torch.from_numpy(initial_guess(r.dims, r.R, seed=r.seed + 10000)).cuda()
+        data.append((r, T, u0))
+    torch.cuda.synchronize()
+    out = {}
+    for slots in slots_list:
+        srv = cpng.Server(0, slots=slots, max_iter=max_iter, precision="bf16x3",
+                          final_precision="fp32in_fp64acc", switch_rho=1e-4)
+        us = {}
+        t0 = time.perf_counter()
+        got = []
+        for r, T, u0 in data:
+            if rate:
+                delay = r.arrival - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+            u = u0.clone()
+            us[r.rid] = u
+            srv.submit(cpng.Tensor(r.dims, T), r.R, 1e-8, u, tag=r.rid)
+            got += srv.poll(0)
+        while len(got) < len(data):
+            got += srv.poll(wait_for=len(data) - len(got))
+        span = time.perf_counter() - t0
+        srv.close()
+        lat = np.array([g["t_end"] - g["t_submit"] for g in got])
+        conv = sum(1 for g in got if g["converged"])
+        out[f"slots{slots}"] = {
+            "requests": len(got), "p50_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_s": round(float(np.percentile(lat, 99)), 4),
+            "solves_per_s": round(len(got) / span, 3), "makespan_s": round(span, 3),
+            "converged": conv, "not_converged": len(got) - conv,
+            "errors": sum(1 for g in got if g["status"] < 0)}
+        log(f"serving slots={slots}: {out[f'slots{slots}']}")
+    return {"load": f"{n} requests, Poisson rate {rate if rate else 'inf (all queued at t=0)'} /s",
+            **out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +189,11 @@ def main():
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-extra", action="store_true")
+    ap.add_argument("--serving", type=int, default=0, metavar="N",
+                    help="only run the serving benchmark with N requests")
+    ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate for --serving")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -116,6 +207,20 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.serving:
+        res = serving(cpng, torch, n=args.serving, rate=args.rate or None)
+        print(json.dumps({"metric": "serving p50/p99 latency and solves/s", **res}), flush=True)
+        return
+    if args.copy_reference:
+        # A plain copy of known size: reads and writes exactly 1 GiB, so the
+        # HBM byte counters of this dispatch calibrate those of the MTTKRP.
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes": 4 << 28}), flush=True)
+        return
     s, R, N = args.size, args.rank, 4
     dims = (s,) * N
     log(f"generating dense {dims} float32 Test Problem I, R={R}")
@@ -177,8 +282,12 @@ def main():
     }
     st.close()
     if not args.skip_extra:
+        del Tg, T
+        torch.cuda.empty_cache()
         log("time-to-grad study (200^3, R=10, c=0.9)")
         res["extra"] = {"time_to_grad_200cubed_R10": time_to_grad(h, cpng, torch)}
+        log("sparse MTTKRP (20000^3, ~2e7 nonzeros, R=16)")
+        res["extra"]["sparse_mttkrp_20000cubed_R16"] = sparse_mttkrp(h, cpng, torch)
     if not args.skip_cpu:
         log("cpu baseline (oracle)")
         A = [np.ascontiguousarray(x) for x in

@@ -258,6 +258,55 @@ int cp_ngmres_destroy(cp_handle* h, cp_ngmres_state* st);
 int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const cp_options* opt,
                  double* u_inout, cp_report* rep_out, hipStream_t stream);
 
+/* ---- serving: continuous batching of decomposition requests ------------- */
+
+typedef struct cp_server cp_server;
+
+typedef struct cp_server_opts {
+  int32_t slots;          /* decompositions running at once, each on its own stream (4; max 16) */
+  size_t hbm_budget;      /* bytes the running requests may occupy (0: 80% of free memory) */
+  cp_options decompose;   /* method options of every request (trace ignored) */
+} cp_server_opts;
+
+typedef struct cp_result {
+  int64_t req_id;         /* id returned by cp_server_submit */
+  uint64_t tag;           /* caller's tag */
+  int32_t status;         /* cp_decompose status (CP_OK, CP_MAXITER) or an error */
+  int32_t iters;
+  int32_t converged;
+  int32_t n_fg;
+  int32_t switch_iter;
+  int32_t slot;           /* slot that ran it */
+  double f;
+  double rho;
+  double t_submit;        /* seconds since cp_server_create */
+  double t_start;         /* admitted */
+  double t_end;           /* finished */
+} cp_result;
+
+/* Start a server on `device` with `slots` worker threads, each owning a
+ * handle and a HIP stream (default priority).  Requests are admitted in
+ * arrival order when a slot is free and their footprint (tensor, N-GMRES
+ * window and state, workspace estimate) fits in hbm_budget beside the running
+ * ones.  o nullable (defaults). */
+int cp_server_create(int device, const cp_server_opts* o, cp_server** s);
+/* Queue a decomposition of T (device arrays; prepared by the server) to
+ * rho <= tol from the initial guess in u_inout (device, L doubles), which
+ * receives the result.  T's arrays and u_inout must stay valid until the
+ * result has been polled.  A request larger than the whole budget completes
+ * at once with status CP_ENOMEM. */
+int cp_server_submit(cp_server* s, const cp_tensor* T, int32_t R, double tol, double* u_inout,
+                     uint64_t tag, int64_t* req_id);
+/* Move up to max_out finished results into out (host).  wait_for > 0 blocks
+ * until that many are available or nothing is queued or running. */
+int cp_server_poll(cp_server* s, int32_t wait_for, cp_result* out, int32_t max_out,
+                   int32_t* n_out);
+/* Queue length, running requests, bytes admitted, budget (host, nullable). */
+int cp_server_stats(cp_server* s, int32_t* queued, int32_t* active, size_t* in_use,
+                    size_t* budget);
+/* Stop: running requests finish, queued ones are dropped; joins the workers. */
+int cp_server_destroy(cp_server* s);
+
 /* ---- kernel timing ------------------------------------------------------ */
 
 /* Kernel ids for cp_profile_read. */

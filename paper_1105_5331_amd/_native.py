@@ -62,6 +62,18 @@ class cp_report(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class cp_server_opts(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("hbm_budget", C.c_size_t), ("decompose", cp_options)]
+
+
+class cp_result(C.Structure):
+    _fields_ = [("req_id", C.c_int64), ("tag", C.c_uint64), ("status", C.c_int32),
+                ("iters", C.c_int32), ("converged", C.c_int32), ("n_fg", C.c_int32),
+                ("switch_iter", C.c_int32), ("slot", C.c_int32), ("f", C.c_double),
+                ("rho", C.c_double), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_end", C.c_double)]
+
+
 _lib = None
 
 
@@ -95,6 +107,13 @@ def lib():
             "cp_ngmres_destroy": (C.c_int, [vp, vp]),
             "cp_decompose": (C.c_int, [vp, C.POINTER(cp_tensor), i32, dp, C.POINTER(cp_options),
                                        vp, C.POINTER(cp_report), vp]),
+            "cp_server_create": (C.c_int, [C.c_int, C.POINTER(cp_server_opts), C.POINTER(vp)]),
+            "cp_server_submit": (C.c_int, [vp, C.POINTER(cp_tensor), i32, dp, vp, C.c_uint64,
+                                           C.POINTER(i64)]),
+            "cp_server_poll": (C.c_int, [vp, i32, C.POINTER(cp_result), i32, C.POINTER(i32)]),
+            "cp_server_stats": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i32),
+                                          C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+            "cp_server_destroy": (C.c_int, [vp]),
             "cp_profile": (C.c_int, [vp, i32]),
             "cp_profile_read": (C.c_int, [vp, i32, C.POINTER(i64), C.POINTER(dp)]),
         }
@@ -385,3 +404,70 @@ def cp_decompose(h: Handle, T: Tensor, R: int, tol: float, u_inout, trace_cap=0,
             "rho": rep.rho, "n_fg": rep.n_fg, "n_restarts": rep.n_restarts,
             "n_ls_fallback": rep.n_ls_fallback, "switch_iter": rep.switch_iter,
             "seconds": rep.seconds, "trace": trace}
+
+
+class Server:
+    """Continuous-batching decomposition server (cp_server_* in the C ABI).
+
+    submit() hands a device tensor and initial guess to the native scheduler;
+    the caller's objects are kept alive here until their result is polled."""
+
+    def __init__(self, device=0, slots=4, hbm_budget=0, **opts):
+        o = cp_server_opts()
+        o.slots = int(slots)
+        o.hbm_budget = int(hbm_budget)
+        o.decompose = options(**opts)
+        self._s = C.c_void_p()
+        rc = lib().cp_server_create(int(device), C.byref(o), C.byref(self._s))
+        if rc != CP_OK:
+            raise CpError(rc, "cp_server_create failed")
+        self._keep = {}
+
+    def submit(self, T: Tensor, R: int, tol: float, u_inout, tag: int = 0):
+        rid = C.c_int64()
+        rc = lib().cp_server_submit(self._s, C.byref(T.c), int(R), float(tol),
+                                    _ptr(u_inout, torch.float64, iterate_length(T.dims, R), "u"),
+                                    C.c_uint64(tag), C.byref(rid))
+        if rc != CP_OK:
+            raise CpError(rc, "cp_server_submit failed")
+        self._keep[rid.value] = (T, u_inout)
+        return rid.value
+
+    def poll(self, wait_for=0, max_out=256):
+        buf = (cp_result * max_out)()
+        n = C.c_int32()
+        rc = lib().cp_server_poll(self._s, int(wait_for), buf, int(max_out), C.byref(n))
+        if rc != CP_OK:
+            raise CpError(rc, "cp_server_poll failed")
+        out = []
+        for i in range(n.value):
+            r = buf[i]
+            d = {k: getattr(r, k) for k, _ in cp_result._fields_}
+            d["converged"] = bool(d["converged"])
+            self._keep.pop(r.req_id, None)
+            out.append(d)
+        return out
+
+    def stats(self):
+        q, a = C.c_int32(), C.c_int32()
+        used, budget = C.c_size_t(), C.c_size_t()
+        lib().cp_server_stats(self._s, C.byref(q), C.byref(a), C.byref(used), C.byref(budget))
+        return {"queued": q.value, "active": a.value, "in_use": used.value, "budget": budget.value}
+
+    def close(self):
+        if self._s:
+            lib().cp_server_destroy(self._s)
+            self._s = C.c_void_p()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -36,6 +36,7 @@ struct cp_handle {
   cpng::DevBuf red;      // reduction partials
   cpng::DevBuf carry;    // sparse segment carries
   cpng::DevBuf tmpu;     // scratch iterate-sized vectors
+  cpng::DevBuf otab;     // per-launch outer-index tables of the streaming MTTKRP
   double* pinned = nullptr;   // host pinned readback area (64 doubles)
   int* flags = nullptr;       // device status word (ALS solve fallbacks)
   // optional event timing of the main MTTKRP kernels

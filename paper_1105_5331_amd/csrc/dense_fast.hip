@@ -38,6 +38,19 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kThr = 256;
 constexpr int kMaxInner = 512;
 
+// Tuning knobs (compile-time): workgroups per launch of the streaming
+// kernels, and how many (outer index, k-step) operands each lane keeps in
+// flight ahead of the MFMAs that consume them (1 or 2).
+#ifndef CPNG_STREAM_BLOCKS
+#define CPNG_STREAM_BLOCKS 1024
+#endif
+#ifndef CPNG_PREFETCH
+#define CPNG_PREFETCH 1
+#endif
+#ifndef CPNG_ROWSTREAM_TW
+#define CPNG_ROWSTREAM_TW 2
+#endif
+
 struct FastParams {
   int R;
   int nout;                          // number of outer modes
@@ -105,20 +118,23 @@ __device__ inline float outer_scale(const float* __restrict__ fac, const FastPar
   return s;
 }
 
-constexpr int kOChunk = 64;   // outer indices whose base offsets and scales sit in LDS
+constexpr int kOChunk = 64;   // outer indices per LDS table chunk (VALU kernel)
 
-// Base offsets (elements) and scales P(o, r0 + c), c < 32, of outer indices
-// oc .. oc + nc - 1, computed once per chunk instead of once per lane.
-__device__ inline void fill_outer_tables(const float* __restrict__ fac, const FastParams& p,
-                                         int64_t oc, int nc, int r0, int64_t* base_tab,
-                                         float* P_tab) {
-  __syncthreads();   // the previous chunk is no longer read
-  for (int e = threadIdx.x; e < nc * 33; e += kThr) {
-    const int j = e / 33, c = e - (e / 33) * 33;
-    if (c == 32) base_tab[j] = outer_base(p, oc + j);
-    else P_tab[j * 32 + c] = outer_scale(fac, p, oc + j, r0 + c);
-  }
-  __syncthreads();
+// Outer-index tables of one launch: base offset of every outer index o and
+// the scales P(o, r) = prod_{outer modes m} A^(m)(i_m(o), r) for all r < R.
+// Computed once here instead of in every workgroup.
+__global__ void outer_tables_kernel(const float* __restrict__ fac, FastParams p,
+                                    float* __restrict__ Pg, int64_t* __restrict__ bg) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = e / (p.R + 1);
+  const int c = (int)(e - o * (p.R + 1));
+  if (o >= p.O) return;
+  if (c == p.R) bg[o] = outer_base(p, o);
+  else Pg[o * p.R + c] = outer_scale(fac, p, o, c);
+}
+
+__device__ inline float pscale(const float* __restrict__ Pg, const FastParams& p, int64_t o, int r) {
+  return r < p.R ? Pg[o * p.R + r] : 0.f;
 }
 
 // Row-kernel operand: 8 consecutive k of rows (w*MT + mt)*16 + lr, zero outside.
@@ -145,12 +161,12 @@ __device__ inline void load_rows(const float* __restrict__ T, const FastParams& 
 template <int MT>
 __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restrict__ T,
                                                            const float* __restrict__ fac,
+                                                           const float* __restrict__ Pg,
+                                                           const int64_t* __restrict__ bg,
                                                            FastParams p, float* __restrict__ part) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   __bf16* Sh = reinterpret_cast<__bf16*>(dyn_lds);
   __bf16* Sl = Sh + 32 * p.kpad;
-  __shared__ int64_t base_tab[kOChunk];
-  __shared__ float P_tab[kOChunk * 32];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int lr = lane & 15;
@@ -176,12 +192,20 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
 
   const int64_t ob = (int64_t)blockIdx.x * p.o_per_block;
   const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
-  for (int64_t oc = ob; oc < oe; oc += kOChunk) {
-    const int nc = (int)min<int64_t>(kOChunk, oe - oc);
-    fill_outer_tables(fac, p, oc, nc, r0, base_tab, P_tab);
+  {
+    const int64_t oc = ob;
+    const int nc = (int)(oe - ob);
+    const int64_t* base_tab = bg + oc;
     const int nit = nc * p.nks;
-    float v[MT][8], vn[MT][8];
-    load_rows<MT>(T, p, base_tab[0], rowoff, rowok, kb, v);
+    // operand ring: buf[0] is consumed this iteration, buf[1..PF] are in flight
+    constexpr int PF = CPNG_PREFETCH;
+    float buf[PF + 1][MT][8];
+    int jl = 0, kl = 0;   // (outer, k-step) of the next load
+#pragma unroll
+    for (int b = 0; b < PF; ++b) {
+      if (b < nit) load_rows<MT>(T, p, base_tab[jl], rowoff, rowok, kl * 32 + kb, buf[b]);
+      if (++kl == p.nks) { kl = 0; ++jl; }
+    }
     floatx4 Y[MT][2];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -189,13 +213,11 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
       for (int nt = 0; nt < 2; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
     int j = 0, ks = 0;
     for (int it = 0; it < nit; ++it) {
-      // prefetch the operand of the next (o, k-step) before the MFMAs of this one
-      const int ks_n = ks + 1 == p.nks ? 0 : ks + 1;
-      const int j_n = ks + 1 == p.nks ? j + 1 : j;
-      if (it + 1 < nit) load_rows<MT>(T, p, base_tab[j_n], rowoff, rowok, ks_n * 32 + kb, vn);
+      if (it + PF < nit) load_rows<MT>(T, p, base_tab[jl], rowoff, rowok, kl * 32 + kb, buf[PF]);
+      if (++kl == p.nks) { kl = 0; ++jl; }
       bf16x8 ah[MT], al[MT];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) split8(v[mt], ah[mt], al[mt]);
+      for (int mt = 0; mt < MT; ++mt) split8(buf[0][mt], ah[mt], al[mt]);
       const int k = ks * 32 + kb;
       const int so0 = lr * p.kpad + k;
       const int so1 = (16 + lr) * p.kpad + k;
@@ -213,8 +235,8 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
         Y[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh1, Y[mt][1], 0, 0, 0);
       }
       if (ks + 1 == p.nks) {
-        const float P0 = P_tab[j * 32 + lr];
-        const float P1 = P_tab[j * 32 + 16 + lr];
+        const float P0 = pscale(Pg, p, oc + j, r0 + lr);
+        const float P1 = pscale(Pg, p, oc + j, r0 + 16 + lr);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
@@ -225,13 +247,17 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
           Y[mt][0] = floatx4{0.f, 0.f, 0.f, 0.f};
           Y[mt][1] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
+        ks = 0;
+        ++j;
+      } else {
+        ++ks;
       }
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int b = 0; b < PF; ++b)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[mt][q] = vn[mt][q];
-      ks = ks_n;
-      j = j_n;
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) buf[b][mt][q] = buf[b + 1][mt][q];
     }
   }
   float* out = part + (int64_t)blockIdx.x * p.I_n * p.R;
@@ -270,12 +296,12 @@ __device__ inline void load_cols(const float* __restrict__ T, const FastParams& 
 template <int NT>
 __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restrict__ T,
                                                            const float* __restrict__ fac,
+                                                           const float* __restrict__ Pg,
+                                                           const int64_t* __restrict__ bg,
                                                            FastParams p, float* __restrict__ part) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   __bf16* Sh = reinterpret_cast<__bf16*>(dyn_lds);
   __bf16* Sl = Sh + 32 * p.kpad;
-  __shared__ int64_t base_tab[kOChunk];
-  __shared__ float P_tab[kOChunk * 32];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int lr = lane & 15;
@@ -301,12 +327,19 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
 
   const int64_t ob = (int64_t)blockIdx.x * p.o_per_block;
   const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
-  for (int64_t oc = ob; oc < oe; oc += kOChunk) {
-    const int nc = (int)min<int64_t>(kOChunk, oe - oc);
-    fill_outer_tables(fac, p, oc, nc, r0, base_tab, P_tab);
+  {
+    const int64_t oc = ob;
+    const int nc = (int)(oe - ob);
+    const int64_t* base_tab = bg + oc;
     const int nit = nc * p.nks;
-    float v[NT][8], vn[NT][8];
-    load_cols<NT>(T, p, base_tab[0], col, colok, kb, v);
+    constexpr int PF = CPNG_PREFETCH;
+    float buf[PF + 1][NT][8];
+    int jl = 0, kl = 0;
+#pragma unroll
+    for (int b = 0; b < PF; ++b) {
+      if (b < nit) load_cols<NT>(T, p, base_tab[jl], col, colok, kl * 32 + kb, buf[b]);
+      if (++kl == p.nks) { kl = 0; ++jl; }
+    }
     floatx4 Y[2][NT];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
@@ -314,9 +347,8 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
       for (int nt = 0; nt < NT; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
     int j = 0, ks = 0;
     for (int it = 0; it < nit; ++it) {
-      const int ks_n = ks + 1 == p.nks ? 0 : ks + 1;
-      const int j_n = ks + 1 == p.nks ? j + 1 : j;
-      if (it + 1 < nit) load_cols<NT>(T, p, base_tab[j_n], col, colok, ks_n * 32 + kb, vn);
+      if (it + PF < nit) load_cols<NT>(T, p, base_tab[jl], col, colok, kl * 32 + kb, buf[PF]);
+      if (++kl == p.nks) { kl = 0; ++jl; }
       const int k = ks * 32 + kb;
       const int so0 = lr * p.kpad + k;
       const int so1 = (16 + lr) * p.kpad + k;
@@ -327,7 +359,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         bf16x8 bh, bl;
-        split8(v[nt], bh, bl);
+        split8(buf[0][nt], bh, bl);
         Y[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, Y[0][nt], 0, 0, 0);
         Y[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, Y[0][nt], 0, 0, 0);
         Y[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, Y[0][nt], 0, 0, 0);
@@ -340,20 +372,24 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
         for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const float P = P_tab[j * 32 + mt * 16 + (lane >> 4) * 4 + q];
+            const float P = pscale(Pg, p, oc + j, r0 + mt * 16 + (lane >> 4) * 4 + q);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[mt][nt][q] = fmaf(P, Y[mt][nt][q], acc[mt][nt][q]);
           }
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
+        ks = 0;
+        ++j;
+      } else {
+        ++ks;
       }
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
+      for (int b = 0; b < PF; ++b)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[nt][q] = vn[nt][q];
-      ks = ks_n;
-      j = j_n;
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) buf[b][nt][q] = buf[b + 1][nt][q];
     }
   }
   float* out = part + (int64_t)blockIdx.x * p.I_n * p.R;
@@ -369,6 +405,119 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
       }
 }
 
+// Row-stream kernel (n < N-2, long contiguous runs): one output row i per
+// workgroup.  For fixed i the entries T(o, i, k) of consecutive outer
+// indices o are contiguous in memory (runs of I_right elements), so here the
+// MFMA M dimension is the outer index: Y(o, r) = sum_k T(o, i, k) A^(q)(k, r)
+// for 16 consecutive o per tile, then acc(r) += sum_o P(o, r) Y(o, r).  A
+// workgroup streams a contiguous range of o instead of 128 rows far apart.
+// Each wave works on TW o-tiles (16 TW outer indices) at a time; the waves
+// of a workgroup take consecutive groups.
+__global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __restrict__ T,
+                                                                const float* __restrict__ fac,
+                                                                const float* __restrict__ Pg,
+                                                                const int64_t* __restrict__ bg,
+                                                                FastParams p,
+                                                                float* __restrict__ part) {
+  constexpr int TW = CPNG_ROWSTREAM_TW;
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  __bf16* Sh = reinterpret_cast<__bf16*>(dyn_lds);
+  __bf16* Sl = Sh + 32 * p.kpad;
+  __shared__ float red[4][32];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int lr = lane & 15;
+  const int kb = (lane >> 4) * 8;
+  const int r0 = blockIdx.z * 32;
+  const int64_t ioff = (int64_t)blockIdx.y * p.istride;
+  stage_inner(fac, p, r0, Sh, Sl);
+  __syncthreads();
+  float acc0 = 0.f, acc1 = 0.f;   // rank columns r0 + lr and r0 + 16 + lr
+  const int64_t ob = (int64_t)blockIdx.x * p.o_per_block;
+  const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
+  for (int64_t og = ob + w * 16 * TW; og < oe; og += 4 * 16 * TW) {
+    const float* rowp[TW];
+    bool ok[TW];
+#pragma unroll
+    for (int t = 0; t < TW; ++t) {
+      const int64_t o = og + t * 16 + lr;   // this lane's operand row
+      ok[t] = o < oe;
+      rowp[t] = T + (ok[t] ? bg[o] : 0) + ioff;
+    }
+    float v[TW][8], vn[TW][8];
+    auto load = [&](int ks, float (&dst)[TW][8]) {
+      const int k = ks * 32 + kb;
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        if (ok[t] && k < p.K) {
+          const float4 a = *reinterpret_cast<const float4*>(rowp[t] + k);
+          const float4 b = *reinterpret_cast<const float4*>(rowp[t] + k + 4);
+          dst[t][0] = a.x; dst[t][1] = a.y; dst[t][2] = a.z; dst[t][3] = a.w;
+          dst[t][4] = b.x; dst[t][5] = b.y; dst[t][6] = b.z; dst[t][7] = b.w;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) dst[t][q] = 0.f;
+        }
+      }
+    };
+    load(0, v);
+    floatx4 Y[TW][2];
+#pragma unroll
+    for (int t = 0; t < TW; ++t) Y[t][0] = Y[t][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < p.nks; ++ks) {
+      if (ks + 1 < p.nks) load(ks + 1, vn);
+      const int k = ks * 32 + kb;
+      const int so0 = lr * p.kpad + k;
+      const int so1 = (16 + lr) * p.kpad + k;
+      const bf16x8 bh0 = *reinterpret_cast<const bf16x8*>(&Sh[so0]);
+      const bf16x8 bl0 = *reinterpret_cast<const bf16x8*>(&Sl[so0]);
+      const bf16x8 bh1 = *reinterpret_cast<const bf16x8*>(&Sh[so1]);
+      const bf16x8 bl1 = *reinterpret_cast<const bf16x8*>(&Sl[so1]);
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        bf16x8 ah, al;
+        split8(v[t], ah, al);
+        Y[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh0, Y[t][0], 0, 0, 0);
+        Y[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, Y[t][0], 0, 0, 0);
+        Y[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh0, Y[t][0], 0, 0, 0);
+        Y[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh1, Y[t][1], 0, 0, 0);
+        Y[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl1, Y[t][1], 0, 0, 0);
+        Y[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh1, Y[t][1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < TW; ++t)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[t][q] = vn[t][q];
+    }
+    // D rows are outer indices og + t*16 + 4*(lane/16) + q; the column is the rank
+#pragma unroll
+    for (int t = 0; t < TW; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t o = og + t * 16 + (lane >> 4) * 4 + q;
+        if (o < oe) {
+          acc0 = fmaf(pscale(Pg, p, o, r0 + lr), Y[t][0][q], acc0);
+          acc1 = fmaf(pscale(Pg, p, o, r0 + 16 + lr), Y[t][1][q], acc1);
+        }
+      }
+  }
+  // sum the four lane groups (same rank column) in a fixed order, then the waves
+  acc0 += __shfl_xor(acc0, 16);
+  acc0 += __shfl_xor(acc0, 32);
+  acc1 += __shfl_xor(acc1, 16);
+  acc1 += __shfl_xor(acc1, 32);
+  if (lane < 16) {
+    red[w][lr] = acc0;
+    red[w][16 + lr] = acc1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    const int c = threadIdx.x;
+    const float sum = (red[0][c] + red[2][c]) + (red[1][c] + red[3][c]);
+    if (r0 + c < p.R) part[(int64_t)blockIdx.x * p.I_n * p.R + blockIdx.y * p.R + r0 + c] = sum;
+  }
+}
+
 // Two-stage fixed-order sum of the workgroup slots: stage 1 adds the slots of
 // group g (slots g*per .. g*per + per - 1) into part2[g]; stage 2 adds the
 // groups in order.
@@ -379,6 +528,7 @@ __global__ void reduce_groups_f32_kernel(const float* __restrict__ part, int64_t
   const int64_t g = blockIdx.y;
   const int64_t k1 = min<int64_t>(nsplit, (g + 1) * per);
   double s = 0.0;
+#pragma unroll 8
   for (int64_t k = g * per; k < k1; ++k) s += (double)part[k * n + e];
   part2[g * n + e] = s;
 }
@@ -388,6 +538,7 @@ __global__ void reduce_final_kernel(const double* __restrict__ part2, int64_t ng
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   double s = 0.0;
+#pragma unroll 8
   for (int64_t g = 0; g < ngroups; ++g) s += part2[g * n + e];
   out[e] = s;
 }
@@ -586,10 +737,13 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   p.kstride = stride[q];
   p.nks = (int)((K + 31) / 32);
   p.kpad = p.nks * 32 + 8;
-  const int tile = (rows ? (p.I_n > 64 ? 128 : 64) : (p.I_n > 64 ? 128 : 64));
+  // rows of mode n < N-2 are runs of I_right = J' * K >= 16 K contiguous
+  // elements per (left index, i): stream them one output row per workgroup.
+  const bool stream_rows = rows && mode < N - 2 && (stride[mode] / K) >= 16;
+  const int tile = stream_rows ? 1 : (p.I_n > 64 ? 128 : 64);
   const int64_t ychunks = (p.I_n + tile - 1) / tile;
   const int64_t rchunks = (R + 31) / 32;
-  const int64_t target = 1024;
+  const int64_t target = CPNG_STREAM_BLOCKS;
   int64_t ks = std::max<int64_t>(1, std::min<int64_t>(p.O, (target + ychunks * rchunks - 1) / (ychunks * rchunks)));
   p.o_per_block = (p.O + ks - 1) / ks;
   ks = (p.O + p.o_per_block - 1) / p.o_per_block;
@@ -602,14 +756,27 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   double* part2 = reinterpret_cast<double*>(static_cast<char*>(h->part.ptr) + part_bytes);
   dim3 grid((unsigned)ks, (unsigned)ychunks, (unsigned)rchunks);
   const size_t lds = 2 * sizeof(__bf16) * 32 * (size_t)p.kpad;
+  // outer tables: P (O x R floats) then base offsets (O int64)
+  const size_t pbytes = (sizeof(float) * (size_t)(p.O * R) + 255) & ~size_t(255);
+  CP_TRY(ensure(h, h->otab, pbytes + sizeof(int64_t) * (size_t)p.O, st));
+  float* Pg = static_cast<float*>(h->otab.ptr);
+  int64_t* bg = reinterpret_cast<int64_t*>(static_cast<char*>(h->otab.ptr) + pbytes);
+  {
+    const int64_t nt = p.O * (R + 1);
+    hipLaunchKernelGGL(outer_tables_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, fac,
+                       p, Pg, bg);
+    CP_LAUNCH_CHECK(h);
+  }
   {
     KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
-    if (rows) {
-      if (tile == 128) hipLaunchKernelGGL(mttkrp_rows_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, p, part);
-      else hipLaunchKernelGGL(mttkrp_rows_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, p, part);
+    if (stream_rows) {
+      hipLaunchKernelGGL(mttkrp_rowstream_bf16x3, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+    } else if (rows) {
+      if (tile == 128) hipLaunchKernelGGL(mttkrp_rows_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      else hipLaunchKernelGGL(mttkrp_rows_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
     } else {
-      if (tile == 128) hipLaunchKernelGGL(mttkrp_cols_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, p, part);
-      else hipLaunchKernelGGL(mttkrp_cols_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, p, part);
+      if (tile == 128) hipLaunchKernelGGL(mttkrp_cols_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      else hipLaunchKernelGGL(mttkrp_cols_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
     }
   }
   CP_LAUNCH_CHECK(h);

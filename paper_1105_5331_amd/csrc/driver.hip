@@ -376,7 +376,8 @@ int cp_destroy(cp_handle* h) {
   if (!h) return CP_OK;
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&h->part, &h->stage, &h->mbuf, &h->small, &h->red, &h->carry, &h->tmpu};
+  DevBuf* bufs[] = {&h->part, &h->stage, &h->mbuf, &h->small, &h->red, &h->carry, &h->tmpu,
+                    &h->otab};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   if (h->pinned) (void)hipHostFree(h->pinned);

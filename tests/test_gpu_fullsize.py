@@ -1,0 +1,71 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times, on sampled outputs: whole rows M^(n)(i, :) recomputed by the oracle
+from the definition restricted to the sampled indices i.
+
+* dense 128^4 float32, R = 32 (BF16X3 and FP32 kernels, every mode);
+* sparse 20000^3 COO with about 2e7 nonzeros, R = 16 (FP32, every mode).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import cp as ocp
+from workloads import initial_guess, sparse_random_cp, test_problem_1
+
+from helpers import TOL, assert_close_to_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    import paper_1105_5331_amd as cpng
+    with cpng.Handle(0) as handle:
+        yield handle
+
+
+def test_dense_128x4_R32_sampled_rows(h):
+    import paper_1105_5331_amd as cpng
+    dims, R = (128, 128, 128, 128), 32
+    print("case dense 128^4 R=32 full size", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=0, dtype=np.float32)
+    Tg = cpng.Tensor(dims, torch.from_numpy(p.T).cuda().reshape(-1))
+    u0 = initial_guess(dims, R, seed=10000)
+    A = ocp.split_u(u0, dims, R)
+    u = torch.from_numpy(u0).cuda()
+    rows = [0, 77, 127]
+    T64 = p.T   # float32; the oracle widens the sampled slices exactly
+    for n in range(4):
+        sl = np.take(T64, rows, axis=n).astype(np.float64)
+        An = [a if k != n else A[n][rows] for k, a in enumerate(A)]
+        ref = ocp.mttkrp(sl, An, n)
+        bound = ocp.mttkrp(np.abs(sl), [np.abs(a) for a in An], n)
+        for prec in ("bf16x3", "fp32"):
+            M = cpng.cp_mttkrp(h, Tg, u, R, n, prec).cpu().numpy()[rows]
+            assert_close_to_bound(M, ref, bound, TOL[prec], f"mode {n} {prec}")
+
+
+def test_sparse_20000x3_R16_sampled_rows(h):
+    import paper_1105_5331_amd as cpng
+    dims, R = (20000, 20000, 20000), 16
+    print("case sparse 20000^3 nnz~2e7 R=16 full size", flush=True)
+    sp = sparse_random_cp(dims, 20_000_000, 16, seed=0, dtype=np.float32)
+    Tg = cpng.Tensor(dims, torch.from_numpy(sp.values).cuda(),
+                     coords=torch.from_numpy(sp.coords).cuda())
+    cpng.cp_tensor_prepare(h, Tg)
+    rng = np.random.default_rng(1)
+    A = [rng.standard_normal((I, R)) for I in dims]
+    u = torch.from_numpy(ocp.join_u(A)).cuda()
+    vals = sp.values.astype(np.float64)
+    for n in range(3):
+        M = cpng.cp_mttkrp(h, Tg, u, R, n, "fp32").cpu().numpy()
+        rows = np.array([0, 4321, 19999, int(sp.coords[n, 12345])])
+        for i in rows:
+            sel = sp.coords[n] == i
+            ref = ocp.mttkrp_coo(dims, sp.coords[:, sel], vals[sel], A, n)[i]
+            bound = ocp.mttkrp_coo(dims, sp.coords[:, sel], np.abs(vals[sel]),
+                                   [np.abs(a) for a in A], n)[i]
+            assert_close_to_bound(M[i][None], ref[None], bound[None], TOL["fp32"],
+                                  f"mode {n} row {i}")
+    cpng.cp_tensor_release(h, Tg)

@@ -278,3 +278,57 @@ def serving_stream(n_requests: int, rate_per_s: float, seed: int = 7, orders=(3,
 # test module imports them by name.
 test_problem_1.__test__ = False
 test_problem_2.__test__ = False
+
+
+def test_problem_1_torch(dims, R: int, c: float, l1: float = 1.0, l2: float = 1.0, seed: int = 0,
+                         device="cuda", out_dtype=None):
+    """Test Problem I built with torch on a device (for the serving stream).
+
+    The same recipe as ``test_problem_1`` (factors N(0,1) -> QR -> times the
+    upper Cholesky factor of the congruence matrix; homoscedastic then
+    heteroscedastic noise at levels l1, l2; built in float64, rounded once),
+    drawn from a ``torch.Generator(device).manual_seed(seed)`` stream, so the
+    values differ from the numpy generator's for the same seed.  Returns the
+    flat C-order tensor on the device.
+    """
+    import torch
+
+    out_dtype = out_dtype or torch.float32
+    dims = tuple(int(d) for d in dims)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    K = torch.full((R, R), float(c), dtype=torch.float64, device=device)
+    K.fill_diagonal_(1.0)
+    U = torch.linalg.cholesky(K).T
+    factors = []
+    for I in dims:
+        Z = torch.randn((I, R), generator=g, dtype=torch.float64, device=device)
+        if I >= R:
+            Q, _ = torch.linalg.qr(Z)
+            factors.append(Q @ U)
+        else:
+            factors.append((Z / math.sqrt(I)) @ U)
+    split = max(1, len(dims) // 2)
+    left = torch.ones((1, R), dtype=torch.float64, device=device)
+    for A in factors[:split]:
+        left = (left[:, None, :] * A[None, :, :]).reshape(-1, R)
+    right = torch.ones((1, R), dtype=torch.float64, device=device)
+    for A in factors[split:]:
+        right = (right[:, None, :] * A[None, :, :]).reshape(-1, R)
+    T = (left @ right.T).reshape(-1)
+    del left, right
+    s1 = noise_scale(l1)
+    if s1 > 0.0:
+        N1 = torch.randn(T.shape, generator=g, dtype=torch.float64, device=device)
+        T += (s1 * torch.linalg.vector_norm(T) / torch.linalg.vector_norm(N1)) * N1
+        del N1
+    s2 = noise_scale(l2)
+    if s2 > 0.0:
+        N2 = torch.randn(T.shape, generator=g, dtype=torch.float64, device=device)
+        N2 *= T
+        T += (s2 * torch.linalg.vector_norm(T) / torch.linalg.vector_norm(N2)) * N2
+        del N2
+    return T.to(out_dtype)
+
+
+test_problem_1_torch.__test__ = False
