@@ -122,9 +122,10 @@ def sparse_mttkrp(h, cpng, torch, nnz_draw=20_000_000, R=16, reps=10):
         nl, ms = cpng.cp_profile_read(h, cpng.CP_KERNEL_SPARSE_MTTKRP)
         cpng.cp_profile(h, False)
         us = ms / nl * 1e3
-        # sorted copy read once (other two coordinates + value), segment
-        # pointers, the two other factors (float32) and the output (float64)
-        alg = nnz * 12 + (dims[n] + 1) * 8 + 2 * dims[0] * R * 4 + dims[n] * R * 8
+        # sorted copy read once (row index, other two coordinates, value:
+        # 16 B per nonzero), the two other factors (float32) once, the output
+        # (float64) written once
+        alg = nnz * 16 + 2 * dims[0] * R * 4 + dims[n] * R * 8
         per_mode.append({"mode": n, "kernel_us": round(us, 1),
                          "GBs": round(alg / (us * 1e-6) / 1e9, 1),
                          "frac": round(alg / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)})

@@ -128,7 +128,9 @@ typedef struct cp_options {
   int32_t precision;        /* bulk cp_precision for the first phase (CP_PREC_FP64) */
   int32_t final_precision;  /* precision after the switch (CP_PREC_FP64) */
   double switch_rho;        /* switch to final_precision (and restart the window) once
-                               rho <= switch_rho; 0 = never switch (0) */
+                               rho <= switch_rho, or after a line search in the first
+                               precision ends without a Wolfe point; 0 = switch only
+                               when the stopping test would fire (0) */
   int32_t normalize_accel;  /* normalise the accelerated iterate (1) */
   cp_iter_info* trace;      /* host, nullable: per-iteration records */
   int32_t trace_cap;        /* capacity of trace */

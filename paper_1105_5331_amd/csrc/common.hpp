@@ -110,6 +110,7 @@ struct KernelTimer {
 struct SparseMode {
   int32_t* coords = nullptr;   // (N-1) x nnz: the other modes' indices, sorted by this mode
   void* values = nullptr;      // nnz values sorted by this mode
+  int32_t* rows = nullptr;     // nnz: this mode's index of each sorted nonzero
   int64_t* seg = nullptr;      // I_n + 1 segment pointers
 };
 struct SparsePrepared {

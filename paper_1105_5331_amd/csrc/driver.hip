@@ -27,6 +27,7 @@ struct cp_ngmres_state {
   int it = 0;
   double f = 0.0, rho = 0.0, normT = 0.0;
   int n_fg = 0, n_restarts = 0, n_fallback = 0, switch_iter = -1;
+  bool stalled = false;   // a line search in reduced precision ended without a Wolfe point
   // device buffers
   double* mem = nullptr;
   double *u, *g, *ubar, *gbar, *uhat, *d, *ut, *gt, *gbest, *scal;  // scal: 8 doubles
@@ -665,8 +666,6 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
     CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st));
     CP_TRY(objective_grad_impl(h, S->T, S->s, S->ubar, S->R, S->prec, S->scal, S->gbar, S->st));
     S->n_fg++;
-    double fbar;
-    CP_TRY(readback(h, S->scal, 1, &fbar, S->st));
     // Step II over the window
     const double* Up[64];
     const double* Gp[64];
@@ -678,9 +677,10 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
                  S->scal + 8, S->st));
     if (S->opt.normalize_accel) CP_TRY(normalize(h, S->s, S->uhat, S->R, nullptr, S->st));
     CP_TRY(sub_to(h, S->uhat, S->ubar, S->d, S->L, S->st));
-    CP_TRY(dot(h, S->gbar, S->d, S->L, S->scal + 2, S->st));
-    double slope;
-    CP_TRY(readback(h, S->scal + 2, 1, &slope, S->st));
+    CP_TRY(dot(h, S->gbar, S->d, S->L, S->scal + 1, S->st));
+    double fs[2];   // f(u_bar) and the slope g(u_bar)^T d in one readback
+    CP_TRY(readback(h, S->scal, 2, fs, S->st));
+    const double fbar = fs[0], slope = fs[1];
     const double* gnew = S->gbar;
     double fnew = fbar;
     double beta = 0.0;
@@ -700,6 +700,7 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
       if (status != LS_CONVERGED) {
         S->n_fallback++;
         rc = CP_LS_FALLBACK;
+        if (!is_f64_acc(S->prec)) S->stalled = true;
       }
       if (gacc) gnew = gacc;
       else { beta = 0.0; fnew = fbar; gnew = S->gbar; }
@@ -738,8 +739,13 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
   for (;;) {
     // Precision schedule: once rho is small enough (or would stop the run),
     // move the bulk to the final precision, re-evaluate and restart the window.
+    // Triggers: rho below switch_rho; once rho <= 1e-2, a line search that
+    // found no Wolfe point in reduced precision (its objective noise is then
+    // comparable to the decrease it looks for); or the stopping test about to
+    // fire on a gradient that was not accumulated in float64.
     if (!S->switched && S->prec != o.final_precision &&
         ((o.switch_rho > 0.0 && S->rho <= o.switch_rho) ||
+         (o.switch_rho > 0.0 && S->stalled && S->rho <= 1e-2) ||
          (S->rho <= tol && !is_f64_acc(S->prec) && is_f64_acc(o.final_precision)))) {
       S->prec = o.final_precision;
       S->switched = true;

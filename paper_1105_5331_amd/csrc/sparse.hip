@@ -4,24 +4,23 @@
 //
 // Preparation builds, for every mode n, a copy of the nonzeros stably sorted
 // by i_n (other modes' coordinates and the values, structure of arrays) and
-// the segment pointers seg[i] = first nonzero of row i.  The MTTKRP then
-// gives each group of W lanes (lane = rank r) a contiguous, equal-sized range
-// of sorted nonzeros.  A group sums each row it meets in registers: rows that
-// lie strictly inside its range are complete and written directly; the first
-// and the last row it meets may continue in a neighbouring group and are
-// written as two carry slots.  A fix-up kernel adds the carries of each row
-// in slot order.  No atomics: the result is bitwise reproducible.
+// the sorted row index of every nonzero (plus segment pointers).  The MTTKRP
+// gives each wave a contiguous, equal-sized range of sorted nonzeros and
+// works through it 64 nonzeros at a time.  Rows that lie strictly inside a
+// wave's range are complete there and written directly; the first and the
+// last row a wave meets may continue in a neighbouring wave and are written
+// as two carry slots.  A fix-up kernel adds the carries of each row in slot
+// order.  No atomics: the result is bitwise reproducible.
 #include "common.hpp"
 
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace cpng {
 
 namespace {
-
-constexpr int kChunk = 512;   // nonzeros per lane group
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -86,75 +85,175 @@ __global__ void segment_kernel(const int32_t* __restrict__ keys, int64_t nnz, in
 }
 
 struct SparseParams {
-  int N, mode, R;
-  int64_t nnz, I_n, ngroups;
+  int N, mode, R, Rp;             // Rp: factor row stride (R padded)
+  int64_t nnz, I_n;
   const int32_t* coords;          // (N-1) x nnz, other modes in increasing order
   const int64_t* seg;             // I_n + 1
   int64_t foff[CP_MAX_ORDER - 1]; // factor element offsets of the other modes
 };
 
-// W lanes per group (W >= R, power of two), 256 / W groups per workgroup.
-template <typename TT, typename CT, int W>
-__global__ __launch_bounds__(256) void sparse_mttkrp_kernel(const TT* __restrict__ vals,
-                                                            const CT* __restrict__ fac,
-                                                            SparseParams p,
-                                                            double* __restrict__ M,
-                                                            int64_t* __restrict__ carry_row,
-                                                            double* __restrict__ carry_val) {
-  const int lane = threadIdx.x % W;
-  const int64_t gidx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / W;
-  if (gidx >= p.ngroups) return;
-  const int64_t z0 = gidx * kChunk;
-  const int64_t z1 = min<int64_t>(p.nnz, z0 + kChunk);
-  const bool active = lane < p.R;
-  // row of z0: largest i with seg[i] <= z0
-  int64_t lo = 0, hi = p.I_n - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (p.seg[mid] <= z0) lo = mid;
-    else hi = mid - 1;
-  }
-  int64_t row = lo;
-  int64_t next = p.seg[row + 1];
-  const int lr = active ? lane : 0;   // inactive lanes read a valid address
-  CT acc = CT(0);
-  bool first = true;
-  for (int64_t z = z0; z < z1; ++z) {
-    if (z >= next) {
-      // row finished inside this group
-      if (first) {
-        if (active) carry_val[(2 * gidx) * p.R + lane] = (double)acc;
-        if (lane == 0) carry_row[2 * gidx] = row;
-        first = false;
-      } else if (active) {
-        M[row * p.R + lane] = (double)acc;
-      }
-      acc = CT(0);
-      do {
-        ++row;
-        next = p.seg[row + 1];
-      } while (z >= next);
-    }
-    CT prod = (CT)vals[z];
-    for (int k = 0; k < p.N - 1; ++k) {
-      const int32_t c = p.coords[(int64_t)k * p.nnz + z];
-      prod *= fac[p.foff[k] + (int64_t)c * p.R + lr];
-    }
-    acc += prod;
-  }
-  if (first) {
-    if (active) {
-      carry_val[(2 * gidx) * p.R + lane] = (double)acc;
-      carry_val[(2 * gidx + 1) * p.R + lane] = 0.0;
-    }
-    if (lane == 0) {
-      carry_row[2 * gidx] = row;
-      carry_row[2 * gidx + 1] = row;
-    }
+// Wave kernel: one wave per contiguous range of kWaveNnz sorted nonzeros.
+// The factors are read from a copy whose rows are padded to Rp = R rounded
+// up to the vector width VW (4 floats or 2 doubles = 16 bytes), so a lane
+// gathers VW consecutive ranks with one 16-byte load.  A wave is split into
+// G = 64 / L groups of L lanes (L = Rp / VW rounded up to a power of two;
+// lane c of a group holds ranks c*VW .. c*VW + VW - 1).  One step covers
+// S = G * J consecutive nonzeros and group g takes J of them,
+// g*J .. g*J + J - 1, in order.  The step's row indices, values and
+// coordinates are loaded once, one nonzero per lane (coalesced), and handed
+// to the groups by cross-lane shuffles; every gather of the step is issued
+// before any product is formed.  A lane keeps one accumulator per rank it
+// holds for the row being summed.  While a step continues that row, lanes
+// just add; when the row changes the groups are combined (fixed butterfly
+// order) and the finished row is written: directly if it lies strictly
+// inside the wave's range, else into the wave's head or tail carry slot.
+// KM is the number of other modes the kernel is compiled for: 2 (order 3),
+// 3 (order 4) or CP_MAX_ORDER - 1 with a runtime bound (any order).
+constexpr int kWaveNnz = 2048;
+
+template <typename CT>
+struct VecOf;
+template <>
+struct VecOf<float> {
+  static constexpr int n = 4;
+  using type = float4;
+};
+template <>
+struct VecOf<double> {
+  static constexpr int n = 2;
+  using type = double2;
+};
+
+template <typename CT, int VW>
+__device__ inline void load_vec(const CT* __restrict__ p, CT (&x)[VW]) {
+  const typename VecOf<CT>::type v = *reinterpret_cast<const typename VecOf<CT>::type*>(p);
+  if constexpr (VW == 4) {
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
   } else {
-    if (active) carry_val[(2 * gidx + 1) * p.R + lane] = (double)acc;
-    if (lane == 0) carry_row[2 * gidx + 1] = row;
+    x[0] = v.x; x[1] = v.y;
   }
+}
+
+template <typename CT, int VW, int L>
+__device__ inline void group_flush(CT (&acc)[VW], int R, int64_t row, int& nflush, bool final_,
+                                   int lane, int64_t wid, double* __restrict__ M,
+                                   int64_t* __restrict__ crow, double* __restrict__ cval) {
+  CT x[VW];
+#pragma unroll
+  for (int v = 0; v < VW; ++v) {
+    x[v] = acc[v];
+#pragma unroll
+    for (int m = L; m < 64; m <<= 1) x[v] += __shfl_xor(x[v], m);
+    acc[v] = CT(0);
+  }
+  // lanes 0..L-1 (group 0) hold the totals of their ranks
+  if (lane < L) {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      const int r = lane * VW + v;
+      if (r >= R) break;
+      if (nflush == 0) {
+        cval[(2 * wid) * R + r] = (double)x[v];
+        if (final_) cval[(2 * wid + 1) * R + r] = 0.0;
+      } else if (final_) {
+        cval[(2 * wid + 1) * R + r] = (double)x[v];
+      } else {
+        M[row * R + r] = (double)x[v];
+      }
+    }
+    if (lane == 0 && (nflush == 0 || final_)) {
+      if (nflush == 0) crow[2 * wid] = row;
+      if (final_) crow[2 * wid + 1] = row;
+    }
+  }
+  ++nflush;
+}
+
+template <typename TT, typename CT, int L, int KM>
+__global__ __launch_bounds__(256) void sparse_wave_kernel(const TT* __restrict__ vals,
+                                                          const int32_t* __restrict__ rows,
+                                                          const CT* __restrict__ fac,
+                                                          SparseParams p, double* __restrict__ M,
+                                                          int64_t* __restrict__ crow,
+                                                          double* __restrict__ cval) {
+  constexpr int VW = VecOf<CT>::n;
+  constexpr int G = 64 / L;
+  constexpr int J = L < 8 ? L : 8;
+  constexpr int S = G * J;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / L;
+  const int c = lane % L;
+  const bool lane_ok = c * VW < p.Rp;
+  const int cc = lane_ok ? c * VW : 0;   // idle lanes read a valid address
+  const int km = KM < CP_MAX_ORDER - 1 ? KM : p.N - 1;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t z0 = wid * kWaveNnz;
+  if (z0 >= p.nnz) return;   // whole wave
+  const int64_t z1 = min<int64_t>(p.nnz, z0 + kWaveNnz);
+  CT acc[VW];
+#pragma unroll
+  for (int v = 0; v < VW; ++v) acc[v] = CT(0);
+  int64_t cur = rows[z0];
+  int nflush = 0;
+  for (int64_t zb = z0; zb < z1; zb += S) {
+    const int nstep = (int)min<int64_t>(S, z1 - zb);
+    // the step's metadata, one nonzero per lane
+    const bool mine = lane < nstep;
+    const int64_t zm = mine ? zb + lane : z0;
+    const int32_t my_row = mine ? rows[zm] : INT32_MAX;
+    const CT my_val = mine ? (CT)vals[zm] : CT(0);
+    int32_t my_c[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) my_c[k] = k < km ? p.coords[(int64_t)k * p.nnz + zm] : 0;
+    const int32_t last_row = __shfl(my_row, nstep - 1);
+    // gathers of all J sub-steps, then the products
+    int32_t rowj[J];
+    CT contrib[J][VW];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int src = g * J + j;
+      rowj[j] = __shfl(my_row, src);
+      const CT vj = __shfl(my_val, src);
+      CT prod[VW];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) prod[v] = lane_ok ? vj : CT(0);
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (k < km) {
+          const int32_t ck = __shfl(my_c[k], src);
+          CT f[VW];
+          load_vec<CT, VW>(fac + p.foff[k] + (int64_t)ck * p.Rp + cc, f);
+#pragma unroll
+          for (int v = 0; v < VW; ++v) prod[v] *= f[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < VW; ++v) contrib[j][v] = prod[v];
+    }
+    if (last_row == cur) {           // the whole step continues the current row
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[v] += contrib[j][v];
+      continue;
+    }
+    // rows change inside this step: finish each row in order
+    for (;;) {
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[v] += rowj[j] == cur ? contrib[j][v] : CT(0);
+      if (cur == last_row) break;    // the last row may continue in the next step
+      group_flush<CT, VW, L>(acc, p.R, cur, nflush, false, lane, wid, M, crow, cval);
+      int32_t nxt = INT32_MAX;
+#pragma unroll
+      for (int j = 0; j < J; ++j) nxt = (rowj[j] > cur && rowj[j] < nxt) ? rowj[j] : nxt;
+#pragma unroll
+      for (int m = 1; m < 64; m <<= 1) nxt = min(nxt, __shfl_xor(nxt, m));
+      cur = nxt;
+    }
+  }
+  group_flush<CT, VW, L>(acc, p.R, cur, nflush, true, lane, wid, M, crow, cval);
 }
 
 // For each run of equal rows among the carry slots, the first slot of the run
@@ -178,18 +277,29 @@ __global__ void zero_kernel(double* __restrict__ x, int64_t n) {
   if (e < n) x[e] = 0.0;
 }
 
-template <typename TT, typename CT, int W>
-int launch_sparse(cp_handle* h, const TT* vals, const CT* fac, SparseParams p, double* M,
-                  hipStream_t st) {
-  const int64_t nslots = 2 * p.ngroups;
+// y(i, r) = x(i, r) for r < R, 0 for R <= r < Rp (rows padded to Rp)
+template <typename CT>
+__global__ void pad_factors_kernel(const double* __restrict__ x, int64_t rows, int R, int Rp,
+                                   CT* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * Rp) return;
+  const int64_t i = e / Rp;
+  const int r = (int)(e - i * Rp);
+  y[e] = r < R ? (CT)x[i * R + r] : CT(0);
+}
+
+template <typename TT, typename CT, int L, int KM>
+int launch_sparse_wave(cp_handle* h, const TT* vals, const int32_t* rows, const CT* fac,
+                       SparseParams p, double* M, hipStream_t st) {
+  const int64_t nwaves = (p.nnz + kWaveNnz - 1) / kWaveNnz;
+  const int64_t nslots = 2 * nwaves;
   CP_TRY(ensure(h, h->carry, (sizeof(int64_t) + sizeof(double) * p.R) * (size_t)std::max<int64_t>(1, nslots), st));
   int64_t* crow = static_cast<int64_t*>(h->carry.ptr);
   double* cval = reinterpret_cast<double*>(crow + nslots);
-  const int64_t threads = p.ngroups * W;
   {
     KernelTimer timer(h, CP_KERNEL_SPARSE_MTTKRP, st);
-    hipLaunchKernelGGL((sparse_mttkrp_kernel<TT, CT, W>), dim3(nblk(threads, 256)), dim3(256), 0,
-                       st, vals, fac, p, M, crow, cval);
+    hipLaunchKernelGGL((sparse_wave_kernel<TT, CT, L, KM>), dim3(nblk(nwaves * 64, 256)),
+                       dim3(256), 0, st, vals, rows, fac, p, M, crow, cval);
   }
   CP_LAUNCH_CHECK(h);
   hipLaunchKernelGGL(carry_fixup_kernel, dim3(nblk(nslots * p.R, 256)), dim3(256), 0, st, crow,
@@ -198,15 +308,49 @@ int launch_sparse(cp_handle* h, const TT* vals, const CT* fac, SparseParams p, d
   return CP_OK;
 }
 
+template <typename TT, typename CT, int L>
+int dispatch_order(cp_handle* h, const TT* vals, const int32_t* rows, const CT* fac,
+                   const SparseParams& p, double* M, hipStream_t st) {
+  if (p.N == 3) return launch_sparse_wave<TT, CT, L, 2>(h, vals, rows, fac, p, M, st);
+  if (p.N == 4) return launch_sparse_wave<TT, CT, L, 3>(h, vals, rows, fac, p, M, st);
+  return launch_sparse_wave<TT, CT, L, CP_MAX_ORDER - 1>(h, vals, rows, fac, p, M, st);
+}
+
 template <typename TT, typename CT>
-int dispatch_w(cp_handle* h, const TT* vals, const CT* fac, const SparseParams& p, double* M,
-               hipStream_t st) {
-  if (p.R <= 4) return launch_sparse<TT, CT, 4>(h, vals, fac, p, M, st);
-  if (p.R <= 8) return launch_sparse<TT, CT, 8>(h, vals, fac, p, M, st);
-  if (p.R <= 16) return launch_sparse<TT, CT, 16>(h, vals, fac, p, M, st);
-  if (p.R <= 32) return launch_sparse<TT, CT, 32>(h, vals, fac, p, M, st);
-  if (p.R <= 64) return launch_sparse<TT, CT, 64>(h, vals, fac, p, M, st);
+int dispatch_wave(cp_handle* h, const TT* vals, const int32_t* rows, const CT* fac,
+                  const SparseParams& p, double* M, hipStream_t st) {
+  const int lanes = p.Rp / VecOf<CT>::n;
+  if (lanes <= 1) return dispatch_order<TT, CT, 1>(h, vals, rows, fac, p, M, st);
+  if (lanes <= 2) return dispatch_order<TT, CT, 2>(h, vals, rows, fac, p, M, st);
+  if (lanes <= 4) return dispatch_order<TT, CT, 4>(h, vals, rows, fac, p, M, st);
+  if (lanes <= 8) return dispatch_order<TT, CT, 8>(h, vals, rows, fac, p, M, st);
+  if (lanes <= 16) return dispatch_order<TT, CT, 16>(h, vals, rows, fac, p, M, st);
+  if constexpr (VecOf<CT>::n == 2) {
+    if (lanes <= 32) return dispatch_order<TT, CT, 32>(h, vals, rows, fac, p, M, st);
+  }
   return fail(h, CP_EINVAL, "sparse MTTKRP supports R <= 64 (got %d)", p.R);
+}
+
+// The factors as CT with rows padded to Rp; the FP64 factors are used in
+// place when no padding is needed.
+template <typename CT>
+int padded_factors(cp_handle* h, const double* u, int64_t rows, int R, int Rp, const CT** out,
+                   hipStream_t st) {
+  if constexpr (std::is_same<CT, double>::value) {
+    if (Rp == R && reinterpret_cast<uintptr_t>(u) % 16 == 0) {
+      *out = u;
+      return CP_OK;
+    }
+  }
+  CP_TRY(ensure(h, h->stage, sizeof(CT) * (size_t)(rows * Rp), st));
+  CT* y = static_cast<CT*>(h->stage.ptr);
+  if (rows > 0) {
+    hipLaunchKernelGGL(pad_factors_kernel<CT>, dim3(nblk(rows * Rp, 256)), dim3(256), 0, st, u,
+                       rows, R, Rp, y);
+    CP_LAUNCH_CHECK(h);
+  }
+  *out = y;
+  return CP_OK;
 }
 
 template <typename V>
@@ -241,7 +385,8 @@ int prepare_typed(cp_handle* h, cp_tensor* T, const Shape& s, hipStream_t st, Sp
     SparseMode& md = sp->mode[n];
     if (hipMalloc(&md.coords, sizeof(int32_t) * std::max<int64_t>(1, (N - 1) * nnz)) != hipSuccess ||
         hipMalloc(&md.values, sizeof(V) * nnz) != hipSuccess ||
-        hipMalloc(&md.seg, sizeof(int64_t) * (s.dims[n] + 1)) != hipSuccess) {
+        hipMalloc(&md.seg, sizeof(int64_t) * (s.dims[n] + 1)) != hipSuccess ||
+        hipMalloc(&md.rows, sizeof(int32_t) * nnz) != hipSuccess) {
       rc = fail(h, CP_ENOMEM, "sparse prepare: allocation failed");
       break;
     }
@@ -259,6 +404,9 @@ int prepare_typed(cp_handle* h, cp_tensor* T, const Shape& s, hipStream_t st, Sp
                        perm_out, nnz, N, n, md.coords, static_cast<V*>(md.values));
     hipLaunchKernelGGL(segment_kernel, dim3(nblk(s.dims[n] + 1, 256)), dim3(256), 0, st, keys_out,
                        nnz, s.dims[n], md.seg);
+    if (hipMemcpyAsync(md.rows, keys_out, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, st) !=
+        hipSuccess)
+      rc = fail(h, CP_EDEVICE, "sparse prepare: copy of the sorted indices failed");
     if (hipGetLastError() != hipSuccess) rc = fail(h, CP_EDEVICE, "sparse prepare: launch failed");
   }
   if (hipStreamSynchronize(st) != hipSuccess && rc == CP_OK)
@@ -354,12 +502,21 @@ int sparse_release(cp_handle* h, cp_tensor* T) {
     if (sp->mode[n].coords) (void)hipFree(sp->mode[n].coords);
     if (sp->mode[n].values) (void)hipFree(sp->mode[n].values);
     if (sp->mode[n].seg) (void)hipFree(sp->mode[n].seg);
+    if (sp->mode[n].rows) (void)hipFree(sp->mode[n].rows);
   }
   delete sp;
   T->prepared = nullptr;
   (void)h;
   return CP_OK;
 }
+
+namespace {
+void set_offsets(const Shape& s, int mode, SparseParams& p) {
+  int kk = 0;
+  for (int k = 0; k < s.N; ++k)
+    if (k != mode) p.foff[kk++] = s.off[k] * p.Rp;
+}
+}  // namespace
 
 int sparse_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
                   int mode, int prec, double* M, hipStream_t st) {
@@ -376,22 +533,26 @@ int sparse_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double
   p.R = R;
   p.nnz = sp->nnz;
   p.I_n = I;
-  p.ngroups = (sp->nnz + kChunk - 1) / kChunk;
   p.coords = sp->mode[mode].coords;
   p.seg = sp->mode[mode].seg;
-  int kk = 0;
-  for (int k = 0; k < s.N; ++k)
-    if (k != mode) p.foff[kk++] = s.off[k] * R;
   const void* vals = sp->mode[mode].values;
+  const int32_t* rws = sp->mode[mode].rows;
+  const int64_t frows = s.sum_dims();
   if (prec == CP_PREC_FP32) {
     if (sp->dtype != CP_F32) return fail(h, CP_EINVAL, "precision FP32 needs float32 values");
-    float* fac = nullptr;
-    CP_TRY(stage_factors_f32(h, u, s.sum_dims() * R, &fac, st));
-    return dispatch_w<float, float>(h, static_cast<const float*>(vals), fac, p, M, st);
+    p.Rp = (R + 3) / 4 * 4;
+    set_offsets(s, mode, p);
+    const float* fac = nullptr;
+    CP_TRY(padded_factors<float>(h, u, frows, R, p.Rp, &fac, st));
+    return dispatch_wave<float, float>(h, static_cast<const float*>(vals), rws, fac, p, M, st);
   }
+  p.Rp = (R + 1) / 2 * 2;
+  set_offsets(s, mode, p);
+  const double* fac = nullptr;
+  CP_TRY(padded_factors<double>(h, u, frows, R, p.Rp, &fac, st));
   if (sp->dtype == CP_F32)
-    return dispatch_w<float, double>(h, static_cast<const float*>(vals), u, p, M, st);
-  return dispatch_w<double, double>(h, static_cast<const double*>(vals), u, p, M, st);
+    return dispatch_wave<float, double>(h, static_cast<const float*>(vals), rws, fac, p, M, st);
+  return dispatch_wave<double, double>(h, static_cast<const double*>(vals), rws, fac, p, M, st);
 }
 
 }  // namespace cpng
