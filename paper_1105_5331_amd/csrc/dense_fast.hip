@@ -25,6 +25,7 @@
 // indices o); each workgroup writes its float32 partial sums to its own
 // slot; a second kernel adds the slots in slot order in float64.  No atomics.
 #include "common.hpp"
+#include "splitk.hpp"
 
 #include <algorithm>
 
@@ -518,32 +519,6 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
   }
 }
 
-// Two-stage fixed-order sum of the workgroup slots: stage 1 adds the slots of
-// group g (slots g*per .. g*per + per - 1) into part2[g]; stage 2 adds the
-// groups in order.
-__global__ void reduce_groups_f32_kernel(const float* __restrict__ part, int64_t nsplit, int64_t n,
-                                         int64_t per, double* __restrict__ part2) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const int64_t g = blockIdx.y;
-  const int64_t k1 = min<int64_t>(nsplit, (g + 1) * per);
-  double s = 0.0;
-#pragma unroll 8
-  for (int64_t k = g * per; k < k1; ++k) s += (double)part[k * n + e];
-  part2[g * n + e] = s;
-}
-
-__global__ void reduce_final_kernel(const double* __restrict__ part2, int64_t ngroups, int64_t n,
-                                    double* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  double s = 0.0;
-#pragma unroll 8
-  for (int64_t g = 0; g < ngroups; ++g) s += part2[g * n + e];
-  out[e] = s;
-}
-
-
 // ---- vector (VALU) streaming kernel: float32 or float64 arithmetic --------------
 // Same inner/outer split, on the vector ALUs: for each outer index o and
 // each 64-wide chunk of the inner mode the workgroup loads the 64 x 64 tile
@@ -551,14 +526,19 @@ __global__ void reduce_final_kernel(const double* __restrict__ part2, int64_t ng
 // stride index, stores it [k][i] in LDS, builds the Khatri-Rao tile
 // B(k, r) = P(o, r) A^(q)(k0 + k, r) next to it, and every lane (one row i)
 // accumulates acc(r) += T(i, k) B(k, r) over its wave's quarter of the k's.
-// The four waves are summed in a fixed order at the end.
+// The steps (o, k-chunk) are software-pipelined: the tensor tile and the
+// factor values of step s + 1 are loaded into registers while step s is
+// computed from LDS.  The four waves are summed in a fixed order at the end.
 template <typename TT, typename CT, int RB, bool ROWS>
 __global__ __launch_bounds__(kThr) void mttkrp_tiles_vec(const TT* __restrict__ T,
                                                          const CT* __restrict__ fac,
                                                          FastParams p, CT* __restrict__ part) {
-  constexpr int TB = 64;           // tile edge (rows i and inner k)
-  constexpr int TS = TB + 1;       // padded LDS stride
-  constexpr int VE = 16 / sizeof(TT);   // elements per 16-byte load
+  constexpr int TB = 64;                 // tile edge (rows i and inner k)
+  constexpr int TS = TB + 1;             // padded LDS stride
+  constexpr int VE = 16 / sizeof(TT);    // elements per 16-byte load
+  constexpr int NL = TB * TB / VE / kThr;   // tensor loads per thread per step
+  constexpr int NB = TB * RB / kThr;        // factor values per thread per step
+  static_assert(NB >= 1, "RB too small for the B tile split");
   __shared__ CT Ts[TB * TS];       // [k][i]
   __shared__ CT Bs[TB * RB];       // [k][r]
   __shared__ int64_t base_tab[kOChunk];
@@ -574,11 +554,88 @@ __global__ __launch_bounds__(kThr) void mttkrp_tiles_vec(const TT* __restrict__ 
 #pragma unroll
   for (int r = 0; r < RB; ++r) acc[r] = CT(0);
 
+  TT v[NL][VE];   // next tensor tile
+  CT b[NB];       // next factor values A^(q)(k, r)
+
+  // loads of step (j, kc) of the current chunk into v and b
+  auto load_step = [&](int j, int kc) {
+    const int64_t base = base_tab[j];
+    const int64_t k0 = (int64_t)kc * TB;
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+      const int e = tid + t * kThr;
+      if (ROWS) {   // unit stride along k
+        const int ii = e / (TB / VE), kk = (e % (TB / VE)) * VE;
+        const int64_t i = i0 + ii, k = k0 + kk;
+        if (p.vec_ok && i < p.I_n && k + VE <= p.K) {
+          const TT* src = T + base + i * p.istride + k;
+          if constexpr (VE == 4) {
+            const float4 x = *reinterpret_cast<const float4*>(src);
+            v[t][0] = x.x; v[t][1] = x.y; v[t][2] = x.z; v[t][3] = x.w;
+          } else {
+            const double2 x = *reinterpret_cast<const double2*>(src);
+            v[t][0] = x.x; v[t][1] = x.y;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < VE; ++q)
+            v[t][q] = (i < p.I_n && k + q < p.K) ? T[base + i * p.istride + k + q] : TT(0);
+        }
+      } else {      // unit stride along i
+        const int kk = e / (TB / VE), ii = (e % (TB / VE)) * VE;
+        const int64_t i = i0 + ii, k = k0 + kk;
+        if (p.vec_ok && k < p.K && i + VE <= p.I_n) {
+          const TT* src = T + base + k * p.kstride + i;
+          if constexpr (VE == 4) {
+            const float4 x = *reinterpret_cast<const float4*>(src);
+            v[t][0] = x.x; v[t][1] = x.y; v[t][2] = x.z; v[t][3] = x.w;
+          } else {
+            const double2 x = *reinterpret_cast<const double2*>(src);
+            v[t][0] = x.x; v[t][1] = x.y;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < VE; ++q)
+            v[t][q] = (k < p.K && i + q < p.I_n) ? T[base + k * p.kstride + i + q] : TT(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const int e = tid + t * kThr;
+      const int kk = e / RB, rr = e - (e / RB) * RB;
+      const int64_t k = k0 + kk;
+      b[t] = (k < p.K && r0 + rr < p.R) ? fac[p.qfoff + k * p.R + r0 + rr] : CT(0);
+    }
+  };
+  // registers -> LDS for step j (B scaled by P(o_j, r))
+  auto store_step = [&](int j) {
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+      const int e = tid + t * kThr;
+      if (ROWS) {
+        const int ii = e / (TB / VE), kk = (e % (TB / VE)) * VE;
+#pragma unroll
+        for (int q = 0; q < VE; ++q) Ts[(kk + q) * TS + ii] = (CT)v[t][q];
+      } else {
+        const int kk = e / (TB / VE), ii = (e % (TB / VE)) * VE;
+#pragma unroll
+        for (int q = 0; q < VE; ++q) Ts[kk * TS + ii + q] = (CT)v[t][q];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const int e = tid + t * kThr;
+      const int kk = e / RB, rr = e - (e / RB) * RB;
+      Bs[kk * RB + rr] = P_tab[j * RB + rr] * b[t];
+    }
+  };
+
   const int64_t ob = (int64_t)blockIdx.x * p.o_per_block;
   const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
   for (int64_t oc = ob; oc < oe; oc += kOChunk) {
     const int nc = (int)min<int64_t>(kOChunk, oe - oc);
-    __syncthreads();
+    __syncthreads();   // the previous chunk's last step is done with the tables
     for (int e = tid; e < nc * (RB + 1); e += kThr) {
       const int j = e / (RB + 1), c = e - (e / (RB + 1)) * (RB + 1);
       if (c == RB) {
@@ -599,68 +656,19 @@ __global__ __launch_bounds__(kThr) void mttkrp_tiles_vec(const TT* __restrict__ 
       }
     }
     __syncthreads();   // tables complete before any wave reads them
-    for (int j = 0; j < nc; ++j) {
-      const int64_t base = base_tab[j];
-      for (int kc = 0; kc < nkc; ++kc) {
-        const int64_t k0 = (int64_t)kc * TB;
-        __syncthreads();
-        // tensor tile -> Ts[k][i]
-        for (int e = tid; e < TB * TB / VE; e += kThr) {
-          TT v[VE];
-          if (ROWS) {   // unit stride along k
-            const int ii = e / (TB / VE), kk = (e % (TB / VE)) * VE;
-            const int64_t i = i0 + ii, k = k0 + kk;
-            if (p.vec_ok && i < p.I_n && k + VE <= p.K) {
-              const TT* src = T + base + i * p.istride + k;
-              if constexpr (VE == 4) {
-                const float4 x = *reinterpret_cast<const float4*>(src);
-                v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-              } else {
-                const double2 x = *reinterpret_cast<const double2*>(src);
-                v[0] = x.x; v[1] = x.y;
-              }
-            } else {
+    const int nsteps = nc * nkc;
+    load_step(0, 0);
+    for (int s = 0; s < nsteps; ++s) {
+      const int j = s / nkc, kc = s - (s / nkc) * nkc;
+      __syncthreads();   // every wave is done computing the previous step
+      store_step(j);
+      __syncthreads();
+      if (s + 1 < nsteps) load_step((s + 1) / nkc, (s + 1) % nkc);
+      const int kv = (int)min<int64_t>(TB, p.K - (int64_t)kc * TB);   // valid k of this chunk
+      for (int kk = g; kk < kv; kk += 4) {
+        const CT x = Ts[kk * TS + lane];
 #pragma unroll
-              for (int q = 0; q < VE; ++q)
-                v[q] = (i < p.I_n && k + q < p.K) ? T[base + i * p.istride + k + q] : TT(0);
-            }
-#pragma unroll
-            for (int q = 0; q < VE; ++q) Ts[(kk + q) * TS + ii] = (CT)v[q];
-          } else {      // unit stride along i
-            const int kk = e / (TB / VE), ii = (e % (TB / VE)) * VE;
-            const int64_t i = i0 + ii, k = k0 + kk;
-            if (p.vec_ok && k < p.K && i + VE <= p.I_n) {
-              const TT* src = T + base + k * p.kstride + i;
-              if constexpr (VE == 4) {
-                const float4 x = *reinterpret_cast<const float4*>(src);
-                v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-              } else {
-                const double2 x = *reinterpret_cast<const double2*>(src);
-                v[0] = x.x; v[1] = x.y;
-              }
-            } else {
-#pragma unroll
-              for (int q = 0; q < VE; ++q)
-                v[q] = (k < p.K && i + q < p.I_n) ? T[base + k * p.kstride + i + q] : TT(0);
-            }
-#pragma unroll
-            for (int q = 0; q < VE; ++q) Ts[kk * TS + ii + q] = (CT)v[q];
-          }
-        }
-        // Khatri-Rao tile B(k, r) = P(o, r) A^(q)(k0 + k, r)
-        for (int e = tid; e < TB * RB; e += kThr) {
-          const int kk = e / RB, rr = e - (e / RB) * RB;
-          const int64_t k = k0 + kk;
-          CT b = CT(0);
-          if (k < p.K && r0 + rr < p.R) b = P_tab[j * RB + rr] * fac[p.qfoff + k * p.R + r0 + rr];
-          Bs[kk * RB + rr] = b;
-        }
-        __syncthreads();
-        for (int kk = g; kk < TB; kk += 4) {
-          const CT x = Ts[kk * TS + lane];
-#pragma unroll
-          for (int r = 0; r < RB; ++r) acc[r] = fma(x, Bs[kk * RB + r], acc[r]);
-        }
+        for (int r = 0; r < RB; ++r) acc[r] = fma(x, Bs[kk * RB + r], acc[r]);
       }
     }
   }
@@ -688,18 +696,6 @@ __global__ __launch_bounds__(kThr) void mttkrp_tiles_vec(const TT* __restrict__ 
         if (r0 + r < p.R) out[r0 + r] = acc[r] + red[r * TS + lane];
     }
   }
-}
-
-template <typename CT>
-__global__ void reduce_groups_kernel(const CT* __restrict__ part, int64_t nsplit, int64_t n,
-                                     int64_t per, double* __restrict__ part2) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const int64_t g = blockIdx.y;
-  const int64_t k1 = min<int64_t>(nsplit, (g + 1) * per);
-  double s = 0.0;
-  for (int64_t k = g * per; k < k1; ++k) s += (double)part[k * n + e];
-  part2[g * n + e] = s;
 }
 
 }  // namespace
@@ -748,12 +744,8 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   p.o_per_block = (p.O + ks - 1) / ks;
   ks = (p.O + p.o_per_block - 1) / p.o_per_block;
   const int64_t n_out = p.I_n * R;
-  const int64_t per = 32;
-  const int64_t ngroups = (ks + per - 1) / per;
-  const size_t part_bytes = (sizeof(float) * (size_t)(ks * n_out) + 255) & ~size_t(255);
-  CP_TRY(ensure(h, h->part, part_bytes + sizeof(double) * (size_t)(ngroups * n_out), st));
+  CP_TRY(ensure(h, h->part, sizeof(float) * (size_t)(ks * n_out), st));
   float* part = static_cast<float*>(h->part.ptr);
-  double* part2 = reinterpret_cast<double*>(static_cast<char*>(h->part.ptr) + part_bytes);
   dim3 grid((unsigned)ks, (unsigned)ychunks, (unsigned)rchunks);
   const size_t lds = 2 * sizeof(__bf16) * 32 * (size_t)p.kpad;
   // outer tables: P (O x R floats) then base offsets (O int64)
@@ -780,11 +772,7 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
     }
   }
   CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL(reduce_groups_f32_kernel, dim3((unsigned)((n_out + 255) / 256), (unsigned)ngroups),
-                     dim3(256), 0, st, part, ks, n_out, per, part2);
-  CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL(reduce_final_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
-                     part2, ngroups, n_out, M);
+  launch_splitk_reduce(part, ks, n_out, M, st);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
@@ -834,12 +822,8 @@ static int launch_tiles(cp_handle* h, const TT* T, const CT* fac, FastParams p, 
   p.o_per_block = (p.O + ks - 1) / ks;
   ks = (p.O + p.o_per_block - 1) / p.o_per_block;
   const int64_t n_out = p.I_n * p.R;
-  const int64_t per = 32;
-  const int64_t ngroups = (ks + per - 1) / per;
-  const size_t part_bytes = (sizeof(CT) * (size_t)(ks * n_out) + 255) & ~size_t(255);
-  CP_TRY(ensure(h, h->part, part_bytes + sizeof(double) * (size_t)(ngroups * n_out), st));
+  CP_TRY(ensure(h, h->part, sizeof(CT) * (size_t)(ks * n_out), st));
   CT* part = static_cast<CT*>(h->part.ptr);
-  double* part2 = reinterpret_cast<double*>(static_cast<char*>(h->part.ptr) + part_bytes);
   dim3 grid((unsigned)ks, (unsigned)ychunks, (unsigned)rchunks);
   {
     KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
@@ -847,11 +831,7 @@ static int launch_tiles(cp_handle* h, const TT* T, const CT* fac, FastParams p, 
     else hipLaunchKernelGGL((mttkrp_tiles_vec<TT, CT, RB, false>), grid, dim3(kThr), 0, st, T, fac, p, part);
   }
   CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL((reduce_groups_kernel<CT>), dim3((unsigned)((n_out + 255) / 256), (unsigned)ngroups),
-                     dim3(256), 0, st, part, ks, n_out, per, part2);
-  CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL(reduce_final_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
-                     part2, ngroups, n_out, M);
+  launch_splitk_reduce(part, ks, n_out, M, st);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }

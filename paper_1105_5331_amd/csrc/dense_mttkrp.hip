@@ -15,6 +15,7 @@
 // a partial buffer; a second kernel adds the slots in slot order in float64.
 // No atomics anywhere: results are bitwise reproducible.
 #include "common.hpp"
+#include "splitk.hpp"
 
 #include <algorithm>
 
@@ -174,16 +175,6 @@ __global__ __launch_bounds__(kThreads) void mttkrp_vec_kernel(const TT* __restri
   }
 }
 
-// out[e] = sum_{k < nsplit} part[k * n + e], in k order.
-__global__ void reduce_slots_kernel(const double* __restrict__ part, int64_t nsplit, int64_t n,
-                                    double* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  double s = 0.0;
-  for (int64_t k = 0; k < nsplit; ++k) s += part[k * n + e];
-  out[e] = s;
-}
-
 __global__ void to_f32_kernel(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) y[e] = (float)x[e];
@@ -211,8 +202,7 @@ int launch_vec(cp_handle* h, const TT* T, const CT* fac, DenseParams p, double* 
                        part);
   }
   CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL(reduce_slots_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
-                     part, ks, n_out, M);
+  launch_splitk_reduce(part, ks, n_out, M, st);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
@@ -386,8 +376,7 @@ int launch_bf16x3(cp_handle* h, const float* T, const float* fac, DenseParams p,
     hipLaunchKernelGGL((mttkrp_bf16x3_kernel<S>), grid, dim3(kThreads), 0, st, T, fac, p, part);
   }
   CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL(reduce_slots_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
-                     part, ks, n_out, M);
+  launch_splitk_reduce(part, ks, n_out, M, st);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }

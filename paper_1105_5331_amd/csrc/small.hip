@@ -90,8 +90,22 @@ int make_shape(cp_handle* h, int order, const int64_t* dims, Shape* s) {
 
 namespace {
 
-constexpr int kRowsPerChunk = 256;
+constexpr int kRowsPerChunk = 64;
 constexpr int kMaxR = 64;
+
+// sum_{q < n} p[q * stride] in q order; the loads go out 8 at a time so a
+// long sum is not one memory latency per term.
+__device__ inline double ordered_sum(const double* __restrict__ p, int64_t n, int64_t stride) {
+  double s = 0.0;
+  for (int64_t q0 = 0; q0 < n; q0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) v[b] = q0 + b < n ? p[(q0 + b) * stride] : 0.0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) s += v[b];
+  }
+  return s;
+}
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -166,8 +180,8 @@ __global__ void gram_final_kernel(const double* __restrict__ part, ModeTable t,
   for (int pr = threadIdx.x; pr < R * R; pr += blockDim.x) {
     double sk[CP_MAX_ORDER];
     for (int k = 0; k < t.N; ++k) {
-      double s = 0.0;
-      for (int64_t ch = t.coff[k]; ch < t.coff[k + 1]; ++ch) s += part[ch * R * R + pr];
+      const double s = ordered_sum(part + t.coff[k] * R * R + pr, t.coff[k + 1] - t.coff[k],
+                                   (int64_t)R * R);
       sk[k] = s;
       if (S) S[(int64_t)k * R * R + pr] = s;
     }
@@ -188,19 +202,32 @@ __global__ void gram_final_kernel(const double* __restrict__ part, ModeTable t,
 }
 
 // ---- normalisation ------------------------------------------------------------
-__global__ void colsq_partial_kernel(const double* __restrict__ u, ModeTable t,
-                                     double* __restrict__ part) {
+// part[chunk * R + r] = sum over the chunk's rows of A(i, r)^2.  Thread t
+// takes column t % R and rows t / R, t / R + G, ... (G = blockDim / R row
+// groups, blockDim <= 256); the G group sums are added in group order.
+__global__ __launch_bounds__(256) void colsq_partial_kernel(const double* __restrict__ u,
+                                                            ModeTable t,
+                                                            double* __restrict__ part) {
+  __shared__ double sh[256];
   const int R = t.R;
+  const int G = (int)blockDim.x / R;   // blockDim.x <= 256
   const int64_t ch = blockIdx.x;
   int k = 0;
   while (ch >= t.coff[k + 1]) ++k;
   const int64_t i_begin = (ch - t.coff[k]) * kRowsPerChunk;
   const int64_t i_end = min<int64_t>(t.dims[k], i_begin + kRowsPerChunk);
   const double* A = u + t.off[k] * R;
-  for (int r = threadIdx.x; r < R; r += blockDim.x) {
-    double s = 0.0;
-    for (int64_t i = i_begin; i < i_end; ++i) s = fma(A[i * R + r], A[i * R + r], s);
-    part[ch * R + r] = s;
+  const int r = threadIdx.x % R;
+  const int grp = threadIdx.x / R;
+  double s = 0.0;
+  if (grp < G)
+    for (int64_t i = i_begin + grp; i < i_end; i += G) s = fma(A[i * R + r], A[i * R + r], s);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < R) {
+    double tot = 0.0;
+    for (int q = 0; q < G; ++q) tot += sh[q * R + threadIdx.x];
+    part[ch * R + threadIdx.x] = tot;
   }
 }
 
@@ -213,8 +240,7 @@ __global__ void norm_plan_kernel(const double* __restrict__ part, ModeTable t,
   for (int r = threadIdx.x; r < R; r += blockDim.x) {
     double l = 1.0;
     for (int k = 0; k < t.N; ++k) {
-      double s = 0.0;
-      for (int64_t ch = t.coff[k]; ch < t.coff[k + 1]; ++ch) s += part[ch * R + r];
+      const double s = ordered_sum(part + t.coff[k] * R + r, t.coff[k + 1] - t.coff[k], R);
       nu[k][r] = sqrt(s);
       l *= nu[k][r];
     }
@@ -403,17 +429,19 @@ __global__ __launch_bounds__(64) void solve_rows_kernel(const double* __restrict
   double* y = x + threadIdx.x;
 #define Y(r) y[(r) * 64]
   const double* m = M + i * R;
+#pragma unroll 8
+  for (int r = 0; r < R; ++r) Y(r) = m[r];   // the row's loads all go out first
   if (*kind == 2) {
     for (int c = 0; c < R; ++c) {
       double s = 0.0;
-      for (int q = 0; q < R; ++q) s = fma(m[q], f[q * R + c], s);
+      for (int q = 0; q < R; ++q) s = fma(Y(q), f[q * R + c], s);
       A[i * R + c] = s;
     }
     return;
   }
   // forward: L y = m
   for (int r = 0; r < R; ++r) {
-    double s = m[r];
+    double s = Y(r);
     for (int q = 0; q < r; ++q) s -= f[r * R + q] * Y(q);
     Y(r) = s / f[r * R + r];
   }
@@ -591,8 +619,7 @@ __global__ void step2_solve_kernel(const double* __restrict__ part, int nb, int 
   const int npairs = m * (m + 1) / 2;
   const int nval = npairs + m;
   for (int v = threadIdx.x; v < nval; v += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * nval + v];
+    const double s = ordered_sum(part + v, nb, nval);
     if (v < npairs) {
       int j = 0, rem = v;
       while (rem >= m - j) {
@@ -625,19 +652,26 @@ __global__ void step2_solve_kernel(const double* __restrict__ part, int nb, int 
     if (threadIdx.x == 0) *flags = *flags | 4;
     return;
   }
-  if (threadIdx.x == 0) {
-    double y[kMaxWin];
+  // L y = rhs, then L^T alpha = y, by the first wave: after y(r) is known,
+  // lane q > r removes its term; lane q holds row q (m <= 64).
+  if (threadIdx.x < 64) {
+    const int q = threadIdx.x;
+    double* y = rhs;
     for (int r = 0; r < m; ++r) {
-      double s = rhs[r];
-      for (int q = 0; q < r; ++q) s -= B[r * m + q] * y[q];
-      y[r] = s / B[r * m + r];
+      const double yr = y[r] / B[r * m + r];
+      __builtin_amdgcn_wave_barrier();
+      if (q > r && q < m) y[q] -= B[q * m + r] * yr;
+      if (q == r) y[q] = yr;
+      __builtin_amdgcn_wave_barrier();
     }
     for (int r = m - 1; r >= 0; --r) {
-      double s = y[r];
-      for (int q = r + 1; q < m; ++q) s -= B[q * m + r] * y[q];
-      y[r] = s / B[r * m + r];
+      const double xr = y[r] / B[r * m + r];
+      __builtin_amdgcn_wave_barrier();
+      if (q < r) y[q] -= B[r * m + q] * xr;
+      if (q == r) y[q] = xr;
+      __builtin_amdgcn_wave_barrier();
     }
-    for (int r = 0; r < m; ++r) alpha_out[r] = y[r];
+    if (q < m) alpha_out[q] = y[q];
   }
 }
 
@@ -687,7 +721,7 @@ int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStre
   double* scales = static_cast<double*>(h->small.ptr);
   int* perm = reinterpret_cast<int*>(scales + s.N * R);
   double* tmp = static_cast<double*>(h->tmpu.ptr);
-  hipLaunchKernelGGL(colsq_partial_kernel, dim3((unsigned)nch), dim3(64), 0, st, u, t, part);
+  hipLaunchKernelGGL(colsq_partial_kernel, dim3((unsigned)nch), dim3(256), 0, st, u, t, part);
   CP_LAUNCH_CHECK(h);
   hipLaunchKernelGGL(norm_plan_kernel, dim3(1), dim3(64), 0, st, part, t, scales, perm);
   CP_LAUNCH_CHECK(h);
