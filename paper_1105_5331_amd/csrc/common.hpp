@@ -37,6 +37,7 @@ struct cp_handle {
   cpng::DevBuf carry;    // sparse segment carries
   cpng::DevBuf tmpu;     // scratch iterate-sized vectors
   cpng::DevBuf otab;     // per-launch outer-index tables of the streaming MTTKRP
+  uint64_t gen = 0;           // bumped whenever a workspace slice is reallocated
   double* pinned = nullptr;   // host pinned readback area (64 doubles)
   int* flags = nullptr;       // device status word (ALS solve fallbacks)
   // optional event timing of the main MTTKRP kernels
@@ -152,8 +153,22 @@ int axpy_to(cp_handle* h, const double* x, double a, const double* d, double* y,
             hipStream_t st);   // y = x + a*d
 int sub_to(cp_handle* h, const double* a, const double* b, double* y, int64_t n,
            hipStream_t st);    // y = a - b
-int step2(cp_handle* h, int64_t L, int m, const double* const* U, const double* const* G,
-          const double* ubar, const double* gbar, double eps, double* uhat, double* alpha,
-          hipStream_t st);
+
+// Per-call values of the N-GMRES kernels kept in device memory, so that a
+// captured launch sequence can be replayed with new values: the line-search
+// step and the window's current size and oldest slot.
+struct StepPar {
+  double beta;
+  int32_t m;
+  int32_t whead;
+};
+int set_steppar(cp_handle* h, StepPar* p, double beta, int m, int whead, hipStream_t st);
+int axpy_par(cp_handle* h, const double* x, const StepPar* par, const double* d, double* y,
+             int64_t n, hipStream_t st);   // y = x + par->beta * d
+// Window of stored iterates: slot s at ubase + s*L (gbase + s*L); the j-th
+// oldest of par->m entries is slot (par->whead + j) % wcap.
+int step2(cp_handle* h, int64_t L, const double* ubase, const double* gbase, int wcap,
+          const StepPar* par, const double* ubar, const double* gbar, double eps, double* uhat,
+          double* alpha, hipStream_t st);
 
 }  // namespace cpng

@@ -33,6 +33,20 @@ struct cp_ngmres_state {
   double *u, *g, *ubar, *gbar, *uhat, *d, *ut, *gt, *gbest, *scal;  // scal: 8 doubles
   double *winU, *winG;
   int wcap = 0, wcount = 0, whead = 0;   // ring buffer: slot (whead + j) % wcap, j oldest first
+  // Step II / line-search values: host copy (pinned) and device copy
+  StepPar* hpar = nullptr;
+  StepPar* dpar = nullptr;
+  // Captured launch sequences of the two device phases of an iteration
+  // (Steps I-II up to the slope; one line-search evaluation), replayed with
+  // hipGraphLaunch.  Used only on a non-null stream without profiling.
+  struct Captured {
+    hipGraphExec_t exec = nullptr;
+    cp_handle* h = nullptr;
+    uint64_t gen = 0;
+    int prec = -1;
+    bool warm = false;     // ran once eagerly at the current precision
+    bool failed = false;   // capture not possible: stay eager
+  } cap[2];
 };
 
 namespace {
@@ -202,12 +216,97 @@ double mt_step(MTState& m, double stp, double fp, double dp, double stmin, doubl
 
 enum { LS_CONVERGED = 0, LS_MAXFEV = 1, LS_XTOL = 2, LS_STPMAX = 3, LS_STPMIN = 4, LS_ROUNDING = 5 };
 
+enum { PHASE_STEP12 = 0, PHASE_EVAL = 1 };
+
+// The device work of Steps I and II: u_bar = M(u_i), f and g at u_bar, the
+// accelerated u_hat over the window, d = u_hat - u_bar and the slope
+// g(u_bar)^T d (scal[0], scal[1]).
+int enqueue_step12(cp_handle* h, cp_ngmres_state* S) {
+  CP_HIP(h, hipMemcpyAsync(S->dpar, S->hpar, sizeof(StepPar), hipMemcpyHostToDevice, S->st));
+  CP_HIP(h, hipMemcpyAsync(S->ubar, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+  CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st));
+  CP_TRY(objective_grad_impl(h, S->T, S->s, S->ubar, S->R, S->prec, S->scal, S->gbar, S->st));
+  CP_TRY(step2(h, S->L, S->winU, S->winG, S->wcap, S->dpar, S->ubar, S->gbar, S->opt.eps,
+               S->uhat, S->scal + 8, S->st));
+  if (S->opt.normalize_accel) CP_TRY(normalize(h, S->s, S->uhat, S->R, nullptr, S->st));
+  CP_TRY(sub_to(h, S->uhat, S->ubar, S->d, S->L, S->st));
+  CP_TRY(dot(h, S->gbar, S->d, S->L, S->scal + 1, S->st));
+  return CP_OK;
+}
+
+// The device work of one line-search trial: u_t = u_bar + beta d, f and g
+// at u_t, and g(u_t)^T d (scal[0], scal[1]).
+int enqueue_eval(cp_handle* h, cp_ngmres_state* S) {
+  CP_HIP(h, hipMemcpyAsync(S->dpar, S->hpar, sizeof(StepPar), hipMemcpyHostToDevice, S->st));
+  CP_TRY(axpy_par(h, S->ubar, S->dpar, S->d, S->ut, S->L, S->st));
+  CP_TRY(objective_grad_impl(h, S->T, S->s, S->ut, S->R, S->prec, S->scal, S->gt, S->st));
+  CP_TRY(dot(h, S->gt, S->d, S->L, S->scal + 1, S->st));
+  return CP_OK;
+}
+
+void drop_captured(cp_ngmres_state::Captured& c) {
+  if (c.exec) (void)hipGraphExecDestroy(c.exec);
+  c.exec = nullptr;
+  c.warm = false;
+}
+
+// Runs a phase: eagerly the first time at a precision (that sizes every
+// workspace slice), then captured once and replayed.  A capture that fails
+// (e.g. a slice would have to grow) falls back to eager launches for good.
+// The host values in S->hpar are copied to the device inside the phase, so
+// a replay uses the current ones.
+int run_phase(cp_handle* h, cp_ngmres_state* S, int ph) {
+  auto enqueue = [&]() { return ph == PHASE_STEP12 ? enqueue_step12(h, S) : enqueue_eval(h, S); };
+  cp_ngmres_state::Captured& c = S->cap[ph];
+  if (!S->st || h->prof || c.failed) return enqueue();
+  if (c.h != h || c.gen != h->gen || c.prec != S->prec) drop_captured(c);
+  if (c.exec) {
+    CP_HIP(h, hipGraphLaunch(c.exec, S->st));
+    return CP_OK;
+  }
+  if (!c.warm) {
+    CP_TRY(enqueue());
+    c.warm = true;
+    c.h = h;
+    c.gen = h->gen;
+    c.prec = S->prec;
+    return CP_OK;
+  }
+  const uint64_t gen0 = h->gen;
+  if (hipStreamBeginCapture(S->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    c.failed = true;
+    return enqueue();
+  }
+  const int rc = enqueue();
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(S->st, &graph);
+  (void)hipGetLastError();
+  hipGraphExec_t exec = nullptr;
+  bool ok = rc >= 0 && e == hipSuccess && graph && h->gen == gen0;
+  if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    exec = nullptr;
+    ok = false;
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  if (!ok) {   // nothing of the capture ran: do the phase eagerly
+    c.failed = true;
+    return enqueue();
+  }
+  c.exec = exec;
+  c.h = h;
+  c.gen = h->gen;
+  c.prec = S->prec;
+  CP_HIP(h, hipGraphLaunch(c.exec, S->st));
+  return CP_OK;
+}
+
 // Evaluate phi(beta) = f(ubar + beta d), phi'(beta) = g(ubar + beta d)^T d.
 int ls_eval(cp_handle* h, cp_ngmres_state* S, double beta, double* f, double* dphi) {
-  CP_TRY(axpy_to(h, S->ubar, beta, S->d, S->ut, S->L, S->st));
-  CP_TRY(objective_grad_impl(h, S->T, S->s, S->ut, S->R, S->prec, S->scal, S->gt, S->st));
+  S->hpar->beta = beta;
+  CP_TRY(run_phase(h, S, PHASE_EVAL));
   S->n_fg++;
-  CP_TRY(dot(h, S->gt, S->d, S->L, S->scal + 1, S->st));
   double v[2];
   CP_TRY(readback(h, S->scal, 2, v, S->st));
   *f = v[0];
@@ -548,18 +647,11 @@ int ngmres_accelerate(cp_handle* h, int64_t L, int32_t m, const double* U, const
   if (L < 1 || m < 1 || m > 64) return fail(h, CP_EINVAL, "need L >= 1 and 1 <= m <= 64");
   if (!U || !G || !u_bar || !g_bar || !u_hat_out) return fail(h, CP_EINVAL, "null argument");
   if (!(eps >= 0.0)) return fail(h, CP_EINVAL, "eps must be >= 0");
-  const double* Up[64];
-  const double* Gp[64];
-  for (int j = 0; j < m; ++j) {
-    Up[j] = U + (size_t)j * L;
-    Gp[j] = G + (size_t)j * L;
-  }
-  double* alpha = alpha_out;
-  if (!alpha) {
-    CP_TRY(ensure(h, h->small, 64 * 1024, st));
-    alpha = static_cast<double*>(h->small.ptr) + 4096;
-  }
-  return step2(h, L, m, Up, Gp, u_bar, g_bar, eps, u_hat_out, alpha, st);
+  CP_TRY(ensure(h, h->small, 64 * 1024, st));
+  double* alpha = alpha_out ? alpha_out : static_cast<double*>(h->small.ptr) + 4096;
+  StepPar* par = reinterpret_cast<StepPar*>(static_cast<double*>(h->small.ptr) + 4096 + 64);
+  CP_TRY(set_steppar(h, par, 0.0, m, 0, st));
+  return step2(h, L, U, G, m, par, u_bar, g_bar, eps, u_hat_out, alpha, st);
 }
 
 int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_options* opt,
@@ -609,6 +701,14 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
   S->winU = p; p += (size_t)S->wcap * S->L;
   S->winG = p; p += (size_t)S->wcap * S->L;
   S->scal = p;
+  S->dpar = reinterpret_cast<StepPar*>(S->scal + 72);
+  if (hipHostMalloc(reinterpret_cast<void**>(&S->hpar), sizeof(StepPar)) != hipSuccess) {
+    S->hpar = nullptr;
+    (void)hipFree(S->mem);
+    delete S;
+    return fail(h, CP_ENOMEM, "pinned host allocation failed");
+  }
+  *S->hpar = StepPar{0.0, 0, 0};
   int rc = CP_OK;
   if (hipMemcpyAsync(S->u, u0, sizeof(double) * S->L, hipMemcpyDeviceToDevice, st) != hipSuccess)
     rc = fail(h, CP_EDEVICE, "copy of the initial guess failed");
@@ -627,6 +727,8 @@ int cp_ngmres_destroy(cp_handle* h, cp_ngmres_state* S) {
   if (!S) return CP_OK;
   if (h) (void)hipSetDevice(h->device);
   if (S->st) (void)hipStreamSynchronize(S->st);
+  for (auto& c : S->cap) drop_captured(c);
+  if (S->hpar) (void)hipHostFree(S->hpar);
   if (S->mem) (void)hipFree(S->mem);
   delete S;
   return CP_OK;
@@ -661,23 +763,11 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
     CP_TRY(als_sweep_impl(h, S->T, S->s, S->u, S->R, S->prec, 1, S->st));
     CP_TRY(eval_current(h, S));
   } else {
-    // Step I: u_bar = M(u_i); f, g at u_bar
-    CP_HIP(h, hipMemcpyAsync(S->ubar, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
-    CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st));
-    CP_TRY(objective_grad_impl(h, S->T, S->s, S->ubar, S->R, S->prec, S->scal, S->gbar, S->st));
+    // Steps I and II: u_bar = M(u_i); f, g at u_bar; u_hat over the window
+    S->hpar->m = S->wcount;
+    S->hpar->whead = S->whead;
+    CP_TRY(run_phase(h, S, PHASE_STEP12));
     S->n_fg++;
-    // Step II over the window
-    const double* Up[64];
-    const double* Gp[64];
-    for (int j = 0; j < S->wcount; ++j) {
-      Up[j] = win_u(S, j);
-      Gp[j] = win_g(S, j);
-    }
-    CP_TRY(step2(h, S->L, S->wcount, Up, Gp, S->ubar, S->gbar, S->opt.eps, S->uhat,
-                 S->scal + 8, S->st));
-    if (S->opt.normalize_accel) CP_TRY(normalize(h, S->s, S->uhat, S->R, nullptr, S->st));
-    CP_TRY(sub_to(h, S->uhat, S->ubar, S->d, S->L, S->st));
-    CP_TRY(dot(h, S->gbar, S->d, S->L, S->scal + 1, S->st));
     double fs[2];   // f(u_bar) and the slope g(u_bar)^T d in one readback
     CP_TRY(readback(h, S->scal, 2, fs, S->st));
     const double fbar = fs[0], slope = fs[1];
@@ -733,6 +823,32 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
   if (!u_inout) return fail(h, CP_EINVAL, "null iterate");
   if (!(tol >= 0.0)) return fail(h, CP_EINVAL, "tol must be >= 0");
   cp_ngmres_state* S = nullptr;
+  // The null stream cannot be captured: run on a private stream that first
+  // waits for the work the caller queued on it.
+  hipStream_t own = nullptr;
+  if (!st) {
+    hipEvent_t ev = nullptr;
+    CP_HIP(h, hipSetDevice(h->device));
+    if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+        hipEventRecord(ev, st) == hipSuccess && hipStreamWaitEvent(own, ev, 0) == hipSuccess) {
+      st = own;
+    } else if (own) {
+      (void)hipStreamDestroy(own);
+      own = nullptr;
+    }
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipGetLastError();
+  }
+  struct OwnStream {
+    hipStream_t s;
+    ~OwnStream() {
+      if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+      }
+    }
+  } own_guard{own};
   CP_TRY(cp_ngmres_create(h, T, R, &o, u_inout, st, &S));
   int rc = CP_OK;
   int ntr = 0;
@@ -773,8 +889,9 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
     if (o.trace && ntr < o.trace_cap) o.trace[ntr++] = info;
   }
   if (rc >= 0) {
-    CP_HIP(h, hipMemcpyAsync(u_inout, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, st));
-    CP_HIP(h, hipStreamSynchronize(st));
+    if (hipMemcpyAsync(u_inout, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      rc = fail(h, CP_EDEVICE, "copy of the result failed");
   }
   if (rep) {
     rep->iters = S->it;

@@ -30,6 +30,7 @@ int ensure(cp_handle* h, DevBuf& b, size_t bytes, hipStream_t stream) {
     b.ptr = nullptr;
     b.bytes = 0;
   }
+  h->gen++;   // captured launch sequences that used the old slice are stale
   if (hipMalloc(&b.ptr, want) != hipSuccess) {
     b.ptr = nullptr;
     return fail(h, CP_ENOMEM, "device allocation of %zu bytes failed", want);
@@ -542,17 +543,40 @@ __global__ void sub_kernel(const double* __restrict__ a, const double* __restric
 // ---- N-GMRES Step II ----------------------------------------------------------
 constexpr int kMaxWin = 64;
 constexpr int kStepTile = 64;
-struct WinPtrs {
-  const double* u[kMaxWin];
-  const double* g[kMaxWin];
+struct WinDesc {
+  const double* ubase;
+  const double* gbase;
+  int64_t L;
+  int wcap;
 };
+
+__device__ inline const double* win_slot(const double* base, const WinDesc& w, int whead, int j) {
+  return base + (int64_t)((whead + j) % w.wcap) * w.L;
+}
+
+__global__ void set_steppar_kernel(StepPar* p, double beta, int m, int whead) {
+  p->beta = beta;
+  p->m = m;
+  p->whead = whead;
+}
+
+__global__ void axpy_par_kernel(const double* __restrict__ x, const StepPar* __restrict__ par,
+                                const double* __restrict__ d, double* __restrict__ y, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = fma(par->beta, d[e], x[e]);
+}
 
 // Pair sums over a contiguous range of positions: for j <= k < m,
 // B(j,k) = sum p_j p_k and rhs(j) = sum p_j gbar, with p_j = gbar - g_j.
 // Partial slot layout: [pairs m(m+1)/2 in (j,k) row order][m rhs].
-__global__ void step2_partial_kernel(WinPtrs w, int m, const double* __restrict__ gbar,
-                                     int64_t L, int64_t per, double* __restrict__ part) {
+__global__ void step2_partial_kernel(WinDesc w, const StepPar* __restrict__ par,
+                                     const double* __restrict__ gbar, int64_t L, int64_t per,
+                                     double* __restrict__ part) {
   __shared__ double P[kMaxWin + 1][kStepTile];
+  __shared__ const double* gp[kMaxWin];
+  const int m = par->m;
+  const int whead = par->whead;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) gp[j] = win_slot(w.gbase, w, whead, j);
   const int npairs = m * (m + 1) / 2;
   const int nval = npairs + m;
   double acc[9];
@@ -576,6 +600,7 @@ __global__ void step2_partial_kernel(WinPtrs w, int m, const double* __restrict_
     pj[q] = j;
     pk[q] = k;
   }
+  __syncthreads();
   const int64_t b0 = (int64_t)blockIdx.x * per;
   const int64_t b1 = min<int64_t>(L, b0 + per);
   for (int64_t x0 = b0; x0 < b1; x0 += kStepTile) {
@@ -585,7 +610,7 @@ __global__ void step2_partial_kernel(WinPtrs w, int m, const double* __restrict_
       double val = 0.0;
       if (xx < nx) {
         const double gb = gbar[x0 + xx];
-        val = j < m ? gb - w.g[j][x0 + xx] : gb;
+        val = j < m ? gb - gp[j][x0 + xx] : gb;
       }
       P[j][xx] = val;
     }
@@ -610,12 +635,14 @@ __global__ void step2_partial_kernel(WinPtrs w, int m, const double* __restrict_
 }
 
 // One block: reduce partial slots in order, regularise, Cholesky-solve.
-__global__ void step2_solve_kernel(const double* __restrict__ part, int nb, int m, double eps,
+__global__ void step2_solve_kernel(const double* __restrict__ part, int nb,
+                                   const StepPar* __restrict__ par, double eps,
                                    double* __restrict__ alpha_out, int* __restrict__ flags) {
   __shared__ double B[kMaxWin * kMaxWin];
   __shared__ double rhs[kMaxWin];
   __shared__ double ok;
   __shared__ double dmax;
+  const int m = par->m;
   const int npairs = m * (m + 1) / 2;
   const int nval = npairs + m;
   for (int v = threadIdx.x; v < nval; v += blockDim.x) {
@@ -675,14 +702,23 @@ __global__ void step2_solve_kernel(const double* __restrict__ part, int nb, int 
   }
 }
 
-__global__ void step2_combine_kernel(WinPtrs w, int m, const double* __restrict__ ubar,
+__global__ void step2_combine_kernel(WinDesc w, const StepPar* __restrict__ par,
+                                     const double* __restrict__ ubar,
                                      const double* __restrict__ alpha, int64_t L,
                                      double* __restrict__ uhat) {
+  __shared__ const double* up[kMaxWin];
+  __shared__ double al[kMaxWin];
+  const int m = par->m;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    up[j] = win_slot(w.ubase, w, par->whead, j);
+    al[j] = alpha[j];
+  }
+  __syncthreads();
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= L) return;
   const double ub = ubar[x];
   double s = 0.0;
-  for (int j = 0; j < m; ++j) s = fma(alpha[j], ub - w.u[j][x], s);
+  for (int j = 0; j < m; ++j) s = fma(al[j], ub - up[j][x], s);
   uhat[x] = ub + s;
 }
 
@@ -794,26 +830,35 @@ int sub_to(cp_handle* h, const double* a, const double* b, double* y, int64_t n,
   return CP_OK;
 }
 
-int step2(cp_handle* h, int64_t L, int m, const double* const* U, const double* const* G,
-          const double* ubar, const double* gbar, double eps, double* uhat, double* alpha,
-          hipStream_t st) {
-  if (m < 1 || m > kMaxWin) return fail(h, CP_EINVAL, "window size %d outside 1..%d", m, kMaxWin);
-  WinPtrs w{};
-  for (int j = 0; j < m; ++j) {
-    w.u[j] = U[j];
-    w.g[j] = G[j];
-  }
-  const int nval = m * (m + 1) / 2 + m;
+int set_steppar(cp_handle* h, StepPar* p, double beta, int m, int whead, hipStream_t st) {
+  hipLaunchKernelGGL(set_steppar_kernel, dim3(1), dim3(1), 0, st, p, beta, m, whead);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int axpy_par(cp_handle* h, const double* x, const StepPar* par, const double* d, double* y,
+             int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(axpy_par_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, x, par, d, y, n);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int step2(cp_handle* h, int64_t L, const double* ubase, const double* gbase, int wcap,
+          const StepPar* par, const double* ubar, const double* gbar, double eps, double* uhat,
+          double* alpha, hipStream_t st) {
+  if (wcap < 1 || wcap > kMaxWin) return fail(h, CP_EINVAL, "window size %d outside 1..%d", wcap, kMaxWin);
+  const WinDesc w{ubase, gbase, L, wcap};
+  const int nval_max = wcap * (wcap + 1) / 2 + wcap;
   const int64_t per = std::max<int64_t>(kStepTile, ((L + 255) / 256 + kStepTile - 1) / kStepTile * kStepTile);
   const int nb = (int)std::max<int64_t>(1, (L + per - 1) / per);
-  CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)nb * nval, st));
+  CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)nb * nval_max, st));
   double* part = static_cast<double*>(h->red.ptr);
-  hipLaunchKernelGGL(step2_partial_kernel, dim3(nb), dim3(256), 0, st, w, m, gbar, L, per, part);
+  hipLaunchKernelGGL(step2_partial_kernel, dim3(nb), dim3(256), 0, st, w, par, gbar, L, per, part);
   CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL(step2_solve_kernel, dim3(1), dim3(256), 0, st, part, nb, m, eps, alpha,
+  hipLaunchKernelGGL(step2_solve_kernel, dim3(1), dim3(256), 0, st, part, nb, par, eps, alpha,
                      h->flags);
   CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL(step2_combine_kernel, dim3(nblk(L, 256)), dim3(256), 0, st, w, m, ubar, alpha,
+  hipLaunchKernelGGL(step2_combine_kernel, dim3(nblk(L, 256)), dim3(256), 0, st, w, par, ubar, alpha,
                      L, uhat);
   CP_LAUNCH_CHECK(h);
   return CP_OK;

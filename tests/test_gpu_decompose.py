@@ -165,3 +165,56 @@ def test_decompose_rejects_zero_tensor(h):
     cpng.cp_tensor_prepare(h, Tg)
     with pytest.raises(cpng.CpError):
         cpng.cp_decompose(h, Tg, 2, 1e-8, _dev(np.ones(24)))
+
+
+def _run_state(cpng, h, Tg, R, u0, steps, prec, stream):
+    """Steps an NGMRESState; with a side stream the two device phases of an
+    iteration are captured once and replayed, on the null stream they are
+    launched one kernel at a time."""
+    with torch.cuda.stream(stream):
+        st = cpng.NGMRESState(h, Tg, R, _dev(u0), precision=prec, final_precision=prec)
+        infos = [st.step() for _ in range(steps)]
+        u, g, f, rho = st.get()
+        st.close()
+    torch.cuda.synchronize()
+    return infos, u.cpu().numpy(), g.cpu().numpy(), f, rho
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_captured_replay_matches_eager(h, prec):
+    """Every replay of the captured phases (new line-search step, window size
+    and head each time, eager work and host synchronisation in between) gives
+    bitwise the result of launching the same kernels one by one."""
+    import paper_1105_5331_amd as cpng
+    dims, R = (24, 20, 16), 4
+    print(f"case captured replay prec={prec}", flush=True)
+    p = test_problem_1(dims, R, 0.9, 1, 1, seed=21, dtype=np.float64 if prec == "fp64" else np.float32)
+    u0 = initial_guess(dims, R, seed=10021)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    eager = _run_state(cpng, h, Tg, R, u0, 30, prec, torch.cuda.default_stream())
+    side = torch.cuda.Stream()
+    graph = _run_state(cpng, h, Tg, R, u0, 30, prec, side)
+    keys = ("f", "rho", "beta", "nfev", "m", "restart", "ls_status")
+    for k, (a, b) in enumerate(zip(eager[0], graph[0])):
+        for key in keys:
+            va, vb = a[key], b[key]
+            same = (va == vb) or (isinstance(va, float) and np.isnan(va) and np.isnan(vb))
+            assert same, f"iteration {k} {key}: eager {va} vs replayed {vb}"
+    assert np.array_equal(eager[1], graph[1]) and np.array_equal(eager[2], graph[2])
+    assert eager[3] == graph[3] and eager[4] == graph[4]
+
+
+def test_captured_replay_matches_eager_sparse(h):
+    import paper_1105_5331_amd as cpng
+    tp = test_problem_2(2, 4)
+    dims, R = tp.dims, 3
+    print("case captured replay sparse", flush=True)
+    u0 = initial_guess(dims, R, seed=10031)
+    Tg = cpng.Tensor(dims, _dev(tp.values), coords=_dev(tp.coords.astype(np.int32)))
+    cpng.cp_tensor_prepare(h, Tg)
+    eager = _run_state(cpng, h, Tg, R, u0, 20, "fp64", torch.cuda.default_stream())
+    graph = _run_state(cpng, h, Tg, R, u0, 20, "fp64", torch.cuda.Stream())
+    for k, (a, b) in enumerate(zip(eager[0], graph[0])):
+        assert a["f"] == b["f"] and a["rho"] == b["rho"] and a["nfev"] == b["nfev"], k
+    assert np.array_equal(eager[1], graph[1])
