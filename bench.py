@@ -33,6 +33,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# rocprofv3 HBM counters of the default workload's dense MTTKRP, with the
+# hash of the kernel sources they were taken on
+COUNTER_SUMMARY = "profiles/dense_mttkrp_bf16x3_128x4_R32_hbm_counters.txt"
+KERNEL_SOURCES = ("paper_1105_5331_amd/csrc/dense_fast.hip", "paper_1105_5331_amd/csrc/splitk.hpp",
+                  "paper_1105_5331_amd/csrc/dense_mttkrp.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    hs = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            hs.update(fh.read())
+    return hs.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per dense MTTKRP launch (FETCH_SIZE + WRITE_SIZE, calibrated
+    on a copy of known size) from the committed counter summary, or None if
+    the counters were taken on other kernel sources."""
+    try:
+        with open(os.path.join(ROOT, COUNTER_SUMMARY)) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in lines
+                if l.startswith(("kernel_source_sha256: ", "traffic_bytes_per_launch: ")))
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def log(msg):
@@ -65,32 +95,66 @@ def cpu_baseline(T, A, budget_s=12.0):
                       f"float64 arithmetic) of the same tensor, {dt:.2f} s"}
 
 
-def time_to_grad(h, cpng, torch, seed=0):
+def time_to_grad(h, cpng, torch, seeds=(0, 1, 2, 3, 4), taus=(1e-3, 1e-4, 1e-5, 1e-6)):
+    """Dense 200^3, R = 10, congruence 0.9, noise 1%+1%: wall time of
+    cp_decompose to rho = ||g||/||T|| <= 1e-8 (the final rho always from a
+    float64-accumulated gradient).  fp64: float64 tensor, everything float64.
+    Mixed: the float32 tensor, FP32 or BF16x3 bulk until rho <= tau (or a
+    stalled line search once rho <= 1e-2), then float32 values with float64
+    accumulation, window restarted.  Equal accuracy: both converged and
+    |h_mixed - h_fp64| <= 1e-10 with h = sqrt(2f)/||T||."""
     from workloads import initial_guess, test_problem_1
     dims, R, tol = (200, 200, 200), 10, 1e-8
-    p = test_problem_1(dims, R, 0.9, 1, 1, seed=seed, dtype=np.float32)
-    T32 = torch.from_numpy(p.T).cuda().reshape(-1)
-    T64 = T32.double()
-    u0 = initial_guess(dims, R, seed=seed + 10000)
-    out = {}
-    for name, Tv, kw in [
-        ("fp64", T64, dict(precision="fp64")),
-        ("mixed_fp32", T32, dict(precision="fp32", final_precision="fp32in_fp64acc", switch_rho=1e-6)),
-        ("mixed_bf16x3", T32, dict(precision="bf16x3", final_precision="fp32in_fp64acc", switch_rho=1e-6)),
-    ]:
-        Tg = cpng.Tensor(dims, Tv)
-        cpng.cp_tensor_prepare(h, Tg)
-        u = torch.from_numpy(u0).cuda()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = cpng.cp_decompose(h, Tg, R, tol, u, max_iter=3000, **kw)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        hval = float(np.sqrt(max(0.0, 2 * r["f"]) / Tg.norm_sq))
-        out[name] = {"seconds": round(dt, 4), "iters": r["iters"], "rho": r["rho"], "h": hval,
-                     "converged": r["converged"], "n_fg": r["n_fg"], "switch_iter": r["switch_iter"]}
-        log(f"time_to_grad {name}: {dt:.3f} s, {r['iters']} it, rho {r['rho']:.2e}, h {hval:.12f}")
-    return out
+    per_seed = []
+    for seed in seeds:
+        p = test_problem_1(dims, R, 0.9, 1, 1, seed=seed, dtype=np.float32)
+        T32 = torch.from_numpy(p.T).cuda().reshape(-1)
+        T64 = T32.double()
+        u0 = initial_guess(dims, R, seed=seed + 10000)
+        Tg32, Tg64 = cpng.Tensor(dims, T32), cpng.Tensor(dims, T64)
+        cpng.cp_tensor_prepare(h, Tg32)
+        cpng.cp_tensor_prepare(h, Tg64)
+        variants = [("fp64", Tg64, dict(precision="fp64"))]
+        for bulk in ("fp32", "bf16x3"):
+            for tau in taus:
+                variants.append((f"{bulk}_sw{tau:g}", Tg32,
+                                 dict(precision=bulk, final_precision="fp32in_fp64acc", switch_rho=tau)))
+        if seed == seeds[0]:   # first launches, graph instantiation
+            for _, Tg, kw in variants[:2] + variants[5:6]:
+                cpng.cp_decompose(h, Tg, R, tol, torch.from_numpy(u0).cuda(), max_iter=5, **kw)
+        runs = {}
+        for name, Tg, kw in variants:
+            u = torch.from_numpy(u0).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = cpng.cp_decompose(h, Tg, R, tol, u, max_iter=3000, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            runs[name] = {"seconds": round(dt, 4), "iters": r["iters"], "rho": r["rho"],
+                          "h": float(np.sqrt(max(0.0, 2 * r["f"]) / Tg.norm_sq)),
+                          "converged": bool(r["converged"]), "n_fg": r["n_fg"],
+                          "switch_iter": r["switch_iter"]}
+        ref = runs["fp64"]
+        for name, v in runs.items():
+            v["equal_accuracy"] = bool(v["converged"] and ref["converged"]
+                                       and abs(v["h"] - ref["h"]) <= 1e-10)
+            v["speedup_vs_fp64"] = round(ref["seconds"] / v["seconds"], 3)
+        log(f"time_to_grad seed {seed}: " + ", ".join(
+            f"{k} {v['seconds']:.3f}s/{v['iters']}it{'' if v['equal_accuracy'] else '(!)'}"
+            for k, v in runs.items()))
+        per_seed.append({"seed": seed, "runs": runs})
+    summary = {}
+    for name in per_seed[0]["runs"]:
+        sp = [s["runs"][name]["speedup_vs_fp64"] for s in per_seed]
+        eq = sum(s["runs"][name]["equal_accuracy"] for s in per_seed)
+        tot = sum(s["runs"][name]["seconds"] for s in per_seed)
+        summary[name] = {"median_speedup_vs_fp64": float(np.median(sp)),
+                         "total_seconds": round(tot, 3), "equal_accuracy_seeds": eq}
+    best = max((k for k in summary if k != "fp64"),
+               key=lambda k: (summary[k]["equal_accuracy_seeds"], summary[k]["median_speedup_vs_fp64"]))
+    return {"workload": "dense 200^3 float32 Test Problem I, R=10, congruence 0.9, noise 1%+1%, "
+                        "tol 1e-8, seeds " + ",".join(map(str, seeds)),
+            "summary": summary, "best_mixed": best, "per_seed": per_seed}
 
 
 def sparse_mttkrp(h, cpng, torch, nnz_draw=20_000_000, R=16, reps=10):
@@ -134,50 +198,62 @@ def sparse_mttkrp(h, cpng, torch, nnz_draw=20_000_000, R=16, reps=10):
     return {"nnz": int(nnz), "rank": R, "prepare_s": round(prep, 3), "modes": per_mode}
 
 
-def serving(cpng, torch, n=48, rate=None, slots_list=(4, 1), seed=7, max_iter=500):
-    """Poisson stream of decomposition requests (dense 3-/4-way float32, mode
-    sizes U{16..160}, R U{2..24}, congruence U[0, 0.9], noise 1%+1%,
-    tol 1e-8) through the continuous-batching server; p50/p99 latency from
-    submission to result, solves/s, for several slot counts."""
+def _serve(cpng, torch, data, slots, rate, max_iter):
+    srv = cpng.Server(0, slots=slots, max_iter=max_iter, precision="bf16x3",
+                      final_precision="fp32in_fp64acc", switch_rho=1e-4)
+    t0 = time.perf_counter()
+    got = []
+    keep = []
+    for r, T, u0 in data:
+        if rate:
+            delay = r.arrival / rate - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+        u = u0.clone()
+        keep.append((T, u))
+        srv.submit(cpng.Tensor(r.dims, T), r.R, 1e-8, u, tag=r.rid)
+        got += srv.poll(0)
+    while len(got) < len(data):
+        got += srv.poll(wait_for=len(data) - len(got))
+    span = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([g["t_end"] - g["t_submit"] for g in got])
+    conv = sum(1 for g in got if g["converged"])
+    return {"slots": slots, "rate_per_s": round(rate, 3) if rate else None, "requests": len(got),
+            "p50_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_s": round(float(np.percentile(lat, 99)), 4),
+            "solves_per_s": round(len(got) / span, 3), "makespan_s": round(span, 3),
+            "converged": conv, "not_converged": len(got) - conv,
+            "errors": sum(1 for g in got if g["status"] < 0)}
+
+
+def serving(cpng, torch, n=64, slots=4, seed=7, max_iter=500, loads=(0.5, 0.8)):
+    """Stream of decomposition requests (dense 3-/4-way float32, mode sizes
+    U{16..160}, R U{2..24}, congruence U[0, 0.9], noise 1%+1%, tol 1e-8)
+    through the continuous-batching server.  First the saturation throughput
+    (all requests queued at t = 0, `slots` concurrent decompositions); then
+    Poisson arrivals at the given fractions of it, with `slots` concurrent
+    decompositions and one at a time; p50/p99 latency from arrival to result."""
     from workloads import initial_guess, serving_stream, test_problem_1_torch
-    reqs = serving_stream(n, rate_per_s=rate or 1e9, seed=seed)
+    reqs = serving_stream(n, rate_per_s=1.0, seed=seed)   # arrival times for rate 1
     data = []
     for r in reqs:
         T = test_problem_1_torch(r.dims, r.R, r.c, 1, 1, seed=r.seed)
         u0 = torch.from_numpy(initial_guess(r.dims, r.R, seed=r.seed + 10000)).cuda()
         data.append((r, T, u0))
     torch.cuda.synchronize()
-    out = {}
-    for slots in slots_list:
-        srv = cpng.Server(0, slots=slots, max_iter=max_iter, precision="bf16x3",
-                          final_precision="fp32in_fp64acc", switch_rho=1e-4)
-        us = {}
-        t0 = time.perf_counter()
-        got = []
-        for r, T, u0 in data:
-            if rate:
-                delay = r.arrival - (time.perf_counter() - t0)
-                if delay > 0:
-                    time.sleep(delay)
-            u = u0.clone()
-            us[r.rid] = u
-            srv.submit(cpng.Tensor(r.dims, T), r.R, 1e-8, u, tag=r.rid)
-            got += srv.poll(0)
-        while len(got) < len(data):
-            got += srv.poll(wait_for=len(data) - len(got))
-        span = time.perf_counter() - t0
-        srv.close()
-        lat = np.array([g["t_end"] - g["t_submit"] for g in got])
-        conv = sum(1 for g in got if g["converged"])
-        out[f"slots{slots}"] = {
-            "requests": len(got), "p50_s": round(float(np.percentile(lat, 50)), 4),
-            "p99_s": round(float(np.percentile(lat, 99)), 4),
-            "solves_per_s": round(len(got) / span, 3), "makespan_s": round(span, 3),
-            "converged": conv, "not_converged": len(got) - conv,
-            "errors": sum(1 for g in got if g["status"] < 0)}
-        log(f"serving slots={slots}: {out[f'slots{slots}']}")
-    return {"load": f"{n} requests, Poisson rate {rate if rate else 'inf (all queued at t=0)'} /s",
-            **out}
+    _serve(cpng, torch, data[:8], slots, None, max_iter)   # first launches
+    sat = _serve(cpng, torch, data, slots, None, max_iter)
+    log(f"serving saturation: {sat}")
+    out = {"saturation": sat}
+    mu = sat["solves_per_s"]
+    for frac in loads:
+        for sl in (slots, 1):
+            res = _serve(cpng, torch, data, sl, frac * mu, max_iter)
+            log(f"serving load {frac} slots {sl}: {res}")
+            out[f"load{frac:g}_slots{sl}"] = res
+    return {"load": f"{n} requests; Poisson arrivals at {', '.join(f'{x:g}' for x in loads)} x "
+                    f"the saturation rate of {slots} slots", **out}
 
 
 def main():
@@ -192,7 +268,8 @@ def main():
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--serving", type=int, default=0, metavar="N",
                     help="only run the serving benchmark with N requests")
-    ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate for --serving")
+    ap.add_argument("--part", choices=["sparse", "ttg"], default=None,
+                    help="only run one extra study (for profiling it)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -209,8 +286,17 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     if args.serving:
-        res = serving(cpng, torch, n=args.serving, rate=args.rate or None)
+        res = serving(cpng, torch, n=args.serving)
         print(json.dumps({"metric": "serving p50/p99 latency and solves/s", **res}), flush=True)
+        return
+    if args.part:
+        h = cpng.Handle(0)
+        if args.part == "sparse":
+            res = sparse_mttkrp(h, cpng, torch)
+        else:
+            res = time_to_grad(h, cpng, torch, seeds=(0,), taus=(1e-4,))
+        h.close()
+        print(json.dumps({"part": args.part, **res}), flush=True)
         return
     if args.copy_reference:
         # A plain copy of known size: reads and writes exactly 1 GiB, so the
@@ -277,7 +363,8 @@ def main():
                    "dims": list(dims), "rank": R, "precision": args.precision,
                    "mttkrp_passes": passes},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": counter_traffic() if (args.precision, s, R) == ("bf16x3", 128, 32) else None,
                      "kernel": "dense MTTKRP", "launches": launches,
                      "avg_us": round(avg_ms * 1e3, 2), "bytes_per_launch": traffic},
     }
@@ -289,6 +376,8 @@ def main():
         res["extra"] = {"time_to_grad_200cubed_R10": time_to_grad(h, cpng, torch)}
         log("sparse MTTKRP (20000^3, ~2e7 nonzeros, R=16)")
         res["extra"]["sparse_mttkrp_20000cubed_R16"] = sparse_mttkrp(h, cpng, torch)
+        log("serving stream (32 requests)")
+        res["extra"]["serving"] = serving(cpng, torch, n=32)
     if not args.skip_cpu:
         log("cpu baseline (oracle)")
         A = [np.ascontiguousarray(x) for x in
