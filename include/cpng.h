@@ -134,6 +134,10 @@ typedef struct cp_options {
   int32_t normalize_accel;  /* normalise the accelerated iterate (1) */
   cp_iter_info* trace;      /* host, nullable: per-iteration records */
   int32_t trace_cap;        /* capacity of trace */
+  int32_t mttkrp_tree;      /* dense tensors of order >= 3, bulk not BF16X3: form
+                               Y = T x_N A^(N) once per gradient evaluation and per ALS
+                               sweep and take M^(1..N-1) from Y, so T is streamed twice
+                               instead of N times (1); 0 = one pass per mode */
 } cp_options;
 
 typedef struct cp_report {

@@ -52,7 +52,7 @@ class cp_options(C.Structure):
                 ("ls_stpmax", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
                 ("final_precision", C.c_int32), ("switch_rho", C.c_double),
                 ("normalize_accel", C.c_int32), ("trace", C.POINTER(cp_iter_info)),
-                ("trace_cap", C.c_int32)]
+                ("trace_cap", C.c_int32), ("mttkrp_tree", C.c_int32)]
 
 
 class cp_report(C.Structure):

@@ -37,6 +37,7 @@ struct cp_handle {
   cpng::DevBuf carry;    // sparse segment carries
   cpng::DevBuf tmpu;     // scratch iterate-sized vectors
   cpng::DevBuf otab;     // per-launch outer-index tables of the streaming MTTKRP
+  cpng::DevBuf ybuf;     // T contracted with the last factor (two-level evaluation)
   uint64_t gen = 0;           // bumped whenever a workspace slice is reallocated
   double* pinned = nullptr;   // host pinned readback area (64 doubles)
   int* flags = nullptr;       // device status word (ALS solve fallbacks)
@@ -134,6 +135,13 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
 template <typename TT, typename CT>
 int dense_fast_vec(cp_handle* h, const TT* T, const CT* fac, const Shape& s, int R, int mode,
                    double* M, hipStream_t st);
+
+// two-level evaluation of all modes (tree.hip)
+bool tree_applies(const cp_tensor* T, const Shape& s, int prec);
+int tree_contract_last(cp_handle* h, const cp_tensor* T, const Shape& s, const void* fac, int R,
+                       int prec, void* Y, hipStream_t st);
+int tree_mode(cp_handle* h, const Shape& s, const void* Y, const void* fac, int R, int mode,
+              int prec, double* M, hipStream_t st);
 
 // small kernels
 int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, double* Gbar,

@@ -105,14 +105,47 @@ int scratch(cp_handle* h, const Shape& s, int R, hipStream_t st, Scratch* sc) {
   return CP_OK;
 }
 
+// Factors as the kernels of precision `prec` read them: the float64 iterate,
+// or its float32 copy (refreshed by this call).
+int kernel_factors(cp_handle* h, const Shape& s, const double* u, int R, int prec,
+                   const void** fac, hipStream_t st) {
+  if (prec == CP_PREC_FP32) {
+    float* f32 = nullptr;
+    CP_TRY(stage_factors_f32(h, u, s.sum_dims() * R, &f32, st));
+    *fac = f32;
+  } else {
+    *fac = u;
+  }
+  return CP_OK;
+}
+
+// Y = T contracted with the last factor (two-level evaluation, `tree.hip`).
+int tree_start(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R, int prec,
+               const void** fac, void** Y, hipStream_t st) {
+  const size_t eb = prec == CP_PREC_FP32 ? 4 : 8;
+  CP_TRY(ensure(h, h->ybuf, eb * (size_t)(s.total() / s.dims[s.N - 1]) * R, st));
+  *Y = h->ybuf.ptr;
+  CP_TRY(kernel_factors(h, s, u, R, prec, fac, st));
+  return tree_contract_last(h, T, s, *fac, R, prec, *Y, st);
+}
+
+// f and g at u: all N MTTKRPs at the same point (Section 2.3), the gradient
+// epilogue G^(n) = -M^(n) + A^(n) Gammabar^(n) and the objective from the
+// last mode's M and Gamma.  With `tree` (dense, order >= 3, not BF16x3) the
+// first N-1 MTTKRPs come from the contracted Y: T is streamed twice.
 int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
-                        int prec, double* f_out, double* g_out, hipStream_t st) {
+                        int prec, double* f_out, double* g_out, hipStream_t st, bool tree = true) {
   Scratch sc;
   CP_TRY(scratch(h, s, R, st, &sc));
   CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, sc.Gam, st));
+  const bool use_tree = tree && tree_applies(T, s, prec);
+  const void* fac = nullptr;
+  void* Y = nullptr;
+  if (use_tree) CP_TRY(tree_start(h, T, s, u, R, prec, &fac, &Y, st));
   for (int n = 0; n < s.N; ++n) {
     double* Mn = sc.M + s.off[n] * R;
-    CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
+    if (use_tree && n < s.N - 1) CP_TRY(tree_mode(h, s, Y, fac, R, n, prec, Mn, st));
+    else CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
     if (g_out)
       CP_TRY(grad_epilogue(h, Mn, u + s.off[n] * R, sc.Gbar + n * R * R, s.dims[n], R,
                            g_out + s.off[n] * R, st));
@@ -125,14 +158,26 @@ int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const 
   return CP_OK;
 }
 
+// One ALS sweep (Section 2.3): for n = 1..N in order, A^(n) = M^(n) Gammabar^(n)^-1
+// with the factors updated so far.  With `tree`, Y is formed once with A^(N)
+// (untouched until the last mode) and M^(1..N-1) come from it.
 int als_sweep_impl(cp_handle* h, const cp_tensor* T, const Shape& s, double* u, int R, int prec,
-                   int normalize_after, hipStream_t st) {
+                   int normalize_after, hipStream_t st, bool tree = true) {
   Scratch sc;
   CP_TRY(scratch(h, s, R, st, &sc));
+  const bool use_tree = tree && tree_applies(T, s, prec);
+  const void* fac = nullptr;
+  void* Y = nullptr;
+  if (use_tree) CP_TRY(tree_start(h, T, s, u, R, prec, &fac, &Y, st));
   for (int n = 0; n < s.N; ++n) {
     CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, nullptr, st));
     double* Mn = sc.M + s.off[n] * R;
-    CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
+    if (use_tree && n < s.N - 1) {
+      if (n > 0) CP_TRY(kernel_factors(h, s, u, R, prec, &fac, st));   // after the update
+      CP_TRY(tree_mode(h, s, Y, fac, R, n, prec, Mn, st));
+    } else {
+      CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
+    }
     CP_TRY(mode_solve(h, Mn, sc.Gbar + n * R * R, s.dims[n], R, u + s.off[n] * R, st));
   }
   if (normalize_after) CP_TRY(normalize(h, s, u, R, nullptr, st));
@@ -224,8 +269,9 @@ enum { PHASE_STEP12 = 0, PHASE_EVAL = 1 };
 int enqueue_step12(cp_handle* h, cp_ngmres_state* S) {
   CP_HIP(h, hipMemcpyAsync(S->dpar, S->hpar, sizeof(StepPar), hipMemcpyHostToDevice, S->st));
   CP_HIP(h, hipMemcpyAsync(S->ubar, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
-  CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st));
-  CP_TRY(objective_grad_impl(h, S->T, S->s, S->ubar, S->R, S->prec, S->scal, S->gbar, S->st));
+  CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0));
+  CP_TRY(objective_grad_impl(h, S->T, S->s, S->ubar, S->R, S->prec, S->scal, S->gbar, S->st,
+                             S->opt.mttkrp_tree != 0));
   CP_TRY(step2(h, S->L, S->winU, S->winG, S->wcap, S->dpar, S->ubar, S->gbar, S->opt.eps,
                S->uhat, S->scal + 8, S->st));
   if (S->opt.normalize_accel) CP_TRY(normalize(h, S->s, S->uhat, S->R, nullptr, S->st));
@@ -239,7 +285,8 @@ int enqueue_step12(cp_handle* h, cp_ngmres_state* S) {
 int enqueue_eval(cp_handle* h, cp_ngmres_state* S) {
   CP_HIP(h, hipMemcpyAsync(S->dpar, S->hpar, sizeof(StepPar), hipMemcpyHostToDevice, S->st));
   CP_TRY(axpy_par(h, S->ubar, S->dpar, S->d, S->ut, S->L, S->st));
-  CP_TRY(objective_grad_impl(h, S->T, S->s, S->ut, S->R, S->prec, S->scal, S->gt, S->st));
+  CP_TRY(objective_grad_impl(h, S->T, S->s, S->ut, S->R, S->prec, S->scal, S->gt, S->st,
+                             S->opt.mttkrp_tree != 0));
   CP_TRY(dot(h, S->gt, S->d, S->L, S->scal + 1, S->st));
   return CP_OK;
 }
@@ -410,7 +457,8 @@ int window_push(cp_handle* h, cp_ngmres_state* S) {
 }
 
 int eval_current(cp_handle* h, cp_ngmres_state* S) {
-  CP_TRY(objective_grad_impl(h, S->T, S->s, S->u, S->R, S->prec, S->scal, S->g, S->st));
+  CP_TRY(objective_grad_impl(h, S->T, S->s, S->u, S->R, S->prec, S->scal, S->g, S->st,
+                             S->opt.mttkrp_tree != 0));
   S->n_fg++;
   CP_TRY(dot(h, S->g, S->g, S->L, S->scal + 1, S->st));
   double v[2];
@@ -447,6 +495,7 @@ void cp_options_default(cp_options* o) {
   o->normalize_accel = 1;
   o->trace = nullptr;
   o->trace_cap = 0;
+  o->mttkrp_tree = 1;
 }
 
 int cp_create(int device, size_t workspace_bytes, cp_handle** out) {
@@ -477,7 +526,7 @@ int cp_destroy(cp_handle* h) {
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
   DevBuf* bufs[] = {&h->part, &h->stage, &h->mbuf, &h->small, &h->red, &h->carry, &h->tmpu,
-                    &h->otab};
+                    &h->otab, &h->ybuf};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   if (h->pinned) (void)hipHostFree(h->pinned);
@@ -760,7 +809,7 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
   rec.precision = S->prec;
   int rc = CP_OK;
   if (S->opt.method == CP_METHOD_ALS) {
-    CP_TRY(als_sweep_impl(h, S->T, S->s, S->u, S->R, S->prec, 1, S->st));
+    CP_TRY(als_sweep_impl(h, S->T, S->s, S->u, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0));
     CP_TRY(eval_current(h, S));
   } else {
     // Steps I and II: u_bar = M(u_i); f, g at u_bar; u_hat over the window

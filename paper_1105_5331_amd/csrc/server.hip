@@ -74,7 +74,11 @@ size_t request_footprint(const cp_tensor& T, int R, int window) {
   const size_t state = sizeof(double) * L * (9 + 2 * (size_t)window);
   const size_t work = sizeof(double) * (3 * L + 4096) + 2048 * (size_t)maxd * 32 * 8 +
                       ((size_t)64 << 20);
-  return tensor + state + work;
+  // T contracted with its last factor (dense, two-level evaluation)
+  const size_t ybuf = T.sparse || T.order < 3
+                          ? 0
+                          : sizeof(double) * (size_t)(total / T.dims[T.order - 1]) * R;
+  return tensor + state + work + ybuf;
 }
 
 void worker_main(cp_server* s, int slot) {

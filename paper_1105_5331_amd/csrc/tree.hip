@@ -1,0 +1,321 @@
+// Two-level evaluation of all N MTTKRPs of a dense tensor at one point
+// (Section 2.3, M^(n) = T_(n) Phibar^(n) for every n), and the same split for
+// the ALS sweep.  The last mode is contracted once:
+//     Y(i_1..i_{N-1}, r) = sum_k T(i_1..i_{N-1}, k) A^(N)(k, r),
+// after which every M^(n), n < N, is an MTTKRP of the much smaller Y
+// (#T R / I_N entries) that is elementwise in r:
+//     M^(n)(i, r) = sum_{i_m, m != n, m < N} Y(.., i, .., r) prod_{m != n, m < N} A^(m)(i_m, r).
+// The last mode's M^(N) still needs one pass over T (the single-mode
+// kernels), so an objective/gradient evaluation or an ALS sweep streams T
+// twice instead of N times.  In the sweep, Y is formed with A^(N) before the
+// updates of modes 1..N-1, which do not change A^(N), so each M^(n) from Y
+// uses the factors exactly as the sequential update would.
+//
+//  * contract_last_kernel: 64 rows of T (as a rows x I_N matrix) per
+//    workgroup, inner chunks of 64 through LDS (transposed) with the factor
+//    chunk next to them, the next chunk's loads in flight while the current
+//    one is multiplied; lane = row, the four waves take every fourth k and
+//    are added in a fixed order at the end.  Y is complete per workgroup.
+//  * ymttkrp_kernel: thread (i, r) walks a contiguous range of the other
+//    indices (outer o, inner k) of Y for mode n, loads issued 8 at a time;
+//    ranges are split over workgroups and the slots added by the fixed-order
+//    split-K reduction.  No atomics anywhere: results are reproducible.
+#include "common.hpp"
+#include "splitk.hpp"
+
+#include <algorithm>
+
+namespace cpng {
+
+namespace {
+
+constexpr int kThr = 256;
+constexpr int kTB = 64;   // rows and inner chunk per tile
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+struct LastParams {
+  int64_t rows;    // prod_{m < N-1} I_m
+  int64_t K;       // I_{N-1}
+  int R;
+  int64_t qfoff;   // element offset of A^(N-1) in the factors
+  int vec_ok;      // rows start on 16-byte boundaries
+};
+
+template <typename TT, typename CT, int RB>
+__global__ __launch_bounds__(kThr) void contract_last_kernel(const TT* __restrict__ T,
+                                                             const CT* __restrict__ fac,
+                                                             LastParams p, CT* __restrict__ Y) {
+  constexpr int TB = kTB;
+  constexpr int TS = TB + 1;
+  constexpr int VE = 16 / sizeof(TT);
+  constexpr int NL = TB * TB / VE / kThr;
+  constexpr int NB = TB * RB / kThr;
+  static_assert(NB >= 1, "RB too small for the factor tile split");
+  __shared__ CT Ts[TB * TS];   // [k][row]
+  __shared__ CT Bs[TB * RB];   // [k][r]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int g = tid >> 6;
+  const int r0 = blockIdx.y * RB;
+  const int64_t row0 = (int64_t)blockIdx.x * TB;
+  const int nkc = (int)((p.K + TB - 1) / TB);
+
+  CT acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = CT(0);
+  TT v[NL][VE];
+  CT b[NB];
+
+  auto load_chunk = [&](int kc) {
+    const int64_t k0 = (int64_t)kc * TB;
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+      const int e = tid + t * kThr;
+      const int ii = e / (TB / VE), kk = (e % (TB / VE)) * VE;
+      const int64_t row = row0 + ii, k = k0 + kk;
+      if (p.vec_ok && row < p.rows && k + VE <= p.K) {
+        const TT* src = T + row * p.K + k;
+        if constexpr (VE == 4) {
+          const float4 x = *reinterpret_cast<const float4*>(src);
+          v[t][0] = x.x; v[t][1] = x.y; v[t][2] = x.z; v[t][3] = x.w;
+        } else {
+          const double2 x = *reinterpret_cast<const double2*>(src);
+          v[t][0] = x.x; v[t][1] = x.y;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < VE; ++q)
+          v[t][q] = (row < p.rows && k + q < p.K) ? T[row * p.K + k + q] : TT(0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const int e = tid + t * kThr;
+      const int kk = e / RB, rr = e - (e / RB) * RB;
+      const int64_t k = k0 + kk;
+      b[t] = (k < p.K && r0 + rr < p.R) ? fac[p.qfoff + k * p.R + r0 + rr] : CT(0);
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+      const int e = tid + t * kThr;
+      const int ii = e / (TB / VE), kk = (e % (TB / VE)) * VE;
+#pragma unroll
+      for (int q = 0; q < VE; ++q) Ts[(kk + q) * TS + ii] = (CT)v[t][q];
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) Bs[tid + t * kThr] = b[t];
+  };
+
+  load_chunk(0);
+  for (int kc = 0; kc < nkc; ++kc) {
+    __syncthreads();   // every wave is done with the previous chunk
+    store_chunk();
+    __syncthreads();
+    if (kc + 1 < nkc) load_chunk(kc + 1);
+    const int kv = (int)min<int64_t>(TB, p.K - (int64_t)kc * TB);
+    for (int kk = g; kk < kv; kk += 4) {
+      const CT x = Ts[kk * TS + lane];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) acc[r] = fma(x, Bs[kk * RB + r], acc[r]);
+    }
+  }
+  // fixed-order sum of the four waves: (0 + 2) + (1 + 3), then 0 + 1
+  __syncthreads();
+  CT* red = Ts;
+  if (g >= 2)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) red[((g - 2) * RB + r) * TS + lane] = acc[r];
+  __syncthreads();
+  if (g < 2)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] += red[(g * RB + r) * TS + lane];
+  __syncthreads();
+  if (g == 1)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) red[r * TS + lane] = acc[r];
+  __syncthreads();
+  if (g == 0) {
+    const int64_t row = row0 + lane;
+    if (row < p.rows) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r0 + r < p.R) Y[row * p.R + r0 + r] = acc[r] + red[r * TS + lane];
+    }
+  }
+}
+
+struct YParams {
+  int R;
+  int nlo, nhi;                      // modes of Y before / after the target mode
+  int64_t lodims[CP_MAX_ORDER];      // their sizes (in mode order)
+  int64_t hidims[CP_MAX_ORDER];
+  int64_t lofoff[CP_MAX_ORDER];      // their factors' element offsets
+  int64_t hifoff[CP_MAX_ORDER];
+  int64_t O, I, K;                   // prod lodims, target size, prod hidims
+  int64_t per;                       // (o, k) pairs per range
+};
+
+// prod over the nm modes of the multi-index x (last mode fastest) of
+// A^(m)(x_m, r).  Mode sizes fit in 32 bits.
+template <typename CT>
+__device__ inline CT idx_product(int64_t x, int nm, const int64_t* dims, const int64_t* foff,
+                                 const CT* __restrict__ fac, int R, int r) {
+  if (nm == 0) return CT(1);
+  if (nm == 1) return fac[foff[0] + x * R + r];
+  CT s = CT(1);
+  uint32_t xx = (uint32_t)x;
+  for (int m = nm - 1; m >= 0; --m) {
+    const uint32_t d = (uint32_t)dims[m];
+    const uint32_t q = xx / d;
+    s *= fac[foff[m] + (int64_t)(xx - q * d) * R + r];
+    xx = q;
+  }
+  return s;
+}
+
+// part[c][i * R + r] = sum over the c-th range of (o, k) pairs of
+// Y(o, i, k, r) P(o, r) Q(k, r), in range order (o major).
+template <typename CT>
+__global__ __launch_bounds__(kThr) void ymttkrp_kernel(const CT* __restrict__ Y,
+                                                       const CT* __restrict__ fac, YParams p,
+                                                       CT* __restrict__ part) {
+  const int64_t e = (int64_t)blockIdx.x * kThr + threadIdx.x;
+  if (e >= p.I * p.R) return;
+  const int64_t i = e / p.R;
+  const int r = (int)(e - i * p.R);
+  const int64_t f0 = (int64_t)blockIdx.y * p.per;
+  const int64_t f1 = min<int64_t>(p.O * p.K, f0 + p.per);
+  CT acc = CT(0);
+  if (p.K == 1) {   // target is Y's last mode: the pairs are the outer indices o
+    const CT* y = Y + i * p.R + r;
+    const int64_t ostep = p.I * p.R;
+    for (int64_t o = f0; o < f1; o += 8) {
+      CT yv[8], pv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const bool ok = o + j < f1;
+        yv[j] = ok ? y[(o + j) * ostep] : CT(0);
+        pv[j] = ok ? idx_product<CT>(o + j, p.nlo, p.lodims, p.lofoff, fac, p.R, r) : CT(0);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc = fma(yv[j], pv[j], acc);
+    }
+  } else {
+    int64_t f = f0;
+    while (f < f1) {
+      const int64_t o = f / p.K;
+      const int64_t k0 = f - o * p.K;
+      const int64_t k1 = min<int64_t>(p.K, k0 + (f1 - f));
+      const CT P = idx_product<CT>(o, p.nlo, p.lodims, p.lofoff, fac, p.R, r);
+      const CT* y = Y + ((o * p.I + i) * p.K) * p.R + r;
+      CT s = CT(0);
+      for (int64_t k = k0; k < k1; k += 8) {
+        CT yv[8], qv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const bool ok = k + j < k1;
+          yv[j] = ok ? y[(k + j) * p.R] : CT(0);
+          qv[j] = ok ? idx_product<CT>(k + j, p.nhi, p.hidims, p.hifoff, fac, p.R, r) : CT(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s = fma(yv[j], qv[j], s);
+      }
+      acc = fma(P, s, acc);
+      f += k1 - k0;
+    }
+  }
+  part[(int64_t)blockIdx.y * p.I * p.R + e] = acc;
+}
+
+template <typename TT, typename CT>
+int launch_contract_last(cp_handle* h, const TT* T, const CT* fac, const LastParams& p, CT* Y,
+                         hipStream_t st) {
+  const int RB = p.R <= 8 ? 8 : (p.R <= 16 ? 16 : 32);
+  const dim3 grid(nblk(p.rows, kTB), (unsigned)((p.R + RB - 1) / RB));
+  if (RB == 8) hipLaunchKernelGGL((contract_last_kernel<TT, CT, 8>), grid, dim3(kThr), 0, st, T, fac, p, Y);
+  else if (RB == 16) hipLaunchKernelGGL((contract_last_kernel<TT, CT, 16>), grid, dim3(kThr), 0, st, T, fac, p, Y);
+  else hipLaunchKernelGGL((contract_last_kernel<TT, CT, 32>), grid, dim3(kThr), 0, st, T, fac, p, Y);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+}  // namespace
+
+bool tree_applies(const cp_tensor* T, const Shape& s, int prec) {
+  return !T->sparse && s.N >= 3 && prec != CP_PREC_BF16X3 &&
+         !(prec == CP_PREC_FP32 && T->dtype != CP_F32);
+}
+
+int tree_contract_last(cp_handle* h, const cp_tensor* T, const Shape& s, const void* fac, int R,
+                       int prec, void* Y, hipStream_t st) {
+  LastParams p{};
+  p.K = s.dims[s.N - 1];
+  p.rows = s.total() / p.K;
+  p.R = R;
+  p.qfoff = s.off[s.N - 1] * R;
+  const size_t tb = T->dtype == CP_F32 ? 4 : 8;
+  p.vec_ok = (p.K * tb) % 16 == 0 && reinterpret_cast<uintptr_t>(T->values) % 16 == 0;
+  if (prec == CP_PREC_FP32)
+    return launch_contract_last<float, float>(h, static_cast<const float*>(T->values),
+                                              static_cast<const float*>(fac), p,
+                                              static_cast<float*>(Y), st);
+  if (T->dtype == CP_F32)
+    return launch_contract_last<float, double>(h, static_cast<const float*>(T->values),
+                                               static_cast<const double*>(fac), p,
+                                               static_cast<double*>(Y), st);
+  return launch_contract_last<double, double>(h, static_cast<const double*>(T->values),
+                                              static_cast<const double*>(fac), p,
+                                              static_cast<double*>(Y), st);
+}
+
+int tree_mode(cp_handle* h, const Shape& s, const void* Y, const void* fac, int R, int mode,
+              int prec, double* M, hipStream_t st) {
+  const int N1 = s.N - 1;   // modes of Y
+  YParams p{};
+  p.R = R;
+  p.O = 1;
+  p.K = 1;
+  for (int m = 0; m < N1; ++m) {
+    if (m < mode) {
+      p.lodims[p.nlo] = s.dims[m];
+      p.lofoff[p.nlo] = s.off[m] * R;
+      p.O *= s.dims[m];
+      p.nlo++;
+    } else if (m > mode) {
+      p.hidims[p.nhi] = s.dims[m];
+      p.hifoff[p.nhi] = s.off[m] * R;
+      p.K *= s.dims[m];
+      p.nhi++;
+    }
+  }
+  p.I = s.dims[mode];
+  const int64_t n_out = p.I * R;
+  const int64_t work = p.O * p.K;
+  // about 2^18 threads, at least 16 (o, k) pairs each, at most 32768 ranges
+  const int64_t want = std::min<int64_t>(32768, std::max<int64_t>(1, (int64_t(1) << 18) / n_out));
+  p.per = std::max<int64_t>(16, (work + want - 1) / want);
+  const int64_t nch = (work + p.per - 1) / p.per;
+  const dim3 grid(nblk(n_out, kThr), (unsigned)nch);
+  const size_t eb = prec == CP_PREC_FP32 ? 4 : 8;
+  CP_TRY(ensure(h, h->part, eb * (size_t)(nch * n_out), st));
+  if (prec == CP_PREC_FP32) {
+    float* part = static_cast<float*>(h->part.ptr);
+    hipLaunchKernelGGL(ymttkrp_kernel<float>, grid, dim3(kThr), 0, st,
+                       static_cast<const float*>(Y), static_cast<const float*>(fac), p, part);
+    CP_LAUNCH_CHECK(h);
+    launch_splitk_reduce(part, nch, n_out, M, st);
+  } else {
+    double* part = static_cast<double*>(h->part.ptr);
+    hipLaunchKernelGGL(ymttkrp_kernel<double>, grid, dim3(kThr), 0, st,
+                       static_cast<const double*>(Y), static_cast<const double*>(fac), p, part);
+    CP_LAUNCH_CHECK(h);
+    launch_splitk_reduce(part, nch, n_out, M, st);
+  }
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+}  // namespace cpng

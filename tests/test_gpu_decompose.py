@@ -60,19 +60,20 @@ def _compare(trace, ref_trace, half, what):
     return n
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_ngmres_trajectory_small_dense_fp64(h, seed):
-    """Dense 20x20x20, R = 3, c = 0.5, l1 = l2 = 1 (Table 1 row 1), FP64."""
+@pytest.mark.parametrize("seed,tree", [(0, 1), (1, 1), (2, 1), (0, 0)])
+def test_ngmres_trajectory_small_dense_fp64(h, seed, tree):
+    """Dense 20x20x20, R = 3, c = 0.5, l1 = l2 = 1 (Table 1 row 1), FP64; with
+    the two-level evaluation of the MTTKRPs (tree) and with one pass per mode."""
     import paper_1105_5331_amd as cpng
     dims, R, tol = (20, 20, 20), 3, 1e-8
-    print(f"case ngmres trajectory seed={seed}", flush=True)
+    print(f"case ngmres trajectory seed={seed} tree={tree}", flush=True)
     p = test_problem_1(dims, R, 0.5, 1, 1, seed=seed)
     u0 = initial_guess(dims, R, seed=seed + 10000)
     ref = ngmres(CPProblem(ocp.DenseTensor(p.T), R), u0, tol=tol, max_iter=300)
     Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
     cpng.cp_tensor_prepare(h, Tg)
     u = _dev(u0)
-    out = cpng.cp_decompose(h, Tg, R, tol, u, trace_cap=400, max_iter=300)
+    out = cpng.cp_decompose(h, Tg, R, tol, u, trace_cap=400, max_iter=300, mttkrp_tree=tree)
     half = 0.5 * np.sum(p.T ** 2)
     n = _compare(out["trace"], ref.trace, half, f"seed {seed}")
     assert n >= min(len(ref.trace), 5)

@@ -149,18 +149,26 @@ def test_normalize_zero_term(h):
 
 
 @pytest.mark.parametrize("dims,R,c", [((20, 20, 20), 3, 0.5), ((13, 30, 8, 5), 6, 0.9),
-                                      ((70, 9, 66), 10, 0.3)])
-def test_objective_grad_parity(h, dims, R, c):
+                                      ((70, 9, 66), 10, 0.3), ((5, 7, 6, 4, 3), 40, 0.5),
+                                      ((130, 3, 70), 64, 0.2), ((3, 90), 7, 0.4)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32in_fp64acc"])
+def test_objective_grad_parity(h, dims, R, c, prec):
+    """All N MTTKRPs at one point (dense order >= 3: last mode contracted once,
+    the others from the contracted tensor) and the gradient epilogue, float64
+    accumulation, against the oracle on the same (float64 or float32) tensor."""
     cpng = _cpng()
-    p = test_problem_1(dims, R, c, 1, 1, seed=3)
+    print(f"case objective_grad dims={dims} R={R} prec={prec}", flush=True)
+    dt = np.float64 if prec == "fp64" else np.float32
+    p = test_problem_1(dims, R, c, 1, 1, seed=3, dtype=dt)
+    T64 = p.T.astype(np.float64)
     Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
     cpng.cp_tensor_prepare(h, Tg)
-    half = 0.5 * np.sum(p.T ** 2)
+    half = 0.5 * np.sum(T64 ** 2)
     assert abs(Tg.norm_sq - 2 * half) <= 1e-12 * 2 * half
     A = _factors(dims, R, 11, scale=0.5)
-    f, g = cpng.cp_objective_grad(h, Tg, _dev(ocp.join_u(A)), R, "fp64")
-    fo = ocp.objective_direct(p.T, A)
-    go = ocp.join_u(ocp.gradient_from_mttkrps(A, [ocp.mttkrp(p.T, A, n) for n in range(len(dims))]))
+    f, g = cpng.cp_objective_grad(h, Tg, _dev(ocp.join_u(A)), R, prec)
+    fo = ocp.objective_direct(T64, A)
+    go = ocp.join_u(ocp.gradient_from_mttkrps(A, [ocp.mttkrp(T64, A, n) for n in range(len(dims))]))
     assert abs(f.item() - fo) <= 1e-12 * half
     assert np.linalg.norm(g.cpu().numpy() - go) <= 1e-12 * np.sqrt(2 * half)
 
@@ -184,16 +192,21 @@ def test_objective_grad_reduced_precision(h, prec, tol):
     assert np.linalg.norm(g.cpu().numpy() - go) / np.sqrt(2 * half) <= tol
 
 
-@pytest.mark.parametrize("dims,R,c", [((20, 20, 20), 3, 0.5), ((9, 14, 6, 11), 5, 0.9)])
-def test_als_sweep_parity(h, dims, R, c):
+@pytest.mark.parametrize("dims,R,c,prec", [((20, 20, 20), 3, 0.5, "fp64"), ((9, 14, 6, 11), 5, 0.9, "fp64"),
+                                           ((33, 70, 65), 12, 0.5, "fp32in_fp64acc"),
+                                           ((6, 5, 7, 4, 6), 36, 0.3, "fp64")])
+def test_als_sweep_parity(h, dims, R, c, prec):
+    """One ALS sweep (modes 1..N-1 from the tensor contracted with A^(N), the
+    last mode from its own pass) against the oracle's sequential sweep."""
     cpng = _cpng()
     from oracle.ngmres import CPProblem
-    p = test_problem_1(dims, R, c, 1, 1, seed=5)
+    print(f"case als_sweep dims={dims} R={R} prec={prec}", flush=True)
+    p = test_problem_1(dims, R, c, 1, 1, seed=5, dtype=np.float64 if prec == "fp64" else np.float32)
     Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
     A = _factors(dims, R, 13)
     u = _dev(ocp.join_u(A))
-    cpng.cp_als_sweep(h, Tg, u, R, "fp64", normalize=True)
-    prob = CPProblem(ocp.DenseTensor(p.T), R)
+    cpng.cp_als_sweep(h, Tg, u, R, prec, normalize=True)
+    prob = CPProblem(ocp.DenseTensor(p.T.astype(np.float64)), R)
     ref, flags = prob.als_sweep(ocp.join_u(A))
     assert flags == [0] * len(dims)
     np.testing.assert_allclose(u.cpu().numpy(), ref, rtol=1e-9, atol=1e-11)
