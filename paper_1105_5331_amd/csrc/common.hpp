@@ -18,6 +18,16 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// A gradient epilogue G(i, r) = -M(i, r) + sum_q A(i, q) Gbar(q, r) that the
+// next dense MTTKRP folds into its final reduction (set by the caller for one
+// call; `used` tells it whether the MTTKRP took it).
+struct GradEpi {
+  const double* A = nullptr;
+  const double* Gbar = nullptr;
+  double* G = nullptr;
+  bool used = false;
+};
+
 struct Status {
   int code = CP_OK;
   std::string msg;
@@ -39,6 +49,7 @@ struct cp_handle {
   cpng::DevBuf otab;     // per-launch outer-index tables of the streaming MTTKRP
   cpng::DevBuf ybuf;     // T contracted with the last factor (two-level evaluation)
   uint64_t gen = 0;           // bumped whenever a workspace slice is reallocated
+  cpng::GradEpi epi;          // pending gradient epilogue for the next dense MTTKRP
   double* pinned = nullptr;   // host pinned readback area (64 doubles)
   int* flags = nullptr;       // device status word (ALS solve fallbacks)
   // optional event timing of the main MTTKRP kernels
@@ -144,9 +155,12 @@ int tree_mode(cp_handle* h, const Shape& s, const void* Y, const void* fac, int 
               int prec, double* M, hipStream_t st);
 
 // small kernels
+// With factor_mode >= 0 also factorises Gammabar^(factor_mode) for the next
+// mode_solve(..., Gbar = nullptr, ...).
 int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, double* Gbar,
-             double* Gam, hipStream_t st);
+             double* Gam, hipStream_t st, int factor_mode = -1);
 int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStream_t st);
+// A = M Gbar^-1 (Gbar nullptr: use the factor gram_all formed).
 int mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int R, double* A,
                hipStream_t st);
 int grad_epilogue(cp_handle* h, const double* M, const double* A, const double* Gbar, int64_t I,
@@ -154,6 +168,10 @@ int grad_epilogue(cp_handle* h, const double* M, const double* A, const double* 
 // out[0] = sum x*y (fixed-order two-stage reduction), device result
 int dot(cp_handle* h, const double* x, const double* y, int64_t n, double* out, hipStream_t st);
 int sumsq_tensor(cp_handle* h, const void* v, int dtype, int64_t n, double* out, hipStream_t st);
+// f = 0.5*normsq - <A, M> + 0.5*sum(Gamma), the dot and the combination in
+// two launches
+int objective_from_dot(cp_handle* h, const double* A, const double* M, int64_t n, double normsq,
+                       const double* Gam, int R, double* f, hipStream_t st);
 // f = 0.5*normsq - dotAM + 0.5*sum(Gamma)
 int objective_combine(cp_handle* h, double normsq, const double* dotAM, const double* Gam, int R,
                       double* f, hipStream_t st);

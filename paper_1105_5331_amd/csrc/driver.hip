@@ -142,18 +142,29 @@ int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const 
   const void* fac = nullptr;
   void* Y = nullptr;
   if (use_tree) CP_TRY(tree_start(h, T, s, u, R, prec, &fac, &Y, st));
+  struct EpiScope {   // the pending epilogue never outlives one MTTKRP call
+    cp_handle* h;
+    ~EpiScope() { h->epi = GradEpi{}; }
+  };
   for (int n = 0; n < s.N; ++n) {
     double* Mn = sc.M + s.off[n] * R;
-    if (use_tree && n < s.N - 1) CP_TRY(tree_mode(h, s, Y, fac, R, n, prec, Mn, st));
-    else CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
-    if (g_out)
-      CP_TRY(grad_epilogue(h, Mn, u + s.off[n] * R, sc.Gbar + n * R * R, s.dims[n], R,
-                           g_out + s.off[n] * R, st));
+    const double* An = u + s.off[n] * R;
+    double* Gn = g_out ? g_out + s.off[n] * R : nullptr;
+    bool fused = false;
+    {
+      EpiScope scope{h};
+      if (Gn) h->epi = GradEpi{An, sc.Gbar + n * R * R, Gn, false};
+      if (use_tree && n < s.N - 1) CP_TRY(tree_mode(h, s, Y, fac, R, n, prec, Mn, st));
+      else CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
+      fused = h->epi.used;
+    }
+    if (Gn && !fused)
+      CP_TRY(grad_epilogue(h, Mn, An, sc.Gbar + n * R * R, s.dims[n], R, Gn, st));
   }
   if (f_out) {
     const int n = s.N - 1;
-    CP_TRY(dot(h, u + s.off[n] * R, sc.M + s.off[n] * R, s.dims[n] * R, sc.dot, st));
-    CP_TRY(objective_combine(h, T->norm_sq, sc.dot, sc.Gam, R, f_out, st));
+    CP_TRY(objective_from_dot(h, u + s.off[n] * R, sc.M + s.off[n] * R, s.dims[n] * R,
+                              T->norm_sq, sc.Gam, R, f_out, st));
   }
   return CP_OK;
 }
@@ -170,7 +181,7 @@ int als_sweep_impl(cp_handle* h, const cp_tensor* T, const Shape& s, double* u, 
   void* Y = nullptr;
   if (use_tree) CP_TRY(tree_start(h, T, s, u, R, prec, &fac, &Y, st));
   for (int n = 0; n < s.N; ++n) {
-    CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, nullptr, st));
+    CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, nullptr, st, n));   // and factorises Gbar^(n)
     double* Mn = sc.M + s.off[n] * R;
     if (use_tree && n < s.N - 1) {
       if (n > 0) CP_TRY(kernel_factors(h, s, u, R, prec, &fac, st));   // after the update
@@ -178,7 +189,7 @@ int als_sweep_impl(cp_handle* h, const cp_tensor* T, const Shape& s, double* u, 
     } else {
       CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
     }
-    CP_TRY(mode_solve(h, Mn, sc.Gbar + n * R * R, s.dims[n], R, u + s.off[n] * R, st));
+    CP_TRY(mode_solve(h, Mn, nullptr, s.dims[n], R, u + s.off[n] * R, st));
   }
   if (normalize_after) CP_TRY(normalize(h, s, u, R, nullptr, st));
   return CP_OK;

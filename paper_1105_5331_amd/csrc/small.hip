@@ -174,9 +174,15 @@ __global__ void gram_partial_kernel(const double* __restrict__ u, ModeTable t,
 
 // S^(k) = sum of that mode's chunk partials (chunk order); Gammabar^(n) and
 // Gamma as products over k in increasing order.
+__device__ void factor_block(const double* __restrict__ G, int R, double* __restrict__ F,
+                             int* __restrict__ kind, int* __restrict__ flags);
+
+// With fmode >= 0 the same block then factorises Gammabar^(fmode) for the
+// ALS mode solve (factor_block).
 __global__ void gram_final_kernel(const double* __restrict__ part, ModeTable t,
                                   double* __restrict__ S, double* __restrict__ Gbar,
-                                  double* __restrict__ Gam) {
+                                  double* __restrict__ Gam, int fmode, double* __restrict__ F,
+                                  int* __restrict__ kind, int* __restrict__ flags) {
   const int R = t.R;
   for (int pr = threadIdx.x; pr < R * R; pr += blockDim.x) {
     double sk[CP_MAX_ORDER];
@@ -199,6 +205,10 @@ __global__ void gram_final_kernel(const double* __restrict__ part, ModeTable t,
       for (int k = 0; k < t.N; ++k) g *= sk[k];
       Gam[pr] = g;
     }
+  }
+  if (fmode >= 0) {
+    __syncthreads();   // this block's Gammabar stores are visible to the block
+    factor_block(Gbar + (int64_t)fmode * R * R, R, F, kind, flags);
   }
 }
 
@@ -258,22 +268,28 @@ __global__ void norm_plan_kernel(const double* __restrict__ part, ModeTable t,
   }
 }
 
-// dst row j-th column = scale[k][perm[j]] * src[row][perm[j]] (u), or
-// src / scale for a gradient (scale 0 -> undivided).
-__global__ void norm_apply_kernel(const double* __restrict__ src, double* __restrict__ dst,
-                                  ModeTable t, const double* __restrict__ scales,
-                                  const int* __restrict__ perm, int gradient) {
+// In place, one thread per row (the row staged in LDS): x(row, j) =
+// scale[k][perm[j]] * x(row, perm[j]) (u), or x / scale for a gradient
+// (scale 0 -> undivided).
+__global__ __launch_bounds__(64) void norm_apply_rows_kernel(double* __restrict__ x, ModeTable t,
+                                                             const double* __restrict__ scales,
+                                                             const int* __restrict__ perm,
+                                                             int gradient) {
+  __shared__ double buf[64 * (kMaxR + 1)];
   const int R = t.R;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= t.off[t.N] * R) return;
-  const int64_t row = e / R;
-  const int j = (int)(e - row * R);
+  const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (row >= t.off[t.N]) return;
   int k = 0;
   while (row >= t.off[k + 1]) ++k;
-  const int r = perm[j];
-  const double s = scales[k * R + r];
-  const double x = src[row * R + r];
-  dst[e] = gradient ? (s != 0.0 ? x / s : x) : s * x;
+  double* b = buf + threadIdx.x * (kMaxR + 1);
+  double* xr = x + row * R;
+  for (int j = 0; j < R; ++j) b[j] = xr[j];
+  for (int j = 0; j < R; ++j) {
+    const int r = perm[j];
+    const double s = scales[k * R + r];
+    const double v = b[r];
+    xr[j] = gradient ? (s != 0.0 ? v / s : v) : s * v;
+  }
 }
 
 // ---- ALS mode solve -----------------------------------------------------------
@@ -305,8 +321,8 @@ __device__ bool chol_lds(double* a, int R, double* piv_ok) {
   return true;
 }
 
-__global__ void factor_kernel(const double* __restrict__ G, int R, double* __restrict__ F,
-                              int* __restrict__ kind, int* __restrict__ flags) {
+__device__ void factor_block(const double* __restrict__ G, int R, double* __restrict__ F,
+                             int* __restrict__ kind, int* __restrict__ flags) {
   __shared__ double a[kMaxR * kMaxR];
   __shared__ double v[kMaxR * kMaxR];
   __shared__ double ok;
@@ -415,7 +431,12 @@ __global__ void factor_kernel(const double* __restrict__ G, int R, double* __res
   }
 }
 
-// A(i,:) = M(i,:) Gammabar^-1 using the factor from factor_kernel.  One
+__global__ void factor_kernel(const double* __restrict__ G, int R, double* __restrict__ F,
+                              int* __restrict__ kind, int* __restrict__ flags) {
+  factor_block(G, R, F, kind, flags);
+}
+
+// A(i,:) = M(i,:) Gammabar^-1 using the factor from factor_block.  One
 // thread per row, its vector in LDS.
 __global__ __launch_bounds__(64) void solve_rows_kernel(const double* __restrict__ M,
                                                         const double* __restrict__ F,
@@ -526,6 +547,20 @@ __global__ void objective_kernel(double normsq, const double* __restrict__ dotAM
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) s += Gam[e];
   s = block_sum(s);
   if (threadIdx.x == 0) *f = 0.5 * normsq - *dotAM + 0.5 * s;
+}
+
+// f = 0.5 normsq - (sum of the dot partials) + 0.5 sum(Gamma): the two sums
+// exactly as sum_final_kernel and objective_kernel form them.
+__global__ void objective_final_kernel(const double* __restrict__ part, int nb, double normsq,
+                                       const double* __restrict__ Gam, int R,
+                                       double* __restrict__ f) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+  const double d = block_sum(s);
+  double sg = 0.0;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sg += Gam[e];
+  sg = block_sum(sg);
+  if (threadIdx.x == 0) *f = 0.5 * normsq - d + 0.5 * sg;
 }
 
 __global__ void axpy_kernel(const double* __restrict__ x, double a, const double* __restrict__ d,
@@ -731,16 +766,28 @@ static size_t small_layout(int N, int R) {
          sizeof(int) * (size_t)(R + 8);
 }
 
+// Location of the mode-solve factor (R x R) and its kind in the small slice.
+static int factor_slot(cp_handle* h, int R, double** F, int** kind, hipStream_t st) {
+  CP_TRY(ensure(h, h->small, small_layout(CP_MAX_ORDER, R) + sizeof(double) * R * R + 4096, st));
+  *F = static_cast<double*>(h->small.ptr) + small_layout(CP_MAX_ORDER, R) / sizeof(double);
+  *kind = reinterpret_cast<int*>(*F + R * R);
+  return CP_OK;
+}
+
 int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, double* Gbar,
-             double* Gam, hipStream_t st) {
+             double* Gam, hipStream_t st, int factor_mode) {
   if (R > kMaxR) return fail(h, CP_EINVAL, "rank %d above the supported %d", R, kMaxR);
   ModeTable t = table(s, R);
   const int64_t nch = t.coff[s.N];
+  double* F = nullptr;
+  int* kind = nullptr;
+  if (factor_mode >= 0) CP_TRY(factor_slot(h, R, &F, &kind, st));
   CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)(nch * R * R), st));
   double* part = static_cast<double*>(h->red.ptr);
   hipLaunchKernelGGL(gram_partial_kernel, dim3((unsigned)nch), dim3(256), 0, st, u, t, part);
   CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL(gram_final_kernel, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam);
+  hipLaunchKernelGGL(gram_final_kernel, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam,
+                     factor_mode, F, kind, h->flags);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
@@ -749,27 +796,23 @@ int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStre
   if (R > kMaxR) return fail(h, CP_EINVAL, "rank %d above the supported %d", R, kMaxR);
   ModeTable t = table(s, R);
   const int64_t nch = t.coff[s.N];
-  const int64_t L = s.sum_dims() * R;
   CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)(nch * R), st));
-  CP_TRY(ensure(h, h->tmpu, sizeof(double) * (size_t)L, st));
   CP_TRY(ensure(h, h->small, small_layout(s.N, R) + 4096, st));
   double* part = static_cast<double*>(h->red.ptr);
   double* scales = static_cast<double*>(h->small.ptr);
   int* perm = reinterpret_cast<int*>(scales + s.N * R);
-  double* tmp = static_cast<double*>(h->tmpu.ptr);
   hipLaunchKernelGGL(colsq_partial_kernel, dim3((unsigned)nch), dim3(256), 0, st, u, t, part);
   CP_LAUNCH_CHECK(h);
   hipLaunchKernelGGL(norm_plan_kernel, dim3(1), dim3(64), 0, st, part, t, scales, perm);
   CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL(norm_apply_kernel, dim3(nblk(L, 256)), dim3(256), 0, st, u, tmp, t, scales,
+  const int64_t rows = s.sum_dims();
+  hipLaunchKernelGGL(norm_apply_rows_kernel, dim3(nblk(rows, 64)), dim3(64), 0, st, u, t, scales,
                      perm, 0);
   CP_LAUNCH_CHECK(h);
-  CP_HIP(h, hipMemcpyAsync(u, tmp, sizeof(double) * L, hipMemcpyDeviceToDevice, st));
   if (g) {
-    hipLaunchKernelGGL(norm_apply_kernel, dim3(nblk(L, 256)), dim3(256), 0, st, g, tmp, t, scales,
+    hipLaunchKernelGGL(norm_apply_rows_kernel, dim3(nblk(rows, 64)), dim3(64), 0, st, g, t, scales,
                        perm, 1);
     CP_LAUNCH_CHECK(h);
-    CP_HIP(h, hipMemcpyAsync(g, tmp, sizeof(double) * L, hipMemcpyDeviceToDevice, st));
   }
   return CP_OK;
 }
@@ -777,11 +820,13 @@ int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStre
 int mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int R, double* A,
                hipStream_t st) {
   if (R > kMaxR) return fail(h, CP_EINVAL, "rank %d above the supported %d", R, kMaxR);
-  CP_TRY(ensure(h, h->small, small_layout(CP_MAX_ORDER, R) + sizeof(double) * R * R + 4096, st));
-  double* F = static_cast<double*>(h->small.ptr) + small_layout(CP_MAX_ORDER, R) / sizeof(double);
-  int* kind = reinterpret_cast<int*>(F + R * R);
-  hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(256), 0, st, Gbar, R, F, kind, h->flags);
-  CP_LAUNCH_CHECK(h);
+  double* F = nullptr;
+  int* kind = nullptr;
+  CP_TRY(factor_slot(h, R, &F, &kind, st));
+  if (Gbar) {   // else the factor was formed by gram_all(..., factor_mode)
+    hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(256), 0, st, Gbar, R, F, kind, h->flags);
+    CP_LAUNCH_CHECK(h);
+  }
   hipLaunchKernelGGL(solve_rows_kernel, dim3(nblk(I, 64)), dim3(64), 0, st, M, F, kind, I, R, A);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
@@ -806,6 +851,20 @@ int sumsq_tensor(cp_handle* h, const void* v, int dtype, int64_t n, double* out,
                                   out, st);
   return dot_impl<double, double>(h, static_cast<const double*>(v), static_cast<const double*>(v),
                                   n, out, st);
+}
+
+int objective_from_dot(cp_handle* h, const double* A, const double* M, int64_t n, double normsq,
+                       const double* Gam, int R, double* f, hipStream_t st) {
+  const int64_t per = std::max<int64_t>(256, ((n + kRedBlocks - 1) / kRedBlocks + 255) / 256 * 256);
+  const int nb = (int)std::max<int64_t>(1, (n + per - 1) / per);
+  CP_TRY(ensure(h, h->red, sizeof(double) * kRedBlocks, st));
+  double* part = static_cast<double*>(h->red.ptr);
+  hipLaunchKernelGGL((dot_partial_kernel<double, double>), dim3(nb), dim3(256), 0, st, A, M, n, per,
+                     part);
+  CP_LAUNCH_CHECK(h);
+  hipLaunchKernelGGL(objective_final_kernel, dim3(1), dim3(256), 0, st, part, nb, normsq, Gam, R, f);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
 }
 
 int objective_combine(cp_handle* h, double normsq, const double* dotAM, const double* Gam, int R,
