@@ -68,6 +68,8 @@ struct FastParams {
   int kpad;                          // LDS row length (bf16) of the staged inner factor
   int nks;                           // K steps of 32
   int vec_ok;                        // 16-byte loads along the unit-stride index are aligned
+  int64_t Opad;                      // O rounded up to 4
+  int ptrans;                        // P table rank-major (row-stream kernel) or o-major
 };
 
 __device__ inline void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
@@ -81,6 +83,10 @@ __device__ inline void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
 
 // Stage the inner factor, columns r0..r0+31: S[r][k] = A^(q)(k, r0 + r) split,
 // zero for r >= R and for k in [K, 32 * nks).
+// First inner index (within a 32-wide k-step) of lane group g's operand:
+// the MFMA operand of g is k = 8g..8g+7.
+__device__ inline int kload_a(int g) { return 8 * g; }
+
 __device__ inline void stage_inner(const float* __restrict__ fac, const FastParams& p, int r0,
                                    __bf16* Sh, __bf16* Sl) {
   const int kr = p.nks * 32;
@@ -124,38 +130,65 @@ constexpr int kOChunk = 64;   // outer indices per LDS table chunk (VALU kernel)
 // Outer-index tables of one launch: base offset of every outer index o and
 // the scales P(o, r) = prod_{outer modes m} A^(m)(i_m(o), r) for all r < R.
 // Computed once here instead of in every workgroup.
+// P table: o-major Pg[o * R + r] for the row and column kernels, which read
+// one o for many ranks; rank-major Pg[r * Opad + o] (zero for o >= O) for the
+// row-stream kernel, whose MFMA D lanes hold four consecutive o of one rank
+// (one 16-byte load).
 __global__ void outer_tables_kernel(const float* __restrict__ fac, FastParams p,
                                     float* __restrict__ Pg, int64_t* __restrict__ bg) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t o = e / (p.R + 1);
   const int c = (int)(e - o * (p.R + 1));
-  if (o >= p.O) return;
-  if (c == p.R) bg[o] = outer_base(p, o);
-  else Pg[o * p.R + c] = outer_scale(fac, p, o, c);
+  if (o >= p.Opad) return;
+  if (c == p.R) {
+    if (o < p.O) bg[o] = outer_base(p, o);
+  } else if (p.ptrans) {
+    Pg[c * p.Opad + o] = o < p.O ? outer_scale(fac, p, o, c) : 0.f;
+  } else if (o < p.O) {
+    Pg[o * p.R + c] = outer_scale(fac, p, o, c);
+  }
 }
 
+// P(o, r) from the o-major table (row and column kernels)
 __device__ inline float pscale(const float* __restrict__ Pg, const FastParams& p, int64_t o, int r) {
   return r < p.R ? Pg[o * p.R + r] : 0.f;
 }
 
-// Row-kernel operand: 8 consecutive k of rows (w*MT + mt)*16 + lr, zero outside.
+// P(o, r) from the rank-major table (row-stream kernel)
+__device__ inline float pscale_t(const float* __restrict__ Pg, const FastParams& p, int64_t o, int r) {
+  return r < p.R ? Pg[r * p.Opad + o] : 0.f;
+}
+
+// P(o..o+3, r) from the rank-major table, o a multiple of 4
+__device__ inline float4 pscale4(const float* __restrict__ Pg, const FastParams& p, int64_t o, int r) {
+  return r < p.R ? *reinterpret_cast<const float4*>(Pg + r * p.Opad + o) : float4{0.f, 0.f, 0.f, 0.f};
+}
+
+// One lane's 8 operand values of a row for the k-step starting at k0 (lane
+// group g = lane / 16), zero outside the row or K.
+// K is a multiple of 8, so each float4 is wholly inside or outside.
+__device__ inline void load_kstep(const float* __restrict__ row, bool ok, int64_t K, int k0, int g,
+                                  float (&v)[8]) {
+  const int k = k0 + kload_a(g);
+  if (ok && k < K) {
+    const float4 a = *reinterpret_cast<const float4*>(row + k);
+    const float4 b = *reinterpret_cast<const float4*>(row + k + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = 0.f;
+  }
+}
+
+// Row-kernel operand: the k-step at k0 of rows (w*MT + mt)*16 + lr.
 template <int MT>
 __device__ inline void load_rows(const float* __restrict__ T, const FastParams& p, int64_t base,
-                                 const int64_t (&rowoff)[MT], const bool (&rowok)[MT], int k,
+                                 const int64_t (&rowoff)[MT], const bool (&rowok)[MT], int k0,
                                  float (&v)[MT][8]) {
+  const int g = (threadIdx.x & 63) >> 4;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    if (rowok[mt] && k < p.K) {
-      const float* src = T + base + rowoff[mt] + k;
-      const float4 a = *reinterpret_cast<const float4*>(src);
-      const float4 b = *reinterpret_cast<const float4*>(src + 4);
-      v[mt][0] = a.x; v[mt][1] = a.y; v[mt][2] = a.z; v[mt][3] = a.w;
-      v[mt][4] = b.x; v[mt][5] = b.y; v[mt][6] = b.z; v[mt][7] = b.w;
-    } else {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[mt][q] = 0.f;
-    }
-  }
+  for (int mt = 0; mt < MT; ++mt) load_kstep(T + base + rowoff[mt], rowok[mt], p.K, k0, g, v[mt]);
 }
 
 // Row kernel: 4 waves x MT row tiles of 16 = 64*MT rows, 32 ranks.
@@ -204,7 +237,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
     int jl = 0, kl = 0;   // (outer, k-step) of the next load
 #pragma unroll
     for (int b = 0; b < PF; ++b) {
-      if (b < nit) load_rows<MT>(T, p, base_tab[jl], rowoff, rowok, kl * 32 + kb, buf[b]);
+      if (b < nit) load_rows<MT>(T, p, base_tab[jl], rowoff, rowok, kl * 32, buf[b]);
       if (++kl == p.nks) { kl = 0; ++jl; }
     }
     floatx4 Y[MT][2];
@@ -214,7 +247,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
       for (int nt = 0; nt < 2; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
     int j = 0, ks = 0;
     for (int it = 0; it < nit; ++it) {
-      if (it + PF < nit) load_rows<MT>(T, p, base_tab[jl], rowoff, rowok, kl * 32 + kb, buf[PF]);
+      if (it + PF < nit) load_rows<MT>(T, p, base_tab[jl], rowoff, rowok, kl * 32, buf[PF]);
       if (++kl == p.nks) { kl = 0; ++jl; }
       bf16x8 ah[MT], al[MT];
 #pragma unroll
@@ -277,8 +310,10 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
 // Column-kernel operand: rows k .. k+7 of columns (w*NT + nt)*16 + lr.
 template <int NT>
 __device__ inline void load_cols(const float* __restrict__ T, const FastParams& p, int64_t base,
-                                 const int64_t (&col)[NT], const bool (&colok)[NT], int k,
+                                 const int64_t (&col)[NT], const bool (&colok)[NT], int k0,
                                  float (&v)[NT][8]) {
+  // the lane group's 8 consecutive k-rows (K is a multiple of 8)
+  const int k = k0 + kload_a((threadIdx.x & 63) >> 4);
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     if (colok[nt] && k < p.K) {
@@ -338,7 +373,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
     int jl = 0, kl = 0;
 #pragma unroll
     for (int b = 0; b < PF; ++b) {
-      if (b < nit) load_cols<NT>(T, p, base_tab[jl], col, colok, kl * 32 + kb, buf[b]);
+      if (b < nit) load_cols<NT>(T, p, base_tab[jl], col, colok, kl * 32, buf[b]);
       if (++kl == p.nks) { kl = 0; ++jl; }
     }
     floatx4 Y[2][NT];
@@ -348,7 +383,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
       for (int nt = 0; nt < NT; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
     int j = 0, ks = 0;
     for (int it = 0; it < nit; ++it) {
-      if (it + PF < nit) load_cols<NT>(T, p, base_tab[jl], col, colok, kl * 32 + kb, buf[PF]);
+      if (it + PF < nit) load_cols<NT>(T, p, base_tab[jl], col, colok, kl * 32, buf[PF]);
       if (++kl == p.nks) { kl = 0; ++jl; }
       const int k = ks * 32 + kb;
       const int so0 = lr * p.kpad + k;
@@ -447,19 +482,8 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
     }
     float v[TW][8], vn[TW][8];
     auto load = [&](int ks, float (&dst)[TW][8]) {
-      const int k = ks * 32 + kb;
 #pragma unroll
-      for (int t = 0; t < TW; ++t) {
-        if (ok[t] && k < p.K) {
-          const float4 a = *reinterpret_cast<const float4*>(rowp[t] + k);
-          const float4 b = *reinterpret_cast<const float4*>(rowp[t] + k + 4);
-          dst[t][0] = a.x; dst[t][1] = a.y; dst[t][2] = a.z; dst[t][3] = a.w;
-          dst[t][4] = b.x; dst[t][5] = b.y; dst[t][6] = b.z; dst[t][7] = b.w;
-        } else {
-#pragma unroll
-          for (int q = 0; q < 8; ++q) dst[t][q] = 0.f;
-        }
-      }
+      for (int t = 0; t < TW; ++t) load_kstep(rowp[t], ok[t], p.K, ks * 32, lane >> 4, dst[t]);
     };
     load(0, v);
     floatx4 Y[TW][2];
@@ -490,17 +514,33 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[t][q] = vn[t][q];
     }
-    // D rows are outer indices og + t*16 + 4*(lane/16) + q; the column is the rank
+    // D rows are outer indices og + t*16 + 4*(lane/16) + q; the column is the
+    // rank.  og is a multiple of 4 (o_per_block is a multiple of 16).
 #pragma unroll
-    for (int t = 0; t < TW; ++t)
+    for (int t = 0; t < TW; ++t) {
+      const int64_t o4 = og + t * 16 + (lane >> 4) * 4;
+      if (o4 + 3 < oe) {
+        const float4 pa = pscale4(Pg, p, o4, r0 + lr);
+        const float4 pb = pscale4(Pg, p, o4, r0 + 16 + lr);
+        acc0 = fmaf(pa.x, Y[t][0][0], acc0);
+        acc0 = fmaf(pa.y, Y[t][0][1], acc0);
+        acc0 = fmaf(pa.z, Y[t][0][2], acc0);
+        acc0 = fmaf(pa.w, Y[t][0][3], acc0);
+        acc1 = fmaf(pb.x, Y[t][1][0], acc1);
+        acc1 = fmaf(pb.y, Y[t][1][1], acc1);
+        acc1 = fmaf(pb.z, Y[t][1][2], acc1);
+        acc1 = fmaf(pb.w, Y[t][1][3], acc1);
+      } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t o = og + t * 16 + (lane >> 4) * 4 + q;
-        if (o < oe) {
-          acc0 = fmaf(pscale(Pg, p, o, r0 + lr), Y[t][0][q], acc0);
-          acc1 = fmaf(pscale(Pg, p, o, r0 + 16 + lr), Y[t][1][q], acc1);
+        for (int q = 0; q < 4; ++q) {
+          const int64_t o = o4 + q;
+          if (o < oe) {
+            acc0 = fmaf(pscale_t(Pg, p, o, r0 + lr), Y[t][0][q], acc0);
+            acc1 = fmaf(pscale_t(Pg, p, o, r0 + 16 + lr), Y[t][1][q], acc1);
+          }
         }
       }
+    }
   }
   // sum the four lane groups (same rank column) in a fixed order, then the waves
   acc0 += __shfl_xor(acc0, 16);
@@ -737,24 +777,26 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   // elements per (left index, i): stream them one output row per workgroup.
   const bool stream_rows = rows && mode < N - 2 && (stride[mode] / K) >= 16;
   const int tile = stream_rows ? 1 : (p.I_n > 64 ? 128 : 64);
+  p.ptrans = stream_rows ? 1 : 0;
   const int64_t ychunks = (p.I_n + tile - 1) / tile;
   const int64_t rchunks = (R + 31) / 32;
   const int64_t target = CPNG_STREAM_BLOCKS;
   int64_t ks = std::max<int64_t>(1, std::min<int64_t>(p.O, (target + ychunks * rchunks - 1) / (ychunks * rchunks)));
-  p.o_per_block = (p.O + ks - 1) / ks;
+  p.o_per_block = ((p.O + ks - 1) / ks + 15) / 16 * 16;
   ks = (p.O + p.o_per_block - 1) / p.o_per_block;
+  p.Opad = (p.O + 3) / 4 * 4;
   const int64_t n_out = p.I_n * R;
   CP_TRY(ensure(h, h->part, sizeof(float) * (size_t)(ks * n_out), st));
   float* part = static_cast<float*>(h->part.ptr);
   dim3 grid((unsigned)ks, (unsigned)ychunks, (unsigned)rchunks);
   const size_t lds = 2 * sizeof(__bf16) * 32 * (size_t)p.kpad;
   // outer tables: P (O x R floats) then base offsets (O int64)
-  const size_t pbytes = (sizeof(float) * (size_t)(p.O * R) + 255) & ~size_t(255);
+  const size_t pbytes = (sizeof(float) * (size_t)(p.Opad * R) + 255) & ~size_t(255);
   CP_TRY(ensure(h, h->otab, pbytes + sizeof(int64_t) * (size_t)p.O, st));
   float* Pg = static_cast<float*>(h->otab.ptr);
   int64_t* bg = reinterpret_cast<int64_t*>(static_cast<char*>(h->otab.ptr) + pbytes);
   {
-    const int64_t nt = p.O * (R + 1);
+    const int64_t nt = p.Opad * (R + 1);
     hipLaunchKernelGGL(outer_tables_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, fac,
                        p, Pg, bg);
     CP_LAUNCH_CHECK(h);
