@@ -198,6 +198,175 @@ def sparse_mttkrp(h, cpng, torch, nnz_draw=20_000_000, R=16, reps=10):
     return {"nnz": int(nnz), "rank": R, "prepare_s": round(prep, 3), "modes": per_mode}
 
 
+def rank_sweep(h, cpng, torch, T, dims, ranks=(1, 2, 4, 8, 16, 32), reps=6):
+    """Dense MTTKRP kernel time per mode on the float32 tensor T, FP32 (vector
+    ALU) vs BF16x3 (matrix cores), for several ranks; GB/s on the tensor bytes."""
+    nT = int(np.prod(dims))
+    Tg = cpng.Tensor(dims, T)
+    out = []
+    for R in ranks:
+        u = torch.rand(sum(dims) * R, dtype=torch.float64, device="cuda")
+        row = {"R": R}
+        for prec in ("fp32", "bf16x3"):
+            us = []
+            for n in range(len(dims)):
+                cpng.cp_mttkrp(h, Tg, u, R, n, prec)
+                torch.cuda.synchronize()
+                cpng.cp_profile(h, True)
+                for _ in range(reps):
+                    cpng.cp_mttkrp(h, Tg, u, R, n, prec)
+                torch.cuda.synchronize()
+                nl, ms = cpng.cp_profile_read(h, cpng.CP_KERNEL_DENSE_MTTKRP)
+                cpng.cp_profile(h, False)
+                us.append(ms / nl * 1e3)
+            mean = float(np.mean(us))
+            row[prec] = {"kernel_us_per_mode": [round(x, 1) for x in us],
+                         "GBs": round(4 * nT / (mean * 1e-6) / 1e9, 1),
+                         "frac": round(4 * nT / (mean * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)}
+        log(f"rank sweep R={R}: fp32 {row['fp32']['GBs']} GB/s, bf16x3 {row['bf16x3']['GBs']} GB/s")
+        out.append(row)
+    return out
+
+
+def precision_study(h, cpng, torch, T, dims, R, u0, iters=10):
+    """First iterates of the BF16x3 N-GMRES run: at each iterate u_i, the
+    single-mode MTTKRPs, f and g in BF16x3 and in FP32 against float64
+    accumulation of the same float32 tensor (the path whose parity with the
+    float64 oracle the tests establish):  ||dM||/||M|| per mode,
+    |df| / (1/2 ||T||^2) and ||dg|| / ||T||."""
+    Tg = cpng.Tensor(dims, T)
+    cpng.cp_tensor_prepare(h, Tg)
+    half = 0.5 * Tg.norm_sq
+    st = cpng.NGMRESState(h, Tg, R, torch.from_numpy(u0).cuda(), precision="bf16x3")
+    rows = []
+    for it in range(iters):
+        u, _, _, rho = st.get()
+        ref = [cpng.cp_mttkrp(h, Tg, u, R, n, "fp32in_fp64acc") for n in range(len(dims))]
+        f64, g64 = cpng.cp_objective_grad(h, Tg, u, R, "fp32in_fp64acc")
+        row = {"it": it, "rho": rho}
+        for prec in ("bf16x3", "fp32"):
+            dm = [float(torch.linalg.norm(cpng.cp_mttkrp(h, Tg, u, R, n, prec) - ref[n]) /
+                        torch.linalg.norm(ref[n])) for n in range(len(dims))]
+            f, g = cpng.cp_objective_grad(h, Tg, u, R, prec)
+            row[prec] = {"dM_rel_max": max(dm), "df_rel": abs(float(f) - float(f64)) / half,
+                         "dg_rel": float(torch.linalg.norm(g - g64)) / float(np.sqrt(2 * half))}
+        rows.append(row)
+        st.step()
+    st.close()
+    worst = {p: {k: max(r[p][k] for r in rows) for k in ("dM_rel_max", "df_rel", "dg_rel")}
+             for p in ("bf16x3", "fp32")}
+    log(f"precision study (max over {iters} iterates): {worst}")
+    return {"reference": "float64 accumulation of the same float32 tensor",
+            "max": worst, "per_iterate": rows}
+
+
+def small_dense(h, cpng, torch, seeds=(0, 1, 2, 3, 4)):
+    """Dense 20^3 float64, R = 3, congruence 0.5, noise 1%+1% (Table 1 row 1):
+    time and iterations to rho <= 1e-8, GPU (cp_decompose, FP64) and the
+    float64 CPU oracle, same seeds and initial guesses."""
+    from oracle import cp as ocp
+    from oracle.ngmres import CPProblem, ngmres
+    from workloads import initial_guess, test_problem_1
+    dims, R, tol = (20, 20, 20), 3, 1e-8
+    rows = []
+    for seed in seeds:
+        p = test_problem_1(dims, R, 0.5, 1, 1, seed=seed)
+        u0 = initial_guess(dims, R, seed=seed + 10000)
+        Tg = cpng.Tensor(dims, torch.from_numpy(p.T).cuda().reshape(-1))
+        cpng.cp_tensor_prepare(h, Tg)
+        if seed == seeds[0]:
+            cpng.cp_decompose(h, Tg, R, tol, torch.from_numpy(u0).cuda(), max_iter=5)
+        u = torch.from_numpy(u0).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = cpng.cp_decompose(h, Tg, R, tol, u, max_iter=1000)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ref = ngmres(CPProblem(ocp.DenseTensor(p.T), R), u0, tol=tol, max_iter=1000)
+        to = time.perf_counter() - t0
+        rows.append({"seed": seed, "gpu_s": round(tg, 4), "gpu_iters": r["iters"],
+                     "oracle_s": round(to, 3), "oracle_iters": len(ref.trace) - 1,
+                     "both_converged": bool(r["converged"] and ref.converged)})
+    log(f"small dense 20^3: {rows}")
+    return rows
+
+
+TP1_CASES = [(20, 0.5, 3, 1, 1), (20, 0.5, 5, 10, 5), (20, 0.9, 3, 0, 0), (20, 0.9, 5, 1, 1),
+             (50, 0.5, 3, 1, 1), (50, 0.5, 5, 10, 5), (50, 0.9, 3, 0, 0), (50, 0.9, 5, 1, 1),
+             (100, 0.5, 3, 1, 1), (100, 0.5, 5, 10, 5), (100, 0.9, 3, 0, 0), (100, 0.9, 5, 1, 1)]
+TP2_CASES = [(4, 8, 6), (4, 16, 3), (6, 4, 2), (6, 8, 5), (8, 4, 2)]
+
+
+def _methods_to_accuracy(h, cpng, torch, Tg, dims, R, u0, max_iter):
+    """ALS, N-GMRES (w = 20) and N-CG from the same initial guess on the GPU;
+    per method the h = sqrt(2 f)/||T|| trace, seconds and iterations."""
+    normT = float(np.sqrt(Tg.norm_sq))
+    runs = {}
+    for method in ("als", "ngmres", "ncg"):
+        u = torch.from_numpy(u0).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = cpng.cp_decompose(h, Tg, R, 1e-12, u, trace_cap=max_iter + 1, max_iter=max_iter,
+                              method=method)
+        torch.cuda.synchronize()
+        runs[method] = {"h": [float(np.sqrt(max(0.0, 2 * t["f"]))) / normT for t in r["trace"]],
+                        "seconds": time.perf_counter() - t0, "iters": r["iters"]}
+    return runs
+
+
+def _accuracy_row(runs, row):
+    """Iterations and seconds to |h_i - h*| <= 1e-3, 1e-6, 1e-10, h* the lowest
+    final h; a method that ends more than 1e-9 above h* is marked."""
+    hstar = min(v["h"][-1] for v in runs.values())
+    row["h_star"] = hstar
+    for method, v in runs.items():
+        hs = v["h"]
+        per_it = v["seconds"] / max(1, v["iters"])
+        row[f"{method}_same_h"] = bool(abs(hs[-1] - hstar) <= 1e-9)
+        for acc in (1e-3, 1e-6, 1e-10):
+            it = next((i for i, x in enumerate(hs) if abs(x - hstar) <= acc), None)
+            row[f"{method}_it_{acc:g}"] = it
+            row[f"{method}_s_{acc:g}"] = None if it is None else round(it * per_it, 4)
+        row[f"{method}_ms_per_iter"] = round(per_it * 1e3, 3)
+    return row
+
+
+def paper_tables(h, cpng, torch, max_iter=2000):
+    """The paper's dense (Test Problem I, Tables 1-3) and sparse (Test Problem
+    II, Tables 4-6) comparisons at the paper's sizes: ALS, N-GMRES and N-CG on
+    the GPU, iterations and seconds until |h(u_i) - h*| <= 1e-3, 1e-6, 1e-10.
+    Seeds are ours (the paper's are not known): the trends are comparable, the
+    exact counts are not."""
+    from workloads import initial_guess, test_problem_1, test_problem_2
+    out = {"tp1": [], "tp2": []}
+    for k, (sz, c, R, l1, l2) in enumerate(TP1_CASES):
+        dims = (sz, sz, sz)
+        p = test_problem_1(dims, R, c, l1, l2, seed=k)
+        Tg = cpng.Tensor(dims, torch.from_numpy(p.T).cuda().reshape(-1))
+        cpng.cp_tensor_prepare(h, Tg)
+        u0 = initial_guess(dims, R, seed=k + 10000)
+        runs = _methods_to_accuracy(h, cpng, torch, Tg, dims, R, u0, max_iter)
+        row = _accuracy_row(runs, {"case": k + 1, "s": sz, "c": c, "R": R, "l1": l1, "l2": l2})
+        log("tp1 case %d: " % (k + 1) + ", ".join(f"{m} it(1e-10)={row[m + '_it_1e-10']}"
+                                                 for m in runs))
+        out["tp1"].append(row)
+    for N, sz, R in TP2_CASES:
+        tp = test_problem_2(N // 2, sz)
+        Tg = cpng.Tensor(tp.dims, torch.from_numpy(tp.values).cuda(),
+                         coords=torch.from_numpy(tp.coords).cuda())
+        cpng.cp_tensor_prepare(h, Tg)
+        for seed in (0, 1):
+            u0 = initial_guess(tp.dims, R, seed=seed + 20000)
+            runs = _methods_to_accuracy(h, cpng, torch, Tg, tp.dims, R, u0, max_iter)
+            row = _accuracy_row(runs, {"N": N, "s": sz, "R": R, "nnz": int(tp.values.size),
+                                       "seed": seed})
+            log(f"tp2 N={N} s={sz} R={R} seed {seed}: " + ", ".join(
+                f"{m} it(1e-10)={row[m + '_it_1e-10']}" for m in runs))
+            out["tp2"].append(row)
+    return out
+
+
 def _serve(cpng, torch, data, slots, rate, max_iter):
     srv = cpng.Server(0, slots=slots, max_iter=max_iter, precision="bf16x3",
                       final_precision="fp32in_fp64acc", switch_rho=1e-4)
@@ -268,7 +437,7 @@ def main():
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--serving", type=int, default=0, metavar="N",
                     help="only run the serving benchmark with N requests")
-    ap.add_argument("--part", choices=["sparse", "ttg"], default=None,
+    ap.add_argument("--part", choices=["sparse", "ttg", "small", "tables"], default=None,
                     help="only run one extra study (for profiling it)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
@@ -293,6 +462,10 @@ def main():
         h = cpng.Handle(0)
         if args.part == "sparse":
             res = sparse_mttkrp(h, cpng, torch)
+        elif args.part == "small":
+            res = {"rows": small_dense(h, cpng, torch)}
+        elif args.part == "tables":
+            res = paper_tables(h, cpng, torch)
         else:
             res = time_to_grad(h, cpng, torch, seeds=(0,), taus=(1e-4,))
         h.close()
@@ -369,15 +542,22 @@ def main():
                      "avg_us": round(avg_ms * 1e3, 2), "bytes_per_launch": traffic},
     }
     st.close()
+    if not args.skip_extra and args.precision != "fp64":
+        log("rank sweep (FP32 vs BF16x3)")
+        res["extra"] = {"rank_sweep_128x4": rank_sweep(h, cpng, torch, T, dims)}
+        log("precision study (first 10 BF16x3 iterates)")
+        res["extra"]["precision_study_128x4_R32"] = precision_study(h, cpng, torch, T, dims, R, u0)
     if not args.skip_extra:
         del Tg, T
         torch.cuda.empty_cache()
         log("time-to-grad study (200^3, R=10, c=0.9)")
-        res["extra"] = {"time_to_grad_200cubed_R10": time_to_grad(h, cpng, torch)}
+        res.setdefault("extra", {})["time_to_grad_200cubed_R10"] = time_to_grad(h, cpng, torch)
         log("sparse MTTKRP (20000^3, ~2e7 nonzeros, R=16)")
         res["extra"]["sparse_mttkrp_20000cubed_R16"] = sparse_mttkrp(h, cpng, torch)
         log("serving stream (32 requests)")
         res["extra"]["serving"] = serving(cpng, torch, n=32)
+        log("small dense 20^3 (GPU vs oracle)")
+        res["extra"]["small_dense_20cubed_R3"] = small_dense(h, cpng, torch)
     if not args.skip_cpu:
         log("cpu baseline (oracle)")
         A = [np.ascontiguousarray(x) for x in

@@ -112,9 +112,14 @@ typedef struct cp_iter_info {
 
 #define CP_METHOD_NGMRES 0
 #define CP_METHOD_ALS    1
+/* Nonlinear conjugate gradients, the paper's comparison method (Section 2.4):
+   Polak-Ribiere coefficient clipped at zero, the same line search, steepest
+   descent when a direction is not a descent direction or after a line search
+   without a Wolfe point; iterates are not normalised after the initial guess. */
+#define CP_METHOD_NCG    2
 
 typedef struct cp_options {
-  int32_t method;           /* CP_METHOD_NGMRES (default) or CP_METHOD_ALS */
+  int32_t method;           /* CP_METHOD_NGMRES (default), CP_METHOD_ALS or CP_METHOD_NCG */
   int32_t window;           /* w, >= 1 (20) */
   double eps;               /* delta = eps * max diag(P^T P) (1e-12) */
   double ls_ftol;           /* sufficient-decrease constant (1e-4) */
@@ -128,9 +133,8 @@ typedef struct cp_options {
   int32_t precision;        /* bulk cp_precision for the first phase (CP_PREC_FP64) */
   int32_t final_precision;  /* precision after the switch (CP_PREC_FP64) */
   double switch_rho;        /* switch to final_precision (and restart the window) once
-                               rho <= switch_rho, or after a line search in the first
-                               precision ends without a Wolfe point; 0 = switch only
-                               when the stopping test would fire (0) */
+                               rho <= switch_rho (see also switch_on_stall); 0 = switch
+                               only when the stopping test would fire (0) */
   int32_t normalize_accel;  /* normalise the accelerated iterate (1) */
   cp_iter_info* trace;      /* host, nullable: per-iteration records */
   int32_t trace_cap;        /* capacity of trace */
@@ -138,6 +142,9 @@ typedef struct cp_options {
                                Y = T x_N A^(N) once per gradient evaluation and per ALS
                                sweep and take M^(1..N-1) from Y, so T is streamed twice
                                instead of N times (1); 0 = one pass per mode */
+  int32_t switch_on_stall;  /* with switch_rho > 0, also switch once rho <= 1e-2 after a
+                               line search in the first precision ends without a Wolfe
+                               point (1) */
 } cp_options;
 
 typedef struct cp_report {

@@ -22,7 +22,7 @@ CP_ESINGULAR, CP_EDUPLICATE, CP_ENOTFINITE = -4, -5, -6
 CP_MAXITER, CP_LS_FALLBACK = 1, 2
 CP_F32, CP_F64 = 0, 1
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp32in_fp64acc": 3}
-CP_METHOD_NGMRES, CP_METHOD_ALS = 0, 1
+CP_METHOD_NGMRES, CP_METHOD_ALS, CP_METHOD_NCG = 0, 1, 2
 LS_STATUS = {0: "converged", 1: "maxfev", 2: "xtol", 3: "stpmax", 4: "stpmin", 5: "rounding",
              -1: ""}
 
@@ -52,7 +52,8 @@ class cp_options(C.Structure):
                 ("ls_stpmax", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
                 ("final_precision", C.c_int32), ("switch_rho", C.c_double),
                 ("normalize_accel", C.c_int32), ("trace", C.POINTER(cp_iter_info)),
-                ("trace_cap", C.c_int32), ("mttkrp_tree", C.c_int32)]
+                ("trace_cap", C.c_int32), ("mttkrp_tree", C.c_int32),
+                ("switch_on_stall", C.c_int32)]
 
 
 class cp_report(C.Structure):
@@ -320,7 +321,7 @@ def options(**kw):
         if k in ("precision", "final_precision") and isinstance(v, str):
             v = PREC[v]
         if k == "method" and isinstance(v, str):
-            v = {"ngmres": CP_METHOD_NGMRES, "als": CP_METHOD_ALS}[v]
+            v = {"ngmres": CP_METHOD_NGMRES, "als": CP_METHOD_ALS, "ncg": CP_METHOD_NCG}[v]
         setattr(o, k, v)
     return o
 

@@ -179,6 +179,8 @@ int axpy_to(cp_handle* h, const double* x, double a, const double* d, double* y,
             hipStream_t st);   // y = x + a*d
 int sub_to(cp_handle* h, const double* a, const double* b, double* y, int64_t n,
            hipStream_t st);    // y = a - b
+int cg_direction(cp_handle* h, const double* g, double gamma, double* d, int64_t n,
+                 hipStream_t st);   // d = -g + gamma d
 
 // Per-call values of the N-GMRES kernels kept in device memory, so that a
 // captured launch sequence can be replayed with new values: the line-search

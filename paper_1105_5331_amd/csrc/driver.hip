@@ -28,6 +28,7 @@ struct cp_ngmres_state {
   double f = 0.0, rho = 0.0, normT = 0.0;
   int n_fg = 0, n_restarts = 0, n_fallback = 0, switch_iter = -1;
   bool stalled = false;   // a line search in reduced precision ended without a Wolfe point
+  bool cg_fresh = true;   // N-CG: the next direction is -g (start, switch, failed search)
   // device buffers
   double* mem = nullptr;
   double *u, *g, *ubar, *gbar, *uhat, *d, *ut, *gt, *gbest, *scal;  // scal: 8 doubles
@@ -481,6 +482,63 @@ int eval_current(cp_handle* h, cp_ngmres_state* S) {
   return CP_OK;
 }
 
+// One N-CG iteration (comparison method, Section 2.4): line search along d
+// from u, then d = -g + gamma d with the Polak-Ribiere gamma clipped at 0.
+// u is not normalised.  S->ubar holds the line search's base point.
+int ncg_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* rec, int* rc_out) {
+  const int64_t L = S->L;
+  if (S->cg_fresh) {
+    CP_TRY(cg_direction(h, S->g, 0.0, S->d, L, S->st));
+    S->cg_fresh = false;
+  }
+  double slope;
+  CP_TRY(dot(h, S->g, S->d, L, S->scal + 1, S->st));
+  CP_TRY(readback(h, S->scal + 1, 1, &slope, S->st));
+  if (!(slope < 0.0)) {   // not a descent direction: steepest descent
+    rec->restart = 1;
+    S->n_restarts++;
+    CP_TRY(cg_direction(h, S->g, 0.0, S->d, L, S->st));
+    CP_TRY(dot(h, S->g, S->d, L, S->scal + 1, S->st));
+    CP_TRY(readback(h, S->scal + 1, 1, &slope, S->st));
+  }
+  CP_HIP(h, hipMemcpyAsync(S->ubar, S->u, sizeof(double) * L, hipMemcpyDeviceToDevice, S->st));
+  double beta = 0.0, fnew = S->f;
+  int nfev = 0, status = 0;
+  const double* gacc = nullptr;
+  CP_TRY(more_thuente(h, S, S->f, slope, &beta, &fnew, &gacc, &nfev, &status));
+  rec->nfev = nfev;
+  rec->ls_status = status;
+  const bool restart_next = status != LS_CONVERGED;
+  if (restart_next) {
+    S->n_fallback++;
+    *rc_out = CP_LS_FALLBACK;
+    if (!is_f64_acc(S->prec)) S->stalled = true;
+  }
+  if (!gacc) {
+    beta = 0.0;
+    fnew = S->f;
+  }
+  rec->beta = beta;
+  const double* gnew = gacc ? gacc : S->g;
+  if (beta != 0.0) CP_TRY(axpy_to(h, S->ubar, beta, S->d, S->u, L, S->st));
+  // g_new . (g_new - g), g . g and g_new . g_new in one readback
+  double v[3];
+  CP_TRY(sub_to(h, gnew, S->g, S->uhat, L, S->st));
+  CP_TRY(dot(h, gnew, S->uhat, L, S->scal + 4, S->st));
+  CP_TRY(dot(h, S->g, S->g, L, S->scal + 5, S->st));
+  CP_TRY(dot(h, gnew, gnew, L, S->scal + 6, S->st));
+  CP_TRY(readback(h, S->scal + 4, 3, v, S->st));
+  const double gamma = restart_next ? 0.0 : std::max(0.0, v[0] / v[1]);
+  CP_TRY(cg_direction(h, gnew, gamma, S->d, L, S->st));
+  if (gnew != S->g)
+    CP_HIP(h, hipMemcpyAsync(S->g, gnew, sizeof(double) * L, hipMemcpyDeviceToDevice, S->st));
+  S->f = fnew;
+  S->rho = std::sqrt(std::max(0.0, v[2])) / S->normT;
+  if (!std::isfinite(S->f) || !std::isfinite(S->rho))
+    return fail(h, CP_ENOTFINITE, "objective or gradient not finite");
+  return CP_OK;
+}
+
 }  // namespace
 
 // ============================== C ABI =====================================
@@ -507,6 +565,7 @@ void cp_options_default(cp_options* o) {
   o->trace = nullptr;
   o->trace_cap = 0;
   o->mttkrp_tree = 1;
+  o->switch_on_stall = 1;
 }
 
 int cp_create(int device, size_t workspace_bytes, cp_handle** out) {
@@ -729,6 +788,8 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
   if (opt) o = *opt;
   else cp_options_default(&o);
   if (o.window < 1 || o.window > 64) return fail(h, CP_EINVAL, "window must be in 1..64");
+  if (o.method != CP_METHOD_NGMRES && o.method != CP_METHOD_ALS && o.method != CP_METHOD_NCG)
+    return fail(h, CP_EINVAL, "unknown method %d", o.method);
   if (o.ls_maxfev < 1 || !(o.ls_stp0 > 0.0)) return fail(h, CP_EINVAL, "bad line-search options");
   CP_TRY(check_prec(h, T, o.precision));
   CP_TRY(check_prec(h, T, o.final_precision));
@@ -742,7 +803,7 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
   S->st = st;
   S->prec = o.precision;
   S->normT = std::sqrt(T->norm_sq);
-  S->wcap = o.method == CP_METHOD_ALS ? 1 : o.window;
+  S->wcap = o.method == CP_METHOD_NGMRES ? o.window : 1;
   const size_t nvec = 9 + 2 * (size_t)S->wcap;
   if (hipMalloc(&S->mem, sizeof(double) * (nvec * S->L + 80)) != hipSuccess) {
     delete S;
@@ -816,12 +877,14 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
   rec.rho = S->rho;
   rec.beta = NAN;
   rec.ls_status = -1;
-  rec.m = S->opt.method == CP_METHOD_ALS ? 0 : S->wcount;
+  rec.m = S->opt.method == CP_METHOD_NGMRES ? S->wcount : 0;
   rec.precision = S->prec;
   int rc = CP_OK;
   if (S->opt.method == CP_METHOD_ALS) {
     CP_TRY(als_sweep_impl(h, S->T, S->s, S->u, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0));
     CP_TRY(eval_current(h, S));
+  } else if (S->opt.method == CP_METHOD_NCG) {
+    CP_TRY(ncg_step(h, S, &rec, &rc));
   } else {
     // Steps I and II: u_bar = M(u_i); f, g at u_bar; u_hat over the window
     S->hpar->m = S->wcount;
@@ -921,7 +984,7 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
     // fire on a gradient that was not accumulated in float64.
     if (!S->switched && S->prec != o.final_precision &&
         ((o.switch_rho > 0.0 && S->rho <= o.switch_rho) ||
-         (o.switch_rho > 0.0 && S->stalled && S->rho <= 1e-2) ||
+         (o.switch_rho > 0.0 && o.switch_on_stall && S->stalled && S->rho <= 1e-2) ||
          (S->rho <= tol && !is_f64_acc(S->prec) && is_f64_acc(o.final_precision)))) {
       S->prec = o.final_precision;
       S->switched = true;
@@ -930,6 +993,7 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
       if (rc < 0) break;
       S->wcount = 0;
       S->whead = 0;
+      S->cg_fresh = true;
       rc = window_push(h, S);
       if (rc < 0) break;
     }
@@ -937,7 +1001,7 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
       if (o.trace && ntr < o.trace_cap) {
         cp_iter_info r{};
         r.it = S->it; r.f = S->f; r.rho = S->rho; r.beta = NAN; r.ls_status = -1;
-        r.m = o.method == CP_METHOD_ALS ? 0 : S->wcount;
+        r.m = o.method == CP_METHOD_NGMRES ? S->wcount : 0;
         r.precision = S->prec;
         o.trace[ntr++] = r;
       }

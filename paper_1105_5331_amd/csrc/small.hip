@@ -569,6 +569,13 @@ __global__ void axpy_kernel(const double* __restrict__ x, double a, const double
   if (e < n) y[e] = fma(a, d[e], x[e]);
 }
 
+// d = -g + gamma d (d = -g exactly when gamma = 0)
+__global__ void cg_direction_kernel(const double* __restrict__ g, double gamma,
+                                    double* __restrict__ d, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) d[e] = gamma == 0.0 ? -g[e] : fma(gamma, d[e], -g[e]);
+}
+
 __global__ void sub_kernel(const double* __restrict__ a, const double* __restrict__ b,
                            double* __restrict__ y, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -878,6 +885,13 @@ int axpy_to(cp_handle* h, const double* x, double a, const double* d, double* y,
             hipStream_t st) {
   if (n == 0) return CP_OK;
   hipLaunchKernelGGL(axpy_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, x, a, d, y, n);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int cg_direction(cp_handle* h, const double* g, double gamma, double* d, int64_t n,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(cg_direction_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, g, gamma, d, n);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }

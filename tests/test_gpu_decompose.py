@@ -22,6 +22,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import cp as ocp
+from oracle.ncg import ncg
 from oracle.ngmres import CPProblem, als, ngmres
 from workloads import initial_guess, test_problem_1, test_problem_2
 
@@ -219,3 +220,23 @@ def test_captured_replay_matches_eager_sparse(h):
     for k, (a, b) in enumerate(zip(eager[0], graph[0])):
         assert a["f"] == b["f"] and a["rho"] == b["rho"] and a["nfev"] == b["nfev"], k
     assert np.array_equal(eager[1], graph[1])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ncg_trajectory_dense_fp64(h, seed):
+    """N-CG (Polak-Ribiere clipped at 0, the same line search) against the
+    oracle's, per iterate until the first discrete divergence."""
+    import paper_1105_5331_amd as cpng
+    dims, R, tol = (20, 20, 20), 3, 1e-6
+    print(f"case ncg trajectory seed={seed}", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=seed)
+    u0 = initial_guess(dims, R, seed=seed + 10000)
+    ref = ncg(CPProblem(ocp.DenseTensor(p.T), R), u0, tol=tol, max_iter=300)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u = _dev(u0)
+    out = cpng.cp_decompose(h, Tg, R, tol, u, trace_cap=400, max_iter=300, method="ncg")
+    half = 0.5 * np.sum(p.T ** 2)
+    n = _compare(out["trace"], ref.trace, half, f"ncg seed {seed}")
+    assert n >= min(len(ref.trace), 10)
+    assert out["converged"] == ref.converged
