@@ -87,12 +87,13 @@ __global__ void segment_kernel(const int32_t* __restrict__ keys, int64_t nnz, in
 struct SparseParams {
   int N, mode, R, Rp;             // Rp: factor row stride (R padded)
   int64_t nnz, I_n;
+  int64_t wave_nnz;               // sorted nonzeros per wave (multiple of 64)
   const int32_t* coords;          // (N-1) x nnz, other modes in increasing order
   const int64_t* seg;             // I_n + 1
   int64_t foff[CP_MAX_ORDER - 1]; // factor element offsets of the other modes
 };
 
-// Wave kernel: one wave per contiguous range of kWaveNnz sorted nonzeros.
+// Wave kernel: one wave per contiguous range of p.wave_nnz sorted nonzeros.
 // The factors are read from a copy whose rows are padded to Rp = R rounded
 // up to the vector width VW (4 floats or 2 doubles = 16 bytes), so a lane
 // gathers VW consecutive ranks with one 16-byte load.  A wave is split into
@@ -109,7 +110,13 @@ struct SparseParams {
 // inside the wave's range, else into the wave's head or tail carry slot.
 // KM is the number of other modes the kernel is compiled for: 2 (order 3),
 // 3 (order 4) or CP_MAX_ORDER - 1 with a runtime bound (any order).
-constexpr int kWaveNnz = 2048;
+// Sorted nonzeros per wave: about 4096 waves per launch, each range a
+// multiple of 64 between 512 and 4096 (longer ranges amortise a wave's first
+// and last rows; fewer than ~4000 waves leave the chip underfilled).
+inline int64_t wave_range(int64_t nnz) {
+  const int64_t r = ((nnz + 4095) / 4096 + 63) / 64 * 64;
+  return std::min<int64_t>(4096, std::max<int64_t>(512, r));
+}
 
 template <typename CT>
 struct VecOf;
@@ -187,9 +194,9 @@ __global__ __launch_bounds__(256) void sparse_wave_kernel(const TT* __restrict__
   const int cc = lane_ok ? c * VW : 0;   // idle lanes read a valid address
   const int km = KM < CP_MAX_ORDER - 1 ? KM : p.N - 1;
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t z0 = wid * kWaveNnz;
+  const int64_t z0 = wid * p.wave_nnz;
   if (z0 >= p.nnz) return;   // whole wave
-  const int64_t z1 = min<int64_t>(p.nnz, z0 + kWaveNnz);
+  const int64_t z1 = min<int64_t>(p.nnz, z0 + p.wave_nnz);
   CT acc[VW];
 #pragma unroll
   for (int v = 0; v < VW; ++v) acc[v] = CT(0);
@@ -291,7 +298,7 @@ __global__ void pad_factors_kernel(const double* __restrict__ x, int64_t rows, i
 template <typename TT, typename CT, int L, int KM>
 int launch_sparse_wave(cp_handle* h, const TT* vals, const int32_t* rows, const CT* fac,
                        SparseParams p, double* M, hipStream_t st) {
-  const int64_t nwaves = (p.nnz + kWaveNnz - 1) / kWaveNnz;
+  const int64_t nwaves = (p.nnz + p.wave_nnz - 1) / p.wave_nnz;
   const int64_t nslots = 2 * nwaves;
   CP_TRY(ensure(h, h->carry, (sizeof(int64_t) + sizeof(double) * p.R) * (size_t)std::max<int64_t>(1, nslots), st));
   int64_t* crow = static_cast<int64_t*>(h->carry.ptr);
@@ -532,6 +539,7 @@ int sparse_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double
   p.mode = mode;
   p.R = R;
   p.nnz = sp->nnz;
+  p.wave_nnz = wave_range(sp->nnz);
   p.I_n = I;
   p.coords = sp->mode[mode].coords;
   p.seg = sp->mode[mode].seg;

@@ -295,6 +295,7 @@ def _sparse(cpng, sp, dtype):
 SPARSE_CASES = [
     ("tp2_d2_s4", lambda: test_problem_2(2, 4)),
     ("tp2_d3_s3", lambda: test_problem_2(3, 3)),
+    ("tp2_d4_s3", lambda: test_problem_2(4, 3)),      # order 8, two waves
     ("rand_small", lambda: random_coo((7, 8, 9), 100, seed=1)),
     ("rand_ragged", lambda: random_coo((300, 40, 50), 9000, seed=2, skew=1.2)),
     ("rand_4way", lambda: random_coo((17, 23, 5, 31), 4000, seed=3)),
