@@ -45,7 +45,6 @@ struct cp_handle {
   cpng::DevBuf small;    // Grams, Gammabar, Gamma, scales, perms, alpha, scalars
   cpng::DevBuf red;      // reduction partials
   cpng::DevBuf carry;    // sparse segment carries
-  cpng::DevBuf tmpu;     // scratch iterate-sized vectors
   cpng::DevBuf otab;     // per-launch outer-index tables of the streaming MTTKRP
   cpng::DevBuf ybuf;     // T contracted with the last factor (two-level evaluation)
   uint64_t gen = 0;           // bumped whenever a workspace slice is reallocated
@@ -172,9 +171,6 @@ int sumsq_tensor(cp_handle* h, const void* v, int dtype, int64_t n, double* out,
 // two launches
 int objective_from_dot(cp_handle* h, const double* A, const double* M, int64_t n, double normsq,
                        const double* Gam, int R, double* f, hipStream_t st);
-// f = 0.5*normsq - dotAM + 0.5*sum(Gamma)
-int objective_combine(cp_handle* h, double normsq, const double* dotAM, const double* Gam, int R,
-                      double* f, hipStream_t st);
 int axpy_to(cp_handle* h, const double* x, double a, const double* d, double* y, int64_t n,
             hipStream_t st);   // y = x + a*d
 int sub_to(cp_handle* h, const double* a, const double* b, double* y, int64_t n,

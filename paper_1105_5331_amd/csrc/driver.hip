@@ -595,8 +595,8 @@ int cp_destroy(cp_handle* h) {
   if (!h) return CP_OK;
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&h->part, &h->stage, &h->mbuf, &h->small, &h->red, &h->carry, &h->tmpu,
-                    &h->otab, &h->ybuf};
+  DevBuf* bufs[] = {&h->part, &h->stage, &h->mbuf, &h->small, &h->red, &h->carry, &h->otab,
+                    &h->ybuf};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   if (h->pinned) (void)hipHostFree(h->pinned);

@@ -541,16 +541,10 @@ int dot_impl(cp_handle* h, const X* x, const Y* y, int64_t n, double* out, hipSt
   return CP_OK;
 }
 
-__global__ void objective_kernel(double normsq, const double* __restrict__ dotAM,
-                                 const double* __restrict__ Gam, int R, double* __restrict__ f) {
-  double s = 0.0;
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) s += Gam[e];
-  s = block_sum(s);
-  if (threadIdx.x == 0) *f = 0.5 * normsq - *dotAM + 0.5 * s;
-}
 
 // f = 0.5 normsq - (sum of the dot partials) + 0.5 sum(Gamma): the two sums
-// exactly as sum_final_kernel and objective_kernel form them.
+// in the same order as the two-launch form (dot partials summed by one block,
+// then the Gamma entries).
 __global__ void objective_final_kernel(const double* __restrict__ part, int nb, double normsq,
                                        const double* __restrict__ Gam, int R,
                                        double* __restrict__ f) {
@@ -874,12 +868,6 @@ int objective_from_dot(cp_handle* h, const double* A, const double* M, int64_t n
   return CP_OK;
 }
 
-int objective_combine(cp_handle* h, double normsq, const double* dotAM, const double* Gam, int R,
-                      double* f, hipStream_t st) {
-  hipLaunchKernelGGL(objective_kernel, dim3(1), dim3(256), 0, st, normsq, dotAM, Gam, R, f);
-  CP_LAUNCH_CHECK(h);
-  return CP_OK;
-}
 
 int axpy_to(cp_handle* h, const double* x, double a, const double* d, double* y, int64_t n,
             hipStream_t st) {
