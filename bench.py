@@ -518,6 +518,17 @@ def main():
     cpng.cp_profile(h, False)
     elem = 8 if args.precision == "fp64" else 4
     value = passes * nT * elem / dt / 1e9
+    # the achievable streaming read of the same buffer (our reference kernel)
+    for _ in range(3):
+        cpng.cp_stream_read(h, T)
+    torch.cuda.synchronize()
+    cpng.cp_profile(h, True)
+    for _ in range(10):
+        cpng.cp_stream_read(h, T)
+    torch.cuda.synchronize()
+    srn, srms = cpng.cp_profile_read(h, cpng.CP_KERNEL_STREAM_READ)
+    cpng.cp_profile(h, False)
+    stream_gbs = nT * elem / (srms / srn * 1e-3) / 1e9
     avg_ms = kms / max(1, launches)
     # algorithmic bytes of one single-mode MTTKRP launch: the tensor once, the
     # (N-1) factor copies it reads, the I_n x R output (float64)
@@ -539,7 +550,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": counter_traffic() if (args.precision, s, R) == ("bf16x3", 128, 32) else None,
                      "kernel": "dense MTTKRP", "launches": launches,
-                     "avg_us": round(avg_ms * 1e3, 2), "bytes_per_launch": traffic},
+                     "avg_us": round(avg_ms * 1e3, 2), "bytes_per_launch": traffic,
+                     "stream_read_GBs": round(stream_gbs, 1),
+                     "frac_of_stream_read": round(achieved / stream_gbs, 4)},
     }
     st.close()
     if not args.skip_extra and args.precision != "fp64":

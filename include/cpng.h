@@ -325,6 +325,7 @@ int cp_server_destroy(cp_server* s);
 /* Kernel ids for cp_profile_read. */
 #define CP_KERNEL_DENSE_MTTKRP  0   /* main dense MTTKRP kernel (any precision) */
 #define CP_KERNEL_SPARSE_MTTKRP 1   /* main sparse segmented-reduction kernel */
+#define CP_KERNEL_STREAM_READ   2   /* cp_stream_read */
 
 /* Enable (1) or disable (0) HIP-event timing of the main MTTKRP kernels on
  * the stream each is launched on; enabling clears the counters. */
@@ -333,6 +334,15 @@ int cp_profile(cp_handle* h, int32_t enable);
  * number of timed launches and their summed duration in milliseconds
  * (host pointers). */
 int cp_profile_read(cp_handle* h, int32_t kernel, int64_t* launches, double* total_ms);
+
+/* Measurement reference (not part of the method): read `bytes` of device
+ * memory at `buf` once, with 16-byte loads spread over the whole chip, and
+ * add them into a per-workgroup value in library workspace so the reads are
+ * kept.  `buf` must be 16-byte aligned and `bytes` a multiple of 16
+ * (CP_EINVAL otherwise).  Timed under CP_KERNEL_STREAM_READ while profiling
+ * is on: the achievable streaming-read bandwidth that the MTTKRP rooflines
+ * are also compared with. */
+int cp_stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -117,6 +117,7 @@ def lib():
             "cp_server_destroy": (C.c_int, [vp]),
             "cp_profile": (C.c_int, [vp, i32]),
             "cp_profile_read": (C.c_int, [vp, i32, C.POINTER(i64), C.POINTER(dp)]),
+            "cp_stream_read": (C.c_int, [vp, vp, C.c_size_t, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -364,7 +365,13 @@ class NGMRESState:
             pass
 
 
-CP_KERNEL_DENSE_MTTKRP, CP_KERNEL_SPARSE_MTTKRP = 0, 1
+CP_KERNEL_DENSE_MTTKRP, CP_KERNEL_SPARSE_MTTKRP, CP_KERNEL_STREAM_READ = 0, 1, 2
+
+
+def cp_stream_read(h: Handle, buf):
+    """Streaming-read reference kernel over a device tensor (measurement only)."""
+    nbytes = buf.numel() * buf.element_size()
+    h.check(lib().cp_stream_read(h._h, buf.data_ptr(), nbytes, _stream()))
 
 
 def cp_profile(h: Handle, enable: bool):

@@ -54,9 +54,9 @@ struct cp_handle {
   // optional event timing of the main MTTKRP kernels
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[2];
-  int64_t prof_launches[2] = {0, 0};
-  double prof_ms[2] = {0.0, 0.0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[3];
+  int64_t prof_launches[3] = {0, 0, 0};
+  double prof_ms[3] = {0.0, 0.0, 0.0};
 };
 
 namespace cpng {
@@ -167,6 +167,7 @@ int grad_epilogue(cp_handle* h, const double* M, const double* A, const double* 
 // out[0] = sum x*y (fixed-order two-stage reduction), device result
 int dot(cp_handle* h, const double* x, const double* y, int64_t n, double* out, hipStream_t st);
 int sumsq_tensor(cp_handle* h, const void* v, int dtype, int64_t n, double* out, hipStream_t st);
+int stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t st);
 // f = 0.5*normsq - <A, M> + 0.5*sum(Gamma), the dot and the combination in
 // two launches
 int objective_from_dot(cp_handle* h, const double* A, const double* M, int64_t n, double normsq,

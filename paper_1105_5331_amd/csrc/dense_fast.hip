@@ -465,11 +465,12 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
   const int lr = lane & 15;
   const int kb = (lane >> 4) * 8;
   const int r0 = blockIdx.z * 32;
-  const int64_t ioff = (int64_t)blockIdx.y * p.istride;
+  const int64_t bx = blockIdx.x, by = blockIdx.y;
+  const int64_t ioff = by * p.istride;
   stage_inner(fac, p, r0, Sh, Sl);
   __syncthreads();
   float acc0 = 0.f, acc1 = 0.f;   // rank columns r0 + lr and r0 + 16 + lr
-  const int64_t ob = (int64_t)blockIdx.x * p.o_per_block;
+  const int64_t ob = bx * p.o_per_block;
   const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
   for (int64_t og = ob + w * 16 * TW; og < oe; og += 4 * 16 * TW) {
     const float* rowp[TW];
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
   if (threadIdx.x < 32) {
     const int c = threadIdx.x;
     const float sum = (red[0][c] + red[2][c]) + (red[1][c] + red[3][c]);
-    if (r0 + c < p.R) part[(int64_t)blockIdx.x * p.I_n * p.R + blockIdx.y * p.R + r0 + c] = sum;
+    if (r0 + c < p.R) part[bx * p.I_n * p.R + by * p.R + r0 + c] = sum;
   }
 }
 

@@ -622,7 +622,7 @@ int cp_profile(cp_handle* h, int32_t enable) {
     }
     v.clear();
   }
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
     h->prof_launches[k] = 0;
     h->prof_ms[k] = 0.0;
   }
@@ -630,8 +630,14 @@ int cp_profile(cp_handle* h, int32_t enable) {
   return CP_OK;
 }
 
+int cp_stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t stream) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  return stream_read(h, buf, bytes, stream);
+}
+
 int cp_profile_read(cp_handle* h, int32_t kernel, int64_t* launches, double* total_ms) {
-  if (!h || kernel < 0 || kernel > 1 || !launches || !total_ms) return CP_EINVAL;
+  if (!h || kernel < 0 || kernel > 2 || !launches || !total_ms) return CP_EINVAL;
   CP_HIP(h, hipSetDevice(h->device));
   auto& v = h->ev_pending[kernel];
   for (auto& pr : v) {

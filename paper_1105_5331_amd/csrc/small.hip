@@ -557,6 +557,34 @@ __global__ void objective_final_kernel(const double* __restrict__ part, int nb, 
   if (threadIdx.x == 0) *f = 0.5 * normsq - d + 0.5 * sg;
 }
 
+// Streaming-read reference: grid-stride float4 loads, U in flight per
+// thread, summed into one value per workgroup; 32 workgroups per CU (many
+// short workgroups balance the end of the pass better than a few long ones;
+// measured best of U in {2..16}, 8..128 workgroups per CU).
+#ifndef CPNG_SR_UNROLL
+#define CPNG_SR_UNROLL 8
+#endif
+#ifndef CPNG_SR_BPC
+#define CPNG_SR_BPC 32
+#endif
+__global__ __launch_bounds__(256) void stream_read_kernel(const float4* __restrict__ x, int64_t n,
+                                                          double* __restrict__ out) {
+  constexpr int U = CPNG_SR_UNROLL;
+  float s = 0.f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; e + (U - 1) * stride < n; e += U * stride) {
+    float4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = x[e + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u].x + v[u].w;
+  }
+  for (; e < n; e += stride) s += x[e].x + x[e].w;
+  const double t = block_sum((double)s);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
 __global__ void axpy_kernel(const double* __restrict__ x, double a, const double* __restrict__ d,
                             double* __restrict__ y, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -838,6 +866,24 @@ int grad_epilogue(cp_handle* h, const double* M, const double* A, const double* 
   if (I * R == 0) return CP_OK;
   hipLaunchKernelGGL(grad_epilogue_kernel, dim3(nblk(I * R, 256)), dim3(256), 0, st, M, A, Gbar,
                      I, R, G);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t st) {
+  if (!buf || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(buf) % 16 != 0)
+    return fail(h, CP_EINVAL, "stream_read needs a 16-byte aligned buffer of 16-byte multiples");
+  int dev = 0, ncu = 0;
+  CP_HIP(h, hipGetDevice(&dev));
+  CP_HIP(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int nb = std::max(1, ncu) * CPNG_SR_BPC;
+  CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)nb, st));
+  {
+    KernelTimer timer(h, CP_KERNEL_STREAM_READ, st);
+    hipLaunchKernelGGL(stream_read_kernel, dim3(nb), dim3(256), 0, st,
+                       static_cast<const float4*>(buf), (int64_t)(bytes / 16),
+                       static_cast<double*>(h->red.ptr));
+  }
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }

@@ -361,3 +361,18 @@ def test_sparse_objective_grad_parity(h):
     half = 0.5 * t.norm2
     assert abs(f.item() - fo) <= 1e-12 * half
     assert np.linalg.norm(g.cpu().numpy() - go) <= 1e-12 * np.sqrt(t.norm2)
+
+
+def test_stream_read_reference(h):
+    """The streaming-read measurement kernel: runs on an aligned buffer, is
+    timed under its own id, and rejects a misaligned or ragged one."""
+    cpng = _cpng()
+    x = torch.ones(1 << 20, dtype=torch.float32, device="cuda")
+    cpng.cp_profile(h, True)
+    cpng.cp_stream_read(h, x)
+    torch.cuda.synchronize()
+    n, ms = cpng.cp_profile_read(h, cpng.CP_KERNEL_STREAM_READ)
+    cpng.cp_profile(h, False)
+    assert n == 1 and ms > 0
+    with pytest.raises(cpng.CpError):
+        cpng.cp_stream_read(h, x[1:])          # 4-byte offset, ragged length
