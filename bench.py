@@ -33,11 +33,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# rocprofv3 HBM counters of the default workload's dense MTTKRP, with the
-# hash of the kernel sources they were taken on
+# rocprofv3 HBM counters of the default workload's dense MTTKRP kernels, with
+# the hash of the source file that holds them (the counters are per kernel)
 COUNTER_SUMMARY = "profiles/dense_mttkrp_bf16x3_128x4_R32_hbm_counters.txt"
-KERNEL_SOURCES = ("paper_1105_5331_amd/csrc/dense_fast.hip", "paper_1105_5331_amd/csrc/splitk.hpp",
-                  "paper_1105_5331_amd/csrc/dense_mttkrp.hip")
+KERNEL_SOURCES = ("paper_1105_5331_amd/csrc/dense_fast.hip",)
 
 
 def kernel_source_hash():

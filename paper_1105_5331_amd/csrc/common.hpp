@@ -40,6 +40,7 @@ struct cp_handle {
   std::string err;
   // Workspace slices, each grown on demand (host calls only).
   cpng::DevBuf part;     // MTTKRP per-workgroup partials
+  cpng::DevBuf part2;    // their group sums (second reduction stage)
   cpng::DevBuf stage;    // float32 copies of the factors
   cpng::DevBuf mbuf;     // MTTKRP outputs used internally (N x maxI x R doubles)
   cpng::DevBuf small;    // Grams, Gammabar, Gamma, scales, perms, alpha, scalars

@@ -815,7 +815,7 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
     }
   }
   CP_LAUNCH_CHECK(h);
-  launch_splitk_reduce(h, part, ks, n_out, R, M, st);
+  CP_TRY(launch_splitk_reduce(h, part, ks, n_out, R, M, st));
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
@@ -874,7 +874,7 @@ static int launch_tiles(cp_handle* h, const TT* T, const CT* fac, FastParams p, 
     else hipLaunchKernelGGL((mttkrp_tiles_vec<TT, CT, RB, false>), grid, dim3(kThr), 0, st, T, fac, p, part);
   }
   CP_LAUNCH_CHECK(h);
-  launch_splitk_reduce(h, part, ks, n_out, p.R, M, st);
+  CP_TRY(launch_splitk_reduce(h, part, ks, n_out, p.R, M, st));
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }

@@ -202,7 +202,7 @@ int launch_vec(cp_handle* h, const TT* T, const CT* fac, DenseParams p, double* 
                        part);
   }
   CP_LAUNCH_CHECK(h);
-  launch_splitk_reduce(h, part, ks, n_out, p.R, M, st);
+  CP_TRY(launch_splitk_reduce(h, part, ks, n_out, p.R, M, st));
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
@@ -376,7 +376,7 @@ int launch_bf16x3(cp_handle* h, const float* T, const float* fac, DenseParams p,
     hipLaunchKernelGGL((mttkrp_bf16x3_kernel<S>), grid, dim3(kThreads), 0, st, T, fac, p, part);
   }
   CP_LAUNCH_CHECK(h);
-  launch_splitk_reduce(h, part, ks, n_out, p.R, M, st);
+  CP_TRY(launch_splitk_reduce(h, part, ks, n_out, p.R, M, st));
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }

@@ -595,7 +595,7 @@ int cp_destroy(cp_handle* h) {
   if (!h) return CP_OK;
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&h->part, &h->stage, &h->mbuf, &h->small, &h->red, &h->carry, &h->otab,
+  DevBuf* bufs[] = {&h->part, &h->part2, &h->stage, &h->mbuf, &h->small, &h->red, &h->carry, &h->otab,
                     &h->ybuf};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);

@@ -436,45 +436,44 @@ __global__ void factor_kernel(const double* __restrict__ G, int R, double* __res
   factor_block(G, R, F, kind, flags);
 }
 
-// A(i,:) = M(i,:) Gammabar^-1 using the factor from factor_block.  One
-// thread per row, its vector in LDS.
-__global__ __launch_bounds__(64) void solve_rows_kernel(const double* __restrict__ M,
-                                                        const double* __restrict__ F,
-                                                        const int* __restrict__ kind, int64_t I,
-                                                        int R, double* __restrict__ A) {
+// A(i,:) = M(i,:) Gammabar^-1 using the factor from factor_block.  One wave
+// per row (grid-stride over rows), lane q holding component q (R <= 64):
+// forward L y = m, then back L^T x = y, one component finished per step and
+// removed from the others by their lanes.
+__global__ __launch_bounds__(256) void solve_rows_kernel(const double* __restrict__ M,
+                                                         const double* __restrict__ F,
+                                                         const int* __restrict__ kind, int64_t I,
+                                                         int R, double* __restrict__ A) {
   __shared__ double f[kMaxR * kMaxR];
-  __shared__ double x[kMaxR * 64];   // x[r * 64 + lane]: conflict-free per r
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) f[e] = F[e];
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (i >= I) return;
-  double* y = x + threadIdx.x;
-#define Y(r) y[(r) * 64]
-  const double* m = M + i * R;
-#pragma unroll 8
-  for (int r = 0; r < R; ++r) Y(r) = m[r];   // the row's loads all go out first
-  if (*kind == 2) {
-    for (int c = 0; c < R; ++c) {
+  const int q = threadIdx.x & 63;
+  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const bool pinv = *kind == 2;
+  for (int64_t i = wave0; i < I; i += nwaves) {
+    double y = q < R ? M[i * R + q] : 0.0;
+    if (pinv) {
       double s = 0.0;
-      for (int q = 0; q < R; ++q) s = fma(Y(q), f[q * R + c], s);
-      A[i * R + c] = s;
+      for (int c = 0; c < R; ++c) {
+        const double mc = __shfl(y, c);
+        if (q < R) s = fma(mc, f[c * R + q], s);
+      }
+      if (q < R) A[i * R + q] = s;
+      continue;
     }
-    return;
+    for (int r = 0; r < R; ++r) {
+      const double yr = __shfl(y, r) / f[r * R + r];
+      if (q == r) y = yr;
+      else if (q > r && q < R) y -= f[q * R + r] * yr;
+    }
+    for (int r = R - 1; r >= 0; --r) {
+      const double xr = __shfl(y, r) / f[r * R + r];
+      if (q == r) y = xr;
+      else if (q < r) y -= f[r * R + q] * xr;
+    }
+    if (q < R) A[i * R + q] = y;
   }
-  // forward: L y = m
-  for (int r = 0; r < R; ++r) {
-    double s = Y(r);
-    for (int q = 0; q < r; ++q) s -= f[r * R + q] * Y(q);
-    Y(r) = s / f[r * R + r];
-  }
-  // backward: L^T x = y
-  for (int r = R - 1; r >= 0; --r) {
-    double s = Y(r);
-    for (int q = r + 1; q < R; ++q) s -= f[q * R + r] * Y(q);
-    Y(r) = s / f[r * R + r];
-  }
-  for (int r = 0; r < R; ++r) A[i * R + r] = Y(r);
-#undef Y
 }
 
 // G(i, r) = -M(i, r) + sum_s A(i, s) Gbar(s, r)
@@ -856,7 +855,11 @@ int mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int
     hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(256), 0, st, Gbar, R, F, kind, h->flags);
     CP_LAUNCH_CHECK(h);
   }
-  hipLaunchKernelGGL(solve_rows_kernel, dim3(nblk(I, 64)), dim3(64), 0, st, M, F, kind, I, R, A);
+  if (I > 0) {
+    const int64_t blocks = std::min<int64_t>((I + 3) / 4, 4096);   // 4 rows (waves) per block
+    hipLaunchKernelGGL(solve_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, M, F, kind, I,
+                       R, A);
+  }
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }

@@ -1,10 +1,11 @@
 // Fixed-order reduction of split-K partial slots, shared by the dense MTTKRP
 // kernels.  part holds nsplit slots of n values (slot-major).  Output e is
-//     M(e) = sum over 16 contiguous slot ranges, in range order, of the
+//     M(e) = sum over contiguous slot ranges, in range order, of the
 //            in-order sum of that range,
 // so the result depends only on nsplit and n, never on timing.  A block
-// covers 16 outputs (16 x 8 B contiguous per slot row) with 16 threads per
-// output; each thread issues its range's loads 8 at a time before adding.
+// covers 16 consecutive outputs with 16 threads per output; each thread
+// issues its range's loads 8 at a time before adding.  Many slots go through
+// a first stage over groups of 64 slots (see launch_splitk_reduce).
 // With a pending gradient epilogue on the handle (M is an I x R MTTKRP) the
 // same kernel also writes G(i, r) = -M(i, r) + sum_q A(i, q) Gbar(q, r), with
 // the sum in q order.
@@ -19,19 +20,20 @@
 namespace cpng {
 namespace {
 
-constexpr int kSplitOut = 16;     // outputs per block
-constexpr int kSplitRanges = 16;  // slot ranges per output
+constexpr int kSplitThreads = 256;
 
-template <typename PT>
-__global__ __launch_bounds__(kSplitOut * kSplitRanges) void splitk_reduce_kernel(
+// OUT outputs per block, RANGES slot ranges per output (OUT * RANGES = 256).
+template <typename PT, int OUT, int RANGES>
+__global__ __launch_bounds__(kSplitThreads) void splitk_reduce_kernel(
     const PT* __restrict__ part, int64_t nsplit, int64_t n, double* __restrict__ M,
     const double* __restrict__ eA, const double* __restrict__ eGbar, double* __restrict__ eG,
     int eR) {
-  __shared__ double sh[kSplitRanges][kSplitOut + 1];
-  const int tx = threadIdx.x % kSplitOut;
-  const int ty = threadIdx.x / kSplitOut;
-  const int64_t e = (int64_t)blockIdx.x * kSplitOut + tx;
-  const int64_t chunk = (nsplit + kSplitRanges - 1) / kSplitRanges;
+  static_assert(OUT * RANGES == kSplitThreads, "block shape");
+  __shared__ double sh[RANGES][OUT + 1];
+  const int tx = threadIdx.x % OUT;
+  const int ty = threadIdx.x / OUT;
+  const int64_t e = (int64_t)blockIdx.x * OUT + tx;
+  const int64_t chunk = (nsplit + RANGES - 1) / RANGES;
   const int64_t s0 = ty * chunk;
   const int64_t s1 = min<int64_t>(nsplit, s0 + chunk);
   double s = 0.0;
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(kSplitOut * kSplitRanges) void splitk_reduce_kernel
   if (ty == 0 && e < n) {
     double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < kSplitRanges; ++q) t += sh[q][tx];
+    for (int q = 0; q < RANGES; ++q) t += sh[q][tx];
     M[e] = t;
     if (eG) {
       const int64_t i = e / eR;
@@ -61,16 +63,58 @@ __global__ __launch_bounds__(kSplitOut * kSplitRanges) void splitk_reduce_kernel
   }
 }
 
-// R: columns of M (for the epilogue).
+// First stage for many slots: block (x, g) adds slots 64g .. 64g + 63 for the
+// 64 outputs 64x .. 64x + 63 (a wave reads 64 consecutive outputs of one slot
+// row), four quarter-ranges of 16 slots in order, into part2[g][e].
 template <typename PT>
-inline void launch_splitk_reduce(cp_handle* h, const PT* part, int64_t nsplit, int64_t n, int R,
-                                 double* M, hipStream_t st) {
+__global__ __launch_bounds__(kSplitThreads) void splitk_group_kernel(const PT* __restrict__ part,
+                                                                     int64_t nsplit, int64_t n,
+                                                                     double* __restrict__ part2) {
+  __shared__ double sh[4][64];
+  const int tx = threadIdx.x & 63;
+  const int ty = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + tx;
+  const int64_t q0 = (int64_t)blockIdx.y * 64 + ty * 16;
+  const int64_t q1 = min<int64_t>(nsplit, q0 + 16);
+  double s = 0.0;
+  if (e < n) {
+    PT v[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = q0 + b < q1 ? part[(q0 + b) * n + e] : PT(0);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) s += (double)v[b];
+  }
+  sh[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && e < n) part2[(int64_t)blockIdx.y * n + e] = (sh[0][tx] + sh[1][tx]) + (sh[2][tx] + sh[3][tx]);
+}
+
+// R: columns of M (for the epilogue).  Up to 256 slots: one pass with 16
+// ranges per output.  More: groups of 64 slots first (coalesced), then the
+// group sums.  The shape depends only on nsplit and n, so the order of the
+// additions is fixed for given sizes.
+template <typename PT>
+inline int launch_splitk_reduce(cp_handle* h, const PT* part, int64_t nsplit, int64_t n, int R,
+                                double* M, hipStream_t st) {
   GradEpi& ep = h->epi;
   const bool epi = ep.G != nullptr && !ep.used;
-  hipLaunchKernelGGL((splitk_reduce_kernel<PT>), dim3((unsigned)((n + kSplitOut - 1) / kSplitOut)),
-                     dim3(kSplitOut * kSplitRanges), 0, st, part, nsplit, n, M,
-                     epi ? ep.A : nullptr, epi ? ep.Gbar : nullptr, epi ? ep.G : nullptr, R);
+  const double* eA = epi ? ep.A : nullptr;
+  const double* eGb = epi ? ep.Gbar : nullptr;
+  double* eG = epi ? ep.G : nullptr;
+  if (nsplit <= 256) {
+    hipLaunchKernelGGL((splitk_reduce_kernel<PT, 16, 16>), dim3((unsigned)((n + 15) / 16)),
+                       dim3(kSplitThreads), 0, st, part, nsplit, n, M, eA, eGb, eG, R);
+  } else {
+    const int64_t groups = (nsplit + 63) / 64;
+    CP_TRY(ensure(h, h->part2, sizeof(double) * (size_t)(groups * n), st));
+    double* part2 = static_cast<double*>(h->part2.ptr);
+    hipLaunchKernelGGL((splitk_group_kernel<PT>), dim3((unsigned)((n + 63) / 64), (unsigned)groups),
+                       dim3(kSplitThreads), 0, st, part, nsplit, n, part2);
+    hipLaunchKernelGGL((splitk_reduce_kernel<double, 16, 16>), dim3((unsigned)((n + 15) / 16)),
+                       dim3(kSplitThreads), 0, st, part2, groups, n, M, eA, eGb, eG, R);
+  }
   if (epi) ep.used = true;
+  return CP_OK;
 }
 
 }  // namespace

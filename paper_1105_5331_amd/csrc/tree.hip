@@ -306,13 +306,13 @@ int tree_mode(cp_handle* h, const Shape& s, const void* Y, const void* fac, int 
     hipLaunchKernelGGL(ymttkrp_kernel<float>, grid, dim3(kThr), 0, st,
                        static_cast<const float*>(Y), static_cast<const float*>(fac), p, part);
     CP_LAUNCH_CHECK(h);
-    launch_splitk_reduce(h, part, nch, n_out, R, M, st);
+    CP_TRY(launch_splitk_reduce(h, part, nch, n_out, R, M, st));
   } else {
     double* part = static_cast<double*>(h->part.ptr);
     hipLaunchKernelGGL(ymttkrp_kernel<double>, grid, dim3(kThr), 0, st,
                        static_cast<const double*>(Y), static_cast<const double*>(fac), p, part);
     CP_LAUNCH_CHECK(h);
-    launch_splitk_reduce(h, part, nch, n_out, R, M, st);
+    CP_TRY(launch_splitk_reduce(h, part, nch, n_out, R, M, st));
   }
   CP_LAUNCH_CHECK(h);
   return CP_OK;
