@@ -133,9 +133,11 @@ def test_step_by_step_state_api(h):
 
 
 @pytest.mark.parametrize("bulk", ["fp32", "bf16x3"])
-def test_mixed_precision_reaches_fp64_certified_tolerance(h, bulk):
-    """Reduced-precision bulk, then FP64 accumulation: the final rho is certified
-    with a float64 gradient and the final h equals the FP64 run's h."""
+@pytest.mark.parametrize("stall", [1, 0])
+def test_mixed_precision_reaches_fp64_certified_tolerance(h, bulk, stall):
+    """Reduced-precision bulk, then FP64 accumulation (with and without the
+    stalled-line-search trigger): the final rho is certified with a float64
+    gradient and the final h equals the FP64 run's h."""
     import paper_1105_5331_amd as cpng
     dims, R, tol = (30, 30, 30), 4, 1e-8
     p = test_problem_1(dims, R, 0.5, 1, 1, seed=9, dtype=np.float32)
@@ -144,7 +146,8 @@ def test_mixed_precision_reaches_fp64_certified_tolerance(h, bulk):
     u0 = initial_guess(dims, R, seed=10009)
     u_mixed = _dev(u0)
     out = cpng.cp_decompose(h, Tg, R, tol, u_mixed, max_iter=400, precision=bulk,
-                            final_precision="fp32in_fp64acc", switch_rho=1e-5)
+                            final_precision="fp32in_fp64acc", switch_rho=1e-5,
+                            switch_on_stall=stall)
     assert out["converged"] and out["switch_iter"] >= 0
     u64 = _dev(u0)
     ref = cpng.cp_decompose(h, Tg, R, tol, u64, max_iter=400)

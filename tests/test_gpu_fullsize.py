@@ -3,7 +3,10 @@ times, on sampled outputs: whole rows M^(n)(i, :) recomputed by the oracle
 from the definition restricted to the sampled indices i.
 
 * dense 128^4 float32, R = 32 (BF16X3 and FP32 kernels, every mode);
-* sparse 20000^3 COO with about 2e7 nonzeros, R = 16 (FP32, every mode).
+* sparse 20000^3 COO with about 2e7 nonzeros, R = 16 (FP32, every mode);
+* dense 200^3, R = 10, congruence 0.9 (the time-to-gradient study): f and g
+  at the initial guess in every precision, whole (the oracle finishes them
+  in about a second).
 """
 import numpy as np
 import pytest
@@ -69,3 +72,27 @@ def test_sparse_20000x3_R16_sampled_rows(h):
             assert_close_to_bound(M[i][None], ref[None], bound[None], TOL["fp32"],
                                   f"mode {n} row {i}")
     cpng.cp_tensor_release(h, Tg)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32in_fp64acc", 1e-12),
+                                      ("fp32", 1e-5), ("bf16x3", 1e-4)])
+def test_dense_200x3_R10_objective_grad(h, prec, tol):
+    """|df| / (1/2 ||T||^2 + |f|) and ||dg|| / (||T|| + ||g||) against the
+    oracle on the same tensor (float64 for "fp64", the float32 tensor widened
+    otherwise).  At the random initial guess f is about 2e5 (1/2 ||T||^2), and
+    the rounding of f and g scales with the terms they are formed from."""
+    import paper_1105_5331_amd as cpng
+    dims, R = (200, 200, 200), 10
+    print(f"case dense 200^3 R=10 objective/gradient {prec}", flush=True)
+    p = test_problem_1(dims, R, 0.9, 1, 1, seed=0, dtype=np.float64 if prec == "fp64" else np.float32)
+    T64 = p.T.astype(np.float64)
+    Tg = cpng.Tensor(dims, torch.from_numpy(p.T).cuda().reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u0 = initial_guess(dims, R, seed=10000)
+    A = ocp.split_u(u0, dims, R)
+    f, g = cpng.cp_objective_grad(h, Tg, torch.from_numpy(u0).cuda(), R, prec)
+    half = 0.5 * float(np.sum(T64 ** 2))
+    fo = ocp.objective_direct(T64, A)
+    go = ocp.join_u(ocp.gradient_from_mttkrps(A, [ocp.mttkrp(T64, A, n) for n in range(3)]))
+    assert abs(f.item() - fo) / (half + abs(fo)) <= tol
+    assert np.linalg.norm(g.cpu().numpy() - go) / (np.sqrt(2 * half) + np.linalg.norm(go)) <= tol
