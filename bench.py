@@ -508,7 +508,7 @@ def main():
     for k in range(args.steps):
         info = st.step()
         infos.append(info)
-        passes += N * (2 + info["nfev"])
+        passes += info["t_passes"]
         log(f"step {k}: f {info['f']:.6e} rho {info['rho']:.3e} nfev {info['nfev']} "
             f"restart {info['restart']}")
     torch.cuda.synchronize()

@@ -108,6 +108,7 @@ typedef struct cp_iter_info {
   int32_t ls_status;   /* 0 converged, 1 maxfev, 2 xtol, 3 stpmax, 4 stpmin, 5 rounding, -1 none */
   int32_t m;           /* window size used by Step II */
   int32_t precision;   /* cp_precision of the bulk MTTKRPs in this iteration */
+  int32_t t_passes;    /* passes over the tensor's values made by this iteration's MTTKRPs */
 } cp_iter_info;
 
 #define CP_METHOD_NGMRES 0
@@ -138,10 +139,13 @@ typedef struct cp_options {
   int32_t normalize_accel;  /* normalise the accelerated iterate (1) */
   cp_iter_info* trace;      /* host, nullable: per-iteration records */
   int32_t trace_cap;        /* capacity of trace */
-  int32_t mttkrp_tree;      /* dense tensors of order >= 3, bulk not BF16X3: form
-                               Y = T x_N A^(N) once per gradient evaluation and per ALS
-                               sweep and take M^(1..N-1) from Y, so T is streamed twice
-                               instead of N times (1); 0 = one pass per mode */
+  int32_t mttkrp_tree;      /* dense tensors of order >= 3: split the modes into a left
+                               and a right group, contract T once with each group's
+                               complement (two partial MTTKRPs on the same kernels and
+                               precision as a per-mode MTTKRP) and take every M^(n) from
+                               its group's partial in float64, so a gradient evaluation
+                               or ALS sweep streams T twice instead of N times (1);
+                               0 = one pass per mode */
   int32_t switch_on_stall;  /* with switch_rho > 0, also switch once rho <= 1e-2 after a
                                line search in the first precision ends without a Wolfe
                                point (1) */
@@ -326,6 +330,8 @@ int cp_server_destroy(cp_server* s);
 #define CP_KERNEL_DENSE_MTTKRP  0   /* main dense MTTKRP kernel (any precision) */
 #define CP_KERNEL_SPARSE_MTTKRP 1   /* main sparse segmented-reduction kernel */
 #define CP_KERNEL_STREAM_READ   2   /* cp_stream_read */
+#define CP_KERNEL_GROUP_MTTKRP  3   /* second level of the two-level evaluation: one mode's
+                                       MTTKRP from its group's partial contraction */
 
 /* Enable (1) or disable (0) HIP-event timing of the main MTTKRP kernels on
  * the stream each is launched on; enabling clears the counters. */

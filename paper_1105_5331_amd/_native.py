@@ -42,7 +42,7 @@ class cp_tensor(C.Structure):
 class cp_iter_info(C.Structure):
     _fields_ = [("it", C.c_int32), ("f", C.c_double), ("rho", C.c_double), ("beta", C.c_double),
                 ("restart", C.c_int32), ("nfev", C.c_int32), ("ls_status", C.c_int32),
-                ("m", C.c_int32), ("precision", C.c_int32)]
+                ("m", C.c_int32), ("precision", C.c_int32), ("t_passes", C.c_int32)]
 
 
 class cp_options(C.Structure):
@@ -365,7 +365,7 @@ class NGMRESState:
             pass
 
 
-CP_KERNEL_DENSE_MTTKRP, CP_KERNEL_SPARSE_MTTKRP, CP_KERNEL_STREAM_READ = 0, 1, 2
+CP_KERNEL_DENSE_MTTKRP, CP_KERNEL_SPARSE_MTTKRP, CP_KERNEL_STREAM_READ, CP_KERNEL_GROUP_MTTKRP = 0, 1, 2, 3
 
 
 def cp_stream_read(h: Handle, buf):
@@ -391,7 +391,7 @@ def ngmres_step(state: NGMRESState):
 def _info_dict(r: cp_iter_info):
     return {"it": r.it, "f": r.f, "rho": r.rho, "beta": r.beta, "restart": bool(r.restart),
             "nfev": r.nfev, "ls_status": LS_STATUS.get(r.ls_status, str(r.ls_status)), "m": r.m,
-            "precision": r.precision}
+            "precision": r.precision, "t_passes": r.t_passes}
 
 
 def cp_decompose(h: Handle, T: Tensor, R: int, tol: float, u_inout, trace_cap=0, **opts):

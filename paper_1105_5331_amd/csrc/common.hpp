@@ -55,9 +55,11 @@ struct cp_handle {
   // optional event timing of the main MTTKRP kernels
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[3];
-  int64_t prof_launches[3] = {0, 0, 0};
-  double prof_ms[3] = {0.0, 0.0, 0.0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[4];
+  int64_t prof_launches[4] = {0, 0, 0, 0};
+  double prof_ms[4] = {0.0, 0.0, 0.0, 0.0};
+  // passes over a tensor's values made by MTTKRP launches (always counted)
+  int64_t t_passes = 0;
 };
 
 namespace cpng {
@@ -147,12 +149,14 @@ template <typename TT, typename CT>
 int dense_fast_vec(cp_handle* h, const TT* T, const CT* fac, const Shape& s, int R, int mode,
                    double* M, hipStream_t st);
 
-// two-level evaluation of all modes (tree.hip)
-bool tree_applies(const cp_tensor* T, const Shape& s, int prec);
-int tree_contract_last(cp_handle* h, const cp_tensor* T, const Shape& s, const void* fac, int R,
-                       int prec, void* Y, hipStream_t st);
-int tree_mode(cp_handle* h, const Shape& s, const void* Y, const void* fac, int R, int mode,
-              int prec, double* M, hipStream_t st);
+// two-level evaluation of all modes (tree.hip): left modes [0, split), right
+// modes [split, N).  tree_split returns the split, or 0 where it does not apply.
+int tree_split(const cp_tensor* T, const Shape& s, int prec);
+size_t tree_partial_elems(const Shape& s, int split, int R, bool left);
+int tree_partial(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R, int prec,
+                 int split, bool left, double* X, hipStream_t st);
+int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, const double* u, int R,
+              int mode, double* M, hipStream_t st);
 
 // small kernels
 // With factor_mode >= 0 also factorises Gammabar^(factor_mode) for the next

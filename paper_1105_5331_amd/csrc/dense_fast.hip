@@ -67,7 +67,7 @@ struct FastParams {
   int64_t o_per_block;
   int kpad;                          // LDS row length (bf16) of the staged inner factor
   int nks;                           // K steps of 32
-  int vec_ok;                        // 16-byte loads along the unit-stride index are aligned
+  int vec_ok;                        // wide loads along the unit-stride index are aligned
   int64_t Opad;                      // O rounded up to 4
   int ptrans;                        // P table rank-major (row-stream kernel) or o-major
 };
@@ -307,22 +307,36 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
       }
 }
 
-// Column-kernel operand: rows k .. k+7 of columns (w*NT + nt)*16 + lr.
+// Column-kernel operand: rows k .. k+7 of the lane's NT consecutive columns
+// col0 .. col0+NT-1 (column col0 + nt feeds MFMA tile nt), one NT-wide load
+// per row when the group lies inside I_n and I_n is a multiple of NT (every
+// row offset is a multiple of I_n, so the load is aligned).
 template <int NT>
 __device__ inline void load_cols(const float* __restrict__ T, const FastParams& p, int64_t base,
-                                 const int64_t (&col)[NT], const bool (&colok)[NT], int k0,
-                                 float (&v)[NT][8]) {
+                                 int64_t col0, int k0, float (&v)[NT][8]) {
   // the lane group's 8 consecutive k-rows (K is a multiple of 8)
   const int k = k0 + kload_a((threadIdx.x & 63) >> 4);
+  const float* src = T + base + (int64_t)k * p.kstride + col0;
+  if (k < p.K && p.vec_ok && col0 < p.I_n) {
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
-    if (colok[nt] && k < p.K) {
-      const float* src = T + base + (int64_t)k * p.kstride + col[nt];
+    for (int q = 0; q < 8; ++q) {
+      const float* s = src + (int64_t)q * p.kstride;
+      if constexpr (NT == 4) {
+        const float4 x = *reinterpret_cast<const float4*>(s);
+        v[0][q] = x.x; v[1][q] = x.y; v[2][q] = x.z; v[3][q] = x.w;
+      } else if constexpr (NT == 2) {
+        const float2 x = *reinterpret_cast<const float2*>(s);
+        v[0][q] = x.x; v[1][q] = x.y;
+      } else {
+        v[0][q] = s[0];
+      }
+    }
+  } else {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[nt][q] = src[(int64_t)q * p.kstride];
-    } else {
+    for (int nt = 0; nt < NT; ++nt) {
+      const bool ok = k < p.K && col0 + nt < p.I_n;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[nt][q] = 0.f;
+      for (int q = 0; q < 8; ++q) v[nt][q] = ok ? src[(int64_t)q * p.kstride + nt] : 0.f;
     }
   }
 }
@@ -347,14 +361,8 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
   stage_inner(fac, p, r0, Sh, Sl);
   __syncthreads();
 
-  int64_t col[NT];
-  bool colok[NT];
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
-    const int64_t i = i0 + (w * NT + nt) * 16 + lr;
-    colok[nt] = i < p.I_n;
-    col[nt] = colok[nt] ? i : 0;
-  }
+  // this lane's columns: col0 + nt for tile nt
+  const int64_t col0 = i0 + (int64_t)w * 16 * NT + lr * NT;
   floatx4 acc[2][NT];
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
@@ -373,7 +381,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
     int jl = 0, kl = 0;
 #pragma unroll
     for (int b = 0; b < PF; ++b) {
-      if (b < nit) load_cols<NT>(T, p, base_tab[jl], col, colok, kl * 32, buf[b]);
+      if (b < nit) load_cols<NT>(T, p, base_tab[jl], col0, kl * 32, buf[b]);
       if (++kl == p.nks) { kl = 0; ++jl; }
     }
     floatx4 Y[2][NT];
@@ -383,7 +391,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
       for (int nt = 0; nt < NT; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
     int j = 0, ks = 0;
     for (int it = 0; it < nit; ++it) {
-      if (it + PF < nit) load_cols<NT>(T, p, base_tab[jl], col, colok, kl * 32, buf[PF]);
+      if (it + PF < nit) load_cols<NT>(T, p, base_tab[jl], col0, kl * 32, buf[PF]);
       if (++kl == p.nks) { kl = 0; ++jl; }
       const int k = ks * 32 + kb;
       const int so0 = lr * p.kpad + k;
@@ -436,13 +444,14 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = r0 + mt * 16 + (lane >> 4) * 4 + q;
-        const int64_t i = i0 + (w * NT + nt) * 16 + lr;
+        const int64_t i = col0 + nt;
         if (i < p.I_n && r < p.R) out[i * p.R + r] = acc[mt][nt][q];
       }
 }
 
-// Row-stream kernel (n < N-2, long contiguous runs): one output row i per
-// workgroup.  For fixed i the entries T(o, i, k) of consecutive outer
+// Row-stream kernel (n < N-2, long contiguous runs): output rows i taken
+// grid-stride by the workgroups (one staging of the inner factor serves all
+// of a workgroup's rows).  For fixed i the entries T(o, i, k) of consecutive outer
 // indices o are contiguous in memory (runs of I_right elements), so here the
 // MFMA M dimension is the outer index: Y(o, r) = sum_k T(o, i, k) A^(q)(k, r)
 // for 16 consecutive o per tile, then acc(r) += sum_o P(o, r) Y(o, r).  A
@@ -465,13 +474,14 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
   const int lr = lane & 15;
   const int kb = (lane >> 4) * 8;
   const int r0 = blockIdx.z * 32;
-  const int64_t bx = blockIdx.x, by = blockIdx.y;
-  const int64_t ioff = by * p.istride;
+  const int64_t bx = blockIdx.x;
   stage_inner(fac, p, r0, Sh, Sl);
   __syncthreads();
-  float acc0 = 0.f, acc1 = 0.f;   // rank columns r0 + lr and r0 + 16 + lr
   const int64_t ob = bx * p.o_per_block;
   const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
+  for (int64_t by = blockIdx.y; by < p.I_n; by += gridDim.y) {
+  const int64_t ioff = by * p.istride;
+  float acc0 = 0.f, acc1 = 0.f;   // rank columns r0 + lr and r0 + 16 + lr
   for (int64_t og = ob + w * 16 * TW; og < oe; og += 4 * 16 * TW) {
     const float* rowp[TW];
     bool ok[TW];
@@ -557,6 +567,8 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
     const int c = threadIdx.x;
     const float sum = (red[0][c] + red[2][c]) + (red[1][c] + red[3][c]);
     if (r0 + c < p.R) part[bx * p.I_n * p.R + by * p.R + r0 + c] = sum;
+  }
+  __syncthreads();   // red is rewritten for the next row
   }
 }
 
@@ -779,9 +791,14 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   const bool stream_rows = rows && mode < N - 2 && (stride[mode] / K) >= 16;
   const int tile = stream_rows ? 1 : (p.I_n > 64 ? 128 : 64);
   p.ptrans = stream_rows ? 1 : 0;
+  // column kernel: one (tile / 64)-wide load per k-row when I_n allows it
+  p.vec_ok = !rows && p.I_n % (tile / 64) == 0;
   const int64_t ychunks = (p.I_n + tile - 1) / tile;
   const int64_t rchunks = (R + 31) / 32;
   const int64_t target = CPNG_STREAM_BLOCKS;
+  // row-stream workgroups loop over rows: at most about `target` of them
+  const int64_t ygrid = stream_rows ? std::min<int64_t>(ychunks, (target + rchunks - 1) / rchunks)
+                                    : ychunks;
   int64_t ks = std::max<int64_t>(1, std::min<int64_t>(p.O, (target + ychunks * rchunks - 1) / (ychunks * rchunks)));
   p.o_per_block = ((p.O + ks - 1) / ks + 15) / 16 * 16;
   ks = (p.O + p.o_per_block - 1) / p.o_per_block;
@@ -789,7 +806,7 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   const int64_t n_out = p.I_n * R;
   CP_TRY(ensure(h, h->part, sizeof(float) * (size_t)(ks * n_out), st));
   float* part = static_cast<float*>(h->part.ptr);
-  dim3 grid((unsigned)ks, (unsigned)ychunks, (unsigned)rchunks);
+  dim3 grid((unsigned)ks, (unsigned)ygrid, (unsigned)rchunks);
   const size_t lds = 2 * sizeof(__bf16) * 32 * (size_t)p.kpad;
   // outer tables: P (O x R floats) then base offsets (O int64)
   const size_t pbytes = (sizeof(float) * (size_t)(p.Opad * R) + 255) & ~size_t(255);

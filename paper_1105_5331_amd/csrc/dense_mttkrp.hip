@@ -415,6 +415,7 @@ int stage_factors_f32(cp_handle* h, const double* u, int64_t L, float** out, hip
 
 int dense_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
                  int mode, int prec, double* M, hipStream_t st) {
+  h->t_passes++;
   DenseParams p = make_params(s, R, mode);
   const int64_t L = s.sum_dims() * R;
 

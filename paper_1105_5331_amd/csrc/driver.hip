@@ -47,6 +47,7 @@ struct cp_ngmres_state {
     int prec = -1;
     bool warm = false;     // ran once eagerly at the current precision
     bool failed = false;   // capture not possible: stay eager
+    int64_t passes = 0;    // passes over T per replay
   } cap[2];
 };
 
@@ -106,43 +107,51 @@ int scratch(cp_handle* h, const Shape& s, int R, hipStream_t st, Scratch* sc) {
   return CP_OK;
 }
 
-// Factors as the kernels of precision `prec` read them: the float64 iterate,
-// or its float32 copy (refreshed by this call).
-int kernel_factors(cp_handle* h, const Shape& s, const double* u, int R, int prec,
-                   const void** fac, hipStream_t st) {
-  if (prec == CP_PREC_FP32) {
-    float* f32 = nullptr;
-    CP_TRY(stage_factors_f32(h, u, s.sum_dims() * R, &f32, st));
-    *fac = f32;
-  } else {
-    *fac = u;
-  }
+// Buffers of the two-level evaluation (tree.hip): the partial of each mode
+// group with more than one mode, float64, in the handle's workspace.
+struct TreeBufs {
+  int split = 0;            // 0: one MTTKRP pass per mode
+  double* XL = nullptr;     // modes [0, split)
+  double* XR = nullptr;     // modes [split, N)
+};
+
+int tree_setup(cp_handle* h, const cp_tensor* T, const Shape& s, int R, int prec, bool tree,
+               hipStream_t st, TreeBufs* tb) {
+  *tb = TreeBufs{};
+  if (!tree) return CP_OK;
+  const int split = tree_split(T, s, prec);
+  if (!split) return CP_OK;
+  const size_t nl = tree_partial_elems(s, split, R, true);
+  const size_t nr = tree_partial_elems(s, split, R, false);
+  CP_TRY(ensure(h, h->ybuf, sizeof(double) * (nl + nr), st));
+  double* b = static_cast<double*>(h->ybuf.ptr);
+  tb->split = split;
+  if (nl) tb->XL = b;
+  if (nr) tb->XR = b + nl;
   return CP_OK;
 }
 
-// Y = T contracted with the last factor (two-level evaluation, `tree.hip`).
-int tree_start(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R, int prec,
-               const void** fac, void** Y, hipStream_t st) {
-  const size_t eb = prec == CP_PREC_FP32 ? 4 : 8;
-  CP_TRY(ensure(h, h->ybuf, eb * (size_t)(s.total() / s.dims[s.N - 1]) * R, st));
-  *Y = h->ybuf.ptr;
-  CP_TRY(kernel_factors(h, s, u, R, prec, fac, st));
-  return tree_contract_last(h, T, s, *fac, R, prec, *Y, st);
+// M^(n) from its group's partial (formed beforehand), or by its own pass over T.
+int mode_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R, int n,
+                int prec, const TreeBufs& tb, double* Mn, hipStream_t st) {
+  if (tb.XL && n < tb.split) return tree_mode(h, s, 0, tb.split, tb.XL, u, R, n, Mn, st);
+  if (tb.XR && n >= tb.split) return tree_mode(h, s, tb.split, s.N, tb.XR, u, R, n, Mn, st);
+  return mttkrp_any(h, T, s, u, R, n, prec, Mn, st);
 }
 
 // f and g at u: all N MTTKRPs at the same point (Section 2.3), the gradient
 // epilogue G^(n) = -M^(n) + A^(n) Gammabar^(n) and the objective from the
-// last mode's M and Gamma.  With `tree` (dense, order >= 3, not BF16x3) the
-// first N-1 MTTKRPs come from the contracted Y: T is streamed twice.
+// last mode's M and Gamma.  With `tree` (dense, order >= 3) the MTTKRPs come
+// from the two group partials: T is streamed twice.
 int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
                         int prec, double* f_out, double* g_out, hipStream_t st, bool tree = true) {
   Scratch sc;
   CP_TRY(scratch(h, s, R, st, &sc));
   CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, sc.Gam, st));
-  const bool use_tree = tree && tree_applies(T, s, prec);
-  const void* fac = nullptr;
-  void* Y = nullptr;
-  if (use_tree) CP_TRY(tree_start(h, T, s, u, R, prec, &fac, &Y, st));
+  TreeBufs tb;
+  CP_TRY(tree_setup(h, T, s, R, prec, tree, st, &tb));
+  if (tb.XL) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, true, tb.XL, st));
+  if (tb.XR) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, false, tb.XR, st));
   struct EpiScope {   // the pending epilogue never outlives one MTTKRP call
     cp_handle* h;
     ~EpiScope() { h->epi = GradEpi{}; }
@@ -155,8 +164,7 @@ int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const 
     {
       EpiScope scope{h};
       if (Gn) h->epi = GradEpi{An, sc.Gbar + n * R * R, Gn, false};
-      if (use_tree && n < s.N - 1) CP_TRY(tree_mode(h, s, Y, fac, R, n, prec, Mn, st));
-      else CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
+      CP_TRY(mode_mttkrp(h, T, s, u, R, n, prec, tb, Mn, st));
       fused = h->epi.used;
     }
     if (Gn && !fused)
@@ -171,25 +179,21 @@ int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const 
 }
 
 // One ALS sweep (Section 2.3): for n = 1..N in order, A^(n) = M^(n) Gammabar^(n)^-1
-// with the factors updated so far.  With `tree`, Y is formed once with A^(N)
-// (untouched until the last mode) and M^(1..N-1) come from it.
+// with the factors updated so far.  With `tree`, the left group's partial is
+// formed first (the right factors are untouched until the split) and the
+// right group's once the left modes are updated.
 int als_sweep_impl(cp_handle* h, const cp_tensor* T, const Shape& s, double* u, int R, int prec,
                    int normalize_after, hipStream_t st, bool tree = true) {
   Scratch sc;
   CP_TRY(scratch(h, s, R, st, &sc));
-  const bool use_tree = tree && tree_applies(T, s, prec);
-  const void* fac = nullptr;
-  void* Y = nullptr;
-  if (use_tree) CP_TRY(tree_start(h, T, s, u, R, prec, &fac, &Y, st));
+  TreeBufs tb;
+  CP_TRY(tree_setup(h, T, s, R, prec, tree, st, &tb));
+  if (tb.XL) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, true, tb.XL, st));
   for (int n = 0; n < s.N; ++n) {
+    if (tb.XR && n == tb.split) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, false, tb.XR, st));
     CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, nullptr, st, n));   // and factorises Gbar^(n)
     double* Mn = sc.M + s.off[n] * R;
-    if (use_tree && n < s.N - 1) {
-      if (n > 0) CP_TRY(kernel_factors(h, s, u, R, prec, &fac, st));   // after the update
-      CP_TRY(tree_mode(h, s, Y, fac, R, n, prec, Mn, st));
-    } else {
-      CP_TRY(mttkrp_any(h, T, s, u, R, n, prec, Mn, st));
-    }
+    CP_TRY(mode_mttkrp(h, T, s, u, R, n, prec, tb, Mn, st));
     CP_TRY(mode_solve(h, Mn, nullptr, s.dims[n], R, u + s.off[n] * R, st));
   }
   if (normalize_after) CP_TRY(normalize(h, s, u, R, nullptr, st));
@@ -321,6 +325,7 @@ int run_phase(cp_handle* h, cp_ngmres_state* S, int ph) {
   if (c.h != h || c.gen != h->gen || c.prec != S->prec) drop_captured(c);
   if (c.exec) {
     CP_HIP(h, hipGraphLaunch(c.exec, S->st));
+    h->t_passes += c.passes;
     return CP_OK;
   }
   if (!c.warm) {
@@ -332,6 +337,7 @@ int run_phase(cp_handle* h, cp_ngmres_state* S, int ph) {
     return CP_OK;
   }
   const uint64_t gen0 = h->gen;
+  const int64_t passes0 = h->t_passes;
   if (hipStreamBeginCapture(S->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
     c.failed = true;
@@ -351,12 +357,14 @@ int run_phase(cp_handle* h, cp_ngmres_state* S, int ph) {
   if (graph) (void)hipGraphDestroy(graph);
   if (!ok) {   // nothing of the capture ran: do the phase eagerly
     c.failed = true;
+    h->t_passes = passes0;
     return enqueue();
   }
   c.exec = exec;
   c.h = h;
   c.gen = h->gen;
   c.prec = S->prec;
+  c.passes = h->t_passes - passes0;   // counted while recording, run by the launch below
   CP_HIP(h, hipGraphLaunch(c.exec, S->st));
   return CP_OK;
 }
@@ -622,7 +630,7 @@ int cp_profile(cp_handle* h, int32_t enable) {
     }
     v.clear();
   }
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     h->prof_launches[k] = 0;
     h->prof_ms[k] = 0.0;
   }
@@ -637,7 +645,7 @@ int cp_stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t stre
 }
 
 int cp_profile_read(cp_handle* h, int32_t kernel, int64_t* launches, double* total_ms) {
-  if (!h || kernel < 0 || kernel > 2 || !launches || !total_ms) return CP_EINVAL;
+  if (!h || kernel < 0 || kernel > 3 || !launches || !total_ms) return CP_EINVAL;
   CP_HIP(h, hipSetDevice(h->device));
   auto& v = h->ev_pending[kernel];
   for (auto& pr : v) {
@@ -885,6 +893,7 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
   rec.ls_status = -1;
   rec.m = S->opt.method == CP_METHOD_NGMRES ? S->wcount : 0;
   rec.precision = S->prec;
+  const int64_t passes0 = h->t_passes;
   int rc = CP_OK;
   if (S->opt.method == CP_METHOD_ALS) {
     CP_TRY(als_sweep_impl(h, S->T, S->s, S->u, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0));
@@ -938,6 +947,7 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
     CP_TRY(window_push(h, S));
   }
   S->it++;
+  rec.t_passes = (int32_t)(h->t_passes - passes0);
   if (info) *info = rec;
   return rc;
 }

@@ -527,6 +527,7 @@ void set_offsets(const Shape& s, int mode, SparseParams& p) {
 
 int sparse_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
                   int mode, int prec, double* M, hipStream_t st) {
+  h->t_passes++;
   auto* sp = static_cast<const SparsePrepared*>(T->prepared);
   if (!sp) return fail(h, CP_EINVAL, "sparse tensor is not prepared (cp_tensor_prepare)");
   if (prec == CP_PREC_BF16X3) return fail(h, CP_EINVAL, "BF16X3 applies to dense tensors only");

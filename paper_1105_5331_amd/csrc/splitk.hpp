@@ -2,10 +2,12 @@
 // kernels.  part holds nsplit slots of n values (slot-major).  Output e is
 //     M(e) = sum over contiguous slot ranges, in range order, of the
 //            in-order sum of that range,
-// so the result depends only on nsplit and n, never on timing.  A block
-// covers 16 consecutive outputs with 16 threads per output; each thread
-// issues its range's loads 8 at a time before adding.  Many slots go through
-// a first stage over groups of 64 slots (see launch_splitk_reduce).
+// so the result depends only on nsplit and n, never on timing.  Up to 16
+// slots, one thread per output adds all slots in order (256 consecutive
+// outputs per block, every slot's load in flight at once).  Up to 256, a
+// block covers 16 consecutive outputs with 16 threads per output; each
+// thread issues its range's loads 8 at a time before adding.  Many slots go
+// through a first stage over groups of 64 slots (see launch_splitk_reduce).
 // With a pending gradient epilogue on the handle (M is an I x R MTTKRP) the
 // same kernel also writes G(i, r) = -M(i, r) + sum_q A(i, q) Gbar(q, r), with
 // the sum in q order.
@@ -63,6 +65,37 @@ __global__ __launch_bounds__(kSplitThreads) void splitk_reduce_kernel(
   }
 }
 
+// Few slots: thread e adds slots 0..nsplit-1 of output e in order.  With the
+// epilogue, Gbar (R x R) is staged in LDS (dynamic, R * R doubles).
+template <typename PT>
+__global__ __launch_bounds__(kSplitThreads) void splitk_flat_kernel(
+    const PT* __restrict__ part, int nsplit, int64_t n, double* __restrict__ M,
+    const double* __restrict__ eA, const double* __restrict__ eGbar, double* __restrict__ eG,
+    int eR) {
+  extern __shared__ double gsh[];
+  const int64_t e = (int64_t)blockIdx.x * kSplitThreads + threadIdx.x;
+  if (eG) {
+    for (int t = threadIdx.x; t < eR * eR; t += kSplitThreads) gsh[t] = eGbar[t];
+    __syncthreads();
+  }
+  if (e >= n) return;
+  PT v[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) v[b] = b < nsplit ? part[(int64_t)b * n + e] : PT(0);
+  double t = 0.0;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) t += (double)v[b];
+  M[e] = t;
+  if (eG) {
+    const int64_t i = e / eR;
+    const int r = (int)(e - i * eR);
+    const double* a = eA + i * eR;
+    double g = 0.0;
+    for (int q = 0; q < eR; ++q) g = fma(a[q], gsh[q * eR + r], g);
+    eG[e] = g - t;
+  }
+}
+
 // First stage for many slots: block (x, g) adds slots 64g .. 64g + 63 for the
 // 64 outputs 64x .. 64x + 63 (a wave reads 64 consecutive outputs of one slot
 // row), four quarter-ranges of 16 slots in order, into part2[g][e].
@@ -101,7 +134,11 @@ inline int launch_splitk_reduce(cp_handle* h, const PT* part, int64_t nsplit, in
   const double* eA = epi ? ep.A : nullptr;
   const double* eGb = epi ? ep.Gbar : nullptr;
   double* eG = epi ? ep.G : nullptr;
-  if (nsplit <= 256) {
+  if (nsplit <= 16) {
+    const size_t lds = epi ? sizeof(double) * (size_t)R * R : 0;
+    hipLaunchKernelGGL((splitk_flat_kernel<PT>), dim3((unsigned)((n + kSplitThreads - 1) / kSplitThreads)),
+                       dim3(kSplitThreads), lds, st, part, (int)nsplit, n, M, eA, eGb, eG, R);
+  } else if (nsplit <= 256) {
     hipLaunchKernelGGL((splitk_reduce_kernel<PT, 16, 16>), dim3((unsigned)((n + 15) / 16)),
                        dim3(kSplitThreads), 0, st, part, nsplit, n, M, eA, eGb, eG, R);
   } else {

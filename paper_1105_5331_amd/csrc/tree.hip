@@ -1,25 +1,33 @@
 // Two-level evaluation of all N MTTKRPs of a dense tensor at one point
 // (Section 2.3, M^(n) = T_(n) Phibar^(n) for every n), and the same split for
-// the ALS sweep.  The last mode is contracted once:
-//     Y(i_1..i_{N-1}, r) = sum_k T(i_1..i_{N-1}, k) A^(N)(k, r),
-// after which every M^(n), n < N, is an MTTKRP of the much smaller Y
-// (#T R / I_N entries) that is elementwise in r:
-//     M^(n)(i, r) = sum_{i_m, m != n, m < N} Y(.., i, .., r) prod_{m != n, m < N} A^(m)(i_m, r).
-// The last mode's M^(N) still needs one pass over T (the single-mode
-// kernels), so an objective/gradient evaluation or an ALS sweep streams T
-// twice instead of N times.  In the sweep, Y is formed with A^(N) before the
-// updates of modes 1..N-1, which do not change A^(N), so each M^(n) from Y
-// uses the factors exactly as the sequential update would.
+// the ALS sweep.  The modes are cut into a left group [0, s) and a right
+// group [s, N).  Two partial contractions stream T once each:
+//     X_L(i_0..i_{s-1}, r) = sum_{i_s..i_{N-1}} T(i) prod_{m >= s} A^(m)(i_m, r),
+//     X_R(i_s..i_{N-1}, r) = sum_{i_0..i_{s-1}} T(i) prod_{m < s}  A^(m)(i_m, r).
+// Each is an ordinary MTTKRP of T seen with one group merged into a single
+// mode: X_L is mode 0 of T as (I_0 ... I_{s-1}, I_s, .., I_{N-1}), X_R the
+// last mode of T as (I_0, .., I_{s-1}, I_s ... I_{N-1}), so they run on the
+// same streaming kernels (and precisions) as the per-mode MTTKRPs.  Every
+// M^(n) is then an MTTKRP of its group's partial that is elementwise in r:
+//     M^(n)(i, r) = sum_{i_m, m in group, m != n} X(.., i, .., r) prod_{m in group, m != n} A^(m)(i_m, r),
+// computed in float64 from the float64 partial.  A group of one mode needs no
+// second level: its partial is M^(n) itself.  T is streamed twice instead of
+// N times.  In the ALS sweep X_L is formed before the updates of the left
+// modes (which leave the right factors alone) and X_R after them, so each
+// M^(n) sees the factors exactly as the sequential update does.
 //
-//  * contract_last_kernel: 64 rows of T (as a rows x I_N matrix) per
-//    workgroup, inner chunks of 64 through LDS (transposed) with the factor
-//    chunk next to them, the next chunk's loads in flight while the current
-//    one is multiplied; lane = row, the four waves take every fourth k and
-//    are added in a fixed order at the end.  Y is complete per workgroup.
-//  * ymttkrp_kernel: thread (i, r) walks a contiguous range of the other
-//    indices (outer o, inner k) of Y for mode n, loads issued 8 at a time;
-//    ranges are split over workgroups and the slots added by the fixed-order
-//    split-K reduction.  No atomics anywhere: results are reproducible.
+// For the split before the last mode in the float32 and float64 vector-ALU
+// precisions, X_L is formed by contract_last_kernel: 64 rows of T (as a
+// rows x I_N matrix) per workgroup, inner chunks of 64 through LDS
+// (transposed) with the factor chunk next to them, the next chunk's loads in
+// flight while the current one is multiplied; lane = row, the four waves
+// take every fourth k and are added in a fixed order at the end.
+//
+// group_mttkrp_kernel: thread (i, r) walks a contiguous range of the other
+// indices (outer o, inner k) of the group for mode n, loads issued 8 at a
+// time; ranges are split over workgroups and the slots added by the
+// fixed-order split-K reduction.  No atomics anywhere: results are
+// reproducible.
 #include "common.hpp"
 #include "splitk.hpp"
 
@@ -30,9 +38,10 @@ namespace cpng {
 namespace {
 
 constexpr int kThr = 256;
-constexpr int kTB = 64;   // rows and inner chunk per tile
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+constexpr int kTB = 64;   // rows and inner chunk per tile of the last-mode contraction
 
 struct LastParams {
   int64_t rows;    // prod_{m < N-1} I_m
@@ -42,10 +51,12 @@ struct LastParams {
   int vec_ok;      // rows start on 16-byte boundaries
 };
 
+// Left partial of the split before the last mode on the vector ALUs:
+// X(row, r) = sum_k T(row, k) A^(N-1)(k, r) for T as a rows x I_{N-1} matrix.
 template <typename TT, typename CT, int RB>
 __global__ __launch_bounds__(kThr) void contract_last_kernel(const TT* __restrict__ T,
                                                              const CT* __restrict__ fac,
-                                                             LastParams p, CT* __restrict__ Y) {
+                                                             LastParams p, double* __restrict__ Y) {
   constexpr int TB = kTB;
   constexpr int TS = TB + 1;
   constexpr int VE = 16 / sizeof(TT);
@@ -142,14 +153,27 @@ __global__ __launch_bounds__(kThr) void contract_last_kernel(const TT* __restric
     if (row < p.rows) {
 #pragma unroll
       for (int r = 0; r < RB; ++r)
-        if (r0 + r < p.R) Y[row * p.R + r0 + r] = acc[r] + red[r * TS + lane];
+        if (r0 + r < p.R) Y[row * p.R + r0 + r] = (double)(acc[r] + red[r * TS + lane]);
     }
   }
 }
 
-struct YParams {
+template <typename TT, typename CT>
+int launch_contract_last(cp_handle* h, const TT* T, const CT* fac, const LastParams& p, double* X,
+                         hipStream_t st) {
+  const int RB = p.R <= 8 ? 8 : (p.R <= 16 ? 16 : 32);
+  const dim3 grid(nblk(p.rows, kTB), (unsigned)((p.R + RB - 1) / RB));
+  KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
+  if (RB == 8) hipLaunchKernelGGL((contract_last_kernel<TT, CT, 8>), grid, dim3(kThr), 0, st, T, fac, p, X);
+  else if (RB == 16) hipLaunchKernelGGL((contract_last_kernel<TT, CT, 16>), grid, dim3(kThr), 0, st, T, fac, p, X);
+  else hipLaunchKernelGGL((contract_last_kernel<TT, CT, 32>), grid, dim3(kThr), 0, st, T, fac, p, X);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+struct GroupParams {
   int R;
-  int nlo, nhi;                      // modes of Y before / after the target mode
+  int nlo, nhi;                      // group modes before / after the target mode
   int64_t lodims[CP_MAX_ORDER];      // their sizes (in mode order)
   int64_t hidims[CP_MAX_ORDER];
   int64_t lofoff[CP_MAX_ORDER];      // their factors' element offsets
@@ -159,13 +183,12 @@ struct YParams {
 };
 
 // prod over the nm modes of the multi-index x (last mode fastest) of
-// A^(m)(x_m, r).  Mode sizes fit in 32 bits.
-template <typename CT>
-__device__ inline CT idx_product(int64_t x, int nm, const int64_t* dims, const int64_t* foff,
-                                 const CT* __restrict__ fac, int R, int r) {
-  if (nm == 0) return CT(1);
+// A^(m)(x_m, r).  Group sizes fit in 32 bits.
+__device__ inline double idx_product(int64_t x, int nm, const int64_t* dims, const int64_t* foff,
+                                     const double* __restrict__ fac, int R, int r) {
+  if (nm == 0) return 1.0;
   if (nm == 1) return fac[foff[0] + x * R + r];
-  CT s = CT(1);
+  double s = 1.0;
   uint32_t xx = (uint32_t)x;
   for (int m = nm - 1; m >= 0; --m) {
     const uint32_t d = (uint32_t)dims[m];
@@ -177,31 +200,31 @@ __device__ inline CT idx_product(int64_t x, int nm, const int64_t* dims, const i
 }
 
 // part[c][i * R + r] = sum over the c-th range of (o, k) pairs of
-// Y(o, i, k, r) P(o, r) Q(k, r), in range order (o major).
-template <typename CT>
-__global__ __launch_bounds__(kThr) void ymttkrp_kernel(const CT* __restrict__ Y,
-                                                       const CT* __restrict__ fac, YParams p,
-                                                       CT* __restrict__ part) {
+// X(o, i, k, r) P(o, r) Q(k, r), in range order (o major).
+__global__ __launch_bounds__(kThr) void group_mttkrp_kernel(const double* __restrict__ X,
+                                                            const double* __restrict__ fac,
+                                                            GroupParams p,
+                                                            double* __restrict__ part) {
   const int64_t e = (int64_t)blockIdx.x * kThr + threadIdx.x;
   if (e >= p.I * p.R) return;
   const int64_t i = e / p.R;
   const int r = (int)(e - i * p.R);
   const int64_t f0 = (int64_t)blockIdx.y * p.per;
   const int64_t f1 = min<int64_t>(p.O * p.K, f0 + p.per);
-  CT acc = CT(0);
-  if (p.K == 1) {   // target is Y's last mode: the pairs are the outer indices o
-    const CT* y = Y + i * p.R + r;
+  double acc = 0.0;
+  if (p.K == 1) {   // target is the group's last mode: the pairs are the outer indices o
+    const double* x = X + i * p.R + r;
     const int64_t ostep = p.I * p.R;
     for (int64_t o = f0; o < f1; o += 8) {
-      CT yv[8], pv[8];
+      double xv[8], pv[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const bool ok = o + j < f1;
-        yv[j] = ok ? y[(o + j) * ostep] : CT(0);
-        pv[j] = ok ? idx_product<CT>(o + j, p.nlo, p.lodims, p.lofoff, fac, p.R, r) : CT(0);
+        xv[j] = ok ? x[(o + j) * ostep] : 0.0;
+        pv[j] = ok ? idx_product(o + j, p.nlo, p.lodims, p.lofoff, fac, p.R, r) : 0.0;
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc = fma(yv[j], pv[j], acc);
+      for (int j = 0; j < 8; ++j) acc = fma(xv[j], pv[j], acc);
     }
   } else {
     int64_t f = f0;
@@ -209,19 +232,19 @@ __global__ __launch_bounds__(kThr) void ymttkrp_kernel(const CT* __restrict__ Y,
       const int64_t o = f / p.K;
       const int64_t k0 = f - o * p.K;
       const int64_t k1 = min<int64_t>(p.K, k0 + (f1 - f));
-      const CT P = idx_product<CT>(o, p.nlo, p.lodims, p.lofoff, fac, p.R, r);
-      const CT* y = Y + ((o * p.I + i) * p.K) * p.R + r;
-      CT s = CT(0);
+      const double P = idx_product(o, p.nlo, p.lodims, p.lofoff, fac, p.R, r);
+      const double* x = X + ((o * p.I + i) * p.K) * p.R + r;
+      double s = 0.0;
       for (int64_t k = k0; k < k1; k += 8) {
-        CT yv[8], qv[8];
+        double xv[8], qv[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const bool ok = k + j < k1;
-          yv[j] = ok ? y[(k + j) * p.R] : CT(0);
-          qv[j] = ok ? idx_product<CT>(k + j, p.nhi, p.hidims, p.hifoff, fac, p.R, r) : CT(0);
+          xv[j] = ok ? x[(k + j) * p.R] : 0.0;
+          qv[j] = ok ? idx_product(k + j, p.nhi, p.hidims, p.hifoff, fac, p.R, r) : 0.0;
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) s = fma(yv[j], qv[j], s);
+        for (int j = 0; j < 8; ++j) s = fma(xv[j], qv[j], s);
       }
       acc = fma(P, s, acc);
       f += k1 - k0;
@@ -230,55 +253,96 @@ __global__ __launch_bounds__(kThr) void ymttkrp_kernel(const CT* __restrict__ Y,
   part[(int64_t)blockIdx.y * p.I * p.R + e] = acc;
 }
 
-template <typename TT, typename CT>
-int launch_contract_last(cp_handle* h, const TT* T, const CT* fac, const LastParams& p, CT* Y,
-                         hipStream_t st) {
-  const int RB = p.R <= 8 ? 8 : (p.R <= 16 ? 16 : 32);
-  const dim3 grid(nblk(p.rows, kTB), (unsigned)((p.R + RB - 1) / RB));
-  if (RB == 8) hipLaunchKernelGGL((contract_last_kernel<TT, CT, 8>), grid, dim3(kThr), 0, st, T, fac, p, Y);
-  else if (RB == 16) hipLaunchKernelGGL((contract_last_kernel<TT, CT, 16>), grid, dim3(kThr), 0, st, T, fac, p, Y);
-  else hipLaunchKernelGGL((contract_last_kernel<TT, CT, 32>), grid, dim3(kThr), 0, st, T, fac, p, Y);
-  CP_LAUNCH_CHECK(h);
-  return CP_OK;
+int64_t group_size(const Shape& s, int lo, int hi) {
+  int64_t t = 1;
+  for (int m = lo; m < hi; ++m) t *= s.dims[m];
+  return t;
 }
 
 }  // namespace
 
-bool tree_applies(const cp_tensor* T, const Shape& s, int prec) {
-  return !T->sparse && s.N >= 3 && prec != CP_PREC_BF16X3 &&
-         !(prec == CP_PREC_FP32 && T->dtype != CP_F32);
+int tree_split(const cp_tensor* T, const Shape& s, int prec) {
+  if (T->sparse || s.N < 3) return 0;
+  if ((prec == CP_PREC_FP32 || prec == CP_PREC_BF16X3) && T->dtype != CP_F32) return 0;
+  // the split whose second-level partials are smallest (ties to the larger
+  // s), among those whose partials have at most 2^22 rows (the partial
+  // MTTKRP puts its output rows on the second grid dimension)
+  constexpr int64_t kMaxRows = int64_t(1) << 22;
+  int best = 0;
+  int64_t cost = 0;
+  for (int k = 1; k < s.N; ++k) {
+    const int64_t l = k > 1 ? group_size(s, 0, k) : 0;
+    const int64_t r = s.N - k > 1 ? group_size(s, k, s.N) : 0;
+    if (l > kMaxRows || r > kMaxRows) continue;
+    if (best == 0 || l + r <= cost) {
+      best = k;
+      cost = l + r;
+    }
+  }
+  return best;
 }
 
-int tree_contract_last(cp_handle* h, const cp_tensor* T, const Shape& s, const void* fac, int R,
-                       int prec, void* Y, hipStream_t st) {
-  LastParams p{};
-  p.K = s.dims[s.N - 1];
-  p.rows = s.total() / p.K;
-  p.R = R;
-  p.qfoff = s.off[s.N - 1] * R;
-  const size_t tb = T->dtype == CP_F32 ? 4 : 8;
-  p.vec_ok = (p.K * tb) % 16 == 0 && reinterpret_cast<uintptr_t>(T->values) % 16 == 0;
-  if (prec == CP_PREC_FP32)
-    return launch_contract_last<float, float>(h, static_cast<const float*>(T->values),
-                                              static_cast<const float*>(fac), p,
-                                              static_cast<float*>(Y), st);
-  if (T->dtype == CP_F32)
-    return launch_contract_last<float, double>(h, static_cast<const float*>(T->values),
-                                               static_cast<const double*>(fac), p,
-                                               static_cast<double*>(Y), st);
-  return launch_contract_last<double, double>(h, static_cast<const double*>(T->values),
-                                              static_cast<const double*>(fac), p,
-                                              static_cast<double*>(Y), st);
+size_t tree_partial_elems(const Shape& s, int split, int R, bool left) {
+  const int64_t n = left ? (split > 1 ? group_size(s, 0, split) : 0)
+                         : (s.N - split > 1 ? group_size(s, split, s.N) : 0);
+  return (size_t)n * (size_t)R;
 }
 
-int tree_mode(cp_handle* h, const Shape& s, const void* Y, const void* fac, int R, int mode,
-              int prec, double* M, hipStream_t st) {
-  const int N1 = s.N - 1;   // modes of Y
-  YParams p{};
+int tree_partial(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R, int prec,
+                 int split, bool left, double* X, hipStream_t st) {
+  if (left && split == s.N - 1 && prec != CP_PREC_BF16X3) {
+    // T as a rows x I_{N-1} matrix times the last factor, on the vector ALUs
+    LastParams p{};
+    p.K = s.dims[s.N - 1];
+    p.rows = s.total() / p.K;
+    p.R = R;
+    p.qfoff = s.off[s.N - 1] * R;
+    const size_t tb = T->dtype == CP_F32 ? 4 : 8;
+    p.vec_ok = (p.K * tb) % 16 == 0 && reinterpret_cast<uintptr_t>(T->values) % 16 == 0;
+    h->t_passes++;
+    if (prec == CP_PREC_FP32) {
+      float* f32 = nullptr;
+      CP_TRY(stage_factors_f32(h, u, s.sum_dims() * R, &f32, st));
+      return launch_contract_last<float, float>(h, static_cast<const float*>(T->values), f32, p, X, st);
+    }
+    if (T->dtype == CP_F32)
+      return launch_contract_last<float, double>(h, static_cast<const float*>(T->values), u, p, X, st);
+    return launch_contract_last<double, double>(h, static_cast<const double*>(T->values), u, p, X, st);
+  }
+  // T seen with the other group merged into one mode; the merged mode's
+  // factor offset is never read (it is the output mode).
+  Shape v{};
+  int mode;
+  if (left) {
+    v.N = s.N - split + 1;
+    v.dims[0] = group_size(s, 0, split);
+    v.off[0] = 0;
+    for (int m = split; m < s.N; ++m) {
+      v.dims[m - split + 1] = s.dims[m];
+      v.off[m - split + 1] = s.off[m];
+    }
+    mode = 0;
+  } else {
+    v.N = split + 1;
+    for (int m = 0; m < split; ++m) {
+      v.dims[m] = s.dims[m];
+      v.off[m] = s.off[m];
+    }
+    v.dims[split] = group_size(s, split, s.N);
+    v.off[split] = 0;
+    mode = split;
+  }
+  v.off[v.N] = s.off[s.N];   // all factor rows (precision staging converts them all)
+  return dense_mttkrp(h, T, v, u, R, mode, prec, X, st);
+}
+
+int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, const double* u, int R,
+              int mode, double* M, hipStream_t st) {
+  GroupParams p{};
   p.R = R;
   p.O = 1;
   p.K = 1;
-  for (int m = 0; m < N1; ++m) {
+  for (int m = lo; m < hi; ++m) {
     if (m < mode) {
       p.lodims[p.nlo] = s.dims[m];
       p.lofoff[p.nlo] = s.off[m] * R;
@@ -294,26 +358,20 @@ int tree_mode(cp_handle* h, const Shape& s, const void* Y, const void* fac, int 
   p.I = s.dims[mode];
   const int64_t n_out = p.I * R;
   const int64_t work = p.O * p.K;
-  // about 2^18 threads, at least 16 (o, k) pairs each, at most 32768 ranges
-  const int64_t want = std::min<int64_t>(32768, std::max<int64_t>(1, (int64_t(1) << 18) / n_out));
-  p.per = std::max<int64_t>(16, (work + want - 1) / want);
+  // about 2^19 threads, at least 8 (o, k) pairs each (one batch of loads),
+  // at most 32768 ranges
+  const int64_t want = std::min<int64_t>(32768, std::max<int64_t>(1, (int64_t(1) << 19) / n_out));
+  p.per = std::max<int64_t>(8, (work + want - 1) / want);
   const int64_t nch = (work + p.per - 1) / p.per;
   const dim3 grid(nblk(n_out, kThr), (unsigned)nch);
-  const size_t eb = prec == CP_PREC_FP32 ? 4 : 8;
-  CP_TRY(ensure(h, h->part, eb * (size_t)(nch * n_out), st));
-  if (prec == CP_PREC_FP32) {
-    float* part = static_cast<float*>(h->part.ptr);
-    hipLaunchKernelGGL(ymttkrp_kernel<float>, grid, dim3(kThr), 0, st,
-                       static_cast<const float*>(Y), static_cast<const float*>(fac), p, part);
-    CP_LAUNCH_CHECK(h);
-    CP_TRY(launch_splitk_reduce(h, part, nch, n_out, R, M, st));
-  } else {
-    double* part = static_cast<double*>(h->part.ptr);
-    hipLaunchKernelGGL(ymttkrp_kernel<double>, grid, dim3(kThr), 0, st,
-                       static_cast<const double*>(Y), static_cast<const double*>(fac), p, part);
-    CP_LAUNCH_CHECK(h);
-    CP_TRY(launch_splitk_reduce(h, part, nch, n_out, R, M, st));
+  CP_TRY(ensure(h, h->part, sizeof(double) * (size_t)(nch * n_out), st));
+  double* part = static_cast<double*>(h->part.ptr);
+  {
+    KernelTimer timer(h, CP_KERNEL_GROUP_MTTKRP, st);
+    hipLaunchKernelGGL(group_mttkrp_kernel, grid, dim3(kThr), 0, st, X, u, p, part);
   }
+  CP_LAUNCH_CHECK(h);
+  CP_TRY(launch_splitk_reduce(h, part, nch, n_out, R, M, st));
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }

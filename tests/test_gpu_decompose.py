@@ -200,7 +200,7 @@ def test_captured_replay_matches_eager(h, prec):
     eager = _run_state(cpng, h, Tg, R, u0, 30, prec, torch.cuda.default_stream())
     side = torch.cuda.Stream()
     graph = _run_state(cpng, h, Tg, R, u0, 30, prec, side)
-    keys = ("f", "rho", "beta", "nfev", "m", "restart", "ls_status")
+    keys = ("f", "rho", "beta", "nfev", "m", "restart", "ls_status", "t_passes")
     for k, (a, b) in enumerate(zip(eager[0], graph[0])):
         for key in keys:
             va, vb = a[key], b[key]
@@ -223,6 +223,29 @@ def test_captured_replay_matches_eager_sparse(h):
     for k, (a, b) in enumerate(zip(eager[0], graph[0])):
         assert a["f"] == b["f"] and a["rho"] == b["rho"] and a["nfev"] == b["nfev"], k
     assert np.array_equal(eager[1], graph[1])
+
+
+@pytest.mark.parametrize("tree,prec", [(1, "fp64"), (1, "bf16x3"), (0, "fp64")])
+def test_step_reports_tensor_passes(h, tree, prec):
+    """An N-GMRES iteration makes one ALS sweep, one gradient at its result and
+    nfev line-search evaluations; each streams T twice with the two-level
+    evaluation and N times without.  Replayed graph phases count the same."""
+    import paper_1105_5331_amd as cpng
+    dims, R = (10, 12, 8, 16), 3
+    print(f"case t_passes tree={tree} prec={prec}", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=3, dtype=np.float32)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u0 = initial_guess(dims, R, seed=10003)
+    per = 2 if tree else len(dims)
+    with torch.cuda.stream(torch.cuda.Stream()):
+        st = cpng.NGMRESState(h, Tg, R, _dev(u0), precision=prec, final_precision=prec,
+                              mttkrp_tree=tree)
+        infos = [st.step() for _ in range(8)]
+        st.close()
+    torch.cuda.synchronize()
+    for k, info in enumerate(infos):
+        assert info["t_passes"] == per * (2 + info["nfev"]), (k, info)
 
 
 @pytest.mark.parametrize("seed", [0, 1])
