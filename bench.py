@@ -503,12 +503,14 @@ def main():
     cpng.cp_profile(h, True)
     torch.cuda.synchronize()
     passes = 0
+    evals = 0   # objective/gradient evaluations and ALS sweeps (one T-traversal each)
     t0 = time.perf_counter()
     infos = []
     for k in range(args.steps):
         info = st.step()
         infos.append(info)
         passes += info["t_passes"]
+        evals += 2 + info["nfev"]
         log(f"step {k}: f {info['f']:.6e} rho {info['rho']:.3e} nfev {info['nfev']} "
             f"restart {info['restart']}")
     torch.cuda.synchronize()
@@ -545,6 +547,7 @@ def main():
                                f"noise 1%+1%, one N-GMRES iteration per step",
                    "dims": list(dims), "rank": R, "precision": args.precision,
                    "mttkrp_passes": passes},
+        "evals": evals, "ms_per_eval": round(dt / evals * 1e3, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": counter_traffic() if (args.precision, s, R) == ("bf16x3", 128, 32) else None,

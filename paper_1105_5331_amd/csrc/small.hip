@@ -179,7 +179,7 @@ __device__ void factor_block(const double* __restrict__ G, int R, double* __rest
 
 // With fmode >= 0 the same block then factorises Gammabar^(fmode) for the
 // ALS mode solve (factor_block).
-__global__ void gram_final_kernel(const double* __restrict__ part, ModeTable t,
+__global__ __launch_bounds__(256) void gram_final_kernel(const double* __restrict__ part, ModeTable t,
                                   double* __restrict__ S, double* __restrict__ Gbar,
                                   double* __restrict__ Gam, int fmode, double* __restrict__ F,
                                   int* __restrict__ kind, int* __restrict__ flags) {
@@ -321,17 +321,70 @@ __device__ bool chol_lds(double* a, int R, double* piv_ok) {
   return true;
 }
 
+// Value of v in lane `lane` (a constant), for the whole wave.
+__device__ inline double wave_bcast(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cholesky of the symmetric R x R matrix G (R <= RM <= 64) by the first wave,
+// in registers: lane c holds column c of the trailing matrix, both
+// triangles.  Step j: the pivot d = a(j, j) from lane j; every lane forms its
+// multiplier L(c, j) = a(j, c) / sqrt(d) (its own register j, since the
+// trailing matrix is symmetric) and removes L(i, j) L(c, j) from a(i, c) for
+// i > j, L(i, j) taken from lane i.  The same operations in the same order as
+// the right-looking block factorisation (chol_lds), without barriers.  Lane c
+// writes row c of L into F (zero above the diagonal).  Returns false (F then
+// partly written) at the first pivot that is not positive and finite.
+template <int RM>
+__device__ bool chol_wave(const double* __restrict__ G, int R, double* __restrict__ F) {
+  const int c = threadIdx.x & 63;
+  double a[RM];
+#pragma unroll
+  for (int i = 0; i < RM; ++i) a[i] = (c < R && i < R) ? G[i * R + c] : 0.0;
+  bool ok = true;   // uniform across the wave
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    if (j < R && ok) {
+      const double d = wave_bcast(a[j], j);
+      if (d > 0.0 && isfinite(d)) {
+        const double djj = sqrt(d);
+        const double m = a[j] / djj;   // L(c, j) for c > j
+        if (c < R) F[c * R + j] = c > j ? m : (c == j ? djj : 0.0);
+#pragma unroll
+        for (int i = j + 1; i < RM; ++i)
+          if (i < R) a[i] -= wave_bcast(m, i) * m;
+      } else {
+        ok = false;
+      }
+    }
+  }
+  return ok;
+}
+
 __device__ void factor_block(const double* __restrict__ G, int R, double* __restrict__ F,
                              int* __restrict__ kind, int* __restrict__ flags) {
   __shared__ double a[kMaxR * kMaxR];
   __shared__ double v[kMaxR * kMaxR];
   __shared__ double ok;
   __shared__ double shift;
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) a[e] = G[e];
+  __shared__ int plain_ok;
+  // plain Cholesky by the first wave
+  if (threadIdx.x < 64) {
+    const bool good = R <= 16 ? chol_wave<16>(G, R, F)
+                              : (R <= 32 ? chol_wave<32>(G, R, F) : chol_wave<64>(G, R, F));
+    if (threadIdx.x == 0) plain_ok = good ? 1 : 0;
+  }
   __syncthreads();
+  if (plain_ok) {
+    if (threadIdx.x == 0) *kind = 0;
+    return;
+  }
   int k = 0;
-  bool good = chol_lds(a, R, &ok);
-  if (!good) {
+  bool good = false;
+  {
     if (threadIdx.x == 0) {
       double tr = 0.0;
       for (int i = 0; i < R; ++i) tr += G[i * R + i];
@@ -431,7 +484,7 @@ __device__ void factor_block(const double* __restrict__ G, int R, double* __rest
   }
 }
 
-__global__ void factor_kernel(const double* __restrict__ G, int R, double* __restrict__ F,
+__global__ __launch_bounds__(256) void factor_kernel(const double* __restrict__ G, int R, double* __restrict__ F,
                               int* __restrict__ kind, int* __restrict__ flags) {
   factor_block(G, R, F, kind, flags);
 }

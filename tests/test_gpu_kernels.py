@@ -290,6 +290,30 @@ def test_mode_solve_paths(h, case):
     np.testing.assert_allclose(A.cpu().numpy(), ref, rtol=1e-10, atol=1e-12)
 
 
+@pytest.mark.parametrize("R,case", [(1, "spd"), (16, "spd"), (17, "spd"), (32, "spd"), (33, "spd"),
+                                    (64, "spd"), (40, "zero_row"), (24, "zero_row")])
+def test_mode_solve_rank_widths(h, R, case):
+    """The register Cholesky at every width it is compiled for (R <= 16, 32,
+    64) and across the boundaries; a zero row makes it fail at that pivot and
+    the shifted factorisation take over, as in the oracle."""
+    cpng = _cpng()
+    print(f"case mode_solve R={R} {case}", flush=True)
+    rng = np.random.default_rng(100 + R)
+    I = 53
+    M = rng.standard_normal((I, R))
+    Q = rng.standard_normal((R, R))
+    G = Q @ Q.T + R * np.eye(R)
+    if case == "zero_row":
+        k = R // 2
+        G[k, :] = 0.0
+        G[:, k] = 0.0
+        M[:, k] = 0.0
+    A, kind = cpng.cp_mode_solve(h, _dev(M), _dev(G))
+    ref, flag = ocp.mode_solve(M, G)
+    assert kind == flag == (0 if case == "spd" else 1)
+    np.testing.assert_allclose(A.cpu().numpy(), ref, rtol=1e-10, atol=1e-12)
+
+
 @pytest.mark.parametrize("L,m", [(1, 1), (1000, 5), (40000, 20), (333, 64)])
 def test_ngmres_accelerate_parity(h, L, m):
     cpng = _cpng()
