@@ -47,7 +47,7 @@ struct cp_handle {
   cpng::DevBuf red;      // reduction partials
   cpng::DevBuf carry;    // sparse segment carries
   cpng::DevBuf otab;     // per-launch outer-index tables of the streaming MTTKRP
-  cpng::DevBuf ybuf;     // T contracted with the last factor (two-level evaluation)
+  cpng::DevBuf ybuf;     // mode-group partials of the two-level evaluation (float64)
   uint64_t gen = 0;           // bumped whenever a workspace slice is reallocated
   cpng::GradEpi epi;          // pending gradient epilogue for the next dense MTTKRP
   double* pinned = nullptr;   // host pinned readback area (64 doubles)

@@ -74,10 +74,20 @@ size_t request_footprint(const cp_tensor& T, int R, int window) {
   const size_t state = sizeof(double) * L * (9 + 2 * (size_t)window);
   const size_t work = sizeof(double) * (3 * L + 4096) + 2048 * (size_t)maxd * 32 * 8 +
                       ((size_t)64 << 20);
-  // T contracted with its last factor (dense, two-level evaluation)
-  const size_t ybuf = T.sparse || T.order < 3
-                          ? 0
-                          : sizeof(double) * (size_t)(total / T.dims[T.order - 1]) * R;
+  // the mode-group partials of the two-level evaluation (dense, order >= 3)
+  size_t ybuf = 0;
+  if (!T.sparse && T.order >= 3 && T.order <= CP_MAX_ORDER) {
+    cpng::Shape sh;
+    sh.N = T.order;
+    for (int k = 0; k < T.order; ++k) {
+      sh.dims[k] = T.dims[k];
+      sh.off[k + 1] = sh.off[k] + T.dims[k];
+    }
+    const int split = cpng::tree_split(&T, sh, CP_PREC_FP64);
+    if (split)
+      ybuf = sizeof(double) * (cpng::tree_partial_elems(sh, split, R, true) +
+                               cpng::tree_partial_elems(sh, split, R, false));
+  }
   return tensor + state + work + ybuf;
 }
 

@@ -580,8 +580,143 @@ __global__ void sum_final_kernel(const double* __restrict__ part, int nb, double
   if (threadIdx.x == 0) *out = s;
 }
 
+// ---- one workgroup for short vectors ---------------------------------------------
+// Iterate-length vectors (L = R sum_n I_n) are short: up to kSmallVec entries
+// a dot product, the objective and the normalisation take one launch
+// instead of two to four.  Thread t adds its entries t, t + 256, ... in
+// order (loads 8 at a time), then the fixed-order block sum.
+constexpr int64_t kSmallVec = 32768;
+
+template <typename X, typename Y>
+__device__ double thread_dot(const X* __restrict__ x, const Y* __restrict__ y, int64_t n) {
+  double s = 0.0;
+  for (int64_t e0 = threadIdx.x; e0 < n; e0 += 8 * 256) {
+    double xv[8], yv[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int64_t e = e0 + (int64_t)b * 256;
+      xv[b] = e < n ? (double)x[e] : 0.0;
+      yv[b] = e < n ? (double)y[e] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) s = fma(xv[b], yv[b], s);
+  }
+  return s;
+}
+
+template <typename X, typename Y>
+__global__ __launch_bounds__(256) void dot_small_kernel(const X* __restrict__ x,
+                                                        const Y* __restrict__ y, int64_t n,
+                                                        double* __restrict__ out) {
+  const double s = block_sum(thread_dot(x, y, n));
+  if (threadIdx.x == 0) *out = s;
+}
+
+// f = 0.5 normsq - <A, M> + 0.5 sum(Gamma)
+__global__ __launch_bounds__(256) void objective_small_kernel(const double* __restrict__ A,
+                                                              const double* __restrict__ M,
+                                                              int64_t n, double normsq,
+                                                              const double* __restrict__ Gam,
+                                                              int R, double* __restrict__ f) {
+  const double d = block_sum(thread_dot(A, M, n));
+  double sg = 0.0;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sg += Gam[e];
+  sg = block_sum(sg);
+  if (threadIdx.x == 0) *f = 0.5 * normsq - d + 0.5 * sg;
+}
+
+// Normalisation (Section 2.3 end; the same plan as norm_plan_kernel) of u and
+// the gradient g at the same point, one workgroup: per mode the column norms
+// nu (thread (group, r) adds rows group, group + G, ... in order, then the G
+// groups in order), lambda_r = prod_n nu_r^(n), scales lambda^(1/N) / nu, the
+// stable descending order of lambda, then every row rescaled and permuted in
+// place through an LDS tile.
+__global__ __launch_bounds__(256) void normalize_small_kernel(double* __restrict__ u,
+                                                              double* __restrict__ g,
+                                                              ModeTable t) {
+  constexpr int kTile = 4096;
+  __shared__ double nu[CP_MAX_ORDER][kMaxR];
+  __shared__ double scl[CP_MAX_ORDER][kMaxR];
+  __shared__ double lam[kMaxR];
+  __shared__ int perm[kMaxR];
+  __shared__ double red[256];
+  __shared__ double tile[kTile];
+  const int R = t.R;
+  const int G = 256 / R;   // R <= 64
+  const int c = threadIdx.x % R, grp = threadIdx.x / R;
+  for (int k = 0; k < t.N; ++k) {
+    const double* A = u + t.off[k] * R;
+    const int64_t I = t.dims[k];
+    double s = 0.0;
+    if (grp < G) {
+      for (int64_t i0 = grp; i0 < I; i0 += 8 * (int64_t)G) {
+        double v[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int64_t i = i0 + (int64_t)b * G;
+          v[b] = i < I ? A[i * R + c] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < 8; ++b) s = fma(v[b], v[b], s);
+      }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < R) {
+      double tot = 0.0;
+      for (int q = 0; q < G; ++q) tot += red[q * R + threadIdx.x];
+      nu[k][threadIdx.x] = sqrt(tot);
+    }
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < R) {
+    const int r = threadIdx.x;
+    double l = 1.0;
+    for (int k = 0; k < t.N; ++k) l *= nu[k][r];
+    lam[r] = l;
+    const double root = pow(l, 1.0 / (double)t.N);
+    for (int k = 0; k < t.N; ++k) scl[k][r] = l > 0.0 ? root / nu[k][r] : 0.0;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < R) {
+    const int r = threadIdx.x;
+    int pos = 0;
+    for (int q = 0; q < R; ++q)
+      if (lam[q] > lam[r] || (lam[q] == lam[r] && q < r)) ++pos;
+    perm[pos] = r;   // perm[new position] = old term index
+  }
+  __syncthreads();
+  const int64_t rows = t.off[t.N];
+  const int64_t tr = kTile / R;   // rows per tile
+  for (int pass = 0; pass < (g ? 2 : 1); ++pass) {
+    double* x = pass == 0 ? u : g;
+    for (int64_t r0 = 0; r0 < rows; r0 += tr) {
+      const int64_t n = min<int64_t>(tr, rows - r0) * R;
+      for (int64_t e = threadIdx.x; e < n; e += 256) tile[e] = x[r0 * R + e];
+      __syncthreads();
+      for (int64_t e = threadIdx.x; e < n; e += 256) {
+        const int64_t lr = e / R;
+        const int j = (int)(e - lr * R);
+        const int64_t row = r0 + lr;
+        int k = 0;
+        while (row >= t.off[k + 1]) ++k;
+        const int pj = perm[j];
+        const double sc = scl[k][pj];
+        const double v = tile[lr * R + pj];
+        x[row * R + j] = pass ? (sc != 0.0 ? v / sc : v) : sc * v;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <typename X, typename Y>
 int dot_impl(cp_handle* h, const X* x, const Y* y, int64_t n, double* out, hipStream_t st) {
+  if (n <= kSmallVec) {
+    hipLaunchKernelGGL((dot_small_kernel<X, Y>), dim3(1), dim3(256), 0, st, x, y, n, out);
+    CP_LAUNCH_CHECK(h);
+    return CP_OK;
+  }
   const int64_t per = std::max<int64_t>(256, ((n + kRedBlocks - 1) / kRedBlocks + 255) / 256 * 256);
   const int nb = (int)std::max<int64_t>(1, (n + per - 1) / per);
   CP_TRY(ensure(h, h->red, sizeof(double) * kRedBlocks, st));
@@ -876,6 +1011,11 @@ int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, do
 int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStream_t st) {
   if (R > kMaxR) return fail(h, CP_EINVAL, "rank %d above the supported %d", R, kMaxR);
   ModeTable t = table(s, R);
+  if (s.sum_dims() * R <= kSmallVec) {
+    hipLaunchKernelGGL(normalize_small_kernel, dim3(1), dim3(256), 0, st, u, g, t);
+    CP_LAUNCH_CHECK(h);
+    return CP_OK;
+  }
   const int64_t nch = t.coff[s.N];
   CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)(nch * R), st));
   CP_TRY(ensure(h, h->small, small_layout(s.N, R) + 4096, st));
@@ -958,6 +1098,11 @@ int sumsq_tensor(cp_handle* h, const void* v, int dtype, int64_t n, double* out,
 
 int objective_from_dot(cp_handle* h, const double* A, const double* M, int64_t n, double normsq,
                        const double* Gam, int R, double* f, hipStream_t st) {
+  if (n <= kSmallVec) {
+    hipLaunchKernelGGL(objective_small_kernel, dim3(1), dim3(256), 0, st, A, M, n, normsq, Gam, R, f);
+    CP_LAUNCH_CHECK(h);
+    return CP_OK;
+  }
   const int64_t per = std::max<int64_t>(256, ((n + kRedBlocks - 1) / kRedBlocks + 255) / 256 * 256);
   const int nb = (int)std::max<int64_t>(1, (n + per - 1) / per);
   CP_TRY(ensure(h, h->red, sizeof(double) * kRedBlocks, st));

@@ -153,9 +153,10 @@ def test_normalize_zero_term(h):
                                       ((130, 3, 70), 64, 0.2), ((3, 90), 7, 0.4)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32in_fp64acc"])
 def test_objective_grad_parity(h, dims, R, c, prec):
-    """All N MTTKRPs at one point (dense order >= 3: last mode contracted once,
-    the others from the contracted tensor) and the gradient epilogue, float64
-    accumulation, against the oracle on the same (float64 or float32) tensor."""
+    """All N MTTKRPs at one point (dense order >= 3: the two mode-group
+    partials, then each mode from its group's partial) and the gradient
+    epilogue, float64 accumulation, against the oracle on the same (float64 or
+    float32) tensor."""
     cpng = _cpng()
     print(f"case objective_grad dims={dims} R={R} prec={prec}", flush=True)
     dt = np.float64 if prec == "fp64" else np.float32
