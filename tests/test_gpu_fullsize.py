@@ -2,7 +2,10 @@
 times, on sampled outputs: whole rows M^(n)(i, :) recomputed by the oracle
 from the definition restricted to the sampled indices i.
 
-* dense 128^4 float32, R = 32 (BF16X3 and FP32 kernels, every mode);
+* dense 128^4 float32, R = 32 (BF16X3 and FP32 kernels, every mode), as
+  single-mode MTTKRPs and as the gradient of the two-level evaluation that
+  the benchmark step runs (both mode-group partials on the reshaped tensor,
+  the float64 second level and the fused epilogue);
 * sparse 20000^3 COO with about 2e7 nonzeros, R = 16 (FP32, every mode);
 * dense 200^3, R = 10, congruence 0.9 (the time-to-gradient study): f and g
   at the initial guess in every precision, whole (the oracle finishes them
@@ -47,6 +50,36 @@ def test_dense_128x4_R32_sampled_rows(h):
         for prec in ("bf16x3", "fp32"):
             M = cpng.cp_mttkrp(h, Tg, u, R, n, prec).cpu().numpy()[rows]
             assert_close_to_bound(M, ref, bound, TOL[prec], f"mode {n} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_dense_128x4_R32_gradient_rows(h, prec):
+    """G^(n)(i, :) = -M^(n)(i, :) + A^(n)(i, :) Gammabar^(n) on sampled rows of
+    every mode, from cp_objective_grad (the two-level evaluation), against the
+    oracle's rows; the bound adds |A| |Gammabar| to the MTTKRP bound."""
+    import paper_1105_5331_amd as cpng
+    dims, R = (128, 128, 128, 128), 32
+    print(f"case dense 128^4 R=32 gradient rows {prec}", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=0, dtype=np.float32)
+    Tg = cpng.Tensor(dims, torch.from_numpy(p.T).cuda().reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u0 = initial_guess(dims, R, seed=10000)
+    A = ocp.split_u(u0, dims, R)
+    _, g = cpng.cp_objective_grad(h, Tg, torch.from_numpy(u0).cuda(), R, prec)
+    G = ocp.split_u(g.cpu().numpy(), dims, R)
+    grams = [a.T @ a for a in A]
+    rows = [0, 77, 127]
+    for n in range(4):
+        sl = np.take(p.T, rows, axis=n).astype(np.float64)
+        An = [a if k != n else A[n][rows] for k, a in enumerate(A)]
+        gb = np.ones((R, R))
+        for k in range(4):
+            if k != n:
+                gb = gb * grams[k]
+        ref = -ocp.mttkrp(sl, An, n) + A[n][rows] @ gb
+        bound = (ocp.mttkrp(np.abs(sl), [np.abs(a) for a in An], n)
+                 + np.abs(A[n][rows]) @ np.abs(gb))
+        assert_close_to_bound(G[n][rows], ref, bound, TOL[prec], f"mode {n} {prec}")
 
 
 def test_sparse_20000x3_R16_sampled_rows(h):
