@@ -107,7 +107,8 @@ def test_mttkrp_argument_errors(h):
         cpng.cp_mttkrp(h, Tg, u, 0, 0, "fp64")
 
 
-@pytest.mark.parametrize("dims,R", [((5, 300, 7), 4), ((20, 20, 20, 3), 33), ((1, 1, 2), 1)])
+@pytest.mark.parametrize("dims,R", [((5, 300, 7), 4), ((20, 20, 20, 3), 33), ((1, 1, 2), 1),
+                                    ((130, 3, 64), 64), ((5000, 3000, 10), 16)])
 def test_gram_parity(h, dims, R):
     cpng = _cpng()
     A = _factors(dims, R, 7)
@@ -122,7 +123,10 @@ def test_gram_parity(h, dims, R):
     np.testing.assert_allclose(G, refg, rtol=1e-11, atol=1e-12 * np.abs(refg).max())
 
 
-@pytest.mark.parametrize("dims,R", [((6, 7, 8), 5), ((30, 4, 9, 3), 12), ((3, 2), 1)])
+# one-workgroup form (L = R sum_k I_k <= 32768) and, for (3000, 40), the
+# multi-block form
+@pytest.mark.parametrize("dims,R", [((6, 7, 8), 5), ((30, 4, 9, 3), 12), ((3, 2), 1),
+                                    ((300, 200, 100), 40), ((3000, 40), 16)])
 def test_normalize_parity(h, dims, R):
     cpng = _cpng()
     A = _factors(dims, R, 8)
