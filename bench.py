@@ -399,7 +399,8 @@ def serving(cpng, torch, n=64, slots=4, seed=7, max_iter=500, loads=(0.5, 0.8)):
     """Stream of decomposition requests (dense 3-/4-way float32, mode sizes
     U{16..160}, R U{2..24}, congruence U[0, 0.9], noise 1%+1%, tol 1e-8)
     through the continuous-batching server.  First the saturation throughput
-    (all requests queued at t = 0, `slots` concurrent decompositions); then
+    (all requests queued at t = 0, `slots` concurrent decompositions, and one
+    at a time); then
     Poisson arrivals at the given fractions of it, with `slots` concurrent
     decompositions and one at a time; p50/p99 latency from arrival to result."""
     from workloads import initial_guess, serving_stream, test_problem_1_torch
@@ -413,7 +414,9 @@ def serving(cpng, torch, n=64, slots=4, seed=7, max_iter=500, loads=(0.5, 0.8)):
     _serve(cpng, torch, data[:8], slots, None, max_iter)   # first launches
     sat = _serve(cpng, torch, data, slots, None, max_iter)
     log(f"serving saturation: {sat}")
-    out = {"saturation": sat}
+    sat1 = _serve(cpng, torch, data, 1, None, max_iter)
+    log(f"serving saturation, one at a time: {sat1}")
+    out = {"saturation": sat, "saturation_slots1": sat1}
     mu = sat["solves_per_s"]
     for frac in loads:
         for sl in (slots, 1):
