@@ -160,9 +160,10 @@ int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, con
 
 // small kernels
 // With factor_mode >= 0 also factorises Gammabar^(factor_mode) for the next
-// mode_solve(..., Gbar = nullptr, ...).
+// mode_solve(..., Gbar = nullptr, ...).  With only_mode >= 0 only that mode's
+// Gram is recomputed; S must hold the other modes' Grams of the same factors.
 int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, double* Gbar,
-             double* Gam, hipStream_t st, int factor_mode = -1);
+             double* Gam, hipStream_t st, int factor_mode = -1, int only_mode = -1);
 int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStream_t st);
 // A = M Gbar^-1 (Gbar nullptr: use the factor gram_all formed).
 int mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int R, double* A,

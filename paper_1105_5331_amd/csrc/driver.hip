@@ -191,7 +191,8 @@ int als_sweep_impl(cp_handle* h, const cp_tensor* T, const Shape& s, double* u, 
   if (tb.XL) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, true, tb.XL, st));
   for (int n = 0; n < s.N; ++n) {
     if (tb.XR && n == tb.split) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, false, tb.XR, st));
-    CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, nullptr, st, n));   // and factorises Gbar^(n)
+    // Grams (after mode 0 only the mode updated last changed) and the factor of Gbar^(n)
+    CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, nullptr, st, n, n == 0 ? -1 : n - 1));
     double* Mn = sc.M + s.off[n] * R;
     CP_TRY(mode_mttkrp(h, T, s, u, R, n, prec, tb, Mn, st));
     CP_TRY(mode_solve(h, Mn, nullptr, s.dims[n], R, u + s.off[n] * R, st));

@@ -133,12 +133,12 @@ ModeTable table(const Shape& s, int R) {
 
 // ---- Grams -----------------------------------------------------------------
 // part[(chunk) * R * R + r * R + q] = sum_{rows in chunk} A(i, r) A(i, q); the
-// chunk index runs over every mode's chunks (blockIdx.x).
-__global__ void gram_partial_kernel(const double* __restrict__ u, ModeTable t,
+// chunk index ch0 + blockIdx.x runs over every mode's chunks (or one mode's).
+__global__ void gram_partial_kernel(const double* __restrict__ u, ModeTable t, int64_t ch0,
                                     double* __restrict__ part) {
   __shared__ double rows[32][kMaxR];
   const int R = t.R;
-  const int64_t ch = blockIdx.x;
+  const int64_t ch = ch0 + blockIdx.x;
   int k = 0;
   while (ch >= t.coff[k + 1]) ++k;
   const int64_t i_begin = (ch - t.coff[k]) * kRowsPerChunk;
@@ -178,15 +178,20 @@ __device__ void factor_block(const double* __restrict__ G, int R, double* __rest
                              int* __restrict__ kind, int* __restrict__ flags);
 
 // With fmode >= 0 the same block then factorises Gammabar^(fmode) for the
-// ALS mode solve (factor_block).
+// ALS mode solve (factor_block).  With only >= 0 the partials hold mode
+// `only` alone and S already holds the other modes' Grams.
 __global__ __launch_bounds__(256) void gram_final_kernel(const double* __restrict__ part, ModeTable t,
                                   double* __restrict__ S, double* __restrict__ Gbar,
                                   double* __restrict__ Gam, int fmode, double* __restrict__ F,
-                                  int* __restrict__ kind, int* __restrict__ flags) {
+                                  int* __restrict__ kind, int* __restrict__ flags, int only) {
   const int R = t.R;
   for (int pr = threadIdx.x; pr < R * R; pr += blockDim.x) {
     double sk[CP_MAX_ORDER];
     for (int k = 0; k < t.N; ++k) {
+      if (only >= 0 && k != only) {
+        sk[k] = S[(int64_t)k * R * R + pr];
+        continue;
+      }
       const double s = ordered_sum(part + t.coff[k] * R * R + pr, t.coff[k + 1] - t.coff[k],
                                    (int64_t)R * R);
       sk[k] = s;
@@ -991,19 +996,22 @@ static int factor_slot(cp_handle* h, int R, double** F, int** kind, hipStream_t 
 }
 
 int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, double* Gbar,
-             double* Gam, hipStream_t st, int factor_mode) {
+             double* Gam, hipStream_t st, int factor_mode, int only_mode) {
   if (R > kMaxR) return fail(h, CP_EINVAL, "rank %d above the supported %d", R, kMaxR);
+  if (only_mode >= 0 && !S) return fail(h, CP_EINVAL, "one-mode Gram update without S");
   ModeTable t = table(s, R);
   const int64_t nch = t.coff[s.N];
+  const int64_t ch0 = only_mode >= 0 ? t.coff[only_mode] : 0;
+  const int64_t nrun = only_mode >= 0 ? t.coff[only_mode + 1] - ch0 : nch;
   double* F = nullptr;
   int* kind = nullptr;
   if (factor_mode >= 0) CP_TRY(factor_slot(h, R, &F, &kind, st));
   CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)(nch * R * R), st));
   double* part = static_cast<double*>(h->red.ptr);
-  hipLaunchKernelGGL(gram_partial_kernel, dim3((unsigned)nch), dim3(256), 0, st, u, t, part);
+  hipLaunchKernelGGL(gram_partial_kernel, dim3((unsigned)nrun), dim3(256), 0, st, u, t, ch0, part);
   CP_LAUNCH_CHECK(h);
   hipLaunchKernelGGL(gram_final_kernel, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam,
-                     factor_mode, F, kind, h->flags);
+                     factor_mode, F, kind, h->flags, only_mode);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
