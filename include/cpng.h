@@ -220,7 +220,9 @@ int cp_normalize(cp_handle* h, int32_t order, const int64_t* dims, double* u_ino
  * updated earlier ones; then, if normalize != 0, cp_normalize.  A
  * Gammabar^(n) that is not positive definite is retried with a shift of
  * 1e-14 tr/R and then solved by a pseudo-inverse (cyclic Jacobi eigen-
- * decomposition), as the float64 reference does. */
+ * decomposition), as the float64 reference does.  Dense tensors of order
+ * >= 3 take their MTTKRPs from the two mode-group partials (two passes over
+ * T, the right group's formed after the left modes are updated). */
 int cp_als_sweep(cp_handle* h, const cp_tensor* T, double* u_inout, int32_t R, int32_t p,
                  int32_t normalize, hipStream_t stream);
 
@@ -238,7 +240,8 @@ int cp_mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, 
  *   f = 1/2 ||T||^2 - <A^(N), M^(N)> + 1/2 sum_{r,s} Gamma(r,s)
  *   G^(n) = -M^(n) + A^(n) Gammabar^(n)           for every n
  * f_out: device, 1 double; g_out: device, L doubles (nullable: f only still
- * runs every MTTKRP it needs).  T must be prepared (for ||T||^2). */
+ * runs every MTTKRP it needs).  T must be prepared (for ||T||^2).  Dense
+ * tensors of order >= 3: the two-level evaluation, two passes over T. */
 int cp_objective_grad(cp_handle* h, const cp_tensor* T, const double* u, int32_t R, int32_t p,
                       double* f_out, double* g_out, hipStream_t stream);
 
