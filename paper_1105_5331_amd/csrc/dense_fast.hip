@@ -310,7 +310,11 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
 // Column-kernel operand: rows k .. k+7 of the lane's NT consecutive columns
 // col0 .. col0+NT-1 (column col0 + nt feeds MFMA tile nt), one NT-wide load
 // per row when the group lies inside I_n and I_n is a multiple of NT (every
-// row offset is a multiple of I_n, so the load is aligned).
+// row offset is a multiple of I_n, so the load is aligned).  The 2-wide load
+// is non-temporal: each instruction reads whole 128-byte lines of a tensor
+// that is read exactly once, so they need not stay in the caches (the last
+// mode at 128^4 went from 199 to 177 us; the row kernels, whose lines are
+// split over two instructions, got slower with the hint and do not use it).
 template <int NT>
 __device__ inline void load_cols(const float* __restrict__ T, const FastParams& p, int64_t base,
                                  int64_t col0, int k0, float (&v)[NT][8]) {
@@ -325,7 +329,8 @@ __device__ inline void load_cols(const float* __restrict__ T, const FastParams& 
         const float4 x = *reinterpret_cast<const float4*>(s);
         v[0][q] = x.x; v[1][q] = x.y; v[2][q] = x.z; v[3][q] = x.w;
       } else if constexpr (NT == 2) {
-        const float2 x = *reinterpret_cast<const float2*>(s);
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        const f2v x = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(s));
         v[0][q] = x.x; v[1][q] = x.y;
       } else {
         v[0][q] = s[0];
