@@ -84,6 +84,46 @@ def test_ngmres_trajectory_small_dense_fp64(h, seed, tree):
     assert abs(hg - ho) <= 1e-10
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ngmres_trajectory_4way_dense_fp64(h, seed):
+    """Order 4 (both mode groups of the two-level evaluation hold two modes,
+    so every MTTKRP comes from a group partial), FP64, against the oracle."""
+    import paper_1105_5331_amd as cpng
+    dims, R, tol = (9, 11, 8, 10), 3, 1e-8
+    print(f"case ngmres trajectory 4-way seed={seed}", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=40 + seed)
+    u0 = initial_guess(dims, R, seed=10040 + seed)
+    ref = ngmres(CPProblem(ocp.DenseTensor(p.T), R), u0, tol=tol, max_iter=300)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u = _dev(u0)
+    out = cpng.cp_decompose(h, Tg, R, tol, u, trace_cap=400, max_iter=300)
+    half = 0.5 * np.sum(p.T ** 2)
+    n = _compare(out["trace"], ref.trace, half, f"4-way seed {seed}")
+    assert n >= min(len(ref.trace), 5)
+    assert out["converged"] and ref.converged
+    hg = np.sqrt(2 * ocp.objective_direct(p.T, ocp.split_u(u.cpu().numpy(), dims, R))) / np.sqrt(2 * half)
+    ho = np.sqrt(2 * ocp.objective_direct(p.T, ocp.split_u(ref.u, dims, R))) / np.sqrt(2 * half)
+    assert abs(hg - ho) <= 1e-10
+
+
+def test_als_trajectory_4way_dense_fp64(h):
+    """ALS on an order-4 tensor through the two-level sweep (left group's
+    partial before its updates, right group's after), iterate by iterate."""
+    import paper_1105_5331_amd as cpng
+    dims, R = (8, 9, 7, 10), 4
+    print("case als trajectory 4-way", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=47)
+    u0 = initial_guess(dims, R, seed=10047)
+    ref = als(CPProblem(ocp.DenseTensor(p.T), R), u0, tol=1e-8, max_iter=200)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    out = cpng.cp_decompose(h, Tg, R, 1e-8, _dev(u0), trace_cap=300, max_iter=200, method="als")
+    half = 0.5 * np.sum(p.T ** 2)
+    n = _compare(out["trace"], ref.trace, half, "als 4-way")
+    assert n == len(ref.trace) == len(out["trace"])
+
+
 def test_als_trajectory_dense_fp64(h):
     import paper_1105_5331_amd as cpng
     dims, R = (15, 12, 10), 3
