@@ -10,16 +10,19 @@
 // hi + lo once per workgroup and kept in LDS.  Y_o is a small GEMM on MFMA
 // (v_mfma_f32_16x16x32_bf16, three products hi*hi + hi*lo + lo*hi, float32
 // accumulation); the P(o, r) scaling is one FMA per accumulator.  The tensor
-// is read exactly once, straight from HBM into registers in the MFMA operand
-// layout (no LDS round trip), and split into bf16 hi + lo in registers.
+// is read exactly once, with non-temporal loads that each cover whole
+// 128-byte lines, and split into bf16 hi + lo in registers.
 //
-//  * row kernel (n < N-1): inner mode q = N-1, contiguous in memory.  Lane
-//    l reads rows i (l % 16) as two float4 of 8 consecutive k: the A operand.
+//  * row kernels (n < N-1): inner mode q = N-1, contiguous in memory.  The A
+//    operand is 8 consecutive k of a row per lane (rows l % 16), so only four
+//    lanes share a row: each wave reads its k-step rows as whole lines into
+//    registers, writes them to its own LDS area and reads the operands back
+//    (wave-level ordering only).
 //  * column kernel (n = N-1): inner mode q = N-2; the output index i is the
 //    contiguous one.  The MFMA computes Y^T = A^(q)^T T_o with the factor as
 //    the A operand (from LDS) and the tensor as the B operand: lane l reads
-//    8 rows k of one column i (l % 16), i.e. 16 consecutive floats per k-row
-//    across the lane group.
+//    8 rows k of two adjacent columns i, straight into registers (16 lanes
+//    read a whole line per k-row).
 //
 // Split-K over workgroups (blockIdx.x owns a contiguous range of outer
 // indices o); each workgroup writes its float32 partial sums to its own
@@ -164,33 +167,6 @@ __device__ inline float4 pscale4(const float* __restrict__ Pg, const FastParams&
   return r < p.R ? *reinterpret_cast<const float4*>(Pg + r * p.Opad + o) : float4{0.f, 0.f, 0.f, 0.f};
 }
 
-// One lane's 8 operand values of a row for the k-step starting at k0 (lane
-// group g = lane / 16), zero outside the row or K.
-// K is a multiple of 8, so each float4 is wholly inside or outside.
-__device__ inline void load_kstep(const float* __restrict__ row, bool ok, int64_t K, int k0, int g,
-                                  float (&v)[8]) {
-  const int k = k0 + kload_a(g);
-  if (ok && k < K) {
-    const float4 a = *reinterpret_cast<const float4*>(row + k);
-    const float4 b = *reinterpret_cast<const float4*>(row + k + 4);
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-  } else {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = 0.f;
-  }
-}
-
-// Row-kernel operand: the k-step at k0 of rows (w*MT + mt)*16 + lr.
-template <int MT>
-__device__ inline void load_rows(const float* __restrict__ T, const FastParams& p, int64_t base,
-                                 const int64_t (&rowoff)[MT], const bool (&rowok)[MT], int k0,
-                                 float (&v)[MT][8]) {
-  const int g = (threadIdx.x & 63) >> 4;
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) load_kstep(T + base + rowoff[mt], rowok[mt], p.K, k0, g, v[mt]);
-}
-
 // Row kernel: 4 waves x MT row tiles of 16 = 64*MT rows, 32 ranks.
 template <int MT>
 __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restrict__ T,
@@ -207,17 +183,32 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
   const int kb = (lane >> 4) * 8;
   const int r0 = blockIdx.z * 32;
   const int64_t i0 = (int64_t)blockIdx.y * (64 * MT);
+  constexpr int kRS = 36;              // staging row stride (floats)
+  constexpr int NQ = 16 * MT * 8 / 64; // 16-byte loads per lane per k-step
+  float* stg = reinterpret_cast<float*>(Sl + 32 * p.kpad) + w * (16 * MT * kRS);
   stage_inner(fac, p, r0, Sh, Sl);
   __syncthreads();
 
-  int64_t rowoff[MT];
-  bool rowok[MT];
+  // whole-line loads: lane l reads 16 bytes at chunk l % 8 of the wave's rows
+  // q*8 + l/8 (output rows i0 + 16 MT w + that)
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  int64_t lrowoff[NQ];
+  bool lrowok[NQ];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    const int64_t i = i0 + (w * MT + mt) * 16 + lr;
-    rowok[mt] = i < p.I_n;
-    rowoff[mt] = rowok[mt] ? i * p.istride : 0;
+  for (int q = 0; q < NQ; ++q) {
+    const int64_t i = i0 + (int64_t)w * MT * 16 + q * 8 + (lane >> 3);
+    lrowok[q] = i < p.I_n;
+    lrowoff[q] = lrowok[q] ? i * p.istride : 0;
   }
+  const int c4 = (lane & 7) * 4;
+  auto gload = [&](int64_t base, int k0, f4v (&dst)[NQ]) {
+    const int k = k0 + c4;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      dst[q] = (lrowok[q] && k < p.K)
+                   ? __builtin_nontemporal_load(reinterpret_cast<const f4v*>(T + base + lrowoff[q] + k))
+                   : f4v{0.f, 0.f, 0.f, 0.f};
+  };
   floatx4 acc[MT][2];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -231,13 +222,13 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
     const int nc = (int)(oe - ob);
     const int64_t* base_tab = bg + oc;
     const int nit = nc * p.nks;
-    // operand ring: buf[0] is consumed this iteration, buf[1..PF] are in flight
+    // load ring: buf[0] is consumed this iteration, buf[1..PF] are in flight
     constexpr int PF = CPNG_PREFETCH;
-    float buf[PF + 1][MT][8];
+    f4v buf[PF + 1][NQ];
     int jl = 0, kl = 0;   // (outer, k-step) of the next load
 #pragma unroll
     for (int b = 0; b < PF; ++b) {
-      if (b < nit) load_rows<MT>(T, p, base_tab[jl], rowoff, rowok, kl * 32, buf[b]);
+      if (b < nit) gload(base_tab[jl], kl * 32, buf[b]);
       if (++kl == p.nks) { kl = 0; ++jl; }
     }
     floatx4 Y[MT][2];
@@ -247,11 +238,29 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
       for (int nt = 0; nt < 2; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
     int j = 0, ks = 0;
     for (int it = 0; it < nit; ++it) {
-      if (it + PF < nit) load_rows<MT>(T, p, base_tab[jl], rowoff, rowok, kl * 32, buf[PF]);
+      if (it + PF < nit) gload(base_tab[jl], kl * 32, buf[PF]);
       if (++kl == p.nks) { kl = 0; ++jl; }
+      // stage the step's rows, then read back this lane's operands (8 k of a row)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        *reinterpret_cast<f4v*>(stg + (q * 8 + (lane >> 3)) * kRS + c4) = buf[0][q];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      float v[MT][8];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const f4v a = *reinterpret_cast<const f4v*>(stg + (mt * 16 + lr) * kRS + kb);
+        const f4v b = *reinterpret_cast<const f4v*>(stg + (mt * 16 + lr) * kRS + kb + 4);
+        v[mt][0] = a.x; v[mt][1] = a.y; v[mt][2] = a.z; v[mt][3] = a.w;
+        v[mt][4] = b.x; v[mt][5] = b.y; v[mt][6] = b.z; v[mt][7] = b.w;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       bf16x8 ah[MT], al[MT];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) split8(buf[0][mt], ah[mt], al[mt]);
+      for (int mt = 0; mt < MT; ++mt) split8(v[mt], ah[mt], al[mt]);
       const int k = ks * 32 + kb;
       const int so0 = lr * p.kpad + k;
       const int so1 = (16 + lr) * p.kpad + k;
@@ -289,9 +298,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
 #pragma unroll
       for (int b = 0; b < PF; ++b)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-          for (int q = 0; q < 8; ++q) buf[b][mt][q] = buf[b + 1][mt][q];
+        for (int q = 0; q < NQ; ++q) buf[b][q] = buf[b + 1][q];
     }
   }
   float* out = part + (int64_t)blockIdx.x * p.I_n * p.R;
@@ -462,7 +469,13 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
 // for 16 consecutive o per tile, then acc(r) += sum_o P(o, r) Y(o, r).  A
 // workgroup streams a contiguous range of o instead of 128 rows far apart.
 // Each wave works on TW o-tiles (16 TW outer indices) at a time; the waves
-// of a workgroup take consecutive groups.
+// of a workgroup take consecutive groups.  The MFMA operand layout gives
+// only four lanes to a row, so loading operands directly would split every
+// 128-byte line over two instructions; instead each k-step's rows are read
+// as whole lines (lane l: 16 bytes at chunk l % 8 of row l / 8, non-temporal,
+// one step ahead), written to the wave's own LDS area (row stride 36 floats)
+// and read back in the operand layout, ordered by wave-level fences only
+// (modes 1-2 at 128^4, R = 32: 194 -> 178 us).
 __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __restrict__ T,
                                                                 const float* __restrict__ fac,
                                                                 const float* __restrict__ Pg,
@@ -480,6 +493,9 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
   const int kb = (lane >> 4) * 8;
   const int r0 = blockIdx.z * 32;
   const int64_t bx = blockIdx.x;
+  constexpr int kRS = 36;                  // staging row stride (floats)
+  constexpr int NQ = 16 * TW * 8 / 64;     // 16-byte loads per lane per k-step
+  float* stg = reinterpret_cast<float*>(Sl + 32 * p.kpad) + w * (16 * TW * kRS);
   stage_inner(fac, p, r0, Sh, Sl);
   __syncthreads();
   const int64_t ob = bx * p.o_per_block;
@@ -488,25 +504,49 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
   const int64_t ioff = by * p.istride;
   float acc0 = 0.f, acc1 = 0.f;   // rank columns r0 + lr and r0 + 16 + lr
   for (int64_t og = ob + w * 16 * TW; og < oe; og += 4 * 16 * TW) {
-    const float* rowp[TW];
-    bool ok[TW];
+    // whole-line loads: lane l reads 16 bytes at chunk l % 8 of rows q*8 + l/8
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const float* lrow[NQ];
+    bool lok[NQ];
 #pragma unroll
-    for (int t = 0; t < TW; ++t) {
-      const int64_t o = og + t * 16 + lr;   // this lane's operand row
-      ok[t] = o < oe;
-      rowp[t] = T + (ok[t] ? bg[o] : 0) + ioff;
+    for (int q = 0; q < NQ; ++q) {
+      const int64_t o = og + q * 8 + (lane >> 3);
+      lok[q] = o < oe;
+      lrow[q] = T + (lok[q] ? bg[o] + ioff : 0);
     }
-    float v[TW][8], vn[TW][8];
-    auto load = [&](int ks, float (&dst)[TW][8]) {
+    const int c4 = (lane & 7) * 4;
+    f4v ld[NQ];
+    auto gload = [&](int ks) {
+      const int k = ks * 32 + c4;
 #pragma unroll
-      for (int t = 0; t < TW; ++t) load_kstep(rowp[t], ok[t], p.K, ks * 32, lane >> 4, dst[t]);
+      for (int q = 0; q < NQ; ++q)
+        ld[q] = (lok[q] && k < p.K) ? __builtin_nontemporal_load(reinterpret_cast<const f4v*>(lrow[q] + k))
+                                    : f4v{0.f, 0.f, 0.f, 0.f};
     };
-    load(0, v);
+    float v[TW][8];
+    gload(0);
     floatx4 Y[TW][2];
 #pragma unroll
     for (int t = 0; t < TW; ++t) Y[t][0] = Y[t][1] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int ks = 0; ks < p.nks; ++ks) {
-      if (ks + 1 < p.nks) load(ks + 1, vn);
+      // stage the step's rows, then read back this lane's operand (8 k of one row)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        *reinterpret_cast<f4v*>(stg + (q * 8 + (lane >> 3)) * kRS + c4) = ld[q];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        const f4v a = *reinterpret_cast<const f4v*>(stg + (t * 16 + lr) * kRS + kb);
+        const f4v b = *reinterpret_cast<const f4v*>(stg + (t * 16 + lr) * kRS + kb + 4);
+        v[t][0] = a.x; v[t][1] = a.y; v[t][2] = a.z; v[t][3] = a.w;
+        v[t][4] = b.x; v[t][5] = b.y; v[t][6] = b.z; v[t][7] = b.w;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (ks + 1 < p.nks) gload(ks + 1);
       const int k = ks * 32 + kb;
       const int so0 = lr * p.kpad + k;
       const int so1 = (16 + lr) * p.kpad + k;
@@ -525,10 +565,6 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
         Y[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl1, Y[t][1], 0, 0, 0);
         Y[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh1, Y[t][1], 0, 0, 0);
       }
-#pragma unroll
-      for (int t = 0; t < TW; ++t)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) v[t][q] = vn[t][q];
     }
     // D rows are outer indices og + t*16 + 4*(lane/16) + q; the column is the
     // rank.  og is a multiple of 4 (o_per_block is a multiple of 16).
@@ -812,7 +848,9 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   CP_TRY(ensure(h, h->part, sizeof(float) * (size_t)(ks * n_out), st));
   float* part = static_cast<float*>(h->part.ptr);
   dim3 grid((unsigned)ks, (unsigned)ygrid, (unsigned)rchunks);
-  const size_t lds = 2 * sizeof(__bf16) * 32 * (size_t)p.kpad;
+  // the row kernels stage each wave's k-step rows (16 per tile, 36-float stride)
+  const int wave_rows = stream_rows ? 16 * CPNG_ROWSTREAM_TW : (rows ? tile / 4 : 0);
+  const size_t lds = 2 * sizeof(__bf16) * 32 * (size_t)p.kpad + sizeof(float) * 4 * 36 * (size_t)wave_rows;
   // outer tables: P (O x R floats) then base offsets (O int64)
   const size_t pbytes = (sizeof(float) * (size_t)(p.Opad * R) + 255) & ~size_t(255);
   CP_TRY(ensure(h, h->otab, pbytes + sizeof(int64_t) * (size_t)p.O, st));
