@@ -123,8 +123,8 @@ def test_gram_parity(h, dims, R):
     np.testing.assert_allclose(G, refg, rtol=1e-11, atol=1e-12 * np.abs(refg).max())
 
 
-# one-workgroup form (L = R sum_k I_k <= 32768) and, for (3000, 40), the
-# multi-block form
+# one-workgroup form (L = R sum_k I_k <= 8192) and, for (300, 200, 100) and
+# (3000, 40), the multi-block form
 @pytest.mark.parametrize("dims,R", [((6, 7, 8), 5), ((30, 4, 9, 3), 12), ((3, 2), 1),
                                     ((300, 200, 100), 40), ((3000, 40), 16)])
 def test_normalize_parity(h, dims, R):
