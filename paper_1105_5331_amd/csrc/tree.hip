@@ -23,10 +23,12 @@
 // flight while the current one is multiplied; lane = row, the four waves
 // take every fourth k and are added in a fixed order at the end.
 //
-// group_mttkrp_kernel: thread (i, r) walks a contiguous range of the other
-// indices (outer o, inner k) of the group for mode n, loads issued 8 at a
-// time; ranges are split over workgroups and the slots added by the
-// fixed-order split-K reduction.  No atomics anywhere: results are
+// Second level: thread (i, r) walks a contiguous range of the other indices
+// (outer o, inner k) of the group for mode n, loads issued 8 at a time.
+// Short sums take one launch (group_fused_kernel: four waves per 64 outputs,
+// the quarters added in a fixed order, the gradient epilogue fused); long
+// ones are split over workgroups (group_mttkrp_kernel) and the slots added by
+// the fixed-order split-K reduction.  No atomics anywhere: results are
 // reproducible.
 #include "common.hpp"
 #include "splitk.hpp"
@@ -199,18 +201,11 @@ __device__ inline double idx_product(int64_t x, int nm, const int64_t* dims, con
   return s;
 }
 
-// part[c][i * R + r] = sum over the c-th range of (o, k) pairs of
-// X(o, i, k, r) P(o, r) Q(k, r), in range order (o major).
-__global__ __launch_bounds__(kThr) void group_mttkrp_kernel(const double* __restrict__ X,
-                                                            const double* __restrict__ fac,
-                                                            GroupParams p,
-                                                            double* __restrict__ part) {
-  const int64_t e = (int64_t)blockIdx.x * kThr + threadIdx.x;
-  if (e >= p.I * p.R) return;
-  const int64_t i = e / p.R;
-  const int r = (int)(e - i * p.R);
-  const int64_t f0 = (int64_t)blockIdx.y * p.per;
-  const int64_t f1 = min<int64_t>(p.O * p.K, f0 + p.per);
+// Sum over the (o, k) pairs f0 .. f1-1 (o major) of X(o, i, k, r) P(o, r) Q(k, r),
+// in pair order, loads issued 8 at a time.
+__device__ inline double group_range(const double* __restrict__ X, const double* __restrict__ fac,
+                                     const GroupParams& p, int64_t i, int r, int64_t f0,
+                                     int64_t f1) {
   double acc = 0.0;
   if (p.K == 1) {   // target is the group's last mode: the pairs are the outer indices o
     const double* x = X + i * p.R + r;
@@ -226,31 +221,86 @@ __global__ __launch_bounds__(kThr) void group_mttkrp_kernel(const double* __rest
 #pragma unroll
       for (int j = 0; j < 8; ++j) acc = fma(xv[j], pv[j], acc);
     }
-  } else {
-    int64_t f = f0;
-    while (f < f1) {
-      const int64_t o = f / p.K;
-      const int64_t k0 = f - o * p.K;
-      const int64_t k1 = min<int64_t>(p.K, k0 + (f1 - f));
-      const double P = idx_product(o, p.nlo, p.lodims, p.lofoff, fac, p.R, r);
-      const double* x = X + ((o * p.I + i) * p.K) * p.R + r;
-      double s = 0.0;
-      for (int64_t k = k0; k < k1; k += 8) {
-        double xv[8], qv[8];
+    return acc;
+  }
+  int64_t f = f0;
+  while (f < f1) {
+    const int64_t o = f / p.K;
+    const int64_t k0 = f - o * p.K;
+    const int64_t k1 = min<int64_t>(p.K, k0 + (f1 - f));
+    const double P = idx_product(o, p.nlo, p.lodims, p.lofoff, fac, p.R, r);
+    const double* x = X + ((o * p.I + i) * p.K) * p.R + r;
+    double s = 0.0;
+    for (int64_t k = k0; k < k1; k += 8) {
+      double xv[8], qv[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const bool ok = k + j < k1;
-          xv[j] = ok ? x[(k + j) * p.R] : 0.0;
-          qv[j] = ok ? idx_product(k + j, p.nhi, p.hidims, p.hifoff, fac, p.R, r) : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) s = fma(xv[j], qv[j], s);
+      for (int j = 0; j < 8; ++j) {
+        const bool ok = k + j < k1;
+        xv[j] = ok ? x[(k + j) * p.R] : 0.0;
+        qv[j] = ok ? idx_product(k + j, p.nhi, p.hidims, p.hifoff, fac, p.R, r) : 0.0;
       }
-      acc = fma(P, s, acc);
-      f += k1 - k0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s = fma(xv[j], qv[j], s);
+    }
+    acc = fma(P, s, acc);
+    f += k1 - k0;
+  }
+  return acc;
+}
+
+// part[c][i * R + r] = the c-th range of (o, k) pairs (group_range).
+__global__ __launch_bounds__(kThr) void group_mttkrp_kernel(const double* __restrict__ X,
+                                                            const double* __restrict__ fac,
+                                                            GroupParams p,
+                                                            double* __restrict__ part) {
+  const int64_t e = (int64_t)blockIdx.x * kThr + threadIdx.x;
+  if (e >= p.I * p.R) return;
+  const int64_t i = e / p.R;
+  const int r = (int)(e - i * p.R);
+  const int64_t f0 = (int64_t)blockIdx.y * p.per;
+  const int64_t f1 = min<int64_t>(p.O * p.K, f0 + p.per);
+  part[(int64_t)blockIdx.y * p.I * p.R + e] = group_range(X, fac, p, i, r, f0, f1);
+}
+
+// Short sums (O K <= kFusedPairs) in one launch: block b covers outputs
+// 64 b .. 64 b + 63 (lane = output), wave w adds the w-th quarter of the pairs,
+// the quarters are added in a fixed order, and with a pending gradient
+// epilogue G(i, r) = -M(i, r) + sum_q A(i, q) Gbar(q, r) (Gbar staged in LDS).
+constexpr int64_t kFusedPairs = 2048;
+
+__global__ __launch_bounds__(kThr) void group_fused_kernel(const double* __restrict__ X,
+                                                           const double* __restrict__ fac,
+                                                           GroupParams p, double* __restrict__ M,
+                                                           const double* __restrict__ eA,
+                                                           const double* __restrict__ eGbar,
+                                                           double* __restrict__ eG) {
+  extern __shared__ double gsh[];
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t n = p.I * p.R;
+  if (eG)
+    for (int t = threadIdx.x; t < p.R * p.R; t += kThr) gsh[t] = eGbar[t];
+  double s = 0.0;
+  const int64_t i = e / p.R;
+  const int r = (int)(e - i * p.R);
+  if (e < n) {
+    const int64_t work = p.O * p.K, q4 = (work + 3) / 4;
+    const int64_t f0 = w * q4, f1 = min<int64_t>(work, f0 + q4);
+    if (f0 < f1) s = group_range(X, fac, p, i, r, f0, f1);
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && e < n) {
+    const double t = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    M[e] = t;
+    if (eG) {
+      const double* a = eA + i * p.R;
+      double g = 0.0;
+      for (int q = 0; q < p.R; ++q) g = fma(a[q], gsh[q * p.R + r], g);
+      eG[e] = g - t;
     }
   }
-  part[(int64_t)blockIdx.y * p.I * p.R + e] = acc;
 }
 
 int64_t group_size(const Shape& s, int lo, int hi) {
@@ -358,6 +408,19 @@ int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, con
   p.I = s.dims[mode];
   const int64_t n_out = p.I * R;
   const int64_t work = p.O * p.K;
+  if (work <= kFusedPairs) {
+    GradEpi& ep = h->epi;
+    const bool epi = ep.G != nullptr && !ep.used;
+    {
+      KernelTimer timer(h, CP_KERNEL_GROUP_MTTKRP, st);
+      hipLaunchKernelGGL(group_fused_kernel, dim3(nblk(n_out, 64)), dim3(kThr),
+                         epi ? sizeof(double) * (size_t)R * R : 0, st, X, u, p, M,
+                         epi ? ep.A : nullptr, epi ? ep.Gbar : nullptr, epi ? ep.G : nullptr);
+    }
+    CP_LAUNCH_CHECK(h);
+    if (epi) ep.used = true;
+    return CP_OK;
+  }
   // about 2^19 threads, at least 8 (o, k) pairs each (one batch of loads),
   // at most 32768 ranges
   const int64_t want = std::min<int64_t>(32768, std::max<int64_t>(1, (int64_t(1) << 19) / n_out));

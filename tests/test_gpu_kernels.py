@@ -152,9 +152,12 @@ def test_normalize_zero_term(h):
     np.testing.assert_allclose(u.cpu().numpy(), ocp.join_u(B), rtol=1e-12, atol=1e-14)
 
 
+# (5, 2500, 6): the left group's mode 0 sums 2500 pairs per output (split-K
+# second level); every other case has short sums (one-launch second level)
 @pytest.mark.parametrize("dims,R,c", [((20, 20, 20), 3, 0.5), ((13, 30, 8, 5), 6, 0.9),
                                       ((70, 9, 66), 10, 0.3), ((5, 7, 6, 4, 3), 40, 0.5),
-                                      ((130, 3, 70), 64, 0.2), ((3, 90), 7, 0.4)])
+                                      ((130, 3, 70), 64, 0.2), ((3, 90), 7, 0.4),
+                                      ((5, 2500, 6), 3, 0.5)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32in_fp64acc"])
 def test_objective_grad_parity(h, dims, R, c, prec):
     """All N MTTKRPs at one point (dense order >= 3: the two mode-group
