@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void colsq_partial_kernel(const double* __rest
     for (int64_t i = i_begin + grp; i < i_end; i += G) s = fma(A[i * R + r], A[i * R + r], s);
   sh[threadIdx.x] = s;
   __syncthreads();
-  if (threadIdx.x < R) {
+  if ((int)threadIdx.x < R) {
     double tot = 0.0;
     for (int q = 0; q < G; ++q) tot += sh[q * R + threadIdx.x];
     part[ch * R + threadIdx.x] = tot;
