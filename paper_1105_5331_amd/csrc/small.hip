@@ -696,11 +696,19 @@ __global__ __launch_bounds__(256) void normalize_small_kernel(double* __restrict
   __syncthreads();
   const int64_t rows = t.off[t.N];
   const int64_t tr = kTile / R;   // rows per tile
+  constexpr int kPer = kTile / 256;   // tile entries per thread
   for (int pass = 0; pass < (g ? 2 : 1); ++pass) {
     double* x = pass == 0 ? u : g;
     for (int64_t r0 = 0; r0 < rows; r0 += tr) {
       const int64_t n = min<int64_t>(tr, rows - r0) * R;
-      for (int64_t e = threadIdx.x; e < n; e += 256) tile[e] = x[r0 * R + e];
+      double v[kPer];   // every load of the tile in flight before the LDS stores
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int64_t e = threadIdx.x + (int64_t)q * 256;
+        v[q] = e < n ? x[r0 * R + e] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) tile[threadIdx.x + q * 256] = v[q];
       __syncthreads();
       for (int64_t e = threadIdx.x; e < n; e += 256) {
         const int64_t lr = e / R;
