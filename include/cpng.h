@@ -71,7 +71,11 @@ typedef enum { CP_F32 = 0, CP_F64 = 1 } cp_dtype;
  *                           per-workgroup sums, float64 across workgroups
  *   CP_PREC_BF16X3          dense only: tensor and Khatri-Rao rows split x = hi + lo
  *                           (both bfloat16); hi*hi + hi*lo + lo*hi on MFMA with
- *                           float32 accumulation; float64 across workgroups
+ *                           float32 accumulation; float64 across workgroups.  MTTKRPs
+ *                           whose inner mode (the last; the next-to-last for the last
+ *                           mode) has a length that is not a multiple of 8 or above
+ *                           512 run the CP_PREC_FP32 kernels instead (faster there,
+ *                           and at least as accurate)
  *   CP_PREC_FP32IN_FP64ACC  float32 tensor widened to float64, float64 factors,
  *                           products and sums (the same kernels as CP_PREC_FP64) */
 typedef enum {

@@ -167,8 +167,15 @@ __device__ inline float4 pscale4(const float* __restrict__ Pg, const FastParams&
   return r < p.R ? *reinterpret_cast<const float4*>(Pg + r * p.Opad + o) : float4{0.f, 0.f, 0.f, 0.f};
 }
 
+// 16-byte load of T; NTR: non-temporal (rows are whole 128-byte lines)
+template <bool NTR>
+__device__ inline floatx4 load_t4(const float* ptr) {
+  if constexpr (NTR) return __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(ptr));
+  else return *reinterpret_cast<const floatx4*>(ptr);
+}
+
 // Row kernel: 4 waves x MT row tiles of 16 = 64*MT rows, 32 ranks.
-template <int MT>
+template <int MT, bool NTR>
 __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restrict__ T,
                                                            const float* __restrict__ fac,
                                                            const float* __restrict__ Pg,
@@ -206,8 +213,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
       dst[q] = (lrowok[q] && k < p.K)
-                   ? __builtin_nontemporal_load(reinterpret_cast<const f4v*>(T + base + lrowoff[q] + k))
-                   : f4v{0.f, 0.f, 0.f, 0.f};
+                   ? load_t4<NTR>(T + base + lrowoff[q] + k) : f4v{0.f, 0.f, 0.f, 0.f};
   };
   floatx4 acc[MT][2];
 #pragma unroll
@@ -472,10 +478,12 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
 // of a workgroup take consecutive groups.  The MFMA operand layout gives
 // only four lanes to a row, so loading operands directly would split every
 // 128-byte line over two instructions; instead each k-step's rows are read
-// as whole lines (lane l: 16 bytes at chunk l % 8 of row l / 8, non-temporal,
-// one step ahead), written to the wave's own LDS area (row stride 36 floats)
+// as whole lines (lane l: 16 bytes at chunk l % 8 of row l / 8, one step
+// ahead; non-temporal when rows are whole lines), written to the wave's own
+// LDS area (row stride 36 floats)
 // and read back in the operand layout, ordered by wave-level fences only
 // (modes 1-2 at 128^4, R = 32: 194 -> 178 us).
+template <bool NTR>
 __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __restrict__ T,
                                                                 const float* __restrict__ fac,
                                                                 const float* __restrict__ Pg,
@@ -520,8 +528,8 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
       const int k = ks * 32 + c4;
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        ld[q] = (lok[q] && k < p.K) ? __builtin_nontemporal_load(reinterpret_cast<const f4v*>(lrow[q] + k))
-                                    : f4v{0.f, 0.f, 0.f, 0.f};
+        ld[q] = (lok[q] && k < p.K)
+                    ? load_t4<NTR>(lrow[q] + k) : f4v{0.f, 0.f, 0.f, 0.f};
     };
     float v[TW][8];
     gload(0);
@@ -832,6 +840,10 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   const bool stream_rows = rows && mode < N - 2 && (stride[mode] / K) >= 16;
   const int tile = stream_rows ? 1 : (p.I_n > 64 ? 128 : 64);
   p.ptrans = stream_rows ? 1 : 0;
+  // non-temporal row loads only when every row is whole 128-byte lines: with
+  // rows of other lengths a line is shared by two rows and ordinary loads
+  // keep it for the second (104^4: 145 vs 166 us, 128^4: 178 vs 195 us)
+  const bool ntr = K % 32 == 0;
   // column kernel: one (tile / 64)-wide load per k-row when I_n allows it
   p.vec_ok = !rows && p.I_n % (tile / 64) == 0;
   const int64_t ychunks = (p.I_n + tile - 1) / tile;
@@ -841,7 +853,11 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   const int64_t ygrid = stream_rows ? std::min<int64_t>(ychunks, (target + rchunks - 1) / rchunks)
                                     : ychunks;
   int64_t ks = std::max<int64_t>(1, std::min<int64_t>(p.O, (target + ychunks * rchunks - 1) / (ychunks * rchunks)));
-  p.o_per_block = ((p.O + ks - 1) / ks + 15) / 16 * 16;
+  // the row-stream epilogue reads P for four consecutive o at a time from
+  // o = multiples of 4: its ranges are multiples of 16; the other kernels
+  // split O evenly (rounding there left 20 workgroups for a 152^3 tensor)
+  p.o_per_block = (p.O + ks - 1) / ks;
+  if (stream_rows) p.o_per_block = (p.o_per_block + 15) / 16 * 16;
   ks = (p.O + p.o_per_block - 1) / p.o_per_block;
   p.Opad = (p.O + 3) / 4 * 4;
   const int64_t n_out = p.I_n * R;
@@ -865,10 +881,16 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   {
     KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
     if (stream_rows) {
-      hipLaunchKernelGGL(mttkrp_rowstream_bf16x3, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      if (ntr) hipLaunchKernelGGL(mttkrp_rowstream_bf16x3<true>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      else hipLaunchKernelGGL(mttkrp_rowstream_bf16x3<false>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
     } else if (rows) {
-      if (tile == 128) hipLaunchKernelGGL(mttkrp_rows_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
-      else hipLaunchKernelGGL(mttkrp_rows_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      if (tile == 128) {
+        if (ntr) hipLaunchKernelGGL((mttkrp_rows_bf16x3<2, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+        else hipLaunchKernelGGL((mttkrp_rows_bf16x3<2, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      } else {
+        if (ntr) hipLaunchKernelGGL((mttkrp_rows_bf16x3<1, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+        else hipLaunchKernelGGL((mttkrp_rows_bf16x3<1, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      }
     } else {
       if (tile == 128) hipLaunchKernelGGL(mttkrp_cols_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
       else hipLaunchKernelGGL(mttkrp_cols_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
