@@ -343,6 +343,11 @@ int cp_server_destroy(cp_server* s);
 /* Enable (1) or disable (0) HIP-event timing of the main MTTKRP kernels on
  * the stream each is launched on; enabling clears the counters. */
 int cp_profile(cp_handle* h, int32_t enable);
+/* Which kernel ids cp_profile times: bit k of kernel_mask selects id k
+ * (default 0xF, all four).  Each timed launch adds two event records to its
+ * stream, so timing only the kernel being measured keeps the others' launch
+ * gaps out of a timed run.  CP_EINVAL for bits above 3. */
+int cp_profile_select(cp_handle* h, uint32_t kernel_mask);
 /* Synchronise the recorded events and return, for kernel id `kernel`, the
  * number of timed launches and their summed duration in milliseconds
  * (host pointers). */

@@ -116,6 +116,7 @@ def lib():
                                           C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
             "cp_server_destroy": (C.c_int, [vp]),
             "cp_profile": (C.c_int, [vp, i32]),
+            "cp_profile_select": (C.c_int, [vp, C.c_uint32]),
             "cp_profile_read": (C.c_int, [vp, i32, C.POINTER(i64), C.POINTER(dp)]),
             "cp_stream_read": (C.c_int, [vp, vp, C.c_size_t, vp]),
         }
@@ -376,6 +377,11 @@ def cp_stream_read(h: Handle, buf):
 
 def cp_profile(h: Handle, enable: bool):
     h.check(lib().cp_profile(h._h, int(bool(enable))))
+
+
+def cp_profile_select(h: Handle, kernel_mask: int):
+    """Time only the kernel ids whose bits are set in kernel_mask."""
+    h.check(lib().cp_profile_select(h._h, int(kernel_mask)))
 
 
 def cp_profile_read(h: Handle, kernel: int):

@@ -645,6 +645,12 @@ int cp_stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t stre
   return stream_read(h, buf, bytes, stream);
 }
 
+int cp_profile_select(cp_handle* h, uint32_t kernel_mask) {
+  if (!h || (kernel_mask & ~0xFu) != 0) return CP_EINVAL;
+  h->prof_mask = kernel_mask;
+  return CP_OK;
+}
+
 int cp_profile_read(cp_handle* h, int32_t kernel, int64_t* launches, double* total_ms) {
   if (!h || kernel < 0 || kernel > 3 || !launches || !total_ms) return CP_EINVAL;
   CP_HIP(h, hipSetDevice(h->device));

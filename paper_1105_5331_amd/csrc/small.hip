@@ -51,7 +51,7 @@ static hipEvent_t pool_event(cp_handle* h) {
 }
 
 KernelTimer::KernelTimer(cp_handle* h_, int id_, hipStream_t st_) : h(h_), id(id_), st(st_) {
-  if (!h->prof) return;
+  if (!h->prof || !((h->prof_mask >> id) & 1u)) return;
   a = pool_event(h);
   b = pool_event(h);
   if (a) (void)hipEventRecord(a, st);
@@ -134,86 +134,128 @@ ModeTable table(const Shape& s, int R) {
 // ---- Grams -----------------------------------------------------------------
 // part[(chunk) * R * R + r * R + q] = sum_{rows in chunk} A(i, r) A(i, q); the
 // chunk index ch0 + blockIdx.x runs over every mode's chunks (or one mode's).
-__global__ void gram_partial_kernel(const double* __restrict__ u, ModeTable t, int64_t ch0,
-                                    double* __restrict__ part) {
-  __shared__ double rows[32][kMaxR];
+// The chunk's rows (at most 64 x 64 values, 16 per thread) are loaded with
+// every load in flight, staged in LDS, and each entry summed in row order.
+__global__ __launch_bounds__(256) void gram_partial_kernel(const double* __restrict__ u,
+                                                           ModeTable t, int64_t ch0,
+                                                           double* __restrict__ part) {
+  static_assert(kRowsPerChunk * kMaxR == 16 * 256, "16 staged values per thread");
+  __shared__ double rows[kRowsPerChunk * kMaxR];
   const int R = t.R;
   const int64_t ch = ch0 + blockIdx.x;
   int k = 0;
   while (ch >= t.coff[k + 1]) ++k;
   const int64_t i_begin = (ch - t.coff[k]) * kRowsPerChunk;
-  const int64_t i_end = min<int64_t>(t.dims[k], i_begin + kRowsPerChunk);
-  const double* A = u + t.off[k] * R;
-  double acc[16];
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  for (int64_t i0 = i_begin; i0 < i_end; i0 += 32) {
-    const int nr = (int)min<int64_t>(32, i_end - i0);
-    for (int e = threadIdx.x; e < 32 * R; e += blockDim.x) {
-      const int ii = e / R, r = e - (e / R) * R;
-      rows[ii][r] = ii < nr ? A[(i0 + ii) * R + r] : 0.0;
-    }
-    __syncthreads();
+  const int nr = (int)min<int64_t>(kRowsPerChunk, t.dims[k] - i_begin);
+  const double* A = u + (t.off[k] + i_begin) * R;   // the chunk's rows, contiguous
+  const int n = nr * R;
+  double v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int pr = threadIdx.x + q * blockDim.x;
-      if (pr < R * R) {
-        const int r = pr / R, c = pr - (pr / R) * R;
-        double s = acc[q];
-        for (int ii = 0; ii < nr; ++ii) s = fma(rows[ii][r], rows[ii][c], s);
-        acc[q] = s;
-      }
-    }
-    __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + q * 256;
+    v[q] = e < n ? A[e] : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    const int pr = threadIdx.x + q * blockDim.x;
-    if (pr < R * R) part[ch * R * R + pr] = acc[q];
+    const int e = threadIdx.x + q * 256;
+    if (e < n) rows[e] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int pr = threadIdx.x + q * 256;
+    if (pr < R * R) {
+      const int r = pr / R, c = pr - (pr / R) * R;
+      double s = 0.0;
+      for (int ii = 0; ii < nr; ++ii) s = fma(rows[ii * R + r], rows[ii * R + c], s);
+      part[ch * R * R + pr] = s;
+    }
   }
 }
 
 // S^(k) = sum of that mode's chunk partials (chunk order); Gammabar^(n) and
 // Gamma as products over k in increasing order.
-__device__ void factor_block(const double* __restrict__ G, int R, double* __restrict__ F,
-                             int* __restrict__ kind, int* __restrict__ flags);
+template <int RM>
+__device__ __attribute__((noinline)) void factor_block(const double* __restrict__ G, int R,
+                                                      double* __restrict__ F,
+                                                      int* __restrict__ kind,
+                                                      int* __restrict__ flags, bool try_plain);
+template <int RM>
+__device__ __forceinline__ bool chol_wave(const double* __restrict__ G, int R,
+                                          double* __restrict__ F);
 
 // With fmode >= 0 the same block then factorises Gammabar^(fmode) for the
 // ALS mode solve (factor_block).  With only >= 0 the partials hold mode
-// `only` alone and S already holds the other modes' Grams.
+// `only` alone and S already holds the other modes' Grams.  Two phases: the
+// chunk sums into S, then (after the block barrier) the products, with the
+// loads of two entries in flight at a time; Gammabar^(fmode) is also kept
+// in LDS for the factorisation (RM: R rounded up to 16, 32 or 64).
+template <int RM>
 __global__ __launch_bounds__(256) void gram_final_kernel(const double* __restrict__ part, ModeTable t,
                                   double* __restrict__ S, double* __restrict__ Gbar,
                                   double* __restrict__ Gam, int fmode, double* __restrict__ F,
                                   int* __restrict__ kind, int* __restrict__ flags, int only) {
+  __shared__ double gl[kMaxR * kMaxR];
   const int R = t.R;
-  for (int pr = threadIdx.x; pr < R * R; pr += blockDim.x) {
-    double sk[CP_MAX_ORDER];
-    for (int k = 0; k < t.N; ++k) {
-      if (only >= 0 && k != only) {
-        sk[k] = S[(int64_t)k * R * R + pr];
-        continue;
-      }
-      const double s = ordered_sum(part + t.coff[k] * R * R + pr, t.coff[k + 1] - t.coff[k],
-                                   (int64_t)R * R);
-      sk[k] = s;
-      if (S) S[(int64_t)k * R * R + pr] = s;
+  const int RR = R * R;
+  const int k0 = only >= 0 ? only : 0;
+  const int k1 = only >= 0 ? only + 1 : t.N;
+  for (int k = k0; k < k1; ++k) {
+    const int64_t nc = t.coff[k + 1] - t.coff[k];
+    const double* pk = part + t.coff[k] * RR;
+    for (int pr = threadIdx.x; pr < RR; pr += 256) S[(int64_t)k * RR + pr] = ordered_sum(pk + pr, nc, RR);
+  }
+  __syncthreads();   // S stores visible to the block
+  constexpr int kGE = 2;   // entries per thread with their loads in flight together
+  for (int p0 = threadIdx.x; p0 < RR; p0 += kGE * 256) {
+    double sk[kGE][CP_MAX_ORDER];
+#pragma unroll
+    for (int q = 0; q < kGE; ++q) {
+      const int pr = p0 + q * 256;
+#pragma unroll
+      for (int k = 0; k < CP_MAX_ORDER; ++k)
+        sk[q][k] = (pr < RR && k < t.N) ? S[(int64_t)k * RR + pr] : 0.0;
     }
-    if (Gbar) {
-      for (int n = 0; n < t.N; ++n) {
-        double gb = 1.0;
-        for (int k = 0; k < t.N; ++k)
-          if (k != n) gb *= sk[k];
-        Gbar[(int64_t)n * R * R + pr] = gb;
+#pragma unroll
+    for (int q = 0; q < kGE; ++q) {
+      const int pr = p0 + q * 256;
+      if (pr >= RR) break;
+      if (Gbar) {
+#pragma unroll
+        for (int n = 0; n < CP_MAX_ORDER; ++n) {
+          if (n >= t.N) break;
+          double gb = 1.0;
+#pragma unroll
+          for (int k = 0; k < CP_MAX_ORDER; ++k)
+            if (k < t.N && k != n) gb *= sk[q][k];
+          Gbar[(int64_t)n * RR + pr] = gb;
+          if (n == fmode) gl[pr] = gb;
+        }
       }
-    }
-    if (Gam) {
-      double g = 1.0;
-      for (int k = 0; k < t.N; ++k) g *= sk[k];
-      Gam[pr] = g;
+      if (Gam) {
+        double g = 1.0;
+#pragma unroll
+        for (int k = 0; k < CP_MAX_ORDER; ++k)
+          if (k < t.N) g *= sk[q][k];
+        Gam[pr] = g;
+      }
     }
   }
   if (fmode >= 0) {
-    __syncthreads();   // this block's Gammabar stores are visible to the block
-    factor_block(Gbar + (int64_t)fmode * R * R, R, F, kind, flags);
+    __syncthreads();   // Gammabar^(fmode) complete in LDS and in global memory
+    // the plain factorisation from LDS by the first wave; the shifted and
+    // eigenvalue paths (factor_block) read the global copy when it fails
+    __shared__ int plain_ok;
+    if (threadIdx.x < 64) {
+      const bool good = chol_wave<RM>(gl, R, F);
+      if (threadIdx.x == 0) plain_ok = good ? 1 : 0;
+    }
+    __syncthreads();
+    if (plain_ok) {
+      if (threadIdx.x == 0) *kind = 0;
+    } else {
+      factor_block<RM>(Gbar + (int64_t)fmode * RR, R, F, kind, flags, false);
+    }
   }
 }
 
@@ -336,41 +378,43 @@ __device__ inline double wave_bcast(double v, int lane) {
 
 // Cholesky of the symmetric R x R matrix G (R <= RM <= 64) by the first wave,
 // in registers: lane c holds column c of the trailing matrix, both
-// triangles.  Step j: the pivot d = a(j, j) from lane j; every lane forms its
-// multiplier L(c, j) = a(j, c) / sqrt(d) (its own register j, since the
-// trailing matrix is symmetric) and removes L(i, j) L(c, j) from a(i, c) for
-// i > j, L(i, j) taken from lane i.  The same operations in the same order as
-// the right-looking block factorisation (chol_lds), without barriers.  Lane c
-// writes row c of L into F (zero above the diagonal).  Returns false (F then
-// partly written) at the first pivot that is not positive and finite.
+// triangles, padded to RM x RM with the identity (so no step needs a bound
+// test and the padding leaves the R x R factor unchanged).  Step j: the pivot
+// d = a(j, j) from lane j; every lane forms its multiplier L(c, j) =
+// a(j, c) / sqrt(d) (its own register j, since the trailing matrix is
+// symmetric) and removes L(i, j) L(c, j) from a(i, c) for i > j, L(i, j)
+// taken from lane i.  The same operations in the same order as the
+// right-looking block factorisation (chol_lds), without barriers.  Lane c
+// writes row c of L into F (zero above the diagonal).  Returns false at a
+// pivot that is not positive and finite (the later steps still run, on
+// values that are then discarded, and F is partly garbage).
 template <int RM>
-__device__ bool chol_wave(const double* __restrict__ G, int R, double* __restrict__ F) {
+__device__ __forceinline__ bool chol_wave(const double* __restrict__ G, int R, double* __restrict__ F) {
   const int c = threadIdx.x & 63;
   double a[RM];
 #pragma unroll
-  for (int i = 0; i < RM; ++i) a[i] = (c < R && i < R) ? G[i * R + c] : 0.0;
+  for (int i = 0; i < RM; ++i) a[i] = (c < R && i < R) ? G[i * R + c] : (i == c ? 1.0 : 0.0);
   bool ok = true;   // uniform across the wave
 #pragma unroll
   for (int j = 0; j < RM; ++j) {
-    if (j < R && ok) {
-      const double d = wave_bcast(a[j], j);
-      if (d > 0.0 && isfinite(d)) {
-        const double djj = sqrt(d);
-        const double m = a[j] / djj;   // L(c, j) for c > j
-        if (c < R) F[c * R + j] = c > j ? m : (c == j ? djj : 0.0);
+    const double d = wave_bcast(a[j], j);
+    ok = ok && d > 0.0 && isfinite(d);
+    const double djj = sqrt(d);
+    const double m = a[j] / djj;   // L(c, j) for c > j
+    if (j < R && c < R) F[c * R + j] = c > j ? m : (c == j ? djj : 0.0);
 #pragma unroll
-        for (int i = j + 1; i < RM; ++i)
-          if (i < R) a[i] -= wave_bcast(m, i) * m;
-      } else {
-        ok = false;
-      }
-    }
+    for (int i = j + 1; i < RM; ++i) a[i] -= wave_bcast(m, i) * m;
   }
   return ok;
 }
 
-__device__ void factor_block(const double* __restrict__ G, int R, double* __restrict__ F,
-                             int* __restrict__ kind, int* __restrict__ flags) {
+// try_plain: start with the one-wave factorisation (callers that already
+// tried it pass false).  RM: R rounded up to 16, 32 or 64.
+template <int RM>
+__device__ __attribute__((noinline)) void factor_block(const double* __restrict__ G, int R,
+                                                      double* __restrict__ F,
+                                                      int* __restrict__ kind,
+                                                      int* __restrict__ flags, bool try_plain) {
   __shared__ double a[kMaxR * kMaxR];
   __shared__ double v[kMaxR * kMaxR];
   __shared__ double ok;
@@ -378,8 +422,7 @@ __device__ void factor_block(const double* __restrict__ G, int R, double* __rest
   __shared__ int plain_ok;
   // plain Cholesky by the first wave
   if (threadIdx.x < 64) {
-    const bool good = R <= 16 ? chol_wave<16>(G, R, F)
-                              : (R <= 32 ? chol_wave<32>(G, R, F) : chol_wave<64>(G, R, F));
+    const bool good = try_plain && chol_wave<RM>(G, R, F);
     if (threadIdx.x == 0) plain_ok = good ? 1 : 0;
   }
   __syncthreads();
@@ -489,21 +532,27 @@ __device__ void factor_block(const double* __restrict__ G, int R, double* __rest
   }
 }
 
-__global__ __launch_bounds__(256) void factor_kernel(const double* __restrict__ G, int R, double* __restrict__ F,
-                              int* __restrict__ kind, int* __restrict__ flags) {
-  factor_block(G, R, F, kind, flags);
+template <int RM>
+__global__ __launch_bounds__(256) void factor_kernel(const double* __restrict__ G, int R,
+                                                     double* __restrict__ F,
+                                                     int* __restrict__ kind,
+                                                     int* __restrict__ flags) {
+  factor_block<RM>(G, R, F, kind, flags, true);
 }
 
 // A(i,:) = M(i,:) Gammabar^-1 using the factor from factor_block.  One wave
 // per row (grid-stride over rows), lane q holding component q (R <= 64):
-// forward L y = m, then back L^T x = y, one component finished per step and
+// forward L y = m, then back L^T x = y, one component finished per step
+// (broadcast from its lane with readlane, times the reciprocal pivot) and
 // removed from the others by their lanes.
 __global__ __launch_bounds__(256) void solve_rows_kernel(const double* __restrict__ M,
                                                          const double* __restrict__ F,
                                                          const int* __restrict__ kind, int64_t I,
                                                          int R, double* __restrict__ A) {
   __shared__ double f[kMaxR * kMaxR];
+  __shared__ double rdiag[kMaxR];
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) f[e] = F[e];
+  for (int r = threadIdx.x; r < R; r += blockDim.x) rdiag[r] = 1.0 / F[r * R + r];
   __syncthreads();
   const int q = threadIdx.x & 63;
   const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -521,12 +570,12 @@ __global__ __launch_bounds__(256) void solve_rows_kernel(const double* __restric
       continue;
     }
     for (int r = 0; r < R; ++r) {
-      const double yr = __shfl(y, r) / f[r * R + r];
+      const double yr = wave_bcast(y, r) * rdiag[r];
       if (q == r) y = yr;
       else if (q > r && q < R) y -= f[q * R + r] * yr;
     }
     for (int r = R - 1; r >= 0; --r) {
-      const double xr = __shfl(y, r) / f[r * R + r];
+      const double xr = wave_bcast(y, r) * rdiag[r];
       if (q == r) y = xr;
       else if (q < r) y -= f[r * R + q] * xr;
     }
@@ -1017,7 +1066,7 @@ static int factor_slot(cp_handle* h, int R, double** F, int** kind, hipStream_t 
 int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, double* Gbar,
              double* Gam, hipStream_t st, int factor_mode, int only_mode) {
   if (R > kMaxR) return fail(h, CP_EINVAL, "rank %d above the supported %d", R, kMaxR);
-  if (only_mode >= 0 && !S) return fail(h, CP_EINVAL, "one-mode Gram update without S");
+  if (!S) return fail(h, CP_EINVAL, "Gram without S");
   ModeTable t = table(s, R);
   const int64_t nch = t.coff[s.N];
   const int64_t ch0 = only_mode >= 0 ? t.coff[only_mode] : 0;
@@ -1029,8 +1078,15 @@ int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, do
   double* part = static_cast<double*>(h->red.ptr);
   hipLaunchKernelGGL(gram_partial_kernel, dim3((unsigned)nrun), dim3(256), 0, st, u, t, ch0, part);
   CP_LAUNCH_CHECK(h);
-  hipLaunchKernelGGL(gram_final_kernel, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam,
-                     factor_mode, F, kind, h->flags, only_mode);
+  if (R <= 16)
+    hipLaunchKernelGGL(gram_final_kernel<16>, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam,
+                       factor_mode, F, kind, h->flags, only_mode);
+  else if (R <= 32)
+    hipLaunchKernelGGL(gram_final_kernel<32>, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam,
+                       factor_mode, F, kind, h->flags, only_mode);
+  else
+    hipLaunchKernelGGL(gram_final_kernel<64>, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam,
+                       factor_mode, F, kind, h->flags, only_mode);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
@@ -1072,7 +1128,12 @@ int mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int
   int* kind = nullptr;
   CP_TRY(factor_slot(h, R, &F, &kind, st));
   if (Gbar) {   // else the factor was formed by gram_all(..., factor_mode)
-    hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(256), 0, st, Gbar, R, F, kind, h->flags);
+    if (R <= 16)
+      hipLaunchKernelGGL(factor_kernel<16>, dim3(1), dim3(256), 0, st, Gbar, R, F, kind, h->flags);
+    else if (R <= 32)
+      hipLaunchKernelGGL(factor_kernel<32>, dim3(1), dim3(256), 0, st, Gbar, R, F, kind, h->flags);
+    else
+      hipLaunchKernelGGL(factor_kernel<64>, dim3(1), dim3(256), 0, st, Gbar, R, F, kind, h->flags);
     CP_LAUNCH_CHECK(h);
   }
   if (I > 0) {

@@ -207,11 +207,12 @@ __global__ __launch_bounds__(256) void sparse_wave_kernel(const TT* __restrict__
     // the step's metadata, one nonzero per lane
     const bool mine = lane < nstep;
     const int64_t zm = mine ? zb + lane : z0;
-    const int32_t my_row = mine ? rows[zm] : INT32_MAX;
-    const CT my_val = mine ? (CT)vals[zm] : CT(0);
+    const int32_t my_row = mine ? __builtin_nontemporal_load(rows + zm) : INT32_MAX;
+    const CT my_val = mine ? (CT)__builtin_nontemporal_load(vals + zm) : CT(0);
     int32_t my_c[KM];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) my_c[k] = k < km ? p.coords[(int64_t)k * p.nnz + zm] : 0;
+    for (int k = 0; k < KM; ++k)
+      my_c[k] = k < km ? __builtin_nontemporal_load(p.coords + (int64_t)k * p.nnz + zm) : 0;
     const int32_t last_row = __shfl(my_row, nstep - 1);
     // gathers of all J sub-steps, then the products
     int32_t rowj[J];

@@ -5,6 +5,7 @@ import os
 import re
 import shutil
 import subprocess
+import tempfile
 
 import pytest
 
@@ -58,17 +59,16 @@ int main() {
   return 0;
 }
 '''
-    tmp = os.path.join(ROOT, "_work")
-    os.makedirs(tmp, exist_ok=True)
-    cpp = os.path.join(tmp, "abi_layout.cpp")
-    exe = os.path.join(tmp, "abi_layout")
-    open(cpp, "w").write(src)
-    r = subprocess.run([gxx, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
-                        "-I" + os.path.join(ROOT, "include"), cpp, "-o", exe],
-                       capture_output=True, text=True)
-    if r.returncode != 0:
-        pytest.skip("could not compile the layout probe: " + r.stderr[:200])
-    out = subprocess.run([exe], capture_output=True, text=True).stdout.split("\n")
+    with tempfile.TemporaryDirectory() as tmp:
+        cpp = os.path.join(tmp, "abi_layout.cpp")
+        exe = os.path.join(tmp, "abi_layout")
+        open(cpp, "w").write(src)
+        r = subprocess.run([gxx, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                            "-I" + os.path.join(ROOT, "include"), cpp, "-o", exe],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            pytest.skip("could not compile the layout probe: " + r.stderr[:200])
+        out = subprocess.run([exe], capture_output=True, text=True).stdout.split("\n")
     got = dict(line.split() for line in out if line.strip())
     S = {"cp_tensor": nat.cp_tensor, "cp_options": nat.cp_options,
          "cp_iter_info": nat.cp_iter_info, "cp_report": nat.cp_report}

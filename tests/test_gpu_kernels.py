@@ -424,6 +424,35 @@ def test_sparse_objective_grad_parity(h):
     assert np.linalg.norm(g.cpu().numpy() - go) <= 1e-12 * np.sqrt(t.norm2)
 
 
+def test_profile_select_times_only_the_chosen_kernels(h):
+    """With only the dense MTTKRP selected, a two-level objective/gradient
+    evaluation records its group-partial launches and no second-level ones;
+    an unknown id bit is rejected."""
+    cpng = _cpng()
+    dims, R = (24, 20, 18, 16), 3
+    T = _dev(np.random.default_rng(5).standard_normal(dims).astype(np.float32))
+    Tg = cpng.Tensor(dims, T)
+    cpng.cp_tensor_prepare(h, Tg)
+    u = _dev(ocp.join_u(_factors(dims, R, 23)))
+    cpng.cp_profile_select(h, 1 << cpng.CP_KERNEL_DENSE_MTTKRP)
+    cpng.cp_profile(h, True)
+    cpng.cp_objective_grad(h, Tg, u, R, "fp32")
+    torch.cuda.synchronize()
+    nd, msd = cpng.cp_profile_read(h, cpng.CP_KERNEL_DENSE_MTTKRP)
+    ng, _ = cpng.cp_profile_read(h, cpng.CP_KERNEL_GROUP_MTTKRP)
+    cpng.cp_profile(h, False)
+    cpng.cp_profile_select(h, 0xF)
+    assert nd >= 1 and msd > 0 and ng == 0
+    cpng.cp_profile(h, True)
+    cpng.cp_objective_grad(h, Tg, u, R, "fp32")
+    torch.cuda.synchronize()
+    ng, _ = cpng.cp_profile_read(h, cpng.CP_KERNEL_GROUP_MTTKRP)
+    cpng.cp_profile(h, False)
+    assert ng >= 1
+    with pytest.raises(cpng.CpError):
+        cpng.cp_profile_select(h, 1 << 4)
+
+
 def test_stream_read_reference(h):
     """The streaming-read measurement kernel: runs on an aligned buffer, is
     timed under its own id, and rejects a misaligned or ragged one."""
