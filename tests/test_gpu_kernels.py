@@ -361,6 +361,11 @@ SPARSE_CASES = [
     ("rand_ragged", lambda: random_coo((300, 40, 50), 9000, seed=2, skew=1.2)),
     ("rand_4way", lambda: random_coo((17, 23, 5, 31), 4000, seed=3)),
     ("long_rows", lambda: random_coo((3, 200, 200), 20000, seed=4)),
+    # larger modes (thousands of rows), many waves per mode, and with skew
+    # very uneven rows
+    ("blocked_3way", lambda: random_coo((50, 3000, 40), 30000, seed=5)),
+    ("blocked_skew", lambda: random_coo((40, 3000, 30), 6000, seed=6, skew=1.2)),
+    ("blocked_4way", lambda: random_coo((2500, 30, 20, 12), 20000, seed=7)),
 ]
 
 
