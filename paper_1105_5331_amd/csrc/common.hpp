@@ -1,6 +1,7 @@
 // Internal declarations shared by the library's translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -112,7 +113,10 @@ struct Shape {
 
 int make_shape(cp_handle* h, int order, const int64_t* dims, Shape* s);
 
-// Event timing around a main kernel launch (no-op unless h->prof).
+// Event timing of a main kernel launch (no-op unless h->prof selects id):
+// the timer holds a pair of events that CP_TIMED_LAUNCH hands to the launch
+// itself (hipExtLaunchKernelGGL records the kernel's own start and end, with
+// no extra packets on the stream); the destructor files the pair.
 struct KernelTimer {
   cp_handle* h;
   int id;
@@ -121,6 +125,15 @@ struct KernelTimer {
   KernelTimer(cp_handle* h_, int id_, hipStream_t st_);
   ~KernelTimer();
 };
+
+#define CP_TIMED_LAUNCH(timer, kernel, grid, block, lds, stream, ...)                         \
+  do {                                                                                         \
+    if ((timer).a && (timer).b)                                                                \
+      hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, (timer).a, (timer).b, 0,         \
+                            __VA_ARGS__);                                                      \
+    else                                                                                       \
+      hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                       \
+  } while (0)
 
 // Library-owned per-mode sorted copies of a sparse tensor.
 struct SparseMode {

@@ -881,19 +881,19 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   {
     KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
     if (stream_rows) {
-      if (ntr) hipLaunchKernelGGL(mttkrp_rowstream_bf16x3<true>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
-      else hipLaunchKernelGGL(mttkrp_rowstream_bf16x3<false>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      if (ntr) CP_TIMED_LAUNCH(timer, mttkrp_rowstream_bf16x3<true>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      else CP_TIMED_LAUNCH(timer, mttkrp_rowstream_bf16x3<false>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
     } else if (rows) {
       if (tile == 128) {
-        if (ntr) hipLaunchKernelGGL((mttkrp_rows_bf16x3<2, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
-        else hipLaunchKernelGGL((mttkrp_rows_bf16x3<2, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+        if (ntr) CP_TIMED_LAUNCH(timer, (mttkrp_rows_bf16x3<2, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+        else CP_TIMED_LAUNCH(timer, (mttkrp_rows_bf16x3<2, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
       } else {
-        if (ntr) hipLaunchKernelGGL((mttkrp_rows_bf16x3<1, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
-        else hipLaunchKernelGGL((mttkrp_rows_bf16x3<1, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+        if (ntr) CP_TIMED_LAUNCH(timer, (mttkrp_rows_bf16x3<1, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+        else CP_TIMED_LAUNCH(timer, (mttkrp_rows_bf16x3<1, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
       }
     } else {
-      if (tile == 128) hipLaunchKernelGGL(mttkrp_cols_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
-      else hipLaunchKernelGGL(mttkrp_cols_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      if (tile == 128) CP_TIMED_LAUNCH(timer, mttkrp_cols_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      else CP_TIMED_LAUNCH(timer, mttkrp_cols_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
     }
   }
   CP_LAUNCH_CHECK(h);
@@ -952,8 +952,8 @@ static int launch_tiles(cp_handle* h, const TT* T, const CT* fac, FastParams p, 
   dim3 grid((unsigned)ks, (unsigned)ychunks, (unsigned)rchunks);
   {
     KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
-    if (rows) hipLaunchKernelGGL((mttkrp_tiles_vec<TT, CT, RB, true>), grid, dim3(kThr), 0, st, T, fac, p, part);
-    else hipLaunchKernelGGL((mttkrp_tiles_vec<TT, CT, RB, false>), grid, dim3(kThr), 0, st, T, fac, p, part);
+    if (rows) CP_TIMED_LAUNCH(timer, (mttkrp_tiles_vec<TT, CT, RB, true>), grid, dim3(kThr), 0, st, T, fac, p, part);
+    else CP_TIMED_LAUNCH(timer, (mttkrp_tiles_vec<TT, CT, RB, false>), grid, dim3(kThr), 0, st, T, fac, p, part);
   }
   CP_LAUNCH_CHECK(h);
   CP_TRY(launch_splitk_reduce(h, part, ks, n_out, p.R, M, st));

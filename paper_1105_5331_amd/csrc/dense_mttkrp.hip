@@ -198,7 +198,7 @@ int launch_vec(cp_handle* h, const TT* T, const CT* fac, DenseParams p, double* 
   dim3 grid((unsigned)ks, (unsigned)ichunks, (unsigned)rchunks);
   {
     KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
-    hipLaunchKernelGGL((mttkrp_vec_kernel<TT, CT, RB, S>), grid, dim3(kThreads), 0, st, T, fac, p,
+    CP_TIMED_LAUNCH(timer, (mttkrp_vec_kernel<TT, CT, RB, S>), grid, dim3(kThreads), 0, st, T, fac, p,
                        part);
   }
   CP_LAUNCH_CHECK(h);
@@ -373,7 +373,7 @@ int launch_bf16x3(cp_handle* h, const float* T, const float* fac, DenseParams p,
   dim3 grid((unsigned)ks, (unsigned)ichunks, (unsigned)rchunks);
   {
     KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
-    hipLaunchKernelGGL((mttkrp_bf16x3_kernel<S>), grid, dim3(kThreads), 0, st, T, fac, p, part);
+    CP_TIMED_LAUNCH(timer, (mttkrp_bf16x3_kernel<S>), grid, dim3(kThreads), 0, st, T, fac, p, part);
   }
   CP_LAUNCH_CHECK(h);
   CP_TRY(launch_splitk_reduce(h, part, ks, n_out, p.R, M, st));

@@ -54,12 +54,15 @@ KernelTimer::KernelTimer(cp_handle* h_, int id_, hipStream_t st_) : h(h_), id(id
   if (!h->prof || !((h->prof_mask >> id) & 1u)) return;
   a = pool_event(h);
   b = pool_event(h);
-  if (a) (void)hipEventRecord(a, st);
+  if (!a || !b) {   // no timing for this launch
+    if (a) h->ev_pool.push_back(a);
+    if (b) h->ev_pool.push_back(b);
+    a = b = nullptr;
+  }
 }
 
 KernelTimer::~KernelTimer() {
   if (!a || !b) return;
-  (void)hipEventRecord(b, st);
   h->ev_pending[id].emplace_back(a, b);
   if (h->ev_pending[id].size() >= 512) {   // fold old pairs to bound the pool
     for (auto& pr : h->ev_pending[id]) {
@@ -1164,7 +1167,7 @@ int stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t st) {
   CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)nb, st));
   {
     KernelTimer timer(h, CP_KERNEL_STREAM_READ, st);
-    hipLaunchKernelGGL(stream_read_kernel, dim3(nb), dim3(256), 0, st,
+    CP_TIMED_LAUNCH(timer, stream_read_kernel, dim3(nb), dim3(256), 0, st,
                        static_cast<const float4*>(buf), (int64_t)(bytes / 16),
                        static_cast<double*>(h->red.ptr));
   }

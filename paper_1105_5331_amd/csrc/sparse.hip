@@ -306,7 +306,7 @@ int launch_sparse_wave(cp_handle* h, const TT* vals, const int32_t* rows, const 
   double* cval = reinterpret_cast<double*>(crow + nslots);
   {
     KernelTimer timer(h, CP_KERNEL_SPARSE_MTTKRP, st);
-    hipLaunchKernelGGL((sparse_wave_kernel<TT, CT, L, KM>), dim3(nblk(nwaves * 64, 256)),
+    CP_TIMED_LAUNCH(timer, (sparse_wave_kernel<TT, CT, L, KM>), dim3(nblk(nwaves * 64, 256)),
                        dim3(256), 0, st, vals, rows, fac, p, M, crow, cval);
   }
   CP_LAUNCH_CHECK(h);

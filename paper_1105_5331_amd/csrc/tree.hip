@@ -166,9 +166,9 @@ int launch_contract_last(cp_handle* h, const TT* T, const CT* fac, const LastPar
   const int RB = p.R <= 8 ? 8 : (p.R <= 16 ? 16 : 32);
   const dim3 grid(nblk(p.rows, kTB), (unsigned)((p.R + RB - 1) / RB));
   KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
-  if (RB == 8) hipLaunchKernelGGL((contract_last_kernel<TT, CT, 8>), grid, dim3(kThr), 0, st, T, fac, p, X);
-  else if (RB == 16) hipLaunchKernelGGL((contract_last_kernel<TT, CT, 16>), grid, dim3(kThr), 0, st, T, fac, p, X);
-  else hipLaunchKernelGGL((contract_last_kernel<TT, CT, 32>), grid, dim3(kThr), 0, st, T, fac, p, X);
+  if (RB == 8) CP_TIMED_LAUNCH(timer, (contract_last_kernel<TT, CT, 8>), grid, dim3(kThr), 0, st, T, fac, p, X);
+  else if (RB == 16) CP_TIMED_LAUNCH(timer, (contract_last_kernel<TT, CT, 16>), grid, dim3(kThr), 0, st, T, fac, p, X);
+  else CP_TIMED_LAUNCH(timer, (contract_last_kernel<TT, CT, 32>), grid, dim3(kThr), 0, st, T, fac, p, X);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
@@ -413,7 +413,7 @@ int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, con
     const bool epi = ep.G != nullptr && !ep.used;
     {
       KernelTimer timer(h, CP_KERNEL_GROUP_MTTKRP, st);
-      hipLaunchKernelGGL(group_fused_kernel, dim3(nblk(n_out, 64)), dim3(kThr),
+      CP_TIMED_LAUNCH(timer, group_fused_kernel, dim3(nblk(n_out, 64)), dim3(kThr),
                          epi ? sizeof(double) * (size_t)R * R : 0, st, X, u, p, M,
                          epi ? ep.A : nullptr, epi ? ep.Gbar : nullptr, epi ? ep.G : nullptr);
     }
@@ -431,7 +431,7 @@ int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, con
   double* part = static_cast<double*>(h->part.ptr);
   {
     KernelTimer timer(h, CP_KERNEL_GROUP_MTTKRP, st);
-    hipLaunchKernelGGL(group_mttkrp_kernel, grid, dim3(kThr), 0, st, X, u, p, part);
+    CP_TIMED_LAUNCH(timer, group_mttkrp_kernel, grid, dim3(kThr), 0, st, X, u, p, part);
   }
   CP_LAUNCH_CHECK(h);
   CP_TRY(launch_splitk_reduce(h, part, nch, n_out, R, M, st));
