@@ -192,6 +192,9 @@ int stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t st);
 // two launches
 int objective_from_dot(cp_handle* h, const double* A, const double* M, int64_t n, double normsq,
                        const double* Gam, int R, double* f, hipStream_t st);
+// y1 = x1, y2 = x2 (n doubles each) in one launch
+int copy2(cp_handle* h, const double* x1, double* y1, const double* x2, double* y2, int64_t n,
+          hipStream_t st);
 int axpy_to(cp_handle* h, const double* x, double a, const double* d, double* y, int64_t n,
             hipStream_t st);   // y = x + a*d
 int sub_to(cp_handle* h, const double* a, const double* b, double* y, int64_t n,

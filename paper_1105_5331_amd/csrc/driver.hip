@@ -403,10 +403,10 @@ int more_thuente(cp_handle* h, cp_ngmres_state* S, double f0, double g0, double*
     double f, g;
     CP_TRY(ls_eval(h, S, stp, &f, &g));
     ++nfev;
-    if (f < best_f) {
+    const bool better = f < best_f;
+    if (better) {
       best_f = f;
       best_stp = stp;
-      CP_HIP(h, hipMemcpyAsync(S->gbest, S->gt, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
     }
     const double ftest = f0 + stp * gtest;
     if (stage == 1 && f <= ftest && g >= 0.0) stage = 2;
@@ -417,6 +417,10 @@ int more_thuente(cp_handle* h, cp_ngmres_state* S, double f0, double g0, double*
     else if (m.brackt && stmax - stmin <= xtol * stmax) status = LS_XTOL;
     else if (m.brackt && (stp <= stmin || stp >= stmax)) status = LS_ROUNDING;
     else if (nfev >= o.ls_maxfev) status = LS_MAXFEV;
+    // the trial's gradient is kept for a fallback only while the search goes
+    // on (a final trial's gradient is still in S->gt)
+    if (better && status < 0)
+      CP_HIP(h, hipMemcpyAsync(S->gbest, S->gt, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
     if (status >= 0) {
       *nfev_out = nfev;
       *status_out = status;
@@ -427,7 +431,7 @@ int more_thuente(cp_handle* h, cp_ngmres_state* S, double f0, double g0, double*
       } else if (best_f < f0) {
         *beta = best_stp;
         *f_acc = best_f;
-        *g_acc = S->gbest;
+        *g_acc = better ? S->gt : S->gbest;
       } else {
         *beta = 0.0;
         *f_acc = f0;
@@ -471,8 +475,7 @@ int window_push(cp_handle* h, cp_ngmres_state* S) {
     S->wcount--;
   }
   const int j = S->wcount;
-  CP_HIP(h, hipMemcpyAsync(win_u(S, j), S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
-  CP_HIP(h, hipMemcpyAsync(win_g(S, j), S->g, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+  CP_TRY(copy2(h, S->u, win_u(S, j), S->g, win_g(S, j), S->L, S->st));
   S->wcount++;
   return CP_OK;
 }
@@ -940,18 +943,23 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
       if (gacc) gnew = gacc;
       else { beta = 0.0; fnew = fbar; gnew = S->gbar; }
     }
-    if (beta != 0.0) CP_TRY(axpy_to(h, S->ubar, beta, S->d, S->u, S->L, S->st));
-    else CP_HIP(h, hipMemcpyAsync(S->u, S->ubar, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
-    CP_HIP(h, hipMemcpyAsync(S->g, gnew, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+    // u_{i+1} = u_bar + beta d: the accepted trial point itself when its
+    // gradient is the last trial's (the same fma on the same beta), else formed
+    if (beta == 0.0) CP_TRY(copy2(h, S->ubar, S->u, gnew, S->g, S->L, S->st));
+    else if (gnew == S->gt) CP_TRY(copy2(h, S->ut, S->u, gnew, S->g, S->L, S->st));
+    else {
+      CP_TRY(axpy_to(h, S->ubar, beta, S->d, S->u, S->L, S->st));
+      CP_HIP(h, hipMemcpyAsync(S->g, gnew, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+    }
     CP_TRY(normalize(h, S->s, S->u, S->R, S->g, S->st));
     S->f = fnew;
     CP_TRY(dot(h, S->g, S->g, S->L, S->scal + 3, S->st));
+    CP_TRY(window_push(h, S));   // queued before the readback below waits
     double gg;
     CP_TRY(readback(h, S->scal + 3, 1, &gg, S->st));
     S->rho = std::sqrt(std::max(0.0, gg)) / S->normT;
     if (!std::isfinite(S->f) || !std::isfinite(S->rho))
       return fail(h, CP_ENOTFINITE, "objective or gradient not finite");
-    CP_TRY(window_push(h, S));
   }
   S->it++;
   rec.t_passes = (int32_t)(h->t_passes - passes0);

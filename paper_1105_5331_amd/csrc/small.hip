@@ -887,6 +887,16 @@ __global__ void set_steppar_kernel(StepPar* p, double beta, int m, int whead) {
   p->whead = whead;
 }
 
+// y1 = x1 and y2 = x2 (n values each), one launch
+__global__ void copy2_kernel(const double* __restrict__ x1, double* __restrict__ y1,
+                             const double* __restrict__ x2, double* __restrict__ y2, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) {
+    y1[e] = x1[e];
+    y2[e] = x2[e];
+  }
+}
+
 __global__ void axpy_par_kernel(const double* __restrict__ x, const StepPar* __restrict__ par,
                                 const double* __restrict__ d, double* __restrict__ y, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1211,6 +1221,14 @@ int axpy_to(cp_handle* h, const double* x, double a, const double* d, double* y,
             hipStream_t st) {
   if (n == 0) return CP_OK;
   hipLaunchKernelGGL(axpy_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, x, a, d, y, n);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int copy2(cp_handle* h, const double* x1, double* y1, const double* x2, double* y2, int64_t n,
+          hipStream_t st) {
+  if (n == 0) return CP_OK;
+  hipLaunchKernelGGL(copy2_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, x1, y1, x2, y2, n);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
