@@ -194,21 +194,71 @@ __device__ __forceinline__ bool chol_wave(const double* __restrict__ G, int R,
 // loads of two entries in flight at a time; Gammabar^(fmode) is also kept
 // in LDS for the factorisation (RM: R rounded up to 16, 32 or 64).
 template <int RM>
+// With u non-null (only >= 0, R <= 32, at most 4 chunks) the block forms
+// S^(only) itself from the rows in u, chunk by chunk through LDS: each
+// chunk's sum in row order, the chunk sums added in chunk order, as the
+// partial kernel and the chunk sum would (part is then unused).
 __global__ __launch_bounds__(256) void gram_final_kernel(const double* __restrict__ part, ModeTable t,
                                   double* __restrict__ S, double* __restrict__ Gbar,
                                   double* __restrict__ Gam, int fmode, double* __restrict__ F,
-                                  int* __restrict__ kind, int* __restrict__ flags, int only) {
+                                  int* __restrict__ kind, int* __restrict__ flags, int only,
+                                  const double* __restrict__ u) {
   __shared__ double gl[kMaxR * kMaxR];
   const int R = t.R;
   const int RR = R * R;
-  const int k0 = only >= 0 ? only : 0;
-  const int k1 = only >= 0 ? only + 1 : t.N;
-  for (int k = k0; k < k1; ++k) {
-    const int64_t nc = t.coff[k + 1] - t.coff[k];
-    const double* pk = part + t.coff[k] * RR;
-    for (int pr = threadIdx.x; pr < RR; pr += 256) S[(int64_t)k * RR + pr] = ordered_sum(pk + pr, nc, RR);
+  bool direct = false;
+  if constexpr (RM <= 32) {
+    static_assert(kRowsPerChunk * 32 <= 8 * 256 && kMaxR * kMaxR >= kRowsPerChunk * 32, "staging");
+    if (u) {
+      direct = true;
+      const int k = only;
+      const double* A = u + t.off[k] * R;
+      const int64_t I = t.dims[k];
+      double tot[4] = {0.0, 0.0, 0.0, 0.0};   // entries threadIdx.x + q * 256 (R * R <= 1024)
+      for (int64_t i0 = 0; i0 < I; i0 += kRowsPerChunk) {
+        const int nr = (int)min<int64_t>(kRowsPerChunk, I - i0);
+        const int n = nr * R;
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int e = threadIdx.x + q * 256;
+          v[q] = e < n ? A[i0 * R + e] : 0.0;
+        }
+        __syncthreads();   // the previous chunk's reads of gl are done
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int e = threadIdx.x + q * 256;
+          if (e < n) gl[e] = v[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int pr = threadIdx.x + q * 256;
+          if (pr < RR) {
+            const int r = pr / R, c = pr - (pr / R) * R;
+            double p = 0.0;
+            for (int ii = 0; ii < nr; ++ii) p = fma(gl[ii * R + r], gl[ii * R + c], p);
+            tot[q] += p;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int pr = threadIdx.x + q * 256;
+        if (pr < RR) S[(int64_t)k * RR + pr] = tot[q];
+      }
+    }
   }
-  __syncthreads();   // S stores visible to the block
+  if (!direct) {
+    const int k0 = only >= 0 ? only : 0;
+    const int k1 = only >= 0 ? only + 1 : t.N;
+    for (int k = k0; k < k1; ++k) {
+      const int64_t nc = t.coff[k + 1] - t.coff[k];
+      const double* pk = part + t.coff[k] * RR;
+      for (int pr = threadIdx.x; pr < RR; pr += 256) S[(int64_t)k * RR + pr] = ordered_sum(pk + pr, nc, RR);
+    }
+  }
+  __syncthreads();   // S stores visible to the block; the staging in gl is done
   constexpr int kGE = 2;   // entries per thread with their loads in flight together
   for (int p0 = threadIdx.x; p0 < RR; p0 += kGE * 256) {
     double sk[kGE][CP_MAX_ORDER];
@@ -548,10 +598,49 @@ __global__ __launch_bounds__(256) void factor_kernel(const double* __restrict__ 
 // forward L y = m, then back L^T x = y, one component finished per step
 // (broadcast from its lane with readlane, times the reciprocal pivot) and
 // removed from the others by their lanes.
+// RM <= 32: lane q holds row q and column q of L in registers (padded with
+// zeros to RM), so a step reads no memory; the same operations in the same
+// order.  The pseudo-inverse (kind 2) and RM = 64 read L from LDS.
+template <int RM>
 __global__ __launch_bounds__(256) void solve_rows_kernel(const double* __restrict__ M,
                                                          const double* __restrict__ F,
                                                          const int* __restrict__ kind, int64_t I,
                                                          int R, double* __restrict__ A) {
+  if constexpr (RM <= 32) {
+    if (*kind != 2) {
+      const int q = threadIdx.x & 63;
+      double lrow[RM], lcol[RM];
+#pragma unroll
+      for (int r = 0; r < RM; ++r) {
+        lrow[r] = (q < R && r < R) ? F[q * R + r] : 0.0;
+        lcol[r] = (q < R && r < R) ? F[r * R + q] : 0.0;
+      }
+      const double rd = q < R ? 1.0 / F[q * R + q] : 1.0;
+      const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+      const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+      for (int64_t i = wave0; i < I; i += nwaves) {
+        double y = q < R ? M[i * R + q] : 0.0;
+#pragma unroll
+        for (int r = 0; r < RM; ++r) {
+          if (r < R) {
+            const double yr = wave_bcast(y * rd, r);   // y_r / L(r, r) from lane r
+            if (q == r) y = yr;
+            else if (q > r && q < R) y -= lrow[r] * yr;
+          }
+        }
+#pragma unroll
+        for (int r = RM - 1; r >= 0; --r) {
+          if (r < R) {
+            const double xr = wave_bcast(y * rd, r);
+            if (q == r) y = xr;
+            else if (q < r) y -= lcol[r] * xr;
+          }
+        }
+        if (q < R) A[i * R + q] = y;
+      }
+      return;
+    }
+  }
   __shared__ double f[kMaxR * kMaxR];
   __shared__ double rdiag[kMaxR];
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) f[e] = F[e];
@@ -1087,19 +1176,26 @@ int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, do
   double* F = nullptr;
   int* kind = nullptr;
   if (factor_mode >= 0) CP_TRY(factor_slot(h, R, &F, &kind, st));
-  CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)(nch * R * R), st));
-  double* part = static_cast<double*>(h->red.ptr);
-  hipLaunchKernelGGL(gram_partial_kernel, dim3((unsigned)nrun), dim3(256), 0, st, u, t, ch0, part);
-  CP_LAUNCH_CHECK(h);
+  // one updated mode of at most 4 chunks at R <= 32: the final kernel forms
+  // its Gram itself (no partial kernel)
+  const bool direct = only_mode >= 0 && R <= 32 && nrun <= 4;
+  double* part = nullptr;
+  if (!direct) {
+    CP_TRY(ensure(h, h->red, sizeof(double) * (size_t)(nch * R * R), st));
+    part = static_cast<double*>(h->red.ptr);
+    hipLaunchKernelGGL(gram_partial_kernel, dim3((unsigned)nrun), dim3(256), 0, st, u, t, ch0, part);
+    CP_LAUNCH_CHECK(h);
+  }
+  const double* ud = direct ? u : nullptr;
   if (R <= 16)
     hipLaunchKernelGGL(gram_final_kernel<16>, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam,
-                       factor_mode, F, kind, h->flags, only_mode);
+                       factor_mode, F, kind, h->flags, only_mode, ud);
   else if (R <= 32)
     hipLaunchKernelGGL(gram_final_kernel<32>, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam,
-                       factor_mode, F, kind, h->flags, only_mode);
+                       factor_mode, F, kind, h->flags, only_mode, ud);
   else
     hipLaunchKernelGGL(gram_final_kernel<64>, dim3(1), dim3(256), 0, st, part, t, S, Gbar, Gam,
-                       factor_mode, F, kind, h->flags, only_mode);
+                       factor_mode, F, kind, h->flags, only_mode, ud);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
@@ -1151,8 +1247,15 @@ int mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int
   }
   if (I > 0) {
     const int64_t blocks = std::min<int64_t>((I + 3) / 4, 4096);   // 4 rows (waves) per block
-    hipLaunchKernelGGL(solve_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, M, F, kind, I,
-                       R, A);
+    if (R <= 16)
+      hipLaunchKernelGGL(solve_rows_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, st, M, F, kind,
+                         I, R, A);
+    else if (R <= 32)
+      hipLaunchKernelGGL(solve_rows_kernel<32>, dim3((unsigned)blocks), dim3(256), 0, st, M, F, kind,
+                         I, R, A);
+    else
+      hipLaunchKernelGGL(solve_rows_kernel<64>, dim3((unsigned)blocks), dim3(256), 0, st, M, F, kind,
+                         I, R, A);
   }
   CP_LAUNCH_CHECK(h);
   return CP_OK;
