@@ -169,6 +169,12 @@ int tree_split(const cp_tensor* T, const Shape& s, int prec);
 size_t tree_partial_elems(const Shape& s, int split, int R, bool left);
 int tree_partial(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R, int prec,
                  int split, bool left, double* X, hipStream_t st);
+// Every mode's MTTKRP from the two group partials in one launch (order <= 4,
+// every second-level sum short), with the gradient epilogue when g is given:
+// G^(n) = -M^(n) + A^(n) Gbar^(n).  Returns 1 when the shape is not covered.
+int tree_all_modes(cp_handle* h, const Shape& s, int split, const double* XL, const double* XR,
+                   const double* u, int R, double* M, const double* Gbar, double* g,
+                   hipStream_t st);
 int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, const double* u, int R,
               int mode, double* M, hipStream_t st);
 

@@ -156,7 +156,12 @@ int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const 
     cp_handle* h;
     ~EpiScope() { h->epi = GradEpi{}; }
   };
-  for (int n = 0; n < s.N; ++n) {
+  int all = 1;   // every mode from the partials in one launch when covered
+  if (tb.XL && tb.XR) {
+    all = tree_all_modes(h, s, tb.split, tb.XL, tb.XR, u, R, sc.M, sc.Gbar, g_out, st);
+    if (all < 0) return all;
+  }
+  for (int n = 0; n < s.N && all != CP_OK; ++n) {
     double* Mn = sc.M + s.off[n] * R;
     const double* An = u + s.off[n] * R;
     double* Gn = g_out ? g_out + s.off[n] * R : nullptr;

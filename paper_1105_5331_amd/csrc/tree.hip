@@ -268,16 +268,16 @@ __global__ __launch_bounds__(kThr) void group_mttkrp_kernel(const double* __rest
 // epilogue G(i, r) = -M(i, r) + sum_q A(i, q) Gbar(q, r) (Gbar staged in LDS).
 constexpr int64_t kFusedPairs = 2048;
 
-__global__ __launch_bounds__(kThr) void group_fused_kernel(const double* __restrict__ X,
-                                                           const double* __restrict__ fac,
-                                                           GroupParams p, double* __restrict__ M,
-                                                           const double* __restrict__ eA,
-                                                           const double* __restrict__ eGbar,
-                                                           double* __restrict__ eG) {
+__device__ __forceinline__ void group_fused_body(const double* __restrict__ X,
+                                                 const double* __restrict__ fac,
+                                                 const GroupParams& p, double* __restrict__ M,
+                                                 const double* __restrict__ eA,
+                                                 const double* __restrict__ eGbar,
+                                                 double* __restrict__ eG, int64_t bx) {
   extern __shared__ double gsh[];
   __shared__ double red[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t e = bx * 64 + lane;
   const int64_t n = p.I * p.R;
   if (eG)
     for (int t = threadIdx.x; t < p.R * p.R; t += kThr) gsh[t] = eGbar[t];
@@ -302,6 +302,40 @@ __global__ __launch_bounds__(kThr) void group_fused_kernel(const double* __restr
     }
   }
 }
+
+__global__ __launch_bounds__(kThr) void group_fused_kernel(const double* __restrict__ X,
+                                                           const double* __restrict__ fac,
+                                                           GroupParams p, double* __restrict__ M,
+                                                           const double* __restrict__ eA,
+                                                           const double* __restrict__ eGbar,
+                                                           double* __restrict__ eG) {
+  group_fused_body(X, fac, p, M, eA, eGbar, eG, blockIdx.x);
+}
+
+// Every mode of a low-order tensor in one launch: the blocks of mode m are
+// bstart[m] .. bstart[m + 1] - 1, each running the single-mode body.
+constexpr int kMultiModes = 4;
+struct MultiGroup {
+  int nm;
+  int64_t bstart[kMultiModes + 1];
+  GroupParams p[kMultiModes];
+  const double* X[kMultiModes];
+  double* M[kMultiModes];
+  const double* eA[kMultiModes];
+  const double* eGbar[kMultiModes];
+  double* eG[kMultiModes];
+};
+
+static_assert(sizeof(MultiGroup) <= 2048, "kernel argument size");
+
+__global__ __launch_bounds__(kThr) void group_fused_multi_kernel(const double* __restrict__ fac,
+                                                                 MultiGroup mg) {
+  int m = 0;
+  while (m + 1 < mg.nm && (int64_t)blockIdx.x >= mg.bstart[m + 1]) ++m;
+  group_fused_body(mg.X[m], fac, mg.p[m], mg.M[m], mg.eA[m], mg.eGbar[m], mg.eG[m],
+                   (int64_t)blockIdx.x - mg.bstart[m]);
+}
+
 
 int64_t group_size(const Shape& s, int lo, int hi) {
   int64_t t = 1;
@@ -386,8 +420,9 @@ int tree_partial(cp_handle* h, const cp_tensor* T, const Shape& s, const double*
   return dense_mttkrp(h, T, v, u, R, mode, prec, X, st);
 }
 
-int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, const double* u, int R,
-              int mode, double* M, hipStream_t st) {
+namespace {
+// The second-level description of `mode` within the group [lo, hi).
+GroupParams group_params(const Shape& s, int lo, int hi, int mode, int R) {
   GroupParams p{};
   p.R = R;
   p.O = 1;
@@ -406,6 +441,43 @@ int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, con
     }
   }
   p.I = s.dims[mode];
+  return p;
+}
+}  // namespace
+
+int tree_all_modes(cp_handle* h, const Shape& s, int split, const double* XL, const double* XR,
+                   const double* u, int R, double* M, const double* Gbar, double* g,
+                   hipStream_t st) {
+  if (s.N > kMultiModes || !XL || !XR || split < 1 || split >= s.N) return 1;
+  MultiGroup mg{};
+  mg.nm = s.N;
+  int64_t blocks = 0;
+  for (int n = 0; n < s.N; ++n) {
+    const bool left = n < split;
+    const GroupParams p = group_params(s, left ? 0 : split, left ? split : s.N, n, R);
+    if (p.O * p.K > kFusedPairs) return 1;
+    mg.p[n] = p;
+    mg.bstart[n] = blocks;
+    blocks += nblk(p.I * R, 64);
+    mg.X[n] = left ? XL : XR;
+    mg.M[n] = M + s.off[n] * R;
+    mg.eA[n] = g ? u + s.off[n] * R : nullptr;
+    mg.eGbar[n] = g ? Gbar + (int64_t)n * R * R : nullptr;
+    mg.eG[n] = g ? g + s.off[n] * R : nullptr;
+  }
+  mg.bstart[s.N] = blocks;
+  {
+    KernelTimer timer(h, CP_KERNEL_GROUP_MTTKRP, st);
+    CP_TIMED_LAUNCH(timer, group_fused_multi_kernel, dim3((unsigned)blocks), dim3(kThr),
+                    g ? sizeof(double) * (size_t)R * R : 0, st, u, mg);
+  }
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, const double* u, int R,
+              int mode, double* M, hipStream_t st) {
+  GroupParams p = group_params(s, lo, hi, mode, R);
   const int64_t n_out = p.I * R;
   const int64_t work = p.O * p.K;
   if (work <= kFusedPairs) {
