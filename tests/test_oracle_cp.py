@@ -1,5 +1,6 @@
 """Pins of the FP64 oracle's tensor quantities against brute force, closed forms
-and library routines (no GPU).  P-numbers refer to the pin list in the design doc."""
+and library routines (no GPU).  Each test is labelled with its pin number (P1,
+P2, ...) in the project's list of oracle pins."""
 import itertools
 
 import numpy as np
