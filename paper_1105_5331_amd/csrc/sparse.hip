@@ -110,11 +110,16 @@ struct SparseParams {
 // inside the wave's range, else into the wave's head or tail carry slot.
 // KM is the number of other modes the kernel is compiled for: 2 (order 3),
 // 3 (order 4) or CP_MAX_ORDER - 1 with a runtime bound (any order).
-// Sorted nonzeros per wave: about 4096 waves per launch, each range a
-// multiple of 64 between 512 and 4096 (longer ranges amortise a wave's first
-// and last rows; fewer than ~4000 waves leave the chip underfilled).
+// Sorted nonzeros per wave: about CPNG_SP_WAVES waves per launch, each range
+// a multiple of 64 between 512 and 4096 (longer ranges amortise a wave's
+// first and last rows; fewer waves leave latency unhidden, and more than one
+// round of resident waves leaves a tail: 20000^3, 2e7 nonzeros, R = 16 took
+// 231 us with 4096 waves, 228 with 5120, 302 with 8192).
+#ifndef CPNG_SP_WAVES
+#define CPNG_SP_WAVES 5120   // one round at 5 of the 6 waves per SIMD the R <= 16 kernels allow
+#endif
 inline int64_t wave_range(int64_t nnz) {
-  const int64_t r = ((nnz + 4095) / 4096 + 63) / 64 * 64;
+  const int64_t r = ((nnz + CPNG_SP_WAVES - 1) / CPNG_SP_WAVES + 63) / 64 * 64;
   return std::min<int64_t>(4096, std::max<int64_t>(512, r));
 }
 
