@@ -107,6 +107,35 @@ def test_ngmres_trajectory_4way_dense_fp64(h, seed):
     assert abs(hg - ho) <= 1e-10
 
 
+def test_ngmres_trajectory_line_search_fallback(h):
+    """Every line search capped at two trials with a curvature tolerance no
+    trial meets: each search ends without a strong-Wolfe point and takes the
+    better of its trials (or beta = 0), on both sides (the accepted gradient
+    is then the last trial's or the kept best one's)."""
+    import paper_1105_5331_amd as cpng
+    dims, R, tol = (20, 20, 20), 3, 1e-8
+    print("case ngmres trajectory line-search fallback", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=3)
+    u0 = initial_guess(dims, R, seed=10003)
+    ref = ngmres(CPProblem(ocp.DenseTensor(p.T), R), u0, tol=tol, max_iter=40,
+                 ls=dict(maxfev=2, gtol=1e-12))
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u = _dev(u0)
+    out = cpng.cp_decompose(h, Tg, R, tol, u, trace_cap=100, max_iter=40, ls_maxfev=2,
+                            ls_gtol=1e-12)
+    half = 0.5 * np.sum(p.T ** 2)
+    # compared while rho > 1e-4: closer to the solution the two trials'
+    # objectives differ by rounding only, and which one is the better (both
+    # are valid fallbacks) is decided by the order of the additions
+    window = [r for r in ref.trace if r.rho > 1e-4]
+    assert window == ref.trace[:len(window)] and len(window) >= 10
+    n = _compare(out["trace"], window, half, "line-search fallback")
+    assert n == len(window)
+    assert sum(1 for r in window if r.nfev and r.ls_status != "converged") >= 3
+    assert out["n_ls_fallback"] >= 3
+
+
 def test_als_trajectory_4way_dense_fp64(h):
     """ALS on an order-4 tensor through the two-level sweep (left group's
     partial before its updates, right group's after), iterate by iterate."""

@@ -227,7 +227,8 @@ def test_objective_grad_bf16x3_two_level(h, dims, R):
 @pytest.mark.parametrize("dims,R,c,prec", [((20, 20, 20), 3, 0.5, "fp64"), ((9, 14, 6, 11), 5, 0.9, "fp64"),
                                            ((33, 70, 65), 12, 0.5, "fp32in_fp64acc"),
                                            ((6, 5, 7, 4, 6), 36, 0.3, "fp64"),
-                                           ((17, 9, 32), 20, 0.5, "bf16x3")])
+                                           ((17, 9, 32), 20, 0.5, "bf16x3"),
+                                           ((300, 12, 10), 8, 0.5, "fp64")])
 def test_als_sweep_parity(h, dims, R, c, prec):
     """One ALS sweep (every mode's MTTKRP from its group's partial, the right
     group's formed after the left modes' updates) against the oracle's
