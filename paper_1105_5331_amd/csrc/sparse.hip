@@ -388,8 +388,11 @@ int prepare_typed(cp_handle* h, cp_tensor* T, const Shape& s, hipStream_t st, Sp
     cleanup();
     return fail(h, CP_ENOMEM, "sparse prepare: allocation failed");
   }
-  hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, coords, keys_out, perm_in, perm_out,
-                                     (int)nnz, 0, 32, st);
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, coords, keys_out, perm_in, perm_out,
+                                         (int)nnz, 0, 32, st) != hipSuccess) {
+    cleanup();
+    return fail(h, CP_EDEVICE, "sparse prepare: sort workspace query failed");
+  }
   if (hipMalloc(&temp, temp_bytes + 16) != hipSuccess) {
     cleanup();
     return fail(h, CP_ENOMEM, "sparse prepare: sort workspace allocation failed");
@@ -443,45 +446,52 @@ int sparse_prepare(cp_handle* h, cp_tensor* T, const Shape& s, hipStream_t st) {
   int rc = CP_OK;
   if (nnz > 0) {
     int* dflag = nullptr;
-    CP_HIP(h, hipMalloc(&dflag, 2 * sizeof(int)));
-    CP_HIP(h, hipMemsetAsync(dflag, 0, 2 * sizeof(int), st));
-    hipLaunchKernelGGL(bounds_kernel, dim3(nblk(nnz, 256)), dim3(256), 0, st, T->coords, nnz, s.N,
-                       s, dflag);
-    // duplicate check on the full linear index when it fits in 64 bits
-    double lim = 1.0;
-    for (int k = 0; k < s.N; ++k) lim *= (double)s.dims[k];
     uint64_t *key = nullptr, *key2 = nullptr;
     void* temp = nullptr;
-    if (lim < 1.8e19) {
-      size_t tb = 0;
-      if (hipMalloc(&key, sizeof(uint64_t) * nnz) == hipSuccess &&
-          hipMalloc(&key2, sizeof(uint64_t) * nnz) == hipSuccess) {
-        hipcub::DeviceRadixSort::SortKeys(nullptr, tb, key, key2, (int)nnz, 0, 64, st);
-        if (hipMalloc(&temp, tb + 16) == hipSuccess) {
-          hipStreamSynchronize(st);
+    int flags[2] = {0, 0};
+    // records the first failing HIP call; later steps are skipped
+    auto ok = [&](hipError_t e, const char* what) {
+      if (e != hipSuccess && rc == CP_OK)
+        rc = fail(h, CP_EDEVICE, "sparse prepare: %s failed (%s)", what, hipGetErrorString(e));
+      return rc == CP_OK;
+    };
+    if (hipMalloc(&dflag, 2 * sizeof(int)) != hipSuccess)
+      rc = fail(h, CP_ENOMEM, "sparse prepare: allocation failed");
+    if (rc == CP_OK && ok(hipMemsetAsync(dflag, 0, 2 * sizeof(int), st), "flag clear")) {
+      hipLaunchKernelGGL(bounds_kernel, dim3(nblk(nnz, 256)), dim3(256), 0, st, T->coords, nnz,
+                         s.N, s, dflag);
+      // duplicate check on the full linear index when it fits in 64 bits
+      double lim = 1.0;
+      for (int k = 0; k < s.N; ++k) lim *= (double)s.dims[k];
+      if (lim < 1.8e19) {
+        size_t tb = 0;
+        if (hipMalloc(&key, sizeof(uint64_t) * nnz) != hipSuccess ||
+            hipMalloc(&key2, sizeof(uint64_t) * nnz) != hipSuccess) {
+          rc = fail(h, CP_ENOMEM, "sparse prepare: duplicate-check allocation failed");
+        } else if (ok(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, key, key2, (int)nnz, 0, 64, st),
+                      "duplicate-check sort query")) {
           int bad = 0;
-          hipMemcpy(&bad, dflag, sizeof(int), hipMemcpyDeviceToHost);
-          if (!bad) {   // keys are only meaningful with in-range coordinates
+          if (hipMalloc(&temp, tb + 16) != hipSuccess) {
+            rc = fail(h, CP_ENOMEM, "sparse prepare: duplicate-check workspace allocation failed");
+          } else if (ok(hipStreamSynchronize(st), "synchronisation") &&
+                     ok(hipMemcpy(&bad, dflag, sizeof(int), hipMemcpyDeviceToHost), "flag readback") &&
+                     !bad) {   // keys are only meaningful with in-range coordinates
             hipLaunchKernelGGL(linear_key_kernel, dim3(nblk(nnz, 256)), dim3(256), 0, st, T->coords,
                                nnz, s, key);
-            hipcub::DeviceRadixSort::SortKeys(temp, tb, key, key2, (int)nnz, 0, 64, st);
-            hipLaunchKernelGGL(adjacent_equal_kernel, dim3(nblk(nnz, 256)), dim3(256), 0, st, key2,
-                               nnz, dflag + 1);
+            if (ok(hipcub::DeviceRadixSort::SortKeys(temp, tb, key, key2, (int)nnz, 0, 64, st),
+                   "duplicate-check sort"))
+              hipLaunchKernelGGL(adjacent_equal_kernel, dim3(nblk(nnz, 256)), dim3(256), 0, st, key2,
+                                 nnz, dflag + 1);
           }
-        } else {
-          rc = fail(h, CP_ENOMEM, "sparse prepare: duplicate-check workspace allocation failed");
         }
-      } else {
-        rc = fail(h, CP_ENOMEM, "sparse prepare: duplicate-check allocation failed");
       }
+      if (ok(hipGetLastError(), "launch") && ok(hipStreamSynchronize(st), "synchronisation"))
+        ok(hipMemcpy(flags, dflag, 2 * sizeof(int), hipMemcpyDeviceToHost), "flag readback");
     }
-    hipStreamSynchronize(st);
-    int flags[2] = {0, 0};
-    hipMemcpy(flags, dflag, 2 * sizeof(int), hipMemcpyDeviceToHost);
-    if (key) hipFree(key);
-    if (key2) hipFree(key2);
-    if (temp) hipFree(temp);
-    hipFree(dflag);
+    if (key) (void)hipFree(key);
+    if (key2) (void)hipFree(key2);
+    if (temp) (void)hipFree(temp);
+    if (dflag) (void)hipFree(dflag);
     if (rc == CP_OK && flags[0]) rc = fail(h, CP_EINVAL, "sparse tensor has a coordinate out of range");
     if (rc == CP_OK && flags[1]) rc = fail(h, CP_EDUPLICATE, "sparse tensor has repeated coordinates");
   }
@@ -496,9 +506,13 @@ int sparse_prepare(cp_handle* h, cp_tensor* T, const Shape& s, hipStream_t st) {
         rc = fail(h, CP_ENOMEM, "sparse prepare: allocation failed");
         break;
       }
-      hipMemsetAsync(md.seg, 0, sizeof(int64_t) * (s.dims[n] + 1), st);
+      if (hipMemsetAsync(md.seg, 0, sizeof(int64_t) * (s.dims[n] + 1), st) != hipSuccess) {
+        rc = fail(h, CP_EDEVICE, "sparse prepare: clearing the segment pointers failed");
+        break;
+      }
     }
-    hipStreamSynchronize(st);
+    if (rc == CP_OK && hipStreamSynchronize(st) != hipSuccess)
+      rc = fail(h, CP_EDEVICE, "sparse prepare: synchronisation failed");
   }
   T->prepared = sp;
   if (rc != CP_OK) {
