@@ -51,6 +51,23 @@ def test_isolation_alone_vs_mix_bitwise():
         assert a_res["rho"] == m_res["rho"]
 
 
+def test_isolation_50_requests_one_at_a_time_vs_mix():
+    """50 requests of the serving mix: run one at a time (a single slot, so no
+    other request is ever on the device with it) and as a 4-slot mix, every
+    result is the same bits."""
+    print("case serving isolation, 50 requests", flush=True)
+    reqs = _requests(50, seed=11)
+    alone = _run(reqs, slots=1)
+    mix = _run(reqs, slots=4)
+    assert len(alone) == len(mix) == 50
+    for r, _, _ in reqs:
+        a_res, a_u = alone[r.rid]
+        m_res, m_u = mix[r.rid]
+        assert a_res["status"] == m_res["status"] and a_res["iters"] == m_res["iters"], r.rid
+        assert a_res["rho"] == m_res["rho"], r.rid
+        assert np.array_equal(a_u, m_u), f"request {r.rid} differs one at a time vs in the mix"
+
+
 def test_every_request_terminates_and_mixed_precision_certifies():
     reqs = _requests(10, seed=5)
     res = _run(reqs, slots=3, precision="bf16x3", final_precision="fp32in_fp64acc",
