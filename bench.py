@@ -395,6 +395,120 @@ def _serve(cpng, torch, data, slots, rate, max_iter):
             "errors": sum(1 for g in got if g["status"] < 0)}
 
 
+def oracle_side_by_side(h, cpng, torch, sparse_gpu_us=None):
+    """The float64 CPU oracle timed next to the GPU on the other workloads
+    (bounded samples, host cores):
+    - dense 200^3, R = 10: MTTKRP per mode (GPU float32 and float64 kernels),
+      and one N-GMRES iteration (oracle: mean of 3; GPU: mean over 20 steps);
+    - sparse 20000^3 R = 16: the oracle's COO MTTKRP on a 2e6-nonzero sample of
+      the same generator, scaled to the 2e7 of the workload, beside the GPU;
+    - serving: the 8 smallest requests of the serving stream solved to
+      rho <= 1e-8 one at a time by the oracle and by cp_decompose (same
+      tensors, same initial guesses)."""
+    from oracle import cp as ocp
+    from oracle.ngmres import CPProblem, ngmres
+    from workloads import initial_guess, serving_stream, sparse_random_cp, test_problem_1
+    out = {}
+    # dense 200^3
+    dims, R = (200, 200, 200), 10
+    p = test_problem_1(dims, R, 0.9, 1, 1, seed=0, dtype=np.float32)
+    A = ocp.split_u(initial_guess(dims, R, seed=10000), dims, R)
+    T64 = p.T.astype(np.float64)
+    o_s = []
+    for n in range(3):
+        t0 = time.perf_counter()
+        ocp.mttkrp(T64, A, n)
+        o_s.append(round(time.perf_counter() - t0, 4))
+    u = torch.from_numpy(ocp.join_u(A)).cuda()
+    g_us = {}
+    for prec, Tt in (("fp32", torch.from_numpy(p.T).cuda().reshape(-1)),
+                     ("fp64", torch.from_numpy(T64).cuda().reshape(-1))):
+        Tg = cpng.Tensor(dims, Tt)
+        # the oracle just kept the GPU idle for a while: bring the clocks back
+        for _ in range(50):
+            cpng.cp_mttkrp(h, Tg, u, R, 0, prec)
+        per = []
+        for n in range(3):
+            for _ in range(2):
+                cpng.cp_mttkrp(h, Tg, u, R, n, prec)
+            torch.cuda.synchronize()
+            cpng.cp_profile(h, True)
+            for _ in range(10):
+                cpng.cp_mttkrp(h, Tg, u, R, n, prec)
+            torch.cuda.synchronize()
+            nl, ms = cpng.cp_profile_read(h, cpng.CP_KERNEL_DENSE_MTTKRP)
+            cpng.cp_profile(h, False)
+            per.append(round(ms / nl * 1e3, 1))
+        g_us[prec] = per
+    u0 = initial_guess(dims, R, seed=10000)
+    t0 = time.perf_counter()
+    ngmres(CPProblem(ocp.DenseTensor(T64), R), u0, tol=0.0, max_iter=3)
+    o_it = (time.perf_counter() - t0) / 3
+    Tg = cpng.Tensor(dims, torch.from_numpy(T64).cuda().reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    st = cpng.NGMRESState(h, Tg, R, torch.from_numpy(u0).cuda(), precision="fp64")
+    for _ in range(20):
+        st.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        st.step()
+    torch.cuda.synchronize()
+    g_it = (time.perf_counter() - t0) / 20
+    out["dense_200cubed_R10"] = {
+        "mttkrp_per_mode": {"oracle_s": o_s, "gpu_us": g_us},
+        "ngmres_iteration": {"oracle_s": round(o_it, 3), "gpu_fp64_ms": round(g_it * 1e3, 3)}}
+    log(f"oracle vs GPU, 200^3: {out['dense_200cubed_R10']}")
+    # sparse sample
+    sdims = (20000, 20000, 20000)
+    sp = sparse_random_cp(sdims, 2_000_000, 16, seed=0, dtype=np.float32)
+    As = [np.random.default_rng(1).random((d, 16)) for d in sdims]
+    vals = sp.values.astype(np.float64)
+    so = []
+    for n in range(3):
+        t0 = time.perf_counter()
+        ocp.mttkrp_coo(sdims, sp.coords, vals, As, n)
+        so.append(round((time.perf_counter() - t0) * 20_000_000 / sp.values.size, 3))
+    out["sparse_20000cubed_R16"] = {"oracle_s_per_mode_scaled": so,
+                                    "sample_nnz": int(sp.values.size),
+                                    "gpu_us_per_mode": sparse_gpu_us}
+    log(f"oracle vs GPU, sparse: {out['sparse_20000cubed_R16']}")
+    # serving sample
+    reqs = sorted(serving_stream(64, rate_per_s=1.0, seed=7), key=lambda r: int(np.prod(r.dims)))[:8]
+    o_t = g_t = 0.0
+    o_conv = g_conv = 0
+    probs = [(r, test_problem_1(r.dims, r.R, r.c, 1, 1, seed=r.seed, dtype=np.float32),
+              initial_guess(r.dims, r.R, seed=r.seed + 10000)) for r in reqs]
+    for r, pr, u0 in probs:
+        t0 = time.perf_counter()
+        ref = ngmres(CPProblem(ocp.DenseTensor(pr.T.astype(np.float64)), r.R), u0, tol=1e-8,
+                     max_iter=500)
+        o_t += time.perf_counter() - t0
+        o_conv += int(ref.converged)
+    gp = []
+    for r, pr, u0 in probs:
+        Tg = cpng.Tensor(r.dims, torch.from_numpy(pr.T).cuda().reshape(-1))
+        cpng.cp_tensor_prepare(h, Tg)
+        gp.append((r, Tg, u0))
+    for _ in range(2):   # untimed: the clocks back up after the oracle's solves
+        r, Tg, u0 = gp[1]
+        cpng.cp_decompose(h, Tg, r.R, 1e-8, torch.from_numpy(u0).cuda(), max_iter=500)
+    for r, Tg, u0 in gp:
+        uu = torch.from_numpy(u0).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = cpng.cp_decompose(h, Tg, r.R, 1e-8, uu, max_iter=500)
+        torch.cuda.synchronize()
+        g_t += time.perf_counter() - t0
+        g_conv += int(rep["converged"])
+    out["serving_8_smallest"] = {
+        "requests": [list(r.dims) + [r.R] for r in reqs],
+        "oracle_solves_per_s": round(len(reqs) / o_t, 3), "oracle_converged": o_conv,
+        "gpu_one_at_a_time_solves_per_s": round(len(reqs) / g_t, 3), "gpu_converged": g_conv}
+    log(f"oracle vs GPU, serving sample: {out['serving_8_smallest']}")
+    return out
+
+
 def serving(cpng, torch, n=64, slots=4, seed=7, max_iter=500, loads=(0.5, 0.8)):
     """Stream of decomposition requests (dense 3-/4-way float32, mode sizes
     U{16..160}, R U{2..24}, congruence U[0, 0.9], noise 1%+1%, tol 1e-8)
@@ -580,6 +694,10 @@ def main():
         res["extra"]["serving"] = serving(cpng, torch, n=32)
         log("small dense 20^3 (GPU vs oracle)")
         res["extra"]["small_dense_20cubed_R3"] = small_dense(h, cpng, torch)
+        if not args.skip_cpu:
+            log("oracle beside the GPU (200^3, sparse sample, serving sample)")
+            sp_us = [m["kernel_us"] for m in res["extra"]["sparse_mttkrp_20000cubed_R16"]["modes"]]
+            res["extra"]["oracle_side_by_side"] = oracle_side_by_side(h, cpng, torch, sp_us)
     if not args.skip_cpu:
         log("cpu baseline (oracle)")
         A = [np.ascontiguousarray(x) for x in

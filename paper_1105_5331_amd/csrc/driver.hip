@@ -632,13 +632,17 @@ int cp_profile(cp_handle* h, int32_t enable) {
   if (!h) return CP_EINVAL;
   CP_HIP(h, hipSetDevice(h->device));
   CP_HIP(h, hipDeviceSynchronize());
+  // every timing session starts with new events: an event that timed one
+  // launch is not handed to another session's launches
   for (auto& v : h->ev_pending) {
     for (auto& pr : v) {
-      h->ev_pool.push_back(pr.first);
-      h->ev_pool.push_back(pr.second);
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
     }
     v.clear();
   }
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  h->ev_pool.clear();
   for (int k = 0; k < 4; ++k) {
     h->prof_launches[k] = 0;
     h->prof_ms[k] = 0.0;
