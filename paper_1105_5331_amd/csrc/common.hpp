@@ -56,7 +56,6 @@ struct cp_handle {
   // optional event timing of the main MTTKRP kernels
   bool prof = false;
   uint32_t prof_mask = 0xFu;   // kernel ids timed while prof is on
-  std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[4];
   int64_t prof_launches[4] = {0, 0, 0, 0};
   double prof_ms[4] = {0.0, 0.0, 0.0, 0.0};

@@ -623,7 +623,6 @@ int cp_destroy(cp_handle* h) {
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
     }
-  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
   return CP_OK;
 }
@@ -632,8 +631,7 @@ int cp_profile(cp_handle* h, int32_t enable) {
   if (!h) return CP_EINVAL;
   CP_HIP(h, hipSetDevice(h->device));
   CP_HIP(h, hipDeviceSynchronize());
-  // every timing session starts with new events: an event that timed one
-  // launch is not handed to another session's launches
+  // pending events of the previous session are dropped unread
   for (auto& v : h->ev_pending) {
     for (auto& pr : v) {
       (void)hipEventDestroy(pr.first);
@@ -641,8 +639,6 @@ int cp_profile(cp_handle* h, int32_t enable) {
     }
     v.clear();
   }
-  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
-  h->ev_pool.clear();
   for (int k = 0; k < 4; ++k) {
     h->prof_launches[k] = 0;
     h->prof_ms[k] = 0.0;
@@ -673,8 +669,8 @@ int cp_profile_read(cp_handle* h, int32_t kernel, int64_t* launches, double* tot
     CP_HIP(h, hipEventElapsedTime(&ms, pr.first, pr.second));
     h->prof_ms[kernel] += ms;
     h->prof_launches[kernel]++;
-    h->ev_pool.push_back(pr.first);
-    h->ev_pool.push_back(pr.second);
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
   }
   v.clear();
   *launches = h->prof_launches[kernel];

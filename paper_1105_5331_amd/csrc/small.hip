@@ -39,12 +39,10 @@ int ensure(cp_handle* h, DevBuf& b, size_t bytes, hipStream_t stream) {
   return CP_OK;
 }
 
-static hipEvent_t pool_event(cp_handle* h) {
-  if (!h->ev_pool.empty()) {
-    hipEvent_t e = h->ev_pool.back();
-    h->ev_pool.pop_back();
-    return e;
-  }
+// A new event per timed launch boundary, destroyed once its time is read: a
+// reused event (one that already timed another launch) has reported wrong
+// intervals for hipExtLaunchKernelGGL launches.
+static hipEvent_t new_event(cp_handle*) {
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
@@ -52,11 +50,11 @@ static hipEvent_t pool_event(cp_handle* h) {
 
 KernelTimer::KernelTimer(cp_handle* h_, int id_, hipStream_t st_) : h(h_), id(id_), st(st_) {
   if (!h->prof || !((h->prof_mask >> id) & 1u)) return;
-  a = pool_event(h);
-  b = pool_event(h);
+  a = new_event(h);
+  b = new_event(h);
   if (!a || !b) {   // no timing for this launch
-    if (a) h->ev_pool.push_back(a);
-    if (b) h->ev_pool.push_back(b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
     a = b = nullptr;
   }
 }
@@ -72,8 +70,8 @@ KernelTimer::~KernelTimer() {
         h->prof_ms[id] += ms;
         h->prof_launches[id]++;
       }
-      h->ev_pool.push_back(pr.first);
-      h->ev_pool.push_back(pr.second);
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
     }
     h->ev_pending[id].clear();
   }
