@@ -156,7 +156,7 @@ int sparse_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double
 int sparse_prepare(cp_handle* h, cp_tensor* T, const Shape& s, hipStream_t st);
 int sparse_release(cp_handle* h, cp_tensor* T);
 int stage_factors_f32(cp_handle* h, const double* u, int64_t L, float** out, hipStream_t st);
-int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shape& s, int R,
+int dense_fast_bf16x3(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
                       int mode, double* M, hipStream_t st);
 template <typename TT, typename CT>
 int dense_fast_vec(cp_handle* h, const TT* T, const CT* fac, const Shape& s, int R, int mode,

@@ -115,14 +115,18 @@ __device__ inline int64_t outer_base(const FastParams& p, int64_t o) {
   return base;
 }
 
-__device__ inline float outer_scale(const float* __restrict__ fac, const FastParams& p, int64_t o,
+// the float32 product of the outer modes' factor values, each rounded to
+// float32 first (F = double reads the float64 factors and rounds them: the
+// same bits as reading their float32 copy)
+template <typename F>
+__device__ inline float outer_scale(const F* __restrict__ fac, const FastParams& p, int64_t o,
                                     int r) {
   if (r >= p.R) return 0.f;
   float s = 1.f;
   for (int m = p.nout - 1; m >= 0; --m) {
     const int64_t d = p.odims[m];
     const int64_t q = o / d;
-    s *= fac[p.ofoff[m] + (o - q * d) * p.R + r];
+    s *= (float)fac[p.ofoff[m] + (o - q * d) * p.R + r];
     o = q;
   }
   return s;
@@ -137,9 +141,13 @@ constexpr int kOChunk = 64;   // outer indices per LDS table chunk (VALU kernel)
 // one o for many ranks; rank-major Pg[r * Opad + o] (zero for o >= O) for the
 // row-stream kernel, whose MFMA D lanes hold four consecutive o of one rank
 // (one 16-byte load).
-__global__ void outer_tables_kernel(const float* __restrict__ fac, FastParams p,
-                                    float* __restrict__ Pg, int64_t* __restrict__ bg) {
+// The same launch also writes the float32 copy of all L factor values
+// (fac32, read by the MTTKRP kernel for its inner mode).
+__global__ void outer_tables_kernel(const double* __restrict__ fac, FastParams p,
+                                    float* __restrict__ Pg, int64_t* __restrict__ bg,
+                                    float* __restrict__ fac32, int64_t L) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < L) fac32[e] = (float)fac[e];
   const int64_t o = e / (p.R + 1);
   const int c = (int)(e - o * (p.R + 1));
   if (o >= p.Opad) return;
@@ -804,7 +812,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_tiles_vec(const TT* __restrict__ 
 
 // Returns CP_OK after launching, or 1 if the shape is not one the streaming
 // kernels cover (the caller then uses the generic kernel).
-int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shape& s, int R,
+int dense_fast_bf16x3(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
                       int mode, double* M, hipStream_t st) {
   const int N = s.N;
   if (N < 2) return 1;
@@ -813,6 +821,10 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   const int64_t K = s.dims[q];
   if (K % 8 != 0 || K > kMaxInner) return 1;
   if (reinterpret_cast<uintptr_t>(T) % 16 != 0) return 1;
+  // the float32 copy of the factors, written by the table launch below
+  const int64_t L = s.sum_dims() * R;
+  CP_TRY(ensure(h, h->stage, sizeof(float) * (size_t)L, st));
+  const float* fac = static_cast<const float*>(h->stage.ptr);
   FastParams p{};
   p.R = R;
   int64_t stride[CP_MAX_ORDER];
@@ -873,9 +885,9 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const float* fac, const Shap
   float* Pg = static_cast<float*>(h->otab.ptr);
   int64_t* bg = reinterpret_cast<int64_t*>(static_cast<char*>(h->otab.ptr) + pbytes);
   {
-    const int64_t nt = p.Opad * (R + 1);
-    hipLaunchKernelGGL(outer_tables_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, fac,
-                       p, Pg, bg);
+    const int64_t nt = std::max<int64_t>(p.Opad * (R + 1), L);
+    hipLaunchKernelGGL(outer_tables_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, u,
+                       p, Pg, bg, static_cast<float*>(h->stage.ptr), L);
     CP_LAUNCH_CHECK(h);
   }
   {

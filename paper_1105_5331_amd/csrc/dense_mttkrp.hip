@@ -423,20 +423,22 @@ int dense_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double*
     if (T->dtype != CP_F32)
       return fail(h, CP_EINVAL, "precision FP32/BF16X3 needs a float32 tensor");
     float* fac = nullptr;
-    CP_TRY(stage_factors_f32(h, u, L, &fac, st));
     if (prec == CP_PREC_BF16X3) {
-      // the matrix-core streaming kernels; shapes they do not cover (inner
-      // length not a multiple of 8 or above 512) take the float32 vector
-      // kernels, which are faster than the generic BF16x3 tiles there and
-      // at least as accurate; the generic tiles are the last resort
+      // the matrix-core streaming kernels (which stage the float32 factors
+      // in their table launch); shapes they do not cover (inner length not
+      // a multiple of 8 or above 512) take the float32 vector kernels, which
+      // are faster than the generic BF16x3 tiles there and at least as
+      // accurate; the generic tiles are the last resort
       const float* Tv = static_cast<const float*>(T->values);
-      int rc = dense_fast_bf16x3(h, Tv, fac, s, R, mode, M, st);
+      int rc = dense_fast_bf16x3(h, Tv, u, s, R, mode, M, st);
       if (rc <= 0) return rc;   // launched (CP_OK) or failed
+      CP_TRY(stage_factors_f32(h, u, L, &fac, st));
       rc = dense_fast_vec<float, float>(h, Tv, fac, s, R, mode, M, st);
       if (rc <= 0) return rc;
       return p.I_n > 64 ? launch_bf16x3<2>(h, Tv, fac, p, M, st)
                         : launch_bf16x3<1>(h, Tv, fac, p, M, st);
     }
+    CP_TRY(stage_factors_f32(h, u, L, &fac, st));
     {
       const int rc = dense_fast_vec<float, float>(h, static_cast<const float*>(T->values), fac, s, R,
                                                   mode, M, st);
