@@ -162,14 +162,29 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const double* __restr
     if (e < n) rows[e] = v[q];
   }
   __syncthreads();
+  // a thread's entries in groups of four sums run side by side (each still
+  // in row order from zero); entries past R * R read entry 0 and are dropped
+  const int RR = R * R;
+  for (int q0 = 0; q0 * 256 < RR; q0 += 4) {
+    int ra[4], ca[4];
+    double s[4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int pr = threadIdx.x + q * 256;
-    if (pr < R * R) {
-      const int r = pr / R, c = pr - (pr / R) * R;
-      double s = 0.0;
-      for (int ii = 0; ii < nr; ++ii) s = fma(rows[ii * R + r], rows[ii * R + c], s);
-      part[ch * R * R + pr] = s;
+    for (int q = 0; q < 4; ++q) {
+      const int pr = threadIdx.x + (q0 + q) * 256;
+      const int pe = pr < RR ? pr : 0;
+      ra[q] = pe / R;
+      ca[q] = pe - ra[q] * R;
+      s[q] = 0.0;
+    }
+#pragma unroll 4
+    for (int ii = 0; ii < nr; ++ii) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s[q] = fma(rows[ii * R + ra[q]], rows[ii * R + ca[q]], s[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int pr = threadIdx.x + (q0 + q) * 256;
+      if (pr < RR) part[ch * RR + pr] = s[q];
     }
   }
 }
@@ -213,6 +228,14 @@ __global__ __launch_bounds__(256) void gram_final_kernel(const double* __restric
       const double* A = u + t.off[k] * R;
       const int64_t I = t.dims[k];
       double tot[4] = {0.0, 0.0, 0.0, 0.0};   // entries threadIdx.x + q * 256 (R * R <= 1024)
+      int ra[4], ca[4];   // their row and column; entries past R * R read entry 0
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int pr = threadIdx.x + q * 256;
+        const int pe = pr < RR ? pr : 0;
+        ra[q] = pe / R;
+        ca[q] = pe - ra[q] * R;
+      }
       for (int64_t i0 = 0; i0 < I; i0 += kRowsPerChunk) {
         const int nr = (int)min<int64_t>(kRowsPerChunk, I - i0);
         const int n = nr * R;
@@ -229,16 +252,18 @@ __global__ __launch_bounds__(256) void gram_final_kernel(const double* __restric
           if (e < n) gl[e] = v[q];
         }
         __syncthreads();
+        // the four sums side by side, each in row order from zero
+        double p[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int pr = threadIdx.x + q * 256;
-          if (pr < RR) {
-            const int r = pr / R, c = pr - (pr / R) * R;
-            double p = 0.0;
-            for (int ii = 0; ii < nr; ++ii) p = fma(gl[ii * R + r], gl[ii * R + c], p);
-            tot[q] += p;
-          }
+        for (int q = 0; q < 4; ++q) p[q] = 0.0;
+#pragma unroll 4
+        for (int ii = 0; ii < nr; ++ii) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) p[q] = fma(gl[ii * R + ra[q]], gl[ii * R + ca[q]], p[q]);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (threadIdx.x + q * 256 < RR) tot[q] += p[q];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -366,28 +391,31 @@ __global__ void norm_plan_kernel(const double* __restrict__ part, ModeTable t,
   }
 }
 
-// In place, one thread per row (the row staged in LDS): x(row, j) =
-// scale[k][perm[j]] * x(row, perm[j]) (u), or x / scale for a gradient
-// (scale 0 -> undivided).
-__global__ __launch_bounds__(64) void norm_apply_rows_kernel(double* __restrict__ x, ModeTable t,
-                                                             const double* __restrict__ scales,
-                                                             const int* __restrict__ perm,
-                                                             int gradient) {
-  __shared__ double buf[64 * (kMaxR + 1)];
+// In place, one lane per entry with whole rows inside a wave (64 / R rows
+// per wave): lane (row, j) loads x(row, perm[j]) and that term's scale, then
+// stores u(row, j) = scale * value, and for the gradient g(row, j) =
+// value / scale (scale 0 -> undivided).  A row's loads are one wave
+// instruction whose results every store waits for, so no lane overwrites an
+// entry another lane of its row has still to read.
+__global__ __launch_bounds__(256) void norm_apply_rows_kernel(double* __restrict__ u,
+                                                              double* __restrict__ g, ModeTable t,
+                                                              const double* __restrict__ scales,
+                                                              const int* __restrict__ perm) {
   const int R = t.R;
-  const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (row >= t.off[t.N]) return;
+  const int rpw = 64 / R;
+  const int lane = (int)threadIdx.x & 63;
+  const int sub = lane / R;
+  const int j = lane - sub * R;
+  const int64_t row = ((int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * rpw + sub;
+  if (sub >= rpw || row >= t.off[t.N]) return;
   int k = 0;
   while (row >= t.off[k + 1]) ++k;
-  double* b = buf + threadIdx.x * (kMaxR + 1);
-  double* xr = x + row * R;
-  for (int j = 0; j < R; ++j) b[j] = xr[j];
-  for (int j = 0; j < R; ++j) {
-    const int r = perm[j];
-    const double s = scales[k * R + r];
-    const double v = b[r];
-    xr[j] = gradient ? (s != 0.0 ? v / s : v) : s * v;
-  }
+  const int r = perm[j];
+  const double sc = scales[k * R + r];
+  const double vu = u[row * R + r];
+  const double vg = g ? g[row * R + r] : 0.0;
+  u[row * R + j] = sc * vu;
+  if (g) g[row * R + j] = sc != 0.0 ? vg / sc : vg;
 }
 
 // ---- ALS mode solve -----------------------------------------------------------
@@ -1199,7 +1227,7 @@ int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, do
 }
 
 int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStream_t st) {
-  if (R > kMaxR) return fail(h, CP_EINVAL, "rank %d above the supported %d", R, kMaxR);
+  if (R < 1 || R > kMaxR) return fail(h, CP_EINVAL, "rank %d outside 1..%d", R, kMaxR);
   ModeTable t = table(s, R);
   if (s.sum_dims() * R <= kSmallNorm) {
     hipLaunchKernelGGL(normalize_small_kernel, dim3(1), dim3(256), 0, st, u, g, t);
@@ -1217,14 +1245,10 @@ int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStre
   hipLaunchKernelGGL(norm_plan_kernel, dim3(1), dim3(64), 0, st, part, t, scales, perm);
   CP_LAUNCH_CHECK(h);
   const int64_t rows = s.sum_dims();
-  hipLaunchKernelGGL(norm_apply_rows_kernel, dim3(nblk(rows, 64)), dim3(64), 0, st, u, t, scales,
-                     perm, 0);
+  const int64_t rows_per_block = 4 * (64 / R);   // four waves of 64 / R rows (R <= 64)
+  hipLaunchKernelGGL(norm_apply_rows_kernel, dim3(nblk(rows, rows_per_block)), dim3(256), 0, st, u,
+                     g, t, scales, perm);
   CP_LAUNCH_CHECK(h);
-  if (g) {
-    hipLaunchKernelGGL(norm_apply_rows_kernel, dim3(nblk(rows, 64)), dim3(64), 0, st, g, t, scales,
-                       perm, 1);
-    CP_LAUNCH_CHECK(h);
-  }
   return CP_OK;
 }
 

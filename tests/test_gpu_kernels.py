@@ -123,10 +123,12 @@ def test_gram_parity(h, dims, R):
     np.testing.assert_allclose(G, refg, rtol=1e-11, atol=1e-12 * np.abs(refg).max())
 
 
-# one-workgroup form (L = R sum_k I_k <= 8192) and, for (300, 200, 100) and
-# (3000, 40), the multi-block form
+# one-workgroup form (L = R sum_k I_k <= 8192) and, for the larger shapes,
+# the multi-block form (rows packed 64 / R to a wave: 1 at R = 40 and 64, 4 at
+# R = 16, 6 at R = 10 with four idle lanes)
 @pytest.mark.parametrize("dims,R", [((6, 7, 8), 5), ((30, 4, 9, 3), 12), ((3, 2), 1),
-                                    ((300, 200, 100), 40), ((3000, 40), 16)])
+                                    ((300, 200, 100), 40), ((3000, 40), 16),
+                                    ((701, 499, 3), 10), ((200, 100, 50), 64)])
 def test_normalize_parity(h, dims, R):
     cpng = _cpng()
     A = _factors(dims, R, 8)
@@ -140,16 +142,20 @@ def test_normalize_parity(h, dims, R):
     np.testing.assert_allclose(g.cpu().numpy(), ocp.join_u(Gt), rtol=1e-12, atol=1e-14)
 
 
-def test_normalize_zero_term(h):
+@pytest.mark.parametrize("dims,R", [((3, 4), 3), ((3000, 40), 8)])
+def test_normalize_zero_term(h, dims, R):
+    """A zero term goes last; its gradient columns are left undivided."""
     cpng = _cpng()
-    dims, R = (3, 4), 3
     A = _factors(dims, R, 10)
     A[1][:, 0] = 0.0
-    u = _dev(ocp.join_u(A))
-    cpng.cp_normalize(h, dims, u, R)
-    B, _, perm = ocp.normalise(A)
+    G = _factors(dims, R, 11)
+    u, g = _dev(ocp.join_u(A)), _dev(ocp.join_u(G))
+    cpng.cp_normalize(h, dims, u, R, g)
+    B, scales, perm = ocp.normalise(A)
     assert perm[-1] == 0
     np.testing.assert_allclose(u.cpu().numpy(), ocp.join_u(B), rtol=1e-12, atol=1e-14)
+    Gt = ocp.transform_gradient(G, scales, perm)
+    np.testing.assert_allclose(g.cpu().numpy(), ocp.join_u(Gt), rtol=1e-12, atol=1e-14)
 
 
 # (5, 2500, 6): the left group's mode 0 sums 2500 pairs per output (split-K
