@@ -227,15 +227,20 @@ __global__ __launch_bounds__(256) void gram_final_kernel(const double* __restric
       const int k = only;
       const double* A = u + t.off[k] * R;
       const int64_t I = t.dims[k];
-      double tot[4] = {0.0, 0.0, 0.0, 0.0};   // entries threadIdx.x + q * 256 (R * R <= 1024)
-      int ra[4], ca[4];   // their row and column; entries past R * R read entry 0
+      // thread t: column c = t % 32, rows t / 32 + 8 q (q < 4), so a row of
+      // the chunk gives one load of column c and four loads the wave reads
+      // at two addresses; entries outside R x R read entry 0 and are dropped
+      const int c = (int)threadIdx.x & 31;
+      int ra[4];
+      bool on[4];
+      double tot[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int pr = threadIdx.x + q * 256;
-        const int pe = pr < RR ? pr : 0;
-        ra[q] = pe / R;
-        ca[q] = pe - ra[q] * R;
+        const int r = ((int)threadIdx.x >> 5) + 8 * q;
+        on[q] = r < R && c < R;
+        ra[q] = on[q] ? r : 0;
       }
+      const int ce = c < R ? c : 0;
       for (int64_t i0 = 0; i0 < I; i0 += kRowsPerChunk) {
         const int nr = (int)min<int64_t>(kRowsPerChunk, I - i0);
         const int n = nr * R;
@@ -252,24 +257,20 @@ __global__ __launch_bounds__(256) void gram_final_kernel(const double* __restric
           if (e < n) gl[e] = v[q];
         }
         __syncthreads();
-        // the four sums side by side, each in row order from zero
-        double p[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) p[q] = 0.0;
+        // the chunk's four sums, each in row order from zero
+        double p[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
         for (int ii = 0; ii < nr; ++ii) {
+          const double b = gl[ii * R + ce];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) p[q] = fma(gl[ii * R + ra[q]], gl[ii * R + ca[q]], p[q]);
+          for (int q = 0; q < 4; ++q) p[q] = fma(gl[ii * R + ra[q]], b, p[q]);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (threadIdx.x + q * 256 < RR) tot[q] += p[q];
+        for (int q = 0; q < 4; ++q) tot[q] += p[q];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int pr = threadIdx.x + q * 256;
-        if (pr < RR) S[(int64_t)k * RR + pr] = tot[q];
-      }
+      for (int q = 0; q < 4; ++q)
+        if (on[q]) S[(int64_t)k * RR + ra[q] * R + c] = tot[q];
     }
   }
   if (!direct) {
