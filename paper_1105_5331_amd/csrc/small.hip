@@ -162,9 +162,36 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const double* __restr
     if (e < n) rows[e] = v[q];
   }
   __syncthreads();
-  // a thread's entries in groups of four sums run side by side (each still
-  // in row order from zero); entries past R * R read entry 0 and are dropped
   const int RR = R * R;
+  if (R <= 32) {
+    // thread t: column c = t % 32, rows t / 32 + 8 q (q < 4): per row of the
+    // chunk one load of column c and four loads the wave reads at two
+    // addresses; each sum in row order from zero
+    const int c = (int)threadIdx.x & 31;
+    const int ce = c < R ? c : 0;
+    int ra[4];
+    bool on[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = ((int)threadIdx.x >> 5) + 8 * q;
+      on[q] = r < R && c < R;
+      ra[q] = on[q] ? r : 0;
+    }
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int ii = 0; ii < nr; ++ii) {
+      const double b = rows[ii * R + ce];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) p[q] = fma(rows[ii * R + ra[q]], b, p[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (on[q]) part[ch * RR + ra[q] * R + c] = p[q];
+    return;
+  }
+  // R > 32: a thread's entries in groups of four sums run side by side (each
+  // still in row order from zero); entries past R * R read entry 0 and are
+  // dropped
   for (int q0 = 0; q0 * 256 < RR; q0 += 4) {
     int ra[4], ca[4];
     double s[4];
