@@ -163,6 +163,17 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const double* __restr
   }
   __syncthreads();
   const int RR = R * R;
+  if (R <= 16) {
+    // R * R <= 256: one entry per thread, summed in row order from zero
+    const int pr = threadIdx.x;
+    if (pr < RR) {
+      const int r = pr / R, c = pr - (pr / R) * R;
+      double s = 0.0;
+      for (int ii = 0; ii < nr; ++ii) s = fma(rows[ii * R + r], rows[ii * R + c], s);
+      part[ch * RR + pr] = s;
+    }
+    return;
+  }
   if (R <= 32) {
     // thread t: column c = t % 32, rows t / 32 + 8 q (q < 4): per row of the
     // chunk one load of column c and four loads the wave reads at two
@@ -254,9 +265,10 @@ __global__ __launch_bounds__(256) void gram_final_kernel(const double* __restric
       const int k = only;
       const double* A = u + t.off[k] * R;
       const int64_t I = t.dims[k];
-      // thread t: column c = t % 32, rows t / 32 + 8 q (q < 4), so a row of
-      // the chunk gives one load of column c and four loads the wave reads
-      // at two addresses; entries outside R x R read entry 0 and are dropped
+      // R > 16: thread t takes column c = t % 32, rows t / 32 + 8 q (q < 4),
+      // so a row of the chunk gives one load of column c and four loads the
+      // wave reads at two addresses; entries outside R x R read entry 0 and
+      // are dropped.  R <= 16: one entry per thread (tot[0]).
       const int c = (int)threadIdx.x & 31;
       int ra[4];
       bool on[4];
@@ -284,20 +296,35 @@ __global__ __launch_bounds__(256) void gram_final_kernel(const double* __restric
           if (e < n) gl[e] = v[q];
         }
         __syncthreads();
-        // the chunk's four sums, each in row order from zero
-        double p[4] = {0.0, 0.0, 0.0, 0.0};
+        if (R <= 16) {
+          // R * R <= 256: one entry per thread (entry threadIdx.x), its chunk
+          // sum in row order from zero
+          if ((int)threadIdx.x < RR) {
+            const int r = (int)threadIdx.x / R, cc = (int)threadIdx.x - r * R;
+            double p = 0.0;
+            for (int ii = 0; ii < nr; ++ii) p = fma(gl[ii * R + r], gl[ii * R + cc], p);
+            tot[0] += p;
+          }
+        } else {
+          // the chunk's four sums, each in row order from zero
+          double p[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-        for (int ii = 0; ii < nr; ++ii) {
-          const double b = gl[ii * R + ce];
+          for (int ii = 0; ii < nr; ++ii) {
+            const double b = gl[ii * R + ce];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) p[q] = fma(gl[ii * R + ra[q]], b, p[q]);
+            for (int q = 0; q < 4; ++q) p[q] = fma(gl[ii * R + ra[q]], b, p[q]);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) tot[q] += p[q];
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) tot[q] += p[q];
       }
+      if (R <= 16) {
+        if ((int)threadIdx.x < RR) S[(int64_t)k * RR + threadIdx.x] = tot[0];
+      } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (on[q]) S[(int64_t)k * RR + ra[q] * R + c] = tot[q];
+        for (int q = 0; q < 4; ++q)
+          if (on[q]) S[(int64_t)k * RR + ra[q] * R + c] = tot[q];
+      }
     }
   }
   if (!direct) {
