@@ -29,7 +29,7 @@ from __future__ import annotations
 import numpy as np
 
 from .linesearch import more_thuente
-from .ngmres import IterRecord, Result, _rho
+from .ngmres import IterRecord, Result, _rho, accept_trial
 
 __all__ = ["ncg"]
 
@@ -59,16 +59,8 @@ def ncg(problem, u0, tol, max_iter=1000, ls=None):
             return fb, float(gb @ d), gb
         res = more_thuente(phi, f, slope, **ls)
         rec.nfev, rec.ls_status = res.nfev, res.status
-        restart_next = False
-        if res.status == "converged":
-            beta, f_new, g_new = res.stp, res.f, res.payload
-        else:
-            best = min(res.trials, key=lambda t: t[1])
-            if best[1] < f:
-                beta, f_new, g_new = best[0], best[1], best[3]
-            else:
-                beta, f_new, g_new = 0.0, f, g
-            restart_next = True
+        beta, f_new, g_new = accept_trial(res, f, g)
+        restart_next = res.status != "converged"
         rec.beta = beta
         u_new = u + beta * d if beta != 0.0 else u
         if restart_next:

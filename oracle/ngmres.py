@@ -23,9 +23,12 @@ Readings of points the paper leaves open (shared with the GPU library):
   formed; line-search trial points are not normalised; the accepted iterate
   is normalised and its gradient transformed (not recomputed);
 * delta = eps * max diag(P^T P) with eps = 1e-12; if every p_j is zero,
-  alpha = 0 (u_hat = u_bar);
+  alpha = 0 (u_hat = u_bar); if P^T P + delta I is still not positive
+  definite (a Cholesky pivot that is not positive), alpha = 0 as well and the
+  step is flagged;
 * if the line search stops without a strong-Wolfe point, the evaluated trial
-  with the lowest objective is taken when it is below f(u_bar), else beta = 0.
+  with the lowest objective (the earliest of equal ones) is taken when it is
+  below f(u_bar), else beta = 0.
 """
 from __future__ import annotations
 
@@ -38,7 +41,8 @@ import scipy.linalg
 from . import cp
 from .linesearch import more_thuente
 
-__all__ = ["CPProblem", "step2_accelerate", "ngmres", "als", "IterRecord"]
+__all__ = ["CPProblem", "step2_solve", "step2_accelerate", "accept_trial", "ngmres", "als",
+           "IterRecord"]
 
 
 class CPProblem:
@@ -86,27 +90,58 @@ class CPProblem:
         return u2, flags
 
 
-def step2_accelerate(U, Gw, u_bar, g_bar, eps=1e-12):
+def step2_solve(P, g_bar, eps=1e-12):
+    """alpha of Step II from the rows p_j of P and g_bar.
+
+    Normal equations of the linearised residual ||g_bar + P^T alpha||_2:
+    (P P^T + delta I) alpha = -P g_bar with delta = eps * max diag(P P^T)
+    (Section 2.1 Step II and fifth remark; Section 2.4).  Returns
+    (alpha, status): "ok"; "zero" when every p_j is zero (alpha = 0); "not_pd"
+    when the regularised matrix has a Cholesky pivot that is not positive
+    (alpha = 0, so u_hat = u_bar).
+    """
+    B = P @ P.T
+    dmax = float(np.max(np.diag(B))) if B.size else 0.0
+    if not dmax > 0.0:
+        return np.zeros(P.shape[0]), "zero"
+    rhs = -(P @ g_bar)
+    try:
+        c = scipy.linalg.cho_factor(B + eps * dmax * np.eye(B.shape[0]), lower=True)
+    except np.linalg.LinAlgError:
+        return np.zeros(P.shape[0]), "not_pd"
+    return scipy.linalg.cho_solve(c, rhs), "ok"
+
+
+def step2_accelerate(U, Gw, u_bar, g_bar, eps=1e-12, info=None):
     """N-GMRES Step II: u_hat = u_bar + sum_j alpha_j (u_bar - u_j).
 
-    U, Gw: window iterates and their gradients (m x L).  alpha minimises the
-    linearised residual ||g_bar + P alpha||_2 with p_j = g_bar - g_j, via the
-    normal equations (P^T P + delta I) alpha = -P^T g_bar, delta = eps * max
-    diag(P^T P) (Section 2.1 Step II and fifth remark; Section 2.4).
+    U, Gw: window iterates and their gradients (m x L); p_j = g_bar - g_j;
+    alpha from step2_solve.  If ``info`` is a dict, info["status"] receives
+    step2_solve's status.
     """
     U = np.atleast_2d(np.asarray(U, dtype=np.float64))
     Gw = np.atleast_2d(np.asarray(Gw, dtype=np.float64))
     P = g_bar[None, :] - Gw                      # rows are p_j
-    B = P @ P.T
-    dmax = float(np.max(np.diag(B))) if B.size else 0.0
-    if dmax <= 0.0:
-        alpha = np.zeros(U.shape[0])
-    else:
-        rhs = -(P @ g_bar)
-        c = scipy.linalg.cho_factor(B + eps * dmax * np.eye(B.shape[0]), lower=True)
-        alpha = scipy.linalg.cho_solve(c, rhs)
+    alpha, status = step2_solve(P, g_bar, eps)
+    if info is not None:
+        info["status"] = status
     u_hat = u_bar + np.sum(alpha[:, None] * (u_bar[None, :] - U), axis=0)
     return u_hat, alpha
+
+
+def accept_trial(res, f0, g0):
+    """Step accepted after a line search from (f0, g0) at beta = 0.
+
+    A strong-Wolfe exit takes its own point.  Any other exit takes the
+    evaluated trial with the lowest objective (the earliest of equal ones)
+    when it is below f0, else beta = 0.  Returns (beta, f, g).
+    """
+    if res.status == "converged":
+        return res.stp, res.f, res.payload
+    best = min(res.trials, key=lambda t: t[1])
+    if best[1] < f0:
+        return best[0], best[1], best[3]
+    return 0.0, f0, g0
 
 
 @dataclass
@@ -119,6 +154,7 @@ class IterRecord:
     nfev: int = 0
     ls_status: str = ""
     m: int = 0
+    step2: str = ""
 
 
 @dataclass
@@ -159,7 +195,9 @@ def ngmres(problem, u0, tol, max_iter=1000, w=20, eps=1e-12, ls=None,
         # Step II
         U = np.array([p[0] for p in window])
         Gw = np.array([p[1] for p in window])
-        u_hat, _ = step2_accelerate(U, Gw, u_bar, g_bar, eps)
+        s2 = {}
+        u_hat, _ = step2_accelerate(U, Gw, u_bar, g_bar, eps, info=s2)
+        rec.step2 = s2["status"]
         if normalise_accel:
             u_hat, _ = problem.normalise(u_hat)
         d = u_hat - u_bar
@@ -176,14 +214,7 @@ def ngmres(problem, u0, tol, max_iter=1000, w=20, eps=1e-12, ls=None,
                 return fb, float(gb @ d), gb
             res = more_thuente(phi, f_bar, slope, **ls)
             rec.nfev, rec.ls_status = res.nfev, res.status
-            if res.status == "converged":
-                beta, f_new, g_new = res.stp, res.f, res.payload
-            else:
-                best = min(res.trials, key=lambda t: t[1])
-                if best[1] < f_bar:
-                    beta, f_new, g_new = best[0], best[1], best[3]
-                else:
-                    beta, f_new, g_new = 0.0, f_bar, g_bar
+            beta, f_new, g_new = accept_trial(res, f_bar, g_bar)
             rec.beta = beta
             u_new = u_bar + beta * d if beta != 0.0 else u_bar
         u, g = problem.normalise(u_new, g_new)

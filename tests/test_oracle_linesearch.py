@@ -1,9 +1,14 @@
 """Pins of the oracle's Moré–Thuente line search (no GPU).
 
 * the strong Wolfe conditions hold at every 'converged' exit;
-* on a quadratic the first interpolation lands on the exact minimiser;
-* the trial sequence agrees with scipy's independent implementation of the
-  same published method (MINPACK-2 DCSRCH, ``scalar_search_wolfe1``).
+* on a quadratic the first interpolation lands on the exact minimiser, from
+  either side (an overshoot that brackets the minimum, and an extrapolation
+  from a point short of it, both computed by hand);
+* exits without a Wolfe point report the status and keep every trial.
+
+Not a pin: the comparison with scipy's port of MINPACK-2 DCSRCH
+(``scalar_search_wolfe1``).  The oracle follows the same reference form of
+the method, so agreement only guards against regressions in this module.
 """
 import math
 
@@ -78,10 +83,39 @@ def test_rejects_ascent_direction():
         more_thuente(_wrap(lambda s: s, lambda s: 1.0), 0.0, 1.0)
 
 
+def test_p9_extrapolation_step_by_hand():
+    """phi(s) = (s - 3)^2 - 9 from s = 1: phi = -5, phi' = -4 (sufficient
+    decrease, no curvature: gtol is tiny).  Lower value with a smaller slope
+    of the same sign and no bracket: the cubic through (0, 0, -6) and
+    (1, -5, -4) has theta = 3 (0 + 5) / 1 - 6 - 4 = 5, gamma = -1 (the
+    square root of 25/36 - 24/36 times 6, negated since the step increased),
+    p = 8, q = -4, r = -2, so the cubic step is 1 + (-2)(0 - 1) = 3; the
+    secant step on the derivatives is 1 + (-4 / 2)(-1) = 3 as well.  The
+    second trial is therefore the exact minimiser 3, where phi' = 0."""
+    f = lambda s: (s - 3.0) ** 2 - 9.0
+    df = lambda s: 2.0 * (s - 3.0)
+    log = []
+    res = more_thuente(_wrap(f, df, log), 0.0, -6.0, stp=1.0, ftol=FTOL, gtol=1e-12, maxfev=5)
+    assert log == [1.0, 3.0]
+    assert res.status == "converged" and res.stp == 3.0 and res.f == -9.0
+
+
+def test_p9_maxfev_exit_by_hand():
+    """The same function with one evaluation allowed: the trial s = 1 meets
+    sufficient decrease but not curvature, so the search stops with status
+    'maxfev' at that trial, and the trial list holds exactly it."""
+    f = lambda s: (s - 3.0) ** 2 - 9.0
+    df = lambda s: 2.0 * (s - 3.0)
+    res = more_thuente(_wrap(f, df), 0.0, -6.0, stp=1.0, ftol=FTOL, gtol=1e-12, maxfev=1)
+    assert res.status == "maxfev" and res.nfev == 1
+    assert [(t[0], t[1], t[2]) for t in res.trials] == [(1.0, -5.0, -4.0)]
+
+
 @pytest.mark.parametrize("name", list(FUNCS))
 @pytest.mark.parametrize("stp0", [1e-3, 1e-1, 1.0, 10.0])
-def test_p9_agrees_with_scipy_dcsrch(name, stp0):
-    """Same method, independent code: identical trial sequence to rounding."""
+def test_regression_crosscheck_scipy_dcsrch(name, stp0):
+    """Regression cross-check, not a pin: scipy's port of the same reference
+    form (MINPACK-2 DCSRCH) gives the same trial sequence to rounding."""
     f, df = FUNCS[name]
     ours_log, ref_log = [], []
     amin, amax, xtol = 1e-10, 1e4, 1e-14

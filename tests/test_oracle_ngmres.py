@@ -3,7 +3,8 @@ import numpy as np
 import pytest
 
 from oracle import cp
-from oracle.ngmres import CPProblem, als, ngmres, step2_accelerate
+from oracle.linesearch import LineSearchResult
+from oracle.ngmres import CPProblem, accept_trial, als, ngmres, step2_accelerate
 from workloads import initial_guess, test_problem_1, test_problem_2
 
 
@@ -49,6 +50,104 @@ def test_p8_regularised_alpha_matches_lstsq():
     P = (g_bar[None, :] - Gw).T
     ref = np.linalg.lstsq(P, -g_bar, rcond=None)[0]
     np.testing.assert_allclose(alpha, ref, rtol=1e-9, atol=1e-9)
+
+
+def test_r15b_not_positive_definite_gives_alpha_zero():
+    """Two window entries with the same gradient and eps = 0: p_1 = p_2 =
+    (1, 1, 1, 1), so P^T P = [[4, 4], [4, 4]].  Cholesky: first pivot 4 (root
+    2), multiplier 4 / 2 = 2, second pivot 4 - 2 * 2 = 0, not positive: the
+    reading takes alpha = 0 and u_hat = u_bar, and flags the step."""
+    U = np.array([[0.0, 0.0, 0.0, 0.0], [1.0, 0.0, 0.0, 0.0]])
+    Gw = np.zeros((2, 4))
+    u_bar = np.array([5.0, 6.0, 7.0, 8.0])
+    g_bar = np.ones(4)
+    info = {}
+    u_hat, alpha = step2_accelerate(U, Gw, u_bar, g_bar, eps=0.0, info=info)
+    assert info["status"] == "not_pd"
+    assert np.all(alpha == 0.0) and np.array_equal(u_hat, u_bar)
+
+
+def test_r15b_regularised_singular_case_by_hand():
+    """The same window with eps = 1e-12: delta = 4e-12 makes the matrix
+    positive definite; by symmetry alpha_1 = alpha_2 = a with
+    (4 + delta) a + 4 a = -4, so a = -4 / (8 + delta), and
+    u_hat = u_bar + a (u_bar - u_1) + a (u_bar - u_2)."""
+    U = np.array([[0.0, 0.0, 0.0, 0.0], [1.0, 0.0, 0.0, 0.0]])
+    Gw = np.zeros((2, 4))
+    u_bar = np.array([5.0, 6.0, 7.0, 8.0])
+    g_bar = np.ones(4)
+    info = {}
+    u_hat, alpha = step2_accelerate(U, Gw, u_bar, g_bar, eps=1e-12, info=info)
+    a = -4.0 / (8.0 + 4e-12)
+    assert info["status"] == "ok"
+    np.testing.assert_allclose(alpha, [a, a], rtol=1e-9)
+    np.testing.assert_allclose(u_hat, u_bar + a * (2 * u_bar - U[0] - U[1]), rtol=1e-9)
+
+
+def _ls_result(status, trials):
+    last = trials[-1]
+    return LineSearchResult(last[0], last[1], last[2], last[3], len(trials), status, trials)
+
+
+def test_r13_accept_rule_by_hand():
+    """Exits without a Wolfe point: the trial with the lowest objective (the
+    earliest of equal ones) if it is below f(u_bar) = 3, else beta = 0."""
+    g0 = np.array([9.0])
+    trials = [(1.0, 5.0, -1.0, "g1"), (0.3, 2.0, -0.5, "g2"), (0.1, 2.5, -0.4, "g3")]
+    assert accept_trial(_ls_result("maxfev", trials), 3.0, g0) == (0.3, 2.0, "g2")
+    ties = [(1.0, 2.0, -1.0, "g1"), (0.5, 2.0, -0.2, "g2")]
+    assert accept_trial(_ls_result("xtol", ties), 3.0, g0) == (1.0, 2.0, "g1")
+    worse = [(1.0, 5.0, -1.0, "g1"), (0.5, 3.0, -0.2, "g2")]
+    beta, f, g = accept_trial(_ls_result("rounding", worse), 3.0, g0)
+    assert beta == 0.0 and f == 3.0 and g is g0
+    conv = [(1.0, 5.0, -1.0, "g1"), (0.4, 4.0, 0.0, "g2")]
+    assert accept_trial(_ls_result("converged", conv), 3.0, g0) == (0.4, 4.0, "g2")
+
+
+class _HalvingQuadratic:
+    """f(u) = 1/2 ||u||^2 (g = u) with the one-step process M(u) = u / 2 and
+    no normalisation: small enough to follow an N-GMRES iteration by hand."""
+    R = 1
+
+    def __init__(self):
+        self.norm_t, self.nfg = 1.0, 0
+
+    def f_and_g(self, u):
+        self.nfg += 1
+        return 0.5 * float(u @ u), u.copy()
+
+    def normalise(self, u, g=None):
+        return u.copy(), None if g is None else g.copy()
+
+    def als_sweep(self, u, normalise=True):
+        return 0.5 * u, []
+
+
+def test_r13_driver_takes_best_trial_by_hand():
+    """u_0 = (2, 0): u_bar = (1, 0), g_bar = (1, 0), p = g_bar - g_0 = (-1, 0),
+    alpha = 1 / (1 + 1e-12) (delta = 1e-12), u_hat = (1 - alpha, 0),
+    d = (-alpha, 0), slope -alpha.  One trial allowed with a curvature
+    tolerance it cannot meet: phi(1) = (1 - alpha)^2 / 2 < f(u_bar) = 1/2, so
+    the fallback accepts beta = 1 and u_1 = u_hat."""
+    res = ngmres(_HalvingQuadratic(), np.array([2.0, 0.0]), tol=0.0, max_iter=1,
+                 ls=dict(maxfev=1, gtol=1e-15))
+    r0 = res.trace[0]
+    assert r0.ls_status == "maxfev" and r0.nfev == 1 and r0.beta == 1.0 and not r0.restart
+    alpha = 1.0 / (1.0 + 1e-12)
+    assert abs(res.u[0] - (1.0 - alpha)) <= 1e-15 and res.u[1] == 0.0
+    assert abs(res.f - 0.5 * (1.0 - alpha) ** 2) <= 1e-30
+
+
+def test_r13_driver_falls_back_to_u_bar_by_hand():
+    """The same iteration with the first trial at beta = 3: phi(3) =
+    (1 - 3 alpha)^2 / 2 ~ 2 > f(u_bar) = 1/2 and no other trial is allowed, so
+    beta = 0: u_1 = u_bar = (1, 0), f_1 = 1/2, g_1 = g_bar."""
+    res = ngmres(_HalvingQuadratic(), np.array([2.0, 0.0]), tol=0.0, max_iter=1,
+                 ls=dict(maxfev=1, gtol=1e-15, stp=3.0))
+    r0 = res.trace[0]
+    assert r0.ls_status == "maxfev" and r0.beta == 0.0
+    assert np.array_equal(res.u, [1.0, 0.0]) and res.f == 0.5
+    assert np.array_equal(res.g, [1.0, 0.0])
 
 
 def test_step2_zero_residual_differences():
