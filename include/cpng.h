@@ -153,7 +153,22 @@ typedef struct cp_options {
   int32_t switch_on_stall;  /* with switch_rho > 0, also switch once rho <= 1e-2 after a
                                line search in the first precision ends without a Wolfe
                                point (1) */
+  double stop_tol;          /* the stopping tolerance on rho that the precision schedule
+                               anticipates: a state whose bulk precision does not accumulate
+                               in float64 switches to a float64-accumulating final_precision
+                               once rho <= stop_tol, so the stop is certified in float64.
+                               ngmres_step applies the whole schedule (switch_rho,
+                               switch_on_stall, stop_tol) at the start of each iteration;
+                               cp_decompose sets stop_tol to its tol (0) */
+  int32_t init;             /* CP_INIT_GIVEN: the caller's array holds the initial guess;
+                               CP_INIT_SEEDED: it is drawn from `seed` as cp_init_uniform
+                               does, then normalised like a given one (Section 2.4: a
+                               uniformly random initial guess) (CP_INIT_GIVEN) */
+  uint64_t seed;            /* seed of CP_INIT_SEEDED (0) */
 } cp_options;
+
+#define CP_INIT_GIVEN  0
+#define CP_INIT_SEEDED 1
 
 typedef struct cp_report {
   int32_t iters;            /* iterations performed */
@@ -253,16 +268,29 @@ int cp_objective_grad(cp_handle* h, const cp_tensor* T, const double* u, int32_t
  *   p_j = g_bar - G_j, (P^T P + delta I) alpha = -P^T g_bar,
  *   delta = eps * max_j (P^T P)_jj,  u_hat = u_bar + sum_j alpha_j (u_bar - U_j)
  * U, G: m x L row-major (window iterates and gradients), 1 <= m <= 64.
- * If every p_j is zero, alpha = 0.  alpha_out: device m doubles, nullable. */
+ * If every p_j is zero, or P^T P + delta I has a Cholesky pivot that is not
+ * positive (possible with eps = 0 or repeated gradients), alpha = 0 and
+ * u_hat = u_bar.  gTd_out: device, 1 double, nullable: g_bar^T (u_hat - u_bar),
+ * the slope of Step III along d = u_hat - u_bar for this (unnormalised) u_hat
+ * (ngmres_step normalises u_hat first, Section 2.3 end).  alpha_out: device m
+ * doubles, nullable. */
 int ngmres_accelerate(cp_handle* h, int64_t L, int32_t m, const double* U, const double* G,
                       const double* u_bar, const double* g_bar, double eps, double* u_hat_out,
-                      double* alpha_out, hipStream_t stream);
+                      double* gTd_out, double* alpha_out, hipStream_t stream);
+
+/* The seeded uniform initial guess (Section 2.4: uniformly random entries):
+ * u_out[i] = (x_i >> 11) * 2^-53 in [0, 1), x_i the i-th 64-bit output of
+ * Philox-4x64-10 (Salmon et al., SC 2011) under the key (seed, 0), outputs
+ * 4b..4b+3 being the cipher of the counter (b + 1, 0, 0, 0).  u_out: device,
+ * L doubles (the caller normalises it with cp_normalize if wanted). */
+int cp_init_uniform(cp_handle* h, int64_t L, uint64_t seed, double* u_out, hipStream_t stream);
 
 /* ---- the method -------------------------------------------------------- */
 
 /* Create an N-GMRES (or ALS) state on a prepared tensor: copies u0 (device,
- * L doubles), normalises it, evaluates f and g and starts the window.
- * Keeps the window (w iterates and w gradients) on the device. */
+ * L doubles; ignored, and may be NULL, with opt->init = CP_INIT_SEEDED),
+ * normalises it, evaluates f and g and starts the window.  Keeps the window
+ * (w iterates and w gradients) on the device. */
 int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_options* opt,
                      const double* u0, hipStream_t stream, cp_ngmres_state** st);
 /* One iteration (Steps I-III of the algorithm box for N-GMRES; u <- M(u) for
@@ -275,10 +303,45 @@ int cp_ngmres_get(cp_handle* h, cp_ngmres_state* st, double* u_out, double* g_ou
                   double* f_out, double* rho_out);
 int cp_ngmres_destroy(cp_handle* h, cp_ngmres_state* st);
 
+/* Scalar part of a state's checkpoint. */
+typedef struct cp_ngmres_meta {
+  int32_t it;               /* iterations taken */
+  int32_t m;                /* window entries (N-GMRES; 0 otherwise) */
+  int32_t precision;        /* current bulk cp_precision */
+  int32_t switched;         /* the precision schedule has switched */
+  int32_t stalled;          /* a reduced-precision line search ended without a Wolfe point */
+  int32_t cg_fresh;         /* N-CG: the next direction is -g */
+  double f;                 /* objective at u */
+  double rho;               /* ||g||_2 / ||T||_F (recomputed from g by cp_ngmres_load) */
+  int32_t n_fg, n_restarts, n_ls_fallback, switch_iter;
+} cp_ngmres_meta;
+
+/* Checkpoint and resume of the iteration state (Algorithm box: the iterate,
+ * its gradient and the window of stored iterates and gradients).
+ * save: U_out, G_out (device, window x L each, nullable) receive the window
+ * entries oldest first (meta->m rows), u_out, g_out (device, L, nullable) the
+ * iterate and gradient, d_out (device, L, nullable) the N-CG direction;
+ * meta (host) the scalars.  load: replaces all of that in a state created on
+ * the same tensor, rank and options (m <= window; m >= 1 for N-GMRES), and
+ * recomputes rho from g (synchronises the stream).  A loaded state steps
+ * exactly as the saved one would have.  Errors: CP_EINVAL. */
+int cp_ngmres_save(cp_handle* h, cp_ngmres_state* st, double* U_out, double* G_out, double* u_out,
+                   double* g_out, double* d_out, cp_ngmres_meta* meta);
+int cp_ngmres_load(cp_handle* h, cp_ngmres_state* st, const double* U, const double* G,
+                   const double* u, const double* g, const double* d, const cp_ngmres_meta* meta);
+
+/* Intermediate values of the last N-GMRES iteration (Steps I-II): u_bar =
+ * M(u_i), g_bar = g(u_bar), the normalised accelerated iterate u_hat, the
+ * direction d = u_hat - u_bar (device, L each, nullable), f(u_bar) and the
+ * slope g_bar^T d (host, nullable).  CP_EINVAL before the first N-GMRES step. */
+int cp_ngmres_last_step(cp_handle* h, cp_ngmres_state* st, double* u_bar, double* g_bar,
+                        double* u_hat, double* d, double* f_bar, double* slope);
+
 /* Decompose a prepared tensor: iterate until rho = ||g||_2/||T||_F <= tol or
- * max_iter.  u_inout (device, L doubles): initial guess in, result out.
- * opt nullable (defaults).  rep_out: host, nullable.  Returns CP_OK,
- * CP_MAXITER or an error. */
+ * max_iter.  u_inout (device, L doubles): initial guess in (unless
+ * opt->init = CP_INIT_SEEDED), result out.  u_inout = NULL: the seeded guess
+ * of opt->seed is used and only rep_out describes the result.  opt nullable
+ * (defaults).  rep_out: host, nullable.  Returns CP_OK, CP_MAXITER or an error. */
 int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const cp_options* opt,
                  double* u_inout, cp_report* rep_out, hipStream_t stream);
 

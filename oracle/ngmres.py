@@ -41,8 +41,8 @@ import scipy.linalg
 from . import cp
 from .linesearch import more_thuente
 
-__all__ = ["CPProblem", "step2_solve", "step2_accelerate", "accept_trial", "ngmres", "als",
-           "IterRecord"]
+__all__ = ["CPProblem", "step2_solve", "step2_accelerate", "accept_trial", "line_search",
+           "sd_step", "ngmres_iteration", "ngmres", "als", "IterRecord"]
 
 
 class CPProblem:
@@ -173,11 +173,91 @@ def _rho(problem, g):
     return float(np.linalg.norm(g)) / problem.norm_t
 
 
+_LS_DEFAULTS = dict(stp=1.0, ftol=1e-4, gtol=1e-2, maxfev=20, xtol=1e-15, stpmin=1e-15,
+                   stpmax=1e15)
+
+
+def line_search(problem, u, f, g, d, slope, ls):
+    """Moré–Thuente on phi(beta) = f(u + beta d) from phi(0) = f, phi'(0) =
+    slope < 0, then the acceptance rule; returns (beta, f, g, nfev, status)."""
+    def phi(beta):
+        fb, gb = problem.f_and_g(u + beta * d)
+        return fb, float(gb @ d), gb
+    res = more_thuente(phi, f, slope, **ls)
+    beta, f_new, g_new = accept_trial(res, f, g)
+    return beta, f_new, g_new, res.nfev, res.status
+
+
+def sd_step(problem, u, f, g, ls):
+    """Steepest-descent one-step process: u_bar = u + beta d with d = -g/||g||_2
+    and beta from the line search (first trial ls["stp"]); u_bar normalised.
+
+    Returns (u_bar, f_bar, g_bar, nfev): f is unchanged by the normalisation
+    and the gradient is carried over by its transformation (Section 2.3 end),
+    so no further evaluation is needed.  A zero gradient leaves u unchanged.
+    """
+    gn = float(np.linalg.norm(g))
+    if not gn > 0.0:
+        return u, f, g, 0
+    d = -g / gn
+    beta, f_new, g_new, nfev, _ = line_search(problem, u, f, g, d, float(g @ d), ls)
+    u_new = u + beta * d if beta != 0.0 else u
+    u_bar, g_bar = problem.normalise(u_new, g_new)
+    return u_bar, f_new, g_bar, nfev
+
+
+def ngmres_iteration(problem, u, f, g, U, Gw, eps=1e-12, ls=None, normalise_accel=True,
+                     precond="als"):
+    """One iteration of the N-GMRES algorithm box from the iterate (u, f, g)
+    and the window U, Gw (m x L each, oldest first, ending with u).
+
+    Step I: u_bar = M(u) -- one ALS sweep then f, g at u_bar (precond "als",
+    the paper's choice), or the steepest-descent process (precond "sd").
+    Step II: u_hat over the window (step2_accelerate), normalised.  Step III:
+    restart when g_bar^T d >= 0, else the line search along d = u_hat - u_bar.
+    The new iterate is normalised and its gradient transformed.  Returns a
+    dict of every intermediate and the new (u_next, f_next, g_next).
+    """
+    ls = _LS_DEFAULTS | (ls or {})
+    out = {}
+    if precond == "als":
+        u_bar, _ = problem.als_sweep(u)
+        f_bar, g_bar = problem.f_and_g(u_bar)
+        out["nfev_pre"] = 0
+    elif precond == "sd":
+        u_bar, f_bar, g_bar, out["nfev_pre"] = sd_step(problem, u, f, g, ls)
+    else:
+        raise ValueError(f"unknown one-step process {precond!r}")
+    s2 = {}
+    u_hat, _ = step2_accelerate(U, Gw, u_bar, g_bar, eps, info=s2)
+    if normalise_accel:
+        u_hat, _ = problem.normalise(u_hat)
+    d = u_hat - u_bar
+    slope = float(g_bar @ d)
+    out.update(u_bar=u_bar, f_bar=f_bar, g_bar=g_bar, u_hat=u_hat, d=d, slope=slope,
+               step2=s2["status"], beta=float("nan"), nfev=0, ls_status="")
+    if not (slope < 0.0):
+        # restart: no line search, the window starts again from the new iterate
+        out["restart"] = True
+        u_new, f_new, g_new = u_bar, f_bar, g_bar
+    else:
+        out["restart"] = False
+        beta, f_new, g_new, nfev, status = line_search(problem, u_bar, f_bar, g_bar, d, slope, ls)
+        out.update(beta=beta, nfev=nfev, ls_status=status)
+        u_new = u_bar + beta * d if beta != 0.0 else u_bar
+    u_next, g_next = problem.normalise(u_new, g_new)
+    out.update(u_next=u_next, f_next=f_new, g_next=g_next)
+    return out
+
+
 def ngmres(problem, u0, tol, max_iter=1000, w=20, eps=1e-12, ls=None,
-           normalise_accel=True):
-    """Algorithm "N-GMRES optimization algorithm" with the window grown from 1 to w."""
-    ls = dict(stp=1.0, ftol=1e-4, gtol=1e-2, maxfev=20, xtol=1e-15,
-              stpmin=1e-15, stpmax=1e15) | (ls or {})
+           normalise_accel=True, record=None, precond="als"):
+    """Algorithm "N-GMRES optimization algorithm" with the window grown from 1 to w.
+
+    If ``record`` is a list, one dict per iteration is appended: the state it
+    started from (it, u, g, f and the window U, G, oldest first) and every
+    value ngmres_iteration returned.
+    """
     u, _ = problem.normalise(np.asarray(u0, dtype=np.float64))
     f, g = problem.f_and_g(u)
     window = deque([(u, g)])
@@ -189,36 +269,16 @@ def ngmres(problem, u0, tol, max_iter=1000, w=20, eps=1e-12, ls=None,
         trace.append(rec)
         if rho <= tol or it >= max_iter:
             break
-        # Step I
-        u_bar, _ = problem.als_sweep(u)
-        f_bar, g_bar = problem.f_and_g(u_bar)
-        # Step II
         U = np.array([p[0] for p in window])
         Gw = np.array([p[1] for p in window])
-        s2 = {}
-        u_hat, _ = step2_accelerate(U, Gw, u_bar, g_bar, eps, info=s2)
-        rec.step2 = s2["status"]
-        if normalise_accel:
-            u_hat, _ = problem.normalise(u_hat)
-        d = u_hat - u_bar
-        slope = float(g_bar @ d)
-        if not (slope < 0.0):
-            # restart: no line search, window back to one iterate
-            rec.restart = True
-            u_new, f_new, g_new = u_bar, f_bar, g_bar
+        out = ngmres_iteration(problem, u, f, g, U, Gw, eps, ls, normalise_accel, precond)
+        rec.step2, rec.restart = out["step2"], out["restart"]
+        rec.beta, rec.nfev, rec.ls_status = out["beta"], out["nfev"], out["ls_status"]
+        if record is not None:
+            record.append(dict(it=it, u=u, g=g, f=f, U=U, G=Gw) | out)
+        if out["restart"]:
             window.clear()
-        else:
-            # Step III
-            def phi(beta):
-                fb, gb = problem.f_and_g(u_bar + beta * d)
-                return fb, float(gb @ d), gb
-            res = more_thuente(phi, f_bar, slope, **ls)
-            rec.nfev, rec.ls_status = res.nfev, res.status
-            beta, f_new, g_new = accept_trial(res, f_bar, g_bar)
-            rec.beta = beta
-            u_new = u_bar + beta * d if beta != 0.0 else u_bar
-        u, g = problem.normalise(u_new, g_new)
-        f = f_new
+        u, f, g = out["u_next"], out["f_next"], out["g_next"]
         window.append((u, g))
         while len(window) > w:
             window.popleft()

@@ -23,6 +23,7 @@ CP_MAXITER, CP_LS_FALLBACK = 1, 2
 CP_F32, CP_F64 = 0, 1
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp32in_fp64acc": 3}
 CP_METHOD_NGMRES, CP_METHOD_ALS, CP_METHOD_NCG = 0, 1, 2
+CP_INIT_GIVEN, CP_INIT_SEEDED = 0, 1
 LS_STATUS = {0: "converged", 1: "maxfev", 2: "xtol", 3: "stpmax", 4: "stpmin", 5: "rounding",
              -1: ""}
 
@@ -53,7 +54,15 @@ class cp_options(C.Structure):
                 ("final_precision", C.c_int32), ("switch_rho", C.c_double),
                 ("normalize_accel", C.c_int32), ("trace", C.POINTER(cp_iter_info)),
                 ("trace_cap", C.c_int32), ("mttkrp_tree", C.c_int32),
-                ("switch_on_stall", C.c_int32)]
+                ("switch_on_stall", C.c_int32), ("stop_tol", C.c_double), ("init", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class cp_ngmres_meta(C.Structure):
+    _fields_ = [("it", C.c_int32), ("m", C.c_int32), ("precision", C.c_int32),
+                ("switched", C.c_int32), ("stalled", C.c_int32), ("cg_fresh", C.c_int32),
+                ("f", C.c_double), ("rho", C.c_double), ("n_fg", C.c_int32),
+                ("n_restarts", C.c_int32), ("n_ls_fallback", C.c_int32), ("switch_iter", C.c_int32)]
 
 
 class cp_report(C.Structure):
@@ -100,7 +109,11 @@ def lib():
             "cp_als_sweep": (C.c_int, [vp, C.POINTER(cp_tensor), vp, i32, i32, i32, vp]),
             "cp_objective_grad": (C.c_int, [vp, C.POINTER(cp_tensor), vp, i32, i32, vp, vp, vp]),
             "cp_mode_solve": (C.c_int, [vp, vp, vp, i64, i32, vp, C.POINTER(i32), vp]),
-            "ngmres_accelerate": (C.c_int, [vp, i64, i32, vp, vp, vp, vp, dp, vp, vp, vp]),
+            "ngmres_accelerate": (C.c_int, [vp, i64, i32, vp, vp, vp, vp, dp, vp, vp, vp, vp]),
+            "cp_init_uniform": (C.c_int, [vp, i64, C.c_uint64, vp, vp]),
+            "cp_ngmres_save": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, C.POINTER(cp_ngmres_meta)]),
+            "cp_ngmres_load": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, C.POINTER(cp_ngmres_meta)]),
+            "cp_ngmres_last_step": (C.c_int, [vp, vp, vp, vp, vp, vp, C.POINTER(dp), C.POINTER(dp)]),
             "cp_ngmres_create": (C.c_int, [vp, C.POINTER(cp_tensor), i32, C.POINTER(cp_options),
                                            vp, vp, C.POINTER(vp)]),
             "ngmres_step": (C.c_int, [vp, vp, C.POINTER(cp_iter_info)]),
@@ -301,19 +314,33 @@ def cp_objective_grad(h: Handle, T: Tensor, u, R: int, prec="fp64", f_out=None, 
     return f_out, g_out
 
 
-def ngmres_accelerate(h: Handle, U, G, u_bar, g_bar, eps=1e-12, u_hat_out=None, alpha_out=None):
+def ngmres_accelerate(h: Handle, U, G, u_bar, g_bar, eps=1e-12, u_hat_out=None, alpha_out=None,
+                      gTd_out=None):
+    """Step II; returns (u_hat, alpha, gTd) with gTd = g_bar^T (u_hat - u_bar)."""
     m, L = U.shape
     if u_hat_out is None:
         u_hat_out = torch.empty(L, dtype=torch.float64, device=U.device)
     if alpha_out is None:
         alpha_out = torch.empty(m, dtype=torch.float64, device=U.device)
+    if gTd_out is None:
+        gTd_out = torch.empty(1, dtype=torch.float64, device=U.device)
     h.check(lib().ngmres_accelerate(h._h, int(L), int(m), _ptr(U, torch.float64, m * L, "U"),
                                     _ptr(G, torch.float64, m * L, "G"),
                                     _ptr(u_bar, torch.float64, L, "u_bar"),
                                     _ptr(g_bar, torch.float64, L, "g_bar"), float(eps),
                                     _ptr(u_hat_out, torch.float64, L, "u_hat_out"),
+                                    _ptr(gTd_out, torch.float64, 1, "gTd_out"),
                                     _ptr(alpha_out, torch.float64, m, "alpha_out"), _stream()))
-    return u_hat_out, alpha_out
+    return u_hat_out, alpha_out, gTd_out
+
+
+def cp_init_uniform(h: Handle, L: int, seed: int, u_out=None, device="cuda"):
+    """The seeded uniform initial guess (Philox-4x64-10 stream of `seed`)."""
+    if u_out is None:
+        u_out = torch.empty(int(L), dtype=torch.float64, device=device)
+    h.check(lib().cp_init_uniform(h._h, int(L), C.c_uint64(int(seed) & (2**64 - 1)),
+                                  _ptr(u_out, torch.float64, int(L), "u_out"), _stream()))
+    return u_out
 
 
 def options(**kw):
@@ -324,6 +351,8 @@ def options(**kw):
             v = PREC[v]
         if k == "method" and isinstance(v, str):
             v = {"ngmres": CP_METHOD_NGMRES, "als": CP_METHOD_ALS, "ncg": CP_METHOD_NCG}[v]
+        if k == "init" and isinstance(v, str):
+            v = {"given": CP_INIT_GIVEN, "seeded": CP_INIT_SEEDED}[v]
         setattr(o, k, v)
     return o
 
@@ -332,12 +361,51 @@ class NGMRESState:
     """Stateful N-GMRES iteration (cp_ngmres_create / ngmres_step / cp_ngmres_get)."""
 
     def __init__(self, h: Handle, T: Tensor, R: int, u0, **opts):
+        """u0: device initial guess, or None with init="seeded" and a seed."""
         self.h, self.T, self.R = h, T, R
         self.opt = options(**opts)
         self._s = C.c_void_p()
         h.check(lib().cp_ngmres_create(h._h, C.byref(T.c), int(R), C.byref(self.opt),
                                        _ptr(u0, torch.float64, iterate_length(T.dims, R), "u0"),
                                        _stream(), C.byref(self._s)))
+
+    def save(self, device="cuda"):
+        """Checkpoint: (meta dict, U, G, u, g, d) with U, G the window, oldest first."""
+        L = iterate_length(self.T.dims, self.R)
+        w = max(1, int(self.opt.window))
+        U = torch.empty((w, L), dtype=torch.float64, device=device)
+        G = torch.empty((w, L), dtype=torch.float64, device=device)
+        u, g, d = (torch.empty(L, dtype=torch.float64, device=device) for _ in range(3))
+        meta = cp_ngmres_meta()
+        self.h.check(lib().cp_ngmres_save(self.h._h, self._s, _ptr(U), _ptr(G), _ptr(u), _ptr(g),
+                                          _ptr(d), C.byref(meta)))
+        torch.cuda.synchronize()
+        md = {k: getattr(meta, k) for k, _ in cp_ngmres_meta._fields_}
+        return md, U[:md["m"]].clone(), G[:md["m"]].clone(), u, g, d
+
+    def load(self, meta, U, G, u, g, d=None):
+        """Resume from a checkpoint (or teacher-force the state: window, iterate, gradient)."""
+        m = cp_ngmres_meta()
+        for k, _ in cp_ngmres_meta._fields_:
+            if k in meta:
+                setattr(m, k, meta[k])
+        L = iterate_length(self.T.dims, self.R)
+        nU = 0 if U is None else U.shape[0] * L
+        self.h.check(lib().cp_ngmres_load(self.h._h, self._s, _ptr(U, torch.float64, nU, "U"),
+                                          _ptr(G, torch.float64, nU, "G"),
+                                          _ptr(u, torch.float64, L, "u"),
+                                          _ptr(g, torch.float64, L, "g"),
+                                          _ptr(d, torch.float64, L, "d"), C.byref(m)))
+
+    def last_step(self, device="cuda"):
+        """(u_bar, g_bar, u_hat, d, f_bar, slope) of the last N-GMRES iteration."""
+        L = iterate_length(self.T.dims, self.R)
+        vs = [torch.empty(L, dtype=torch.float64, device=device) for _ in range(4)]
+        fb, sl = C.c_double(), C.c_double()
+        self.h.check(lib().cp_ngmres_last_step(self.h._h, self._s, *[_ptr(v) for v in vs],
+                                               C.byref(fb), C.byref(sl)))
+        torch.cuda.synchronize()
+        return (*vs, fb.value, sl.value)
 
     def step(self):
         info = cp_iter_info()
@@ -401,7 +469,8 @@ def _info_dict(r: cp_iter_info):
 
 
 def cp_decompose(h: Handle, T: Tensor, R: int, tol: float, u_inout, trace_cap=0, **opts):
-    """Run the method; u_inout holds the initial guess and receives the result."""
+    """Run the method; u_inout holds the initial guess and receives the result
+    (None: the seeded guess of opts["seed"], result described by the report only)."""
     o = options(**opts)
     buf = None
     if trace_cap > 0:

@@ -207,6 +207,10 @@ int sub_to(cp_handle* h, const double* a, const double* b, double* y, int64_t n,
 int cg_direction(cp_handle* h, const double* g, double gamma, double* d, int64_t n,
                  hipStream_t st);   // d = -g + gamma d
 
+// u[i] = i-th double of the seeded Philox-4x64-10 stream (key (seed, 0),
+// block b from counter b + 1), in [0, 1)
+int init_uniform(cp_handle* h, int64_t L, uint64_t seed, double* u, hipStream_t st);
+
 // Per-call values of the N-GMRES kernels kept in device memory, so that a
 // captured launch sequence can be replayed with new values: the line-search
 // step and the window's current size and oldest slot.

@@ -29,6 +29,9 @@ struct cp_ngmres_state {
   int n_fg = 0, n_restarts = 0, n_fallback = 0, switch_iter = -1;
   bool stalled = false;   // a line search in reduced precision ended without a Wolfe point
   bool cg_fresh = true;   // N-CG: the next direction is -g (start, switch, failed search)
+  // f(u_bar) and the slope g(u_bar)^T d of the last N-GMRES iteration (Steps I-II)
+  bool have_last = false;
+  double last_fbar = 0.0, last_slope = 0.0;
   // device buffers
   double* mem = nullptr;
   double *u, *g, *ubar, *gbar, *uhat, *d, *ut, *gt, *gbest, *scal;  // scal: 8 doubles
@@ -499,6 +502,32 @@ int eval_current(cp_handle* h, cp_ngmres_state* S) {
   return CP_OK;
 }
 
+// Precision schedule: once rho is small enough (or would stop the run), move
+// the bulk to the final precision, re-evaluate at the current iterate and
+// restart the window.  Triggers: rho <= switch_rho; once rho <= 1e-2, a line
+// search that found no Wolfe point in reduced precision (its objective noise
+// is then comparable to the decrease it looks for); or rho <= stop_tol on a
+// gradient that was not accumulated in float64 (so the stop is certified in
+// float64).  *switched_now tells whether it switched.
+int maybe_switch(cp_handle* h, cp_ngmres_state* S, bool* switched_now) {
+  const cp_options& o = S->opt;
+  *switched_now = false;
+  if (S->switched || S->prec == o.final_precision) return CP_OK;
+  const bool trig = (o.switch_rho > 0.0 && S->rho <= o.switch_rho) ||
+                    (o.switch_rho > 0.0 && o.switch_on_stall && S->stalled && S->rho <= 1e-2) ||
+                    (S->rho <= o.stop_tol && !is_f64_acc(S->prec) && is_f64_acc(o.final_precision));
+  if (!trig) return CP_OK;
+  S->prec = o.final_precision;
+  S->switched = true;
+  S->switch_iter = S->it;
+  *switched_now = true;
+  CP_TRY(eval_current(h, S));
+  S->wcount = 0;
+  S->whead = 0;
+  S->cg_fresh = true;
+  return window_push(h, S);
+}
+
 // One N-CG iteration (comparison method, Section 2.4): line search along d
 // from u, then d = -g + gamma d with the Polak-Ribiere gamma clipped at 0.
 // u is not normalised.  S->ubar holds the line search's base point.
@@ -583,6 +612,9 @@ void cp_options_default(cp_options* o) {
   o->trace_cap = 0;
   o->mttkrp_tree = 1;
   o->switch_on_stall = 1;
+  o->stop_tol = 0.0;
+  o->init = CP_INIT_GIVEN;
+  o->seed = 0;
 }
 
 int cp_create(int device, size_t workspace_bytes, cp_handle** out) {
@@ -789,7 +821,7 @@ int cp_objective_grad(cp_handle* h, const cp_tensor* T, const double* u, int32_t
 
 int ngmres_accelerate(cp_handle* h, int64_t L, int32_t m, const double* U, const double* G,
                       const double* u_bar, const double* g_bar, double eps, double* u_hat_out,
-                      double* alpha_out, hipStream_t st) {
+                      double* gTd_out, double* alpha_out, hipStream_t st) {
   if (!h) return CP_EINVAL;
   CP_HIP(h, hipSetDevice(h->device));
   if (L < 1 || m < 1 || m > 64) return fail(h, CP_EINVAL, "need L >= 1 and 1 <= m <= 64");
@@ -799,7 +831,21 @@ int ngmres_accelerate(cp_handle* h, int64_t L, int32_t m, const double* U, const
   double* alpha = alpha_out ? alpha_out : static_cast<double*>(h->small.ptr) + 4096;
   StepPar* par = reinterpret_cast<StepPar*>(static_cast<double*>(h->small.ptr) + 4096 + 64);
   CP_TRY(set_steppar(h, par, 0.0, m, 0, st));
-  return step2(h, L, U, G, m, par, u_bar, g_bar, eps, u_hat_out, alpha, st);
+  CP_TRY(step2(h, L, U, G, m, par, u_bar, g_bar, eps, u_hat_out, alpha, st));
+  if (gTd_out) {   // g_bar^T (u_hat - u_bar), the difference held in the mbuf slice
+    CP_TRY(ensure(h, h->mbuf, sizeof(double) * (size_t)L, st));
+    double* dv = static_cast<double*>(h->mbuf.ptr);
+    CP_TRY(sub_to(h, u_hat_out, u_bar, dv, L, st));
+    CP_TRY(dot(h, g_bar, dv, L, gTd_out, st));
+  }
+  return CP_OK;
+}
+
+int cp_init_uniform(cp_handle* h, int64_t L, uint64_t seed, double* u_out, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  if (L < 0 || (L > 0 && !u_out)) return fail(h, CP_EINVAL, "need L >= 0 and an output");
+  return init_uniform(h, L, seed, u_out, st);
 }
 
 int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_options* opt,
@@ -810,7 +856,8 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
   Shape s;
   CP_TRY(check_tensor(h, T, &s));
   CP_TRY(check_rank(h, R));
-  if (!u0) return fail(h, CP_EINVAL, "null initial guess");
+  if (!u0 && !(opt && opt->init == CP_INIT_SEEDED))
+    return fail(h, CP_EINVAL, "null initial guess");
   if (T->sparse && !T->prepared) return fail(h, CP_EINVAL, "sparse tensor is not prepared");
   if (!(T->norm_sq > 0.0)) return fail(h, CP_EINVAL, "tensor not prepared or zero (||T|| = 0)");
   cp_options o;
@@ -820,6 +867,8 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
   if (o.method != CP_METHOD_NGMRES && o.method != CP_METHOD_ALS && o.method != CP_METHOD_NCG)
     return fail(h, CP_EINVAL, "unknown method %d", o.method);
   if (o.ls_maxfev < 1 || !(o.ls_stp0 > 0.0)) return fail(h, CP_EINVAL, "bad line-search options");
+  if (o.init != CP_INIT_GIVEN && o.init != CP_INIT_SEEDED)
+    return fail(h, CP_EINVAL, "unknown init %d", o.init);
   CP_TRY(check_prec(h, T, o.precision));
   CP_TRY(check_prec(h, T, o.final_precision));
   auto* S = new (std::nothrow) cp_ngmres_state();
@@ -860,7 +909,9 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
   }
   *S->hpar = StepPar{0.0, 0, 0};
   int rc = CP_OK;
-  if (hipMemcpyAsync(S->u, u0, sizeof(double) * S->L, hipMemcpyDeviceToDevice, st) != hipSuccess)
+  if (o.init == CP_INIT_SEEDED)
+    rc = init_uniform(h, S->L, o.seed, S->u, st);
+  else if (hipMemcpyAsync(S->u, u0, sizeof(double) * S->L, hipMemcpyDeviceToDevice, st) != hipSuccess)
     rc = fail(h, CP_EDEVICE, "copy of the initial guess failed");
   if (rc == CP_OK) rc = normalize(h, s, S->u, R, nullptr, st);
   if (rc == CP_OK) rc = eval_current(h, S);
@@ -897,9 +948,93 @@ int cp_ngmres_get(cp_handle* h, cp_ngmres_state* S, double* u_out, double* g_out
   return CP_OK;
 }
 
+int cp_ngmres_save(cp_handle* h, cp_ngmres_state* S, double* U_out, double* G_out, double* u_out,
+                   double* g_out, double* d_out, cp_ngmres_meta* meta) {
+  if (!h || !S) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  const size_t bytes = sizeof(double) * S->L;
+  const int m = S->opt.method == CP_METHOD_NGMRES ? S->wcount : 0;
+  for (int j = 0; j < m; ++j) {
+    if (U_out) CP_HIP(h, hipMemcpyAsync(U_out + (size_t)j * S->L, win_u(S, j), bytes, hipMemcpyDeviceToDevice, S->st));
+    if (G_out) CP_HIP(h, hipMemcpyAsync(G_out + (size_t)j * S->L, win_g(S, j), bytes, hipMemcpyDeviceToDevice, S->st));
+  }
+  if (u_out) CP_HIP(h, hipMemcpyAsync(u_out, S->u, bytes, hipMemcpyDeviceToDevice, S->st));
+  if (g_out) CP_HIP(h, hipMemcpyAsync(g_out, S->g, bytes, hipMemcpyDeviceToDevice, S->st));
+  if (d_out) CP_HIP(h, hipMemcpyAsync(d_out, S->d, bytes, hipMemcpyDeviceToDevice, S->st));
+  if (meta) {
+    meta->it = S->it;
+    meta->m = m;
+    meta->precision = S->prec;
+    meta->switched = S->switched;
+    meta->stalled = S->stalled;
+    meta->cg_fresh = S->cg_fresh;
+    meta->f = S->f;
+    meta->rho = S->rho;
+    meta->n_fg = S->n_fg;
+    meta->n_restarts = S->n_restarts;
+    meta->n_ls_fallback = S->n_fallback;
+    meta->switch_iter = S->switch_iter;
+  }
+  return CP_OK;
+}
+
+int cp_ngmres_load(cp_handle* h, cp_ngmres_state* S, const double* U, const double* G,
+                   const double* u, const double* g, const double* d, const cp_ngmres_meta* meta) {
+  if (!h || !S || !meta || !u || !g) return fail(h, CP_EINVAL, "null state, iterate or meta");
+  CP_HIP(h, hipSetDevice(h->device));
+  const bool ngm = S->opt.method == CP_METHOD_NGMRES;
+  if (ngm && (meta->m < 1 || meta->m > S->wcap || !U || !G))
+    return fail(h, CP_EINVAL, "window of %d entries (capacity %d) needs U and G", meta->m, S->wcap);
+  if (S->opt.method == CP_METHOD_NCG && !meta->cg_fresh && !d)
+    return fail(h, CP_EINVAL, "an N-CG state needs its direction");
+  if (meta->precision < 0 || meta->precision > 3) return fail(h, CP_EINVAL, "bad precision");
+  CP_TRY(check_prec(h, S->T, meta->precision));
+  const size_t bytes = sizeof(double) * S->L;
+  S->whead = 0;
+  S->wcount = ngm ? meta->m : 0;
+  for (int j = 0; j < S->wcount; ++j)
+    CP_TRY(copy2(h, U + (size_t)j * S->L, win_u(S, j), G + (size_t)j * S->L, win_g(S, j), S->L, S->st));
+  CP_TRY(copy2(h, u, S->u, g, S->g, S->L, S->st));
+  if (d) CP_HIP(h, hipMemcpyAsync(S->d, d, bytes, hipMemcpyDeviceToDevice, S->st));
+  S->it = meta->it;
+  S->prec = meta->precision;
+  S->switched = meta->switched != 0;
+  S->stalled = meta->stalled != 0;
+  S->cg_fresh = meta->cg_fresh != 0;
+  S->f = meta->f;
+  S->n_fg = meta->n_fg;
+  S->n_restarts = meta->n_restarts;
+  S->n_fallback = meta->n_ls_fallback;
+  S->switch_iter = meta->switch_iter;
+  S->have_last = false;
+  CP_TRY(dot(h, S->g, S->g, S->L, S->scal + 3, S->st));
+  double gg;
+  CP_TRY(readback(h, S->scal + 3, 1, &gg, S->st));
+  S->rho = std::sqrt(std::max(0.0, gg)) / S->normT;
+  return CP_OK;
+}
+
+int cp_ngmres_last_step(cp_handle* h, cp_ngmres_state* S, double* u_bar, double* g_bar,
+                        double* u_hat, double* d, double* f_bar, double* slope) {
+  if (!h || !S) return CP_EINVAL;
+  if (!S->have_last || S->opt.method != CP_METHOD_NGMRES)
+    return fail(h, CP_EINVAL, "no N-GMRES iteration taken yet");
+  CP_HIP(h, hipSetDevice(h->device));
+  const size_t bytes = sizeof(double) * S->L;
+  if (u_bar) CP_HIP(h, hipMemcpyAsync(u_bar, S->ubar, bytes, hipMemcpyDeviceToDevice, S->st));
+  if (g_bar) CP_HIP(h, hipMemcpyAsync(g_bar, S->gbar, bytes, hipMemcpyDeviceToDevice, S->st));
+  if (u_hat) CP_HIP(h, hipMemcpyAsync(u_hat, S->uhat, bytes, hipMemcpyDeviceToDevice, S->st));
+  if (d) CP_HIP(h, hipMemcpyAsync(d, S->d, bytes, hipMemcpyDeviceToDevice, S->st));
+  if (f_bar) *f_bar = S->last_fbar;
+  if (slope) *slope = S->last_slope;
+  return CP_OK;
+}
+
 int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
   if (!h || !S) return CP_EINVAL;
   CP_HIP(h, hipSetDevice(h->device));
+  bool sw = false;
+  CP_TRY(maybe_switch(h, S, &sw));
   cp_iter_info rec{};
   rec.it = S->it;
   rec.f = S->f;
@@ -924,6 +1059,9 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
     double fs[2];   // f(u_bar) and the slope g(u_bar)^T d in one readback
     CP_TRY(readback(h, S->scal, 2, fs, S->st));
     const double fbar = fs[0], slope = fs[1];
+    S->have_last = true;
+    S->last_fbar = fbar;
+    S->last_slope = slope;
     const double* gnew = S->gbar;
     double fnew = fbar;
     double beta = 0.0;
@@ -979,8 +1117,9 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
   cp_options o;
   if (opt) o = *opt;
   else cp_options_default(&o);
-  if (!u_inout) return fail(h, CP_EINVAL, "null iterate");
   if (!(tol >= 0.0)) return fail(h, CP_EINVAL, "tol must be >= 0");
+  o.stop_tol = tol;
+  if (!u_inout) o.init = CP_INIT_SEEDED;   // the seeded guess; the report describes the result
   cp_ngmres_state* S = nullptr;
   // The null stream cannot be captured: run on a private stream that first
   // waits for the work the caller queued on it.
@@ -1012,27 +1151,11 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
   int rc = CP_OK;
   int ntr = 0;
   for (;;) {
-    // Precision schedule: once rho is small enough (or would stop the run),
-    // move the bulk to the final precision, re-evaluate and restart the window.
-    // Triggers: rho below switch_rho; once rho <= 1e-2, a line search that
-    // found no Wolfe point in reduced precision (its objective noise is then
-    // comparable to the decrease it looks for); or the stopping test about to
-    // fire on a gradient that was not accumulated in float64.
-    if (!S->switched && S->prec != o.final_precision &&
-        ((o.switch_rho > 0.0 && S->rho <= o.switch_rho) ||
-         (o.switch_rho > 0.0 && o.switch_on_stall && S->stalled && S->rho <= 1e-2) ||
-         (S->rho <= tol && !is_f64_acc(S->prec) && is_f64_acc(o.final_precision)))) {
-      S->prec = o.final_precision;
-      S->switched = true;
-      S->switch_iter = S->it;
-      rc = eval_current(h, S);
-      if (rc < 0) break;
-      S->wcount = 0;
-      S->whead = 0;
-      S->cg_fresh = true;
-      rc = window_push(h, S);
-      if (rc < 0) break;
-    }
+    // the precision schedule before the stopping test (ngmres_step applies
+    // it too; here it also covers the last iterate)
+    bool sw = false;
+    rc = maybe_switch(h, S, &sw);
+    if (rc < 0) break;
     if (S->rho <= tol || S->it >= o.max_iter) {
       if (o.trace && ntr < o.trace_cap) {
         cp_iter_info r{};
@@ -1049,7 +1172,8 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
     if (o.trace && ntr < o.trace_cap) o.trace[ntr++] = info;
   }
   if (rc >= 0) {
-    if (hipMemcpyAsync(u_inout, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+    if ((u_inout && hipMemcpyAsync(u_inout, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice,
+                                   st) != hipSuccess) ||
         hipStreamSynchronize(st) != hipSuccess)
       rc = fail(h, CP_EDEVICE, "copy of the result failed");
   }

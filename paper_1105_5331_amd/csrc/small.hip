@@ -1229,6 +1229,44 @@ __global__ void step2_combine_kernel(WinDesc w, const StepPar* __restrict__ par,
   uhat[x] = ub + s;
 }
 
+// ---- seeded uniform numbers -----------------------------------------------------
+// Philox-4x64 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC 2011): one round
+// maps the counter block (c0, c1, c2, c3) under the key (k0, k1) to
+// (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key
+// advances by the Weyl constants before every round after the first.
+__device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// u[4b + q] = (x_q >> 11) 2^-53 for the cipher x of counter (b + 1, 0, 0, 0)
+// under key (seed, 0): one thread per counter block.
+__global__ void uniform_init_kernel(double* __restrict__ u, int64_t L, uint64_t seed) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b * 4 >= L) return;
+  uint64_t c[4] = {(uint64_t)b + 1, 0, 0, 0};
+  philox4x64_10(c, seed, 0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t e = b * 4 + q;
+    if (e < L) u[e] = (double)(c[q] >> 11) * 0x1.0p-53;
+  }
+}
+
 }  // namespace
 
 // ---- host wrappers -----------------------------------------------------------------
@@ -1436,6 +1474,14 @@ int set_steppar(cp_handle* h, StepPar* p, double beta, int m, int whead, hipStre
 int axpy_par(cp_handle* h, const double* x, const StepPar* par, const double* d, double* y,
              int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(axpy_par_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, x, par, d, y, n);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int init_uniform(cp_handle* h, int64_t L, uint64_t seed, double* u, hipStream_t st) {
+  if (L <= 0) return CP_OK;
+  const int64_t nb4 = (L + 3) / 4;
+  hipLaunchKernelGGL(uniform_init_kernel, dim3(nblk(nb4, 256)), dim3(256), 0, st, u, L, seed);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }

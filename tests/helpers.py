@@ -32,3 +32,30 @@ def assert_close_to_bound(got, ref, bound, tol, what=""):
         i = np.unravel_index(np.argmax(err / lim), err.shape)
         raise AssertionError(f"{what}: {bad.sum()} elements over tolerance; worst at {i}: "
                              f"got {got[i]!r} ref {ref[i]!r} bound {bound[i]!r} tol {tol}")
+
+
+# Per-iterate tolerances on a shared N-GMRES trajectory (float64 on both
+# sides; the rationale -- the oracle's own sensitivity to rounding-level
+# changes, amplified by the regularised normal equations -- is in the
+# docstring of test_gpu_decompose.py):
+F_TOL = 1e-10     # |f_gpu - f_oracle| / (1/2 ||T||^2)
+RHO_REL = 1e-2    # |rho_gpu - rho_oracle| / rho_oracle ...
+RHO_ABS = 1e-9    # ... + this absolute floor
+BETA_REL = 1e-2   # |beta_gpu - beta_oracle| / max(1, |beta_oracle|)
+
+
+def compare_trajectory(trace, ref_trace, half, what):
+    """Compare GPU trace records (dicts) with the oracle's IterRecords until
+    the first discrete divergence; returns the number of iterates compared."""
+    n = 0
+    for a, b in zip(trace, ref_trace):
+        assert abs(a["f"] - b.f) <= F_TOL * half, f"{what} it {b.it}: f {a['f']} vs {b.f}"
+        assert abs(a["rho"] - b.rho) <= RHO_REL * b.rho + RHO_ABS, \
+            f"{what} it {b.it}: rho {a['rho']} vs {b.rho}"
+        n += 1
+        if a["restart"] != b.restart or a["m"] != b.m or a["nfev"] != b.nfev:
+            break
+        if b.nfev:
+            assert abs(a["beta"] - b.beta) <= BETA_REL * max(1.0, abs(b.beta)), \
+                f"{what} it {b.it}: beta {a['beta']} vs {b.beta}"
+    return n

@@ -1,0 +1,254 @@
+"""GPU parity of the boundary's method-level calls against the FP64 oracle,
+through the C ABI: Step II with its slope and the non-positive-definite
+branch, the seeded initial guess, checkpoint/resume of the iteration state,
+the precision schedule of the stateful API, and a teacher-forced iteration
+(the GPU state loaded with the oracle's iterate and window, one ngmres_step,
+every intermediate compared).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import cp as ocp
+from oracle.ngmres import CPProblem, ngmres, ngmres_iteration, step2_accelerate
+from oracle.rng import uniform01
+from workloads import initial_guess, test_problem_1
+
+from helpers import compare_trajectory
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    import paper_1105_5331_amd as cpng
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    with cpng.Handle(0) as handle:
+        yield handle
+
+
+def _cpng():
+    import paper_1105_5331_amd as cpng
+    return cpng
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _host(t):
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("L,m", [(1, 1), (1000, 5), (40000, 20)])
+def test_ngmres_accelerate_slope(h, L, m):
+    """gTd = g_bar^T (u_hat - u_bar) beside u_hat and alpha."""
+    cpng = _cpng()
+    print(f"case ngmres_accelerate slope L={L} m={m}", flush=True)
+    rng = np.random.default_rng(7 * L + m)
+    U, G = rng.standard_normal((m, L)), rng.standard_normal((m, L))
+    ub, gb = rng.standard_normal(L), rng.standard_normal(L)
+    uh, alpha, gtd = cpng.ngmres_accelerate(h, _dev(U), _dev(G), _dev(ub), _dev(gb), 1e-12)
+    ref_u, _ = step2_accelerate(U, G, ub, gb, 1e-12)
+    ref = float(gb @ (ref_u - ub))
+    scale = np.linalg.norm(gb) * np.linalg.norm(ref_u - ub)
+    assert abs(gtd.item() - ref) <= 1e-8 * scale + 1e-300
+
+
+def test_ngmres_accelerate_not_positive_definite(h):
+    """Two equal window gradients and eps = 0: P^T P = [[4, 4], [4, 4]] has a
+    zero second Cholesky pivot, so alpha = 0, u_hat = u_bar and the slope is 0
+    on both sides (the reading for a failed factorisation)."""
+    cpng = _cpng()
+    U = np.array([[0.0, 0.0, 0.0, 0.0], [1.0, 0.0, 0.0, 0.0]])
+    G = np.zeros((2, 4))
+    ub, gb = np.array([5.0, 6.0, 7.0, 8.0]), np.ones(4)
+    info = {}
+    ref_u, ref_a = step2_accelerate(U, G, ub, gb, eps=0.0, info=info)
+    assert info["status"] == "not_pd"
+    uh, alpha, gtd = cpng.ngmres_accelerate(h, _dev(U), _dev(G), _dev(ub), _dev(gb), 0.0)
+    assert np.array_equal(_host(alpha), ref_a) and np.array_equal(_host(uh), ref_u)
+    assert gtd.item() == 0.0
+
+
+@pytest.mark.parametrize("L", [1, 3, 4, 5, 1000, 16387])
+@pytest.mark.parametrize("seed", [0, 10000, 2**63 + 5])
+def test_init_uniform_bit_exact(h, L, seed):
+    """The seeded uniform numbers equal the oracle's Philox-4x64-10 stream
+    bit for bit (integer work: the doubles are exact conversions)."""
+    cpng = _cpng()
+    got = _host(cpng.cp_init_uniform(h, L, seed))
+    assert np.array_equal(got, uniform01(seed, L))
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_seeded_decompose_follows_the_oracle(h, seed):
+    """cp_decompose drawing its own initial guess from a seed follows the
+    oracle's N-GMRES started from the same Philox numbers."""
+    cpng = _cpng()
+    dims, R, tol = (20, 20, 20), 3, 1e-8
+    print(f"case seeded decompose seed={seed}", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=seed)
+    L = sum(dims) * R
+    ref = ngmres(CPProblem(ocp.DenseTensor(p.T), R), uniform01(seed + 10000, L), tol=tol,
+                 max_iter=300)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u = torch.full((L,), np.nan, dtype=torch.float64, device="cuda")
+    out = cpng.cp_decompose(h, Tg, R, tol, u, trace_cap=400, max_iter=300, init="seeded",
+                            seed=seed + 10000)
+    half = 0.5 * np.sum(p.T ** 2)
+    n = compare_trajectory(out["trace"], ref.trace, half, f"seeded {seed}")
+    assert n >= min(len(ref.trace), 5)
+    assert out["converged"] and ref.converged
+    # without an output array the report alone describes the same run
+    rep = cpng.cp_decompose(h, Tg, R, tol, None, max_iter=300, seed=seed + 10000)
+    assert rep["iters"] == out["iters"] and rep["f"] == out["f"] and rep["rho"] == out["rho"]
+
+
+@pytest.mark.parametrize("method", ["ngmres", "ncg"])
+def test_checkpoint_resume_is_bitwise(h, method):
+    """Save a state after 6 iterations, load it into a fresh state, and step
+    both 6 more times: identical records and iterates, bit for bit."""
+    cpng = _cpng()
+    dims, R = (16, 14, 12), 3
+    print(f"case checkpoint resume {method}", flush=True)
+    p = test_problem_1(dims, R, 0.9, 1, 1, seed=5)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u0 = _dev(initial_guess(dims, R, seed=10005))
+    a = cpng.NGMRESState(h, Tg, R, u0, method=method)
+    for _ in range(6):
+        a.step()
+    meta, U, G, u, g, d = a.save()
+    b = cpng.NGMRESState(h, Tg, R, _dev(initial_guess(dims, R, seed=77)), method=method)
+    b.load(meta, U if method == "ngmres" else None, G if method == "ngmres" else None, u, g, d)
+    for k in range(6):
+        ia, ib = a.step(), b.step()
+        for key in ("it", "f", "rho", "nfev", "m", "restart", "ls_status"):
+            assert ia[key] == ib[key], (k, key, ia[key], ib[key])
+    ua, ga, fa, ra = a.get()
+    ub, gb, fb, rb = b.get()
+    assert torch.equal(ua, ub) and torch.equal(ga, gb) and fa == fb and ra == rb
+    a.close()
+    b.close()
+
+
+def test_stateful_schedule_matches_decompose(h):
+    """The precision schedule lives in ngmres_step: stepping the stateful API
+    with stop_tol = tol gives the iterations cp_decompose takes."""
+    cpng = _cpng()
+    dims, R, tol = (30, 30, 30), 4, 1e-8
+    print("case stateful schedule", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=9, dtype=np.float32)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u0 = initial_guess(dims, R, seed=10009)
+    kw = dict(precision="fp32", final_precision="fp32in_fp64acc", switch_rho=1e-5)
+    out = cpng.cp_decompose(h, Tg, R, tol, _dev(u0), trace_cap=500, max_iter=400, **kw)
+    assert out["converged"] and out["switch_iter"] >= 0
+    st = cpng.NGMRESState(h, Tg, R, _dev(u0), stop_tol=tol, **kw)
+    recs = []
+    for _ in range(out["iters"]):
+        recs.append(st.step())
+    _, _, f, rho = st.get()
+    st.close()
+    for a, b in zip(recs, out["trace"]):
+        assert a["f"] == b["f"] and a["rho"] == b["rho"] and a["precision"] == b["precision"]
+        assert a["nfev"] == b["nfev"]
+    # the decompose loop applies the schedule once more before its last stopping
+    # test; stepping past the switch certifies rho in float64 too
+    assert recs[-1]["precision"] == cpng.PREC["fp32in_fp64acc"]
+    assert f == out["f"] or rho <= tol
+
+
+# Teacher forcing: the iterates whose (u_i, window) the GPU state is given.
+# The first problem restarts at iteration 1; the second (congruence 0.9,
+# ill-conditioned) restarts at 4 and 30 and reaches a window of 5; the third
+# is of order 4 (every MTTKRP from the two mode-group partials).
+TF_CASES = [
+    ("20cubed_c05", (20, 20, 20), 3, 0.5, 0, [0, 1, 2, 5, 10, 20]),
+    ("20cubed_c09", (20, 20, 20), 3, 0.9, 0, [4, 8, 30, 100]),
+    ("4way_c05", (9, 11, 8, 10), 3, 0.5, 1, [0, 1, 2, 6, 12]),
+]
+TF_MARGIN = 100.0   # times the oracle's own sensitivity to rounding-level input changes
+TF_FLOOR = 1e-12
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _measures(o, r, half, nt):
+    """Differences of one iteration's results o from the reference r."""
+    m = {"u_bar": _rel(o["u_bar"], r["u_bar"]),
+         "f_bar": abs(o["f_bar"] - r["f_bar"]) / half,
+         "g_bar": np.linalg.norm(o["g_bar"] - r["g_bar"]) / nt,
+         "d": _rel(o["d"], r["d"]),
+         "u_hat": _rel(o["u_hat"], r["u_hat"]),
+         "slope": abs(o["slope"] - r["slope"]) / max(abs(r["slope"]), 1e-300),
+         "u_next": _rel(o["u_next"], r["u_next"]),
+         "f_next": abs(o["f_next"] - r["f_next"]) / half,
+         "g_next": np.linalg.norm(o["g_next"] - r["g_next"]) / nt}
+    if not r["restart"]:
+        m["beta"] = abs(o["beta"] - r["beta"]) / max(1.0, abs(r["beta"]))
+    return m
+
+
+@pytest.mark.parametrize("name,dims,R,c,seed,its", TF_CASES, ids=[c[0] for c in TF_CASES])
+def test_teacher_forced_iteration(h, name, dims, R, c, seed, its):
+    """For chosen iterates i of the oracle's run, the GPU state is loaded with
+    the oracle's u_i, g_i, f_i and window; one ngmres_step must reproduce the
+    oracle's u_bar, f(u_bar), g(u_bar), the normalised u_hat, d, the slope,
+    the restart decision, the number of line-search evaluations, beta and the
+    next iterate.  Tolerance per quantity: TF_MARGIN times the largest change
+    that rounding-level (1e-15 relative) perturbations of the same inputs
+    cause in the oracle's own iteration, at least TF_FLOOR.  The Step II
+    normal equations have condition numbers up to 1/eps = 1e12, so d, the
+    slope and beta are the sensitive quantities there."""
+    cpng = _cpng()
+    p = test_problem_1(dims, R, c, 1, 1, seed=seed)
+    prob = CPProblem(ocp.DenseTensor(p.T), R)
+    rec = []
+    ngmres(prob, initial_guess(dims, R, seed=seed + 10000), tol=1e-8, max_iter=max(its) + 1,
+           record=rec)
+    half = 0.5 * np.sum(p.T ** 2)
+    nt = np.sqrt(2 * half)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    st = cpng.NGMRESState(h, Tg, R, _dev(rec[0]["u"]))
+    rng = np.random.default_rng(seed)
+    seen_restart = False
+    for i in its:
+        r = rec[i]
+        print(f"case teacher-forced {name} it={i} m={len(r['U'])} restart={r['restart']}",
+              flush=True)
+        sens = {}
+        for _ in range(3):
+            pert = lambda x: x * (1.0 + 1e-15 * rng.standard_normal(np.shape(x)))
+            o = ngmres_iteration(prob, pert(r["u"]), r["f"], pert(r["g"]), pert(r["U"]),
+                                 pert(r["G"]))
+            assert o["restart"] == r["restart"] and o["nfev"] == r["nfev"]
+            for k, v in _measures(o, r, half, nt).items():
+                sens[k] = max(sens.get(k, 0.0), v)
+        meta = {"it": i, "m": len(r["U"]), "precision": 0, "f": r["f"], "cg_fresh": 1,
+                "switch_iter": -1}
+        st.load(meta, _dev(r["U"]), _dev(r["G"]), _dev(r["u"]), _dev(r["g"]))
+        info = st.step()
+        ub, gb, uh, d, fb, slope = st.last_step()
+        un, gn, fn, _ = st.get()
+        got = {"u_bar": _host(ub), "g_bar": _host(gb), "u_hat": _host(uh), "d": _host(d),
+               "f_bar": fb, "slope": slope, "beta": info["beta"], "u_next": _host(un),
+               "g_next": _host(gn), "f_next": fn, "restart": info["restart"]}
+        assert info["restart"] == r["restart"], f"it {i}: restart"
+        assert info["nfev"] == r["nfev"], f"it {i}: nfev {info['nfev']} vs {r['nfev']}"
+        assert info["m"] == len(r["U"])
+        for k, v in _measures(got, r, half, nt).items():
+            lim = max(TF_MARGIN * sens[k], TF_FLOOR)
+            assert v <= lim, f"it {i}: {k} differs by {v:.3e} (limit {lim:.3e})"
+        seen_restart |= r["restart"]
+    st.close()
+    assert seen_restart

@@ -28,11 +28,7 @@ from workloads import initial_guess, test_problem_1, test_problem_2
 
 pytestmark = pytest.mark.gpu
 
-# Per-iterate tolerances on a shared trajectory (float64 on both sides):
-F_TOL = 1e-10     # |f_gpu - f_oracle| / (1/2 ||T||^2)
-RHO_REL = 1e-2    # |rho_gpu - rho_oracle| / rho_oracle ...
-RHO_ABS = 1e-9    # ... + this absolute floor
-BETA_REL = 1e-2   # |beta_gpu - beta_oracle| / max(1, |beta_oracle|)
+from helpers import BETA_REL, F_TOL, RHO_ABS, RHO_REL, compare_trajectory as _compare  # noqa: E402,F401
 
 
 @pytest.fixture(scope="module")
@@ -44,21 +40,6 @@ def h():
 
 def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
-
-
-def _compare(trace, ref_trace, half, what):
-    n = 0
-    for a, b in zip(trace, ref_trace):
-        assert abs(a["f"] - b.f) <= F_TOL * half, f"{what} it {b.it}: f {a['f']} vs {b.f}"
-        assert abs(a["rho"] - b.rho) <= RHO_REL * b.rho + RHO_ABS, \
-            f"{what} it {b.it}: rho {a['rho']} vs {b.rho}"
-        n += 1
-        if a["restart"] != b.restart or a["m"] != b.m or a["nfev"] != b.nfev:
-            break
-        if b.nfev:
-            assert abs(a["beta"] - b.beta) <= BETA_REL * max(1.0, abs(b.beta)), \
-                f"{what} it {b.it}: beta {a['beta']} vs {b.beta}"
-    return n
 
 
 @pytest.mark.parametrize("seed,tree", [(0, 1), (1, 1), (2, 1), (0, 0)])

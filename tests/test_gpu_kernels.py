@@ -337,7 +337,7 @@ def test_ngmres_accelerate_parity(h, L, m):
     G = rng.standard_normal((m, L))
     ub = rng.standard_normal(L)
     gb = rng.standard_normal(L)
-    uh, alpha = cpng.ngmres_accelerate(h, _dev(U), _dev(G), _dev(ub), _dev(gb), 1e-12)
+    uh, alpha, _ = cpng.ngmres_accelerate(h, _dev(U), _dev(G), _dev(ub), _dev(gb), 1e-12)
     ref_u, ref_a = step2_accelerate(U, G, ub, gb, 1e-12)
     np.testing.assert_allclose(alpha.cpu().numpy(), ref_a, rtol=1e-8, atol=1e-10)
     np.testing.assert_allclose(uh.cpu().numpy(), ref_u, rtol=1e-8, atol=1e-10)
@@ -347,7 +347,7 @@ def test_ngmres_accelerate_zero_differences(h):
     cpng = _cpng()
     L = 50
     g = np.ones(L)
-    uh, alpha = cpng.ngmres_accelerate(h, _dev(np.zeros((2, L))), _dev(np.stack([g, g])),
+    uh, alpha, _ = cpng.ngmres_accelerate(h, _dev(np.zeros((2, L))), _dev(np.stack([g, g])),
                                        _dev(np.arange(L, dtype=float)), _dev(g))
     assert np.all(alpha.cpu().numpy() == 0.0)
     np.testing.assert_array_equal(uh.cpu().numpy(), np.arange(L, dtype=float))
