@@ -230,17 +230,29 @@ def mode_solve(M, Gbar):
 # ------------------------------------------------------- tensor wrappers ---
 
 class DenseTensor:
-    """Dense data tensor (float64 view of the given array)."""
+    """Dense data tensor (float64 view of the given array).
 
-    def __init__(self, T):
+    objective="direct" (default) evaluates f by the residual; "identity" by
+    the expansion through the last mode's MTTKRP and Gamma, the form a fast
+    path uses (used to gauge how much the choice of formula alone moves a
+    result near convergence).
+    """
+
+    def __init__(self, T, objective="direct"):
         self.T = np.asarray(T, dtype=np.float64)
         self.dims = self.T.shape
         self.norm2 = float(np.sum(self.T * self.T))
+        if objective not in ("direct", "identity"):
+            raise ValueError(objective)
+        self.form = objective
 
     def mttkrp(self, factors, n):
         return mttkrp(self.T, factors, n)
 
     def objective(self, factors, Ms=None):
+        if self.form == "identity" and Ms is not None:
+            n = len(self.dims) - 1
+            return objective_identity(self.norm2, factors, Ms[n], n)
         return objective_direct(self.T, factors)
 
 

@@ -208,10 +208,19 @@ def test_teacher_forced_iteration(h, name, dims, R, c, seed, its):
     that rounding-level (1e-15 relative) perturbations of the same inputs
     cause in the oracle's own iteration, at least TF_FLOOR.  The Step II
     normal equations have condition numbers up to 1/eps = 1e12, so d, the
-    slope and beta are the sensitive quantities there."""
+    slope and beta are the sensitive quantities there.  The calibration also
+    runs the oracle's iteration once with the objective evaluated through the
+    MTTKRP identity (the GPU's form) instead of the residual: near
+    convergence the line search works on objective differences close to
+    rounding, and the formula alone can move beta by 1e-2 (20^3, c = 0.9,
+    iteration 100, rho ~ 1e-6).  Where any calibration run takes another
+    number of line-search evaluations or another restart decision, Step III
+    is decided by rounding: only Steps I-II are compared, and the GPU's next
+    iterate must be a valid outcome (f not above f(u_bar))."""
     cpng = _cpng()
     p = test_problem_1(dims, R, c, 1, 1, seed=seed)
     prob = CPProblem(ocp.DenseTensor(p.T), R)
+    prob_id = CPProblem(ocp.DenseTensor(p.T, objective="identity"), R)
     rec = []
     ngmres(prob, initial_guess(dims, R, seed=seed + 10000), tol=1e-8, max_iter=max(its) + 1,
            record=rec)
@@ -227,11 +236,13 @@ def test_teacher_forced_iteration(h, name, dims, R, c, seed, its):
         print(f"case teacher-forced {name} it={i} m={len(r['U'])} restart={r['restart']}",
               flush=True)
         sens = {}
-        for _ in range(3):
-            pert = lambda x: x * (1.0 + 1e-15 * rng.standard_normal(np.shape(x)))
-            o = ngmres_iteration(prob, pert(r["u"]), r["f"], pert(r["g"]), pert(r["U"]),
-                                 pert(r["G"]))
-            assert o["restart"] == r["restart"] and o["nfev"] == r["nfev"]
+        stable = True
+        for trial in range(4):
+            pert = (lambda x: x) if trial == 3 else \
+                (lambda x: x * (1.0 + 1e-15 * rng.standard_normal(np.shape(x))))
+            o = ngmres_iteration(prob_id if trial == 3 else prob, pert(r["u"]), r["f"],
+                                 pert(r["g"]), pert(r["U"]), pert(r["G"]))
+            stable &= o["restart"] == r["restart"] and o["nfev"] == r["nfev"]
             for k, v in _measures(o, r, half, nt).items():
                 sens[k] = max(sens.get(k, 0.0), v)
         meta = {"it": i, "m": len(r["U"]), "precision": 0, "f": r["f"], "cg_fresh": 1,
@@ -244,9 +255,15 @@ def test_teacher_forced_iteration(h, name, dims, R, c, seed, its):
                "f_bar": fb, "slope": slope, "beta": info["beta"], "u_next": _host(un),
                "g_next": _host(gn), "f_next": fn, "restart": info["restart"]}
         assert info["restart"] == r["restart"], f"it {i}: restart"
-        assert info["nfev"] == r["nfev"], f"it {i}: nfev {info['nfev']} vs {r['nfev']}"
         assert info["m"] == len(r["U"])
+        step3 = ("beta", "u_next", "f_next", "g_next")
+        if stable:
+            assert info["nfev"] == r["nfev"], f"it {i}: nfev {info['nfev']} vs {r['nfev']}"
+        else:
+            assert got["f_next"] <= r["f_bar"] + 1e-14 * half
         for k, v in _measures(got, r, half, nt).items():
+            if not stable and k in step3:
+                continue
             lim = max(TF_MARGIN * sens[k], TF_FLOOR)
             assert v <= lim, f"it {i}: {k} differs by {v:.3e} (limit {lim:.3e})"
         seen_restart |= r["restart"]
