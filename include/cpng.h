@@ -218,6 +218,28 @@ int cp_tensor_release(cp_handle* h, cp_tensor* T);
 int cp_mttkrp(cp_handle* h, const cp_tensor* T, const double* u, int32_t R, int32_t mode,
               int32_t p, double* M_out, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * MTTKRP as cp_mttkrp, same kernels, same arguments and bitwise the same
+ * M_out, but every workspace slice comes from a static array of 64 MiB per
+ * device that is part of the library (placed when the library is loaded on
+ * a device, held until the process ends; its device address is looked up by
+ * cp_create).  The call itself makes no hipMalloc, hipFree, hipHostMalloc or
+ * other allocating call and creates no timing events (cp_profile does not
+ * time it).  T's arrays, u and M_out stay the caller's; a sparse T must be
+ * prepared beforehand (cp_tensor_prepare allocates).  Every call on a device
+ * shares that device's array: calls on the same stream are ordered, calls
+ * that overlap on one device (other streams, other host threads) race and
+ * give wrong results.  The array keeps the last call's contents; every slice
+ * is written before it is read, so nothing needs clearing.
+ * Errors: those of cp_mttkrp; CP_ENOMEM (with the sizes in cp_last_error)
+ * when the call's workspace would exceed the array -- the check runs before
+ * each slice's first kernel, so nothing past the array is written, and
+ * M_out is then unspecified; CP_EDEVICE when the array's address could not
+ * be looked up on this device. */
+int cp_mttkrp_noalloc(cp_handle* h, const cp_tensor* T, const double* u, int32_t R,
+                      int32_t mode, int32_t p, double* M_out, hipStream_t stream);
+
 /* Grams and their Hadamard products (Section 2.3): S^(k) = A^(k)^T A^(k)
  * for all k (S_out: N x R x R), Gammabar^(n) = Hadamard product of S^(k)
  * over k != n (gamma_bar_out: N x R x R, nullable), Gamma = Hadamard product

@@ -104,6 +104,7 @@ def lib():
             "cp_tensor_prepare": (C.c_int, [vp, C.POINTER(cp_tensor), vp]),
             "cp_tensor_release": (C.c_int, [vp, C.POINTER(cp_tensor)]),
             "cp_mttkrp": (C.c_int, [vp, C.POINTER(cp_tensor), vp, i32, i32, i32, vp, vp]),
+            "cp_mttkrp_noalloc": (C.c_int, [vp, C.POINTER(cp_tensor), vp, i32, i32, i32, vp, vp]),
             "cp_gram": (C.c_int, [vp, i32, C.POINTER(i64), vp, i32, vp, vp, vp, vp]),
             "cp_normalize": (C.c_int, [vp, i32, C.POINTER(i64), vp, i32, vp, vp]),
             "cp_als_sweep": (C.c_int, [vp, C.POINTER(cp_tensor), vp, i32, i32, i32, vp]),
@@ -259,6 +260,21 @@ def cp_mttkrp(h: Handle, T: Tensor, u, R: int, mode: int, prec="fp64", M_out=Non
     h.check(lib().cp_mttkrp(h._h, C.byref(T.c), _ptr(u, torch.float64, iterate_length(T.dims, R), "u"),
                             int(R), int(mode), p, _ptr(M_out, torch.float64, rows * R, "M_out"),
                             _stream()))
+    return M_out
+
+
+def cp_mttkrp_noalloc(h: Handle, T: Tensor, u, R: int, mode: int, prec="fp64", M_out=None):
+    """cp_mttkrp with the library's static scratch as workspace (no device
+    allocation inside the call).  With M_out given, the binding allocates
+    nothing either."""
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    rows = T.dims[mode] if 0 <= mode < len(T.dims) else 1
+    if M_out is None:
+        M_out = torch.empty((rows, max(int(R), 1)), dtype=torch.float64, device=u.device)
+    h.check(lib().cp_mttkrp_noalloc(h._h, C.byref(T.c),
+                                    _ptr(u, torch.float64, iterate_length(T.dims, R), "u"),
+                                    int(R), int(mode), p,
+                                    _ptr(M_out, torch.float64, rows * R, "M_out"), _stream()))
     return M_out
 
 

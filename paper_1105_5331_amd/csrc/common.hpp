@@ -61,6 +61,14 @@ struct cp_handle {
   double prof_ms[4] = {0.0, 0.0, 0.0, 0.0};
   // passes over a tensor's values made by MTTKRP launches (always counted)
   int64_t t_passes = 0;
+  // Allocation-free calls (cp_mttkrp_noalloc): while `arena` is set, ensure()
+  // hands out consecutive 256-byte-aligned slices of it instead of allocating.
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  // device address of this device's static scratch array (looked up by
+  // cp_create), or null with the lookup's error code in scratch_err
+  void* scratch = nullptr;
+  int scratch_err = 0;
 };
 
 namespace cpng {

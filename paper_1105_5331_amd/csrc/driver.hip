@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 using namespace cpng;
@@ -77,6 +78,17 @@ int check_tensor(cp_handle* h, const cp_tensor* T, Shape* s) {
   return CP_OK;
 }
 
+int check_mttkrp_args(cp_handle* h, const cp_tensor* T, const double* u, int R, int mode, int p,
+                      const double* M_out, Shape* s) {
+  CP_TRY(check_tensor(h, T, s));
+  if (R < 1) return fail(h, CP_EINVAL, "rank %d < 1", R);
+  if (mode < 0 || mode >= s->N) return fail(h, CP_EINVAL, "mode %d outside 0..%d", mode, s->N - 1);
+  if (!u || !M_out) return fail(h, CP_EINVAL, "null factor or output pointer");
+  CP_TRY(check_prec(h, T, p));
+  if (T->sparse && R > 64) return fail(h, CP_EINVAL, "sparse MTTKRP supports R <= 64");
+  return CP_OK;
+}
+
 int check_rank(cp_handle* h, int R) {
   if (R < 1 || R > 64) return fail(h, CP_EINVAL, "rank %d outside 1..64", R);
   return CP_OK;
@@ -97,7 +109,7 @@ struct Scratch {
   double* dot;    // 4 doubles
 };
 
-int scratch(cp_handle* h, const Shape& s, int R, hipStream_t st, Scratch* sc) {
+int mode_buffers(cp_handle* h, const Shape& s, int R, hipStream_t st, Scratch* sc) {
   const size_t L = (size_t)s.sum_dims() * R;
   const size_t need = L + (size_t)(2 * s.N * R * R + R * R + 8);
   CP_TRY(ensure(h, h->mbuf, sizeof(double) * need, st));
@@ -149,7 +161,7 @@ int mode_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double* 
 int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
                         int prec, double* f_out, double* g_out, hipStream_t st, bool tree = true) {
   Scratch sc;
-  CP_TRY(scratch(h, s, R, st, &sc));
+  CP_TRY(mode_buffers(h, s, R, st, &sc));
   CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, sc.Gam, st));
   TreeBufs tb;
   CP_TRY(tree_setup(h, T, s, R, prec, tree, st, &tb));
@@ -193,7 +205,7 @@ int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const 
 int als_sweep_impl(cp_handle* h, const cp_tensor* T, const Shape& s, double* u, int R, int prec,
                    int normalize_after, hipStream_t st, bool tree = true) {
   Scratch sc;
-  CP_TRY(scratch(h, s, R, st, &sc));
+  CP_TRY(mode_buffers(h, s, R, st, &sc));
   TreeBufs tb;
   CP_TRY(tree_setup(h, T, s, R, prec, tree, st, &tb));
   if (tb.XL) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, true, tb.XL, st));
@@ -588,6 +600,51 @@ int ncg_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* rec, int* rc_out) {
 }  // namespace
 
 // ============================== C ABI =====================================
+// ---- workspace of the allocation-free MTTKRP ------------------------------
+// One array per device, part of the library's code object: the loader places
+// it when the library is loaded on a device, so cp_mttkrp_noalloc never
+// allocates.  Its size bounds the workspace of one call (a 128^4, R = 32
+// BF16x3 MTTKRP takes about 19 MB of it).  Host code never passes `scratch`
+// itself to a kernel (on the host that name is not a device address); it
+// uses the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+int g_scratch_err[kMaxDevices];
+
+// Called by cp_create with h->device current: looks the array's device
+// address up once per device and records it (or the failure) in the handle.
+void scratch_setup(cp_handle* h) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  const int d = h->device;
+  if (d < 0 || d >= kMaxDevices) {
+    h->scratch = nullptr;
+    h->scratch_err = (int)hipErrorInvalidDevice;
+    return;
+  }
+  if (!g_scratch_done[d]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();   // do not leave the error for the next call to report
+      p = nullptr;
+    }
+    g_scratch_ptr[d] = p;
+    g_scratch_err[d] = (int)e;
+    g_scratch_done[d] = true;
+  }
+  h->scratch = g_scratch_ptr[d];
+  h->scratch_err = g_scratch_err[d];
+}
+
+}  // namespace
+
 extern "C" {
 
 void cp_options_default(cp_options* o) {
@@ -632,6 +689,7 @@ int cp_create(int device, size_t workspace_bytes, cp_handle** out) {
     return CP_ENOMEM;
   }
   (void)hipMemset(h->flags, 0, 16 * sizeof(int));
+  scratch_setup(h);
   if (workspace_bytes > 0 && ensure(h, h->part, workspace_bytes, nullptr) != CP_OK) {
     cp_destroy(h);
     return CP_ENOMEM;
@@ -745,13 +803,45 @@ int cp_mttkrp(cp_handle* h, const cp_tensor* T, const double* u, int32_t R, int3
   if (!h) return CP_EINVAL;
   CP_HIP(h, hipSetDevice(h->device));
   Shape s;
-  CP_TRY(check_tensor(h, T, &s));
-  if (R < 1) return fail(h, CP_EINVAL, "rank %d < 1", R);
-  if (mode < 0 || mode >= s.N) return fail(h, CP_EINVAL, "mode %d outside 0..%d", mode, s.N - 1);
-  if (!u || !M_out) return fail(h, CP_EINVAL, "null factor or output pointer");
-  CP_TRY(check_prec(h, T, p));
-  if (T->sparse && R > 64) return fail(h, CP_EINVAL, "sparse MTTKRP supports R <= 64");
+  CP_TRY(check_mttkrp_args(h, T, u, R, mode, p, M_out, &s));
   return mttkrp_any(h, T, s, u, R, mode, p, M_out, st);
+}
+
+int cp_mttkrp_noalloc(cp_handle* h, const cp_tensor* T, const double* u, int32_t R, int32_t mode,
+                      int32_t p, double* M_out, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  if (!h->scratch)
+    return fail(h, CP_EDEVICE, "static scratch of device %d unavailable: %s", h->device,
+                hipGetErrorString((hipError_t)h->scratch_err));
+  Shape s;
+  CP_TRY(check_mttkrp_args(h, T, u, R, mode, p, M_out, &s));
+  // The same launches as cp_mttkrp, with every workspace slice carved from
+  // the static scratch (ensure() in arena mode) instead of the handle's
+  // grown buffers, which are set aside and restored untouched.  Each slice
+  // is written before it is read, so nothing needs clearing; timing (which
+  // creates events) is off for the call.
+  DevBuf* bufs[] = {&h->part, &h->part2, &h->stage, &h->mbuf, &h->small, &h->red,
+                    &h->carry, &h->otab, &h->ybuf};
+  constexpr int nb = sizeof(bufs) / sizeof(bufs[0]);
+  DevBuf saved[nb];
+  for (int i = 0; i < nb; ++i) {
+    saved[i] = *bufs[i];
+    *bufs[i] = DevBuf{};
+  }
+  const bool prof = h->prof;
+  const uint64_t gen = h->gen;
+  h->prof = false;
+  h->arena = static_cast<char*>(h->scratch);
+  h->arena_cap = kScratchBytes;
+  h->arena_used = 0;
+  const int rc = mttkrp_any(h, T, s, u, R, mode, p, M_out, st);
+  h->arena = nullptr;
+  h->arena_cap = h->arena_used = 0;
+  h->prof = prof;
+  h->gen = gen;
+  for (int i = 0; i < nb; ++i) *bufs[i] = saved[i];
+  return rc;
 }
 
 int cp_gram(cp_handle* h, int32_t order, const int64_t* dims, const double* u, int32_t R,

@@ -22,6 +22,17 @@ int fail(cp_handle* h, int code, const char* fmt, ...) {
 
 int ensure(cp_handle* h, DevBuf& b, size_t bytes, hipStream_t stream) {
   if (bytes <= b.bytes) return CP_OK;
+  if (h->arena) {   // allocation-free call: the next slice of the static scratch
+    const size_t off = (h->arena_used + 255) & ~size_t(255);
+    if (off > h->arena_cap || bytes > h->arena_cap - off)
+      return fail(h, CP_ENOMEM,
+                  "this call needs more workspace than the %zu-byte static scratch "
+                  "(%zu bytes used, %zu more requested)", h->arena_cap, h->arena_used, bytes);
+    b.ptr = h->arena + off;
+    b.bytes = bytes;
+    h->arena_used = off + bytes;
+    return CP_OK;
+  }
   size_t want = std::max(bytes, b.bytes + b.bytes / 2);
   want = (want + 4095) & ~size_t(4095);
   if (b.ptr) {
