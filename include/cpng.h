@@ -419,19 +419,22 @@ int cp_server_destroy(cp_server* s);
 /* ---- kernel timing ------------------------------------------------------ */
 
 /* Kernel ids for cp_profile_read. */
-#define CP_KERNEL_DENSE_MTTKRP  0   /* main dense MTTKRP kernel (any precision) */
+#define CP_KERNEL_DENSE_MTTKRP  0   /* main dense MTTKRP kernel, float32-accumulating
+                                       precisions (CP_PREC_FP32, CP_PREC_BF16X3) */
 #define CP_KERNEL_SPARSE_MTTKRP 1   /* main sparse segmented-reduction kernel */
 #define CP_KERNEL_STREAM_READ   2   /* cp_stream_read */
 #define CP_KERNEL_GROUP_MTTKRP  3   /* second level of the two-level evaluation: one mode's
                                        MTTKRP from its group's partial contraction */
+#define CP_KERNEL_DENSE_MTTKRP_F64 4 /* main dense MTTKRP kernel, float64-accumulating
+                                       precisions (CP_PREC_FP64, CP_PREC_FP32IN_FP64ACC) */
 
 /* Enable (1) or disable (0) HIP-event timing of the main MTTKRP kernels on
  * the stream each is launched on; enabling clears the counters. */
 int cp_profile(cp_handle* h, int32_t enable);
 /* Which kernel ids cp_profile times: bit k of kernel_mask selects id k
- * (default 0xF, all four).  Each timed launch adds two event records to its
+ * (default 0x1F, all five).  Each timed launch adds two event records to its
  * stream, so timing only the kernel being measured keeps the others' launch
- * gaps out of a timed run.  CP_EINVAL for bits above 3. */
+ * gaps out of a timed run.  CP_EINVAL for bits above 4. */
 int cp_profile_select(cp_handle* h, uint32_t kernel_mask);
 /* Synchronise the recorded events and return, for kernel id `kernel`, the
  * number of timed launches and their summed duration in milliseconds

@@ -429,6 +429,12 @@ class NGMRESState:
                           allow=(CP_OK, CP_LS_FALLBACK))
         return _info_dict(info) | {"rc": rc}
 
+    def scalars(self):
+        """(f, rho) of the current iterate (no device copies)."""
+        f, rho = C.c_double(), C.c_double()
+        self.h.check(lib().cp_ngmres_get(self.h._h, self._s, None, None, C.byref(f), C.byref(rho)))
+        return f.value, rho.value
+
     def get(self, device="cuda"):
         L = iterate_length(self.T.dims, self.R)
         u = torch.empty(L, dtype=torch.float64, device=device)
@@ -451,6 +457,7 @@ class NGMRESState:
 
 
 CP_KERNEL_DENSE_MTTKRP, CP_KERNEL_SPARSE_MTTKRP, CP_KERNEL_STREAM_READ, CP_KERNEL_GROUP_MTTKRP = 0, 1, 2, 3
+CP_KERNEL_DENSE_MTTKRP_F64 = 4
 
 
 def cp_stream_read(h: Handle, buf):

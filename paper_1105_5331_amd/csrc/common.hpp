@@ -55,10 +55,11 @@ struct cp_handle {
   int* flags = nullptr;       // device status word (ALS solve fallbacks)
   // optional event timing of the main MTTKRP kernels
   bool prof = false;
-  uint32_t prof_mask = 0xFu;   // kernel ids timed while prof is on
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[4];
-  int64_t prof_launches[4] = {0, 0, 0, 0};
-  double prof_ms[4] = {0.0, 0.0, 0.0, 0.0};
+  static constexpr int kKernelIds = 5;
+  uint32_t prof_mask = 0x1Fu;   // kernel ids timed while prof is on
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[kKernelIds];
+  int64_t prof_launches[kKernelIds] = {0, 0, 0, 0, 0};
+  double prof_ms[kKernelIds] = {0.0, 0.0, 0.0, 0.0, 0.0};
   // passes over a tensor's values made by MTTKRP launches (always counted)
   int64_t t_passes = 0;
   // Allocation-free calls (cp_mttkrp_noalloc): while `arena` is set, ensure()
@@ -120,6 +121,12 @@ struct Shape {
 
 int make_shape(cp_handle* h, int order, const int64_t* dims, Shape* s);
 
+// Timing id of a dense MTTKRP kernel by its accumulation type.
+template <typename CT>
+constexpr int dense_kernel_id() {
+  return sizeof(CT) == 8 ? CP_KERNEL_DENSE_MTTKRP_F64 : CP_KERNEL_DENSE_MTTKRP;
+}
+
 // Event timing of a main kernel launch (no-op unless h->prof selects id):
 // the timer holds a pair of events that CP_TIMED_LAUNCH hands to the launch
 // itself (hipExtLaunchKernelGGL records the kernel's own start and end, with
@@ -166,6 +173,10 @@ int sparse_release(cp_handle* h, cp_tensor* T);
 int stage_factors_f32(cp_handle* h, const double* u, int64_t L, float** out, hipStream_t st);
 int dense_fast_bf16x3(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
                       int mode, double* M, hipStream_t st);
+int dense_fast_mfma_f32(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
+                        int mode, double* M, hipStream_t st);
+int dense_fast_mfma_f64acc(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
+                           int mode, double* M, hipStream_t st);
 template <typename TT, typename CT>
 int dense_fast_vec(cp_handle* h, const TT* T, const CT* fac, const Shape& s, int R, int mode,
                    double* M, hipStream_t st);

@@ -40,7 +40,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThr = 256;
-constexpr int kMaxInner = 512;
 
 // Tuning knobs (compile-time): workgroups per launch of the streaming
 // kernels, and how many (outer index, k-step) operands each lane keeps in
@@ -84,22 +83,147 @@ __device__ inline void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
   }
 }
 
-// Stage the inner factor, columns r0..r0+31: S[r][k] = A^(q)(k, r0 + r) split,
-// zero for r >= R and for k in [K, 32 * nks).
+// ---- operand flavours of the streaming kernels ------------------------------
+// For one 16x16 tile and one 32-wide k-step every lane holds the eight
+// values k = 8g..8g+7 (g = lane / 16) of its tensor row (or column) and of its
+// factor column; a flavour multiplies the two lane sets on the matrix cores
+// and adds into the tile.  Any fixed grouping of the k's is a valid order of
+// the sum, so the three flavours share the data movement:
+//  * FlavBF16x3: each operand split into bf16 hi + lo, hi*hi + hi*lo + lo*hi
+//    with one v_mfma_f32_16x16x32_bf16 each (float32 accumulation);
+//  * FlavF32: float32 operands, eight v_mfma_f32_16x16x4_f32 (value j of every
+//    lane in the j-th), float32 accumulation;
+//  * FlavF64: the float32 tensor values widened exactly to float64, float64
+//    factors, eight v_mfma_f64_16x16x4_f64 (float64 products and sums).
+// The inner factor is staged in LDS as [r][kpad] in the flavour's form.
+// Operand layouts are the same for all three (lane l: row or column l % 16,
+// k group l / 16); the result tile's rows differ (drow).
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+struct FlavBF16x3 {
+  using S = float;     // outer scales, accumulators, per-workgroup partial sums
+  using V = floatx4;   // one MFMA tile: 4 values per lane
+  using Src = float;   // factor values staged (the float32 copy)
+  static constexpr int kMaxK = 512;
+  static constexpr int kFacBytes = 2 * sizeof(__bf16);   // LDS bytes per staged value
+  // row of the 16x16 tile held by result value q of lane group g (lane / 16)
+  __device__ static int drow(int g, int q) { return 4 * g + q; }
+  struct Op {
+    bf16x8 h, l;
+  };
+  __device__ static Op from_t(const float (&v)[8]) {
+    Op o;
+    split8(v, o.h, o.l);
+    return o;
+  }
+  __device__ static Op from_lds(const unsigned char* lds, int kpad, int off) {
+    const __bf16* Sh = reinterpret_cast<const __bf16*>(lds);
+    return Op{*reinterpret_cast<const bf16x8*>(Sh + off),
+              *reinterpret_cast<const bf16x8*>(Sh + 32 * kpad + off)};
+  }
+  __device__ static void put(unsigned char* lds, int kpad, int r, int k, float v) {
+    __bf16* Sh = reinterpret_cast<__bf16*>(lds);
+    const __bf16 h = (__bf16)v;
+    Sh[r * kpad + k] = h;
+    Sh[32 * kpad + r * kpad + k] = (__bf16)(v - (float)h);
+  }
+  __device__ static V mma(const Op& a, const Op& b, V c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, c, 0, 0, 0);
+    return c;
+  }
+};
+
+struct FlavF32 {
+  using S = float;
+  using V = floatx4;
+  using Src = float;
+  static constexpr int kMaxK = 512;
+  static constexpr int kFacBytes = sizeof(float);
+  __device__ static int drow(int g, int q) { return 4 * g + q; }
+  struct Op {
+    float x[8];
+  };
+  __device__ static Op from_t(const float (&v)[8]) {
+    Op o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o.x[j] = v[j];
+    return o;
+  }
+  __device__ static Op from_lds(const unsigned char* lds, int, int off) {
+    const float* S = reinterpret_cast<const float*>(lds) + off;
+    const floatx4 a = *reinterpret_cast<const floatx4*>(S);
+    const floatx4 b = *reinterpret_cast<const floatx4*>(S + 4);
+    return Op{{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]}};
+  }
+  __device__ static void put(unsigned char* lds, int kpad, int r, int k, float v) {
+    reinterpret_cast<float*>(lds)[r * kpad + k] = v;
+  }
+  __device__ static V mma(const Op& a, const Op& b, V c) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[j], b.x[j], c, 0, 0, 0);
+    return c;
+  }
+};
+
+struct FlavF64 {
+  using S = double;
+  using V = doublex4;
+  using Src = double;   // the float64 factors themselves
+  static constexpr int kMaxK = 256;
+  static constexpr int kFacBytes = sizeof(double);
+  // the float64 16x16 result interleaves its rows: value q of group g is row g + 4q
+  __device__ static int drow(int g, int q) { return g + 4 * q; }
+  struct Op {
+    double x[8];
+  };
+  __device__ static Op from_t(const float (&v)[8]) {
+    Op o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o.x[j] = (double)v[j];
+    return o;
+  }
+  __device__ static Op from_lds(const unsigned char* lds, int, int off) {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const double* S = reinterpret_cast<const double*>(lds) + off;
+    Op o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const d2v x = *reinterpret_cast<const d2v*>(S + 2 * j);
+      o.x[2 * j] = x[0];
+      o.x[2 * j + 1] = x[1];
+    }
+    return o;
+  }
+  __device__ static void put(unsigned char* lds, int kpad, int r, int k, double v) {
+    reinterpret_cast<double*>(lds)[r * kpad + k] = v;
+  }
+  __device__ static V mma(const Op& a, const Op& b, V c) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[j], b.x[j], c, 0, 0, 0);
+    return c;
+  }
+};
+
+__device__ inline float fma_s(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double fma_s(double a, double b, double c) { return fma(a, b, c); }
+
+// Stage the inner factor, columns r0..r0+31: S[r][k] = A^(q)(k, r0 + r) in the
+// flavour's form, zero for r >= R and for k in [K, 32 * nks).
 // First inner index (within a 32-wide k-step) of lane group g's operand:
 // the MFMA operand of g is k = 8g..8g+7.
 __device__ inline int kload_a(int g) { return 8 * g; }
 
-__device__ inline void stage_inner(const float* __restrict__ fac, const FastParams& p, int r0,
-                                   __bf16* Sh, __bf16* Sl) {
+template <class F>
+__device__ inline void stage_inner(const typename F::Src* __restrict__ fac, const FastParams& p,
+                                   int r0, unsigned char* lds) {
   const int kr = p.nks * 32;
   for (int e = threadIdx.x; e < 32 * kr; e += kThr) {
     const int k = e >> 5, r = e & 31;
-    float v = 0.f;
+    typename F::Src v = 0;
     if (k < p.K && r0 + r < p.R) v = fac[p.qfoff + (int64_t)k * p.R + r0 + r];
-    const __bf16 h = (__bf16)v;
-    Sh[r * p.kpad + k] = h;
-    Sl[r * p.kpad + k] = (__bf16)(v - (float)h);
+    F::put(lds, p.kpad, r, k, v);
   }
 }
 
@@ -115,18 +239,18 @@ __device__ inline int64_t outer_base(const FastParams& p, int64_t o) {
   return base;
 }
 
-// the float32 product of the outer modes' factor values, each rounded to
-// float32 first (F = double reads the float64 factors and rounds them: the
-// same bits as reading their float32 copy)
-template <typename F>
-__device__ inline float outer_scale(const F* __restrict__ fac, const FastParams& p, int64_t o,
-                                    int r) {
-  if (r >= p.R) return 0.f;
-  float s = 1.f;
+// the product of the outer modes' factor values in S: for S = float each
+// float64 factor value is rounded to float32 first (the same bits as reading
+// the float32 copy), for S = double the values are used as they are
+template <typename S>
+__device__ inline S outer_scale(const double* __restrict__ fac, const FastParams& p, int64_t o,
+                                int r) {
+  if (r >= p.R) return S(0);
+  S s = S(1);
   for (int m = p.nout - 1; m >= 0; --m) {
     const int64_t d = p.odims[m];
     const int64_t q = o / d;
-    s *= (float)fac[p.ofoff[m] + (o - q * d) * p.R + r];
+    s *= (S)fac[p.ofoff[m] + (o - q * d) * p.R + r];
     o = q;
   }
   return s;
@@ -142,9 +266,11 @@ constexpr int kOChunk = 64;   // outer indices per LDS table chunk (VALU kernel)
 // row-stream kernel, whose MFMA D lanes hold four consecutive o of one rank
 // (one 16-byte load).
 // The same launch also writes the float32 copy of all L factor values
-// (fac32, read by the MTTKRP kernel for its inner mode).
+// (fac32, read by the float32-operand kernels for their inner mode; L = 0
+// for the float64 flavour, which reads the factors themselves).
+template <typename S>
 __global__ void outer_tables_kernel(const double* __restrict__ fac, FastParams p,
-                                    float* __restrict__ Pg, int64_t* __restrict__ bg,
+                                    S* __restrict__ Pg, int64_t* __restrict__ bg,
                                     float* __restrict__ fac32, int64_t L) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < L) fac32[e] = (float)fac[e];
@@ -154,25 +280,42 @@ __global__ void outer_tables_kernel(const double* __restrict__ fac, FastParams p
   if (c == p.R) {
     if (o < p.O) bg[o] = outer_base(p, o);
   } else if (p.ptrans) {
-    Pg[c * p.Opad + o] = o < p.O ? outer_scale(fac, p, o, c) : 0.f;
+    Pg[c * p.Opad + o] = o < p.O ? outer_scale<S>(fac, p, o, c) : S(0);
   } else if (o < p.O) {
-    Pg[o * p.R + c] = outer_scale(fac, p, o, c);
+    Pg[o * p.R + c] = outer_scale<S>(fac, p, o, c);
   }
 }
 
 // P(o, r) from the o-major table (row and column kernels)
-__device__ inline float pscale(const float* __restrict__ Pg, const FastParams& p, int64_t o, int r) {
-  return r < p.R ? Pg[o * p.R + r] : 0.f;
+template <typename S>
+__device__ inline S pscale(const S* __restrict__ Pg, const FastParams& p, int64_t o, int r) {
+  return r < p.R ? Pg[o * p.R + r] : S(0);
 }
 
 // P(o, r) from the rank-major table (row-stream kernel)
-__device__ inline float pscale_t(const float* __restrict__ Pg, const FastParams& p, int64_t o, int r) {
-  return r < p.R ? Pg[r * p.Opad + o] : 0.f;
+template <typename S>
+__device__ inline S pscale_t(const S* __restrict__ Pg, const FastParams& p, int64_t o, int r) {
+  return r < p.R ? Pg[r * p.Opad + o] : S(0);
 }
 
-// P(o..o+3, r) from the rank-major table, o a multiple of 4
-__device__ inline float4 pscale4(const float* __restrict__ Pg, const FastParams& p, int64_t o, int r) {
-  return r < p.R ? *reinterpret_cast<const float4*>(Pg + r * p.Opad + o) : float4{0.f, 0.f, 0.f, 0.f};
+// P(o..o+3, r) from the rank-major table, o a multiple of 4 (Opad is, so the
+// address is 4-element aligned)
+template <typename S>
+struct S4 {
+  S x, y, z, w;
+};
+__device__ inline S4<float> pscale4(const float* __restrict__ Pg, const FastParams& p, int64_t o,
+                                    int r) {
+  if (r >= p.R) return S4<float>{0.f, 0.f, 0.f, 0.f};
+  const float4 v = *reinterpret_cast<const float4*>(Pg + r * p.Opad + o);
+  return S4<float>{v.x, v.y, v.z, v.w};
+}
+__device__ inline S4<double> pscale4(const double* __restrict__ Pg, const FastParams& p, int64_t o,
+                                     int r) {
+  if (r >= p.R) return S4<double>{0.0, 0.0, 0.0, 0.0};
+  const double2 a = *reinterpret_cast<const double2*>(Pg + r * p.Opad + o);
+  const double2 b = *reinterpret_cast<const double2*>(Pg + r * p.Opad + o + 2);
+  return S4<double>{a.x, a.y, b.x, b.y};
 }
 
 // 16-byte load of T; NTR: non-temporal (rows are whole 128-byte lines)
@@ -183,15 +326,17 @@ __device__ inline floatx4 load_t4(const float* ptr) {
 }
 
 // Row kernel: 4 waves x MT row tiles of 16 = 64*MT rows, 32 ranks.
-template <int MT, bool NTR>
-__global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restrict__ T,
-                                                           const float* __restrict__ fac,
-                                                           const float* __restrict__ Pg,
-                                                           const int64_t* __restrict__ bg,
-                                                           FastParams p, float* __restrict__ part) {
+template <class F, int MT, bool NTR>
+__global__ __launch_bounds__(kThr) void mttkrp_rows_mfma(const float* __restrict__ T,
+                                                         const typename F::Src* __restrict__ fac,
+                                                         const typename F::S* __restrict__ Pg,
+                                                         const int64_t* __restrict__ bg,
+                                                         FastParams p,
+                                                         typename F::S* __restrict__ part) {
+  using S = typename F::S;
+  using V = typename F::V;
+  using Op = typename F::Op;
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  __bf16* Sh = reinterpret_cast<__bf16*>(dyn_lds);
-  __bf16* Sl = Sh + 32 * p.kpad;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int lr = lane & 15;
@@ -200,8 +345,9 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
   const int64_t i0 = (int64_t)blockIdx.y * (64 * MT);
   constexpr int kRS = 36;              // staging row stride (floats)
   constexpr int NQ = 16 * MT * 8 / 64; // 16-byte loads per lane per k-step
-  float* stg = reinterpret_cast<float*>(Sl + 32 * p.kpad) + w * (16 * MT * kRS);
-  stage_inner(fac, p, r0, Sh, Sl);
+  float* stg = reinterpret_cast<float*>(dyn_lds + (size_t)F::kFacBytes * 32 * p.kpad) +
+               w * (16 * MT * kRS);
+  stage_inner<F>(fac, p, r0, dyn_lds);
   __syncthreads();
 
   // whole-line loads: lane l reads 16 bytes at chunk l % 8 of the wave's rows
@@ -223,11 +369,11 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
       dst[q] = (lrowok[q] && k < p.K)
                    ? load_t4<NTR>(T + base + lrowoff[q] + k) : f4v{0.f, 0.f, 0.f, 0.f};
   };
-  floatx4 acc[MT][2];
+  V acc[MT][2];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = V{0, 0, 0, 0};
 
   const int64_t ob = (int64_t)blockIdx.x * p.o_per_block;
   const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
@@ -245,11 +391,11 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
       if (b < nit) gload(base_tab[jl], kl * 32, buf[b]);
       if (++kl == p.nks) { kl = 0; ++jl; }
     }
-    floatx4 Y[MT][2];
+    V Y[MT][2];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < 2; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int nt = 0; nt < 2; ++nt) Y[mt][nt] = V{0, 0, 0, 0};
     int j = 0, ks = 0;
     for (int it = 0; it < nit; ++it) {
       if (it + PF < nit) gload(base_tab[jl], kl * 32, buf[PF]);
@@ -272,37 +418,29 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      bf16x8 ah[MT], al[MT];
+      Op a[MT];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) split8(v[mt], ah[mt], al[mt]);
+      for (int mt = 0; mt < MT; ++mt) a[mt] = F::from_t(v[mt]);
       const int k = ks * 32 + kb;
-      const int so0 = lr * p.kpad + k;
-      const int so1 = (16 + lr) * p.kpad + k;
-      const bf16x8 bh0 = *reinterpret_cast<const bf16x8*>(&Sh[so0]);
-      const bf16x8 bl0 = *reinterpret_cast<const bf16x8*>(&Sl[so0]);
-      const bf16x8 bh1 = *reinterpret_cast<const bf16x8*>(&Sh[so1]);
-      const bf16x8 bl1 = *reinterpret_cast<const bf16x8*>(&Sl[so1]);
+      const Op b0 = F::from_lds(dyn_lds, p.kpad, lr * p.kpad + k);
+      const Op b1 = F::from_lds(dyn_lds, p.kpad, (16 + lr) * p.kpad + k);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        Y[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bh0, Y[mt][0], 0, 0, 0);
-        Y[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bl0, Y[mt][0], 0, 0, 0);
-        Y[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh0, Y[mt][0], 0, 0, 0);
-        Y[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bh1, Y[mt][1], 0, 0, 0);
-        Y[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bl1, Y[mt][1], 0, 0, 0);
-        Y[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh1, Y[mt][1], 0, 0, 0);
+        Y[mt][0] = F::mma(a[mt], b0, Y[mt][0]);
+        Y[mt][1] = F::mma(a[mt], b1, Y[mt][1]);
       }
       if (ks + 1 == p.nks) {
-        const float P0 = pscale(Pg, p, oc + j, r0 + lr);
-        const float P1 = pscale(Pg, p, oc + j, r0 + 16 + lr);
+        const S P0 = pscale(Pg, p, oc + j, r0 + lr);
+        const S P1 = pscale(Pg, p, oc + j, r0 + 16 + lr);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            acc[mt][0][q] = fmaf(P0, Y[mt][0][q], acc[mt][0][q]);
-            acc[mt][1][q] = fmaf(P1, Y[mt][1][q], acc[mt][1][q]);
+            acc[mt][0][q] = fma_s(P0, Y[mt][0][q], acc[mt][0][q]);
+            acc[mt][1][q] = fma_s(P1, Y[mt][1][q], acc[mt][1][q]);
           }
-          Y[mt][0] = floatx4{0.f, 0.f, 0.f, 0.f};
-          Y[mt][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+          Y[mt][0] = V{0, 0, 0, 0};
+          Y[mt][1] = V{0, 0, 0, 0};
         }
         ks = 0;
         ++j;
@@ -315,14 +453,14 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_bf16x3(const float* __restri
         for (int q = 0; q < NQ; ++q) buf[b][q] = buf[b + 1][q];
     }
   }
-  float* out = part + (int64_t)blockIdx.x * p.I_n * p.R;
+  S* out = part + (int64_t)blockIdx.x * p.I_n * p.R;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t i = i0 + (w * MT + mt) * 16 + (lane >> 4) * 4 + q;
+        const int64_t i = i0 + (w * MT + mt) * 16 + F::drow(lane >> 4, q);
         const int r = r0 + nt * 16 + lr;
         if (i < p.I_n && r < p.R) out[i * p.R + r] = acc[mt][nt][q];
       }
@@ -369,31 +507,33 @@ __device__ inline void load_cols(const float* __restrict__ T, const FastParams& 
 
 // Column kernel: Y^T(r, i) = sum_k A^(q)(k, r) T(o, k, i); 4 waves x NT column
 // tiles of 16 = 64*NT output rows i, 32 ranks (two 16-row MFMA tiles).
-template <int NT>
-__global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restrict__ T,
-                                                           const float* __restrict__ fac,
-                                                           const float* __restrict__ Pg,
-                                                           const int64_t* __restrict__ bg,
-                                                           FastParams p, float* __restrict__ part) {
+template <class F, int NT>
+__global__ __launch_bounds__(kThr) void mttkrp_cols_mfma(const float* __restrict__ T,
+                                                         const typename F::Src* __restrict__ fac,
+                                                         const typename F::S* __restrict__ Pg,
+                                                         const int64_t* __restrict__ bg,
+                                                         FastParams p,
+                                                         typename F::S* __restrict__ part) {
+  using S = typename F::S;
+  using V = typename F::V;
+  using Op = typename F::Op;
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  __bf16* Sh = reinterpret_cast<__bf16*>(dyn_lds);
-  __bf16* Sl = Sh + 32 * p.kpad;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int lr = lane & 15;
   const int kb = (lane >> 4) * 8;
   const int r0 = blockIdx.z * 32;
   const int64_t i0 = (int64_t)blockIdx.y * (64 * NT);
-  stage_inner(fac, p, r0, Sh, Sl);
+  stage_inner<F>(fac, p, r0, dyn_lds);
   __syncthreads();
 
   // this lane's columns: col0 + nt for tile nt
   const int64_t col0 = i0 + (int64_t)w * 16 * NT + lr * NT;
-  floatx4 acc[2][NT];
+  V acc[2][NT];
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = V{0, 0, 0, 0};
 
   const int64_t ob = (int64_t)blockIdx.x * p.o_per_block;
   const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
@@ -410,44 +550,35 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
       if (b < nit) load_cols<NT>(T, p, base_tab[jl], col0, kl * 32, buf[b]);
       if (++kl == p.nks) { kl = 0; ++jl; }
     }
-    floatx4 Y[2][NT];
+    V Y[2][NT];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int nt = 0; nt < NT; ++nt) Y[mt][nt] = V{0, 0, 0, 0};
     int j = 0, ks = 0;
     for (int it = 0; it < nit; ++it) {
       if (it + PF < nit) load_cols<NT>(T, p, base_tab[jl], col0, kl * 32, buf[PF]);
       if (++kl == p.nks) { kl = 0; ++jl; }
       const int k = ks * 32 + kb;
-      const int so0 = lr * p.kpad + k;
-      const int so1 = (16 + lr) * p.kpad + k;
-      const bf16x8 ah0 = *reinterpret_cast<const bf16x8*>(&Sh[so0]);
-      const bf16x8 al0 = *reinterpret_cast<const bf16x8*>(&Sl[so0]);
-      const bf16x8 ah1 = *reinterpret_cast<const bf16x8*>(&Sh[so1]);
-      const bf16x8 al1 = *reinterpret_cast<const bf16x8*>(&Sl[so1]);
+      const Op a0 = F::from_lds(dyn_lds, p.kpad, lr * p.kpad + k);
+      const Op a1 = F::from_lds(dyn_lds, p.kpad, (16 + lr) * p.kpad + k);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        bf16x8 bh, bl;
-        split8(buf[0][nt], bh, bl);
-        Y[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, Y[0][nt], 0, 0, 0);
-        Y[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, Y[0][nt], 0, 0, 0);
-        Y[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, Y[0][nt], 0, 0, 0);
-        Y[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, Y[1][nt], 0, 0, 0);
-        Y[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, Y[1][nt], 0, 0, 0);
-        Y[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, Y[1][nt], 0, 0, 0);
+        const Op b = F::from_t(buf[0][nt]);
+        Y[0][nt] = F::mma(a0, b, Y[0][nt]);
+        Y[1][nt] = F::mma(a1, b, Y[1][nt]);
       }
       if (ks + 1 == p.nks) {
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const float P = pscale(Pg, p, oc + j, r0 + mt * 16 + (lane >> 4) * 4 + q);
+            const S P = pscale(Pg, p, oc + j, r0 + mt * 16 + F::drow(lane >> 4, q));
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[mt][nt][q] = fmaf(P, Y[mt][nt][q], acc[mt][nt][q]);
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt][q] = fma_s(P, Y[mt][nt][q], acc[mt][nt][q]);
           }
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) Y[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+          for (int nt = 0; nt < NT; ++nt) Y[mt][nt] = V{0, 0, 0, 0};
         }
         ks = 0;
         ++j;
@@ -462,14 +593,14 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
           for (int q = 0; q < 8; ++q) buf[b][nt][q] = buf[b + 1][nt][q];
     }
   }
-  float* out = part + (int64_t)blockIdx.x * p.I_n * p.R;
+  S* out = part + (int64_t)blockIdx.x * p.I_n * p.R;
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r = r0 + mt * 16 + (lane >> 4) * 4 + q;
+        const int r = r0 + mt * 16 + F::drow(lane >> 4, q);
         const int64_t i = col0 + nt;
         if (i < p.I_n && r < p.R) out[i * p.R + r] = acc[mt][nt][q];
       }
@@ -491,18 +622,19 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_bf16x3(const float* __restri
 // LDS area (row stride 36 floats)
 // and read back in the operand layout, ordered by wave-level fences only
 // (modes 1-2 at 128^4, R = 32: 194 -> 178 us).
-template <bool NTR>
-__global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __restrict__ T,
-                                                                const float* __restrict__ fac,
-                                                                const float* __restrict__ Pg,
-                                                                const int64_t* __restrict__ bg,
-                                                                FastParams p,
-                                                                float* __restrict__ part) {
+template <class F, bool NTR>
+__global__ __launch_bounds__(kThr) void mttkrp_rowstream_mfma(const float* __restrict__ T,
+                                                              const typename F::Src* __restrict__ fac,
+                                                              const typename F::S* __restrict__ Pg,
+                                                              const int64_t* __restrict__ bg,
+                                                              FastParams p,
+                                                              typename F::S* __restrict__ part) {
+  using S = typename F::S;
+  using V = typename F::V;
+  using Op = typename F::Op;
   constexpr int TW = CPNG_ROWSTREAM_TW;
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  __bf16* Sh = reinterpret_cast<__bf16*>(dyn_lds);
-  __bf16* Sl = Sh + 32 * p.kpad;
-  __shared__ float red[4][32];
+  __shared__ S red[4][32];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int lr = lane & 15;
@@ -511,14 +643,15 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
   const int64_t bx = blockIdx.x;
   constexpr int kRS = 36;                  // staging row stride (floats)
   constexpr int NQ = 16 * TW * 8 / 64;     // 16-byte loads per lane per k-step
-  float* stg = reinterpret_cast<float*>(Sl + 32 * p.kpad) + w * (16 * TW * kRS);
-  stage_inner(fac, p, r0, Sh, Sl);
+  float* stg = reinterpret_cast<float*>(dyn_lds + (size_t)F::kFacBytes * 32 * p.kpad) +
+               w * (16 * TW * kRS);
+  stage_inner<F>(fac, p, r0, dyn_lds);
   __syncthreads();
   const int64_t ob = bx * p.o_per_block;
   const int64_t oe = min<int64_t>(p.O, ob + p.o_per_block);
   for (int64_t by = blockIdx.y; by < p.I_n; by += gridDim.y) {
   const int64_t ioff = by * p.istride;
-  float acc0 = 0.f, acc1 = 0.f;   // rank columns r0 + lr and r0 + 16 + lr
+  S acc0 = 0, acc1 = 0;   // rank columns r0 + lr and r0 + 16 + lr
   for (int64_t og = ob + w * 16 * TW; og < oe; og += 4 * 16 * TW) {
     // whole-line loads: lane l reads 16 bytes at chunk l % 8 of rows q*8 + l/8
     typedef float f4v __attribute__((ext_vector_type(4)));
@@ -541,9 +674,9 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
     };
     float v[TW][8];
     gload(0);
-    floatx4 Y[TW][2];
+    V Y[TW][2];
 #pragma unroll
-    for (int t = 0; t < TW; ++t) Y[t][0] = Y[t][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < TW; ++t) Y[t][0] = Y[t][1] = V{0, 0, 0, 0};
     for (int ks = 0; ks < p.nks; ++ks) {
       // stage the step's rows, then read back this lane's operand (8 k of one row)
 #pragma unroll
@@ -564,47 +697,40 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (ks + 1 < p.nks) gload(ks + 1);
       const int k = ks * 32 + kb;
-      const int so0 = lr * p.kpad + k;
-      const int so1 = (16 + lr) * p.kpad + k;
-      const bf16x8 bh0 = *reinterpret_cast<const bf16x8*>(&Sh[so0]);
-      const bf16x8 bl0 = *reinterpret_cast<const bf16x8*>(&Sl[so0]);
-      const bf16x8 bh1 = *reinterpret_cast<const bf16x8*>(&Sh[so1]);
-      const bf16x8 bl1 = *reinterpret_cast<const bf16x8*>(&Sl[so1]);
+      const Op b0 = F::from_lds(dyn_lds, p.kpad, lr * p.kpad + k);
+      const Op b1 = F::from_lds(dyn_lds, p.kpad, (16 + lr) * p.kpad + k);
 #pragma unroll
       for (int t = 0; t < TW; ++t) {
-        bf16x8 ah, al;
-        split8(v[t], ah, al);
-        Y[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh0, Y[t][0], 0, 0, 0);
-        Y[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, Y[t][0], 0, 0, 0);
-        Y[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh0, Y[t][0], 0, 0, 0);
-        Y[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh1, Y[t][1], 0, 0, 0);
-        Y[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl1, Y[t][1], 0, 0, 0);
-        Y[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh1, Y[t][1], 0, 0, 0);
+        const Op a = F::from_t(v[t]);
+        Y[t][0] = F::mma(a, b0, Y[t][0]);
+        Y[t][1] = F::mma(a, b1, Y[t][1]);
       }
     }
-    // D rows are outer indices og + t*16 + 4*(lane/16) + q; the column is the
-    // rank.  og is a multiple of 4 (o_per_block is a multiple of 16).
+    // D rows are outer indices og + t*16 + drow(lane/16, q); the column is
+    // the rank.  og is a multiple of 4 (o_per_block is a multiple of 16), so
+    // where the four rows of a lane are consecutive they are one aligned
+    // group of the rank-major P table.
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
-      const int64_t o4 = og + t * 16 + (lane >> 4) * 4;
-      if (o4 + 3 < oe) {
-        const float4 pa = pscale4(Pg, p, o4, r0 + lr);
-        const float4 pb = pscale4(Pg, p, o4, r0 + 16 + lr);
-        acc0 = fmaf(pa.x, Y[t][0][0], acc0);
-        acc0 = fmaf(pa.y, Y[t][0][1], acc0);
-        acc0 = fmaf(pa.z, Y[t][0][2], acc0);
-        acc0 = fmaf(pa.w, Y[t][0][3], acc0);
-        acc1 = fmaf(pb.x, Y[t][1][0], acc1);
-        acc1 = fmaf(pb.y, Y[t][1][1], acc1);
-        acc1 = fmaf(pb.z, Y[t][1][2], acc1);
-        acc1 = fmaf(pb.w, Y[t][1][3], acc1);
+      const int64_t o4 = og + t * 16 + F::drow(lane >> 4, 0);
+      if (F::drow(0, 1) == 1 && o4 + 3 < oe) {
+        const S4<S> pa = pscale4(Pg, p, o4, r0 + lr);
+        const S4<S> pb = pscale4(Pg, p, o4, r0 + 16 + lr);
+        acc0 = fma_s(pa.x, Y[t][0][0], acc0);
+        acc0 = fma_s(pa.y, Y[t][0][1], acc0);
+        acc0 = fma_s(pa.z, Y[t][0][2], acc0);
+        acc0 = fma_s(pa.w, Y[t][0][3], acc0);
+        acc1 = fma_s(pb.x, Y[t][1][0], acc1);
+        acc1 = fma_s(pb.y, Y[t][1][1], acc1);
+        acc1 = fma_s(pb.z, Y[t][1][2], acc1);
+        acc1 = fma_s(pb.w, Y[t][1][3], acc1);
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int64_t o = o4 + q;
+          const int64_t o = og + t * 16 + F::drow(lane >> 4, q);
           if (o < oe) {
-            acc0 = fmaf(pscale_t(Pg, p, o, r0 + lr), Y[t][0][q], acc0);
-            acc1 = fmaf(pscale_t(Pg, p, o, r0 + 16 + lr), Y[t][1][q], acc1);
+            acc0 = fma_s(pscale_t(Pg, p, o, r0 + lr), Y[t][0][q], acc0);
+            acc1 = fma_s(pscale_t(Pg, p, o, r0 + 16 + lr), Y[t][1][q], acc1);
           }
         }
       }
@@ -622,7 +748,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_bf16x3(const float* __r
   __syncthreads();
   if (threadIdx.x < 32) {
     const int c = threadIdx.x;
-    const float sum = (red[0][c] + red[2][c]) + (red[1][c] + red[3][c]);
+    const S sum = (red[0][c] + red[2][c]) + (red[1][c] + red[3][c]);
     if (r0 + c < p.R) part[bx * p.I_n * p.R + by * p.R + r0 + c] = sum;
   }
   __syncthreads();   // red is rewritten for the next row
@@ -808,23 +934,32 @@ __global__ __launch_bounds__(kThr) void mttkrp_tiles_vec(const TT* __restrict__ 
   }
 }
 
-}  // namespace
-
-// Returns CP_OK after launching, or 1 if the shape is not one the streaming
-// kernels cover (the caller then uses the generic kernel).
-int dense_fast_bf16x3(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
-                      int mode, double* M, hipStream_t st) {
+// Launches one streaming MTTKRP in flavour F.  Returns CP_OK after
+// launching, or 1 if the shape is not one the streaming kernels cover (the
+// caller then uses another kernel).
+template <class F>
+int launch_mfma(cp_handle* h, const float* T, const double* u, const Shape& s, int R, int mode,
+                double* M, hipStream_t st) {
+  using S = typename F::S;
+  constexpr bool kF32Src = sizeof(typename F::Src) == 4;
   const int N = s.N;
   if (N < 2) return 1;
   const bool rows = mode < N - 1;
   const int q = rows ? N - 1 : N - 2;
   const int64_t K = s.dims[q];
-  if (K % 8 != 0 || K > kMaxInner) return 1;
+  if (K % 8 != 0 || K > F::kMaxK) return 1;
   if (reinterpret_cast<uintptr_t>(T) % 16 != 0) return 1;
-  // the float32 copy of the factors, written by the table launch below
+  // the float32 copy of the factors (float32-operand flavours), written by
+  // the table launch below; the float64 flavour reads u itself
   const int64_t L = s.sum_dims() * R;
-  CP_TRY(ensure(h, h->stage, sizeof(float) * (size_t)L, st));
-  const float* fac = static_cast<const float*>(h->stage.ptr);
+  float* fac32 = nullptr;
+  if (kF32Src) {
+    CP_TRY(ensure(h, h->stage, sizeof(float) * (size_t)L, st));
+    fac32 = static_cast<float*>(h->stage.ptr);
+  }
+  const typename F::Src* fac = nullptr;
+  if constexpr (kF32Src) fac = fac32;
+  else fac = u;
   FastParams p{};
   p.R = R;
   int64_t stride[CP_MAX_ORDER];
@@ -873,45 +1008,70 @@ int dense_fast_bf16x3(cp_handle* h, const float* T, const double* u, const Shape
   ks = (p.O + p.o_per_block - 1) / p.o_per_block;
   p.Opad = (p.O + 3) / 4 * 4;
   const int64_t n_out = p.I_n * R;
-  CP_TRY(ensure(h, h->part, sizeof(float) * (size_t)(ks * n_out), st));
-  float* part = static_cast<float*>(h->part.ptr);
+  CP_TRY(ensure(h, h->part, sizeof(S) * (size_t)(ks * n_out), st));
+  S* part = static_cast<S*>(h->part.ptr);
   dim3 grid((unsigned)ks, (unsigned)ygrid, (unsigned)rchunks);
   // the row kernels stage each wave's k-step rows (16 per tile, 36-float stride)
   const int wave_rows = stream_rows ? 16 * CPNG_ROWSTREAM_TW : (rows ? tile / 4 : 0);
-  const size_t lds = 2 * sizeof(__bf16) * 32 * (size_t)p.kpad + sizeof(float) * 4 * 36 * (size_t)wave_rows;
-  // outer tables: P (O x R floats) then base offsets (O int64)
-  const size_t pbytes = (sizeof(float) * (size_t)(p.Opad * R) + 255) & ~size_t(255);
+  const size_t lds = (size_t)F::kFacBytes * 32 * (size_t)p.kpad +
+                     sizeof(float) * 4 * 36 * (size_t)wave_rows;
+  // outer tables: P (O x R values of S) then base offsets (O int64)
+  const size_t pbytes = (sizeof(S) * (size_t)(p.Opad * R) + 255) & ~size_t(255);
   CP_TRY(ensure(h, h->otab, pbytes + sizeof(int64_t) * (size_t)p.O, st));
-  float* Pg = static_cast<float*>(h->otab.ptr);
+  S* Pg = static_cast<S*>(h->otab.ptr);
   int64_t* bg = reinterpret_cast<int64_t*>(static_cast<char*>(h->otab.ptr) + pbytes);
   {
-    const int64_t nt = std::max<int64_t>(p.Opad * (R + 1), L);
-    hipLaunchKernelGGL(outer_tables_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, u,
-                       p, Pg, bg, static_cast<float*>(h->stage.ptr), L);
+    const int64_t Lc = kF32Src ? L : 0;
+    const int64_t nt = std::max<int64_t>(p.Opad * (R + 1), Lc);
+    hipLaunchKernelGGL(outer_tables_kernel<S>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st,
+                       u, p, Pg, bg, fac32, Lc);
     CP_LAUNCH_CHECK(h);
   }
   {
-    KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
+    KernelTimer timer(h, dense_kernel_id<S>(), st);
     if (stream_rows) {
-      if (ntr) CP_TIMED_LAUNCH(timer, mttkrp_rowstream_bf16x3<true>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
-      else CP_TIMED_LAUNCH(timer, mttkrp_rowstream_bf16x3<false>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      if (ntr) CP_TIMED_LAUNCH(timer, (mttkrp_rowstream_mfma<F, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      else CP_TIMED_LAUNCH(timer, (mttkrp_rowstream_mfma<F, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
     } else if (rows) {
       if (tile == 128) {
-        if (ntr) CP_TIMED_LAUNCH(timer, (mttkrp_rows_bf16x3<2, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
-        else CP_TIMED_LAUNCH(timer, (mttkrp_rows_bf16x3<2, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+        if (ntr) CP_TIMED_LAUNCH(timer, (mttkrp_rows_mfma<F, 2, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+        else CP_TIMED_LAUNCH(timer, (mttkrp_rows_mfma<F, 2, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
       } else {
-        if (ntr) CP_TIMED_LAUNCH(timer, (mttkrp_rows_bf16x3<1, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
-        else CP_TIMED_LAUNCH(timer, (mttkrp_rows_bf16x3<1, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+        if (ntr) CP_TIMED_LAUNCH(timer, (mttkrp_rows_mfma<F, 1, true>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+        else CP_TIMED_LAUNCH(timer, (mttkrp_rows_mfma<F, 1, false>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
       }
     } else {
-      if (tile == 128) CP_TIMED_LAUNCH(timer, mttkrp_cols_bf16x3<2>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
-      else CP_TIMED_LAUNCH(timer, mttkrp_cols_bf16x3<1>, grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      if (tile == 128) CP_TIMED_LAUNCH(timer, (mttkrp_cols_mfma<F, 2>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
+      else CP_TIMED_LAUNCH(timer, (mttkrp_cols_mfma<F, 1>), grid, dim3(kThr), lds, st, T, fac, Pg, bg, p, part);
     }
   }
   CP_LAUNCH_CHECK(h);
   CP_TRY(launch_splitk_reduce(h, part, ks, n_out, R, M, st));
   CP_LAUNCH_CHECK(h);
   return CP_OK;
+}
+
+}  // namespace
+
+// The streaming matrix-core MTTKRP of one mode, per arithmetic: BF16x3
+// split products, float32 products (both with float32 sums inside a
+// workgroup), or float64 products and sums of the widened float32 tensor.
+// Each returns CP_OK after launching, or 1 if the shape is not one the
+// streaming kernels cover (inner length not a multiple of 8, or above 512;
+// above 256 for float64; a misaligned tensor).
+int dense_fast_bf16x3(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
+                      int mode, double* M, hipStream_t st) {
+  return launch_mfma<FlavBF16x3>(h, T, u, s, R, mode, M, st);
+}
+
+int dense_fast_mfma_f32(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
+                        int mode, double* M, hipStream_t st) {
+  return launch_mfma<FlavF32>(h, T, u, s, R, mode, M, st);
+}
+
+int dense_fast_mfma_f64acc(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
+                           int mode, double* M, hipStream_t st) {
+  return launch_mfma<FlavF64>(h, T, u, s, R, mode, M, st);
 }
 
 }  // namespace cpng
@@ -963,7 +1123,7 @@ static int launch_tiles(cp_handle* h, const TT* T, const CT* fac, FastParams p, 
   CT* part = static_cast<CT*>(h->part.ptr);
   dim3 grid((unsigned)ks, (unsigned)ychunks, (unsigned)rchunks);
   {
-    KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
+    KernelTimer timer(h, dense_kernel_id<CT>(), st);
     if (rows) CP_TIMED_LAUNCH(timer, (mttkrp_tiles_vec<TT, CT, RB, true>), grid, dim3(kThr), 0, st, T, fac, p, part);
     else CP_TIMED_LAUNCH(timer, (mttkrp_tiles_vec<TT, CT, RB, false>), grid, dim3(kThr), 0, st, T, fac, p, part);
   }

@@ -197,7 +197,7 @@ int launch_vec(cp_handle* h, const TT* T, const CT* fac, DenseParams p, double* 
   double* part = static_cast<double*>(h->part.ptr);
   dim3 grid((unsigned)ks, (unsigned)ichunks, (unsigned)rchunks);
   {
-    KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
+    KernelTimer timer(h, dense_kernel_id<CT>(), st);
     CP_TIMED_LAUNCH(timer, (mttkrp_vec_kernel<TT, CT, RB, S>), grid, dim3(kThreads), 0, st, T, fac, p,
                        part);
   }
@@ -438,6 +438,11 @@ int dense_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double*
       return p.I_n > 64 ? launch_bf16x3<2>(h, Tv, fac, p, M, st)
                         : launch_bf16x3<1>(h, Tv, fac, p, M, st);
     }
+    // float32 products: the matrix-core streaming kernels, else the vector ones
+    {
+      const int rc = dense_fast_mfma_f32(h, static_cast<const float*>(T->values), u, s, R, mode, M, st);
+      if (rc <= 0) return rc;
+    }
     CP_TRY(stage_factors_f32(h, u, L, &fac, st));
     {
       const int rc = dense_fast_vec<float, float>(h, static_cast<const float*>(T->values), fac, s, R,
@@ -447,8 +452,11 @@ int dense_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double*
     return dispatch_rank<float, float>(h, static_cast<const float*>(T->values), fac, p, M, st);
   }
   if (T->dtype == CP_F32) {
-    const int rc = dense_fast_vec<float, double>(h, static_cast<const float*>(T->values), u, s, R,
-                                                 mode, M, st);
+    // float64 products and sums of the widened float32 tensor: the matrix-core
+    // streaming kernels (v_mfma_f64_16x16x4_f64), else the vector ones
+    int rc = dense_fast_mfma_f64acc(h, static_cast<const float*>(T->values), u, s, R, mode, M, st);
+    if (rc <= 0) return rc;
+    rc = dense_fast_vec<float, double>(h, static_cast<const float*>(T->values), u, s, R, mode, M, st);
     if (rc <= 0) return rc;
     return dispatch_rank<float, double>(h, static_cast<const float*>(T->values), u, p, M, st);
   }

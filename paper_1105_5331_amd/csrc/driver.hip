@@ -729,7 +729,7 @@ int cp_profile(cp_handle* h, int32_t enable) {
     }
     v.clear();
   }
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < cp_handle::kKernelIds; ++k) {
     h->prof_launches[k] = 0;
     h->prof_ms[k] = 0.0;
   }
@@ -744,13 +744,14 @@ int cp_stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t stre
 }
 
 int cp_profile_select(cp_handle* h, uint32_t kernel_mask) {
-  if (!h || (kernel_mask & ~0xFu) != 0) return CP_EINVAL;
+  if (!h || (kernel_mask & ~0x1Fu) != 0) return CP_EINVAL;
   h->prof_mask = kernel_mask;
   return CP_OK;
 }
 
 int cp_profile_read(cp_handle* h, int32_t kernel, int64_t* launches, double* total_ms) {
-  if (!h || kernel < 0 || kernel > 3 || !launches || !total_ms) return CP_EINVAL;
+  if (!h || kernel < 0 || kernel >= cp_handle::kKernelIds || !launches || !total_ms)
+    return CP_EINVAL;
   CP_HIP(h, hipSetDevice(h->device));
   auto& v = h->ev_pending[kernel];
   for (auto& pr : v) {

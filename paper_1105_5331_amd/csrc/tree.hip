@@ -165,7 +165,7 @@ int launch_contract_last(cp_handle* h, const TT* T, const CT* fac, const LastPar
                          hipStream_t st) {
   const int RB = p.R <= 8 ? 8 : (p.R <= 16 ? 16 : 32);
   const dim3 grid(nblk(p.rows, kTB), (unsigned)((p.R + RB - 1) / RB));
-  KernelTimer timer(h, CP_KERNEL_DENSE_MTTKRP, st);
+  KernelTimer timer(h, dense_kernel_id<CT>(), st);
   if (RB == 8) CP_TIMED_LAUNCH(timer, (contract_last_kernel<TT, CT, 8>), grid, dim3(kThr), 0, st, T, fac, p, X);
   else if (RB == 16) CP_TIMED_LAUNCH(timer, (contract_last_kernel<TT, CT, 16>), grid, dim3(kThr), 0, st, T, fac, p, X);
   else CP_TIMED_LAUNCH(timer, (contract_last_kernel<TT, CT, 32>), grid, dim3(kThr), 0, st, T, fac, p, X);

@@ -453,7 +453,7 @@ def test_profile_select_times_only_the_chosen_kernels(h):
     nd, msd = cpng.cp_profile_read(h, cpng.CP_KERNEL_DENSE_MTTKRP)
     ng, _ = cpng.cp_profile_read(h, cpng.CP_KERNEL_GROUP_MTTKRP)
     cpng.cp_profile(h, False)
-    cpng.cp_profile_select(h, 0xF)
+    cpng.cp_profile_select(h, 0x1F)
     assert nd >= 1 and msd > 0 and ng == 0
     cpng.cp_profile(h, True)
     cpng.cp_objective_grad(h, Tg, u, R, "fp32")
@@ -461,8 +461,17 @@ def test_profile_select_times_only_the_chosen_kernels(h):
     ng, _ = cpng.cp_profile_read(h, cpng.CP_KERNEL_GROUP_MTTKRP)
     cpng.cp_profile(h, False)
     assert ng >= 1
+    # float64-accumulating precisions are timed under their own id
+    cpng.cp_profile(h, True)
+    cpng.cp_mttkrp(h, Tg, u, R, 0, "fp32in_fp64acc")
+    cpng.cp_mttkrp(h, Tg, u, R, 0, "fp32")
+    torch.cuda.synchronize()
+    n64, _ = cpng.cp_profile_read(h, cpng.CP_KERNEL_DENSE_MTTKRP_F64)
+    n32, _ = cpng.cp_profile_read(h, cpng.CP_KERNEL_DENSE_MTTKRP)
+    cpng.cp_profile(h, False)
+    assert n64 == 1 and n32 == 1
     with pytest.raises(cpng.CpError):
-        cpng.cp_profile_select(h, 1 << 4)
+        cpng.cp_profile_select(h, 1 << 5)
 
 
 def test_stream_read_reference(h):
