@@ -113,6 +113,8 @@ typedef struct cp_iter_info {
   int32_t m;           /* window size used by Step II */
   int32_t precision;   /* cp_precision of the bulk MTTKRPs in this iteration */
   int32_t t_passes;    /* passes over the tensor's values made by this iteration's MTTKRPs */
+  int32_t nfev_pre;    /* evaluations of the one-step process's own line search in Step I
+                          (CP_METHOD_NGMRES_SD; 0 otherwise) */
 } cp_iter_info;
 
 #define CP_METHOD_NGMRES 0
@@ -122,9 +124,19 @@ typedef struct cp_iter_info {
    descent when a direction is not a descent direction or after a line search
    without a Wolfe point; iterates are not normalised after the initial guess. */
 #define CP_METHOD_NCG    2
+/* N-GMRES with steepest descent as the one-step process M(.) of Step I in
+   place of ALS (the paper's preconditioning view of N-GMRES, Section 2.2 end,
+   and its Section 5 suggestion to accelerate other methods): u_bar = u_i +
+   beta d with d = -g(u_i)/||g(u_i)||_2 and beta from the same line search as
+   Step III (a search without a Wolfe point takes the R13 fallback), then
+   u_bar normalised with its gradient carried over; f(u_bar) and g(u_bar) are
+   the accepted trial's, so Step I costs its line-search evaluations only.
+   Steps II and III are unchanged. */
+#define CP_METHOD_NGMRES_SD 3
 
 typedef struct cp_options {
-  int32_t method;           /* CP_METHOD_NGMRES (default), CP_METHOD_ALS or CP_METHOD_NCG */
+  int32_t method;           /* CP_METHOD_NGMRES (default), CP_METHOD_ALS, CP_METHOD_NCG or
+                               CP_METHOD_NGMRES_SD */
   int32_t window;           /* w, >= 1 (20) */
   double eps;               /* delta = eps * max diag(P^T P) (1e-12) */
   double ls_ftol;           /* sufficient-decrease constant (1e-4) */

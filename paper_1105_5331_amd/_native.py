@@ -22,7 +22,7 @@ CP_ESINGULAR, CP_EDUPLICATE, CP_ENOTFINITE = -4, -5, -6
 CP_MAXITER, CP_LS_FALLBACK = 1, 2
 CP_F32, CP_F64 = 0, 1
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp32in_fp64acc": 3}
-CP_METHOD_NGMRES, CP_METHOD_ALS, CP_METHOD_NCG = 0, 1, 2
+CP_METHOD_NGMRES, CP_METHOD_ALS, CP_METHOD_NCG, CP_METHOD_NGMRES_SD = 0, 1, 2, 3
 CP_INIT_GIVEN, CP_INIT_SEEDED = 0, 1
 LS_STATUS = {0: "converged", 1: "maxfev", 2: "xtol", 3: "stpmax", 4: "stpmin", 5: "rounding",
              -1: ""}
@@ -43,7 +43,8 @@ class cp_tensor(C.Structure):
 class cp_iter_info(C.Structure):
     _fields_ = [("it", C.c_int32), ("f", C.c_double), ("rho", C.c_double), ("beta", C.c_double),
                 ("restart", C.c_int32), ("nfev", C.c_int32), ("ls_status", C.c_int32),
-                ("m", C.c_int32), ("precision", C.c_int32), ("t_passes", C.c_int32)]
+                ("m", C.c_int32), ("precision", C.c_int32), ("t_passes", C.c_int32),
+                ("nfev_pre", C.c_int32)]
 
 
 class cp_options(C.Structure):
@@ -366,7 +367,8 @@ def options(**kw):
         if k in ("precision", "final_precision") and isinstance(v, str):
             v = PREC[v]
         if k == "method" and isinstance(v, str):
-            v = {"ngmres": CP_METHOD_NGMRES, "als": CP_METHOD_ALS, "ncg": CP_METHOD_NCG}[v]
+            v = {"ngmres": CP_METHOD_NGMRES, "als": CP_METHOD_ALS, "ncg": CP_METHOD_NCG,
+                 "ngmres_sd": CP_METHOD_NGMRES_SD}[v]
         if k == "init" and isinstance(v, str):
             v = {"given": CP_INIT_GIVEN, "seeded": CP_INIT_SEEDED}[v]
         setattr(o, k, v)
@@ -488,7 +490,7 @@ def ngmres_step(state: NGMRESState):
 def _info_dict(r: cp_iter_info):
     return {"it": r.it, "f": r.f, "rho": r.rho, "beta": r.beta, "restart": bool(r.restart),
             "nfev": r.nfev, "ls_status": LS_STATUS.get(r.ls_status, str(r.ls_status)), "m": r.m,
-            "precision": r.precision, "t_passes": r.t_passes}
+            "precision": r.precision, "t_passes": r.t_passes, "nfev_pre": r.nfev_pre}
 
 
 def cp_decompose(h: Handle, T: Tensor, R: int, tol: float, u_inout, trace_cap=0, **opts):

@@ -225,6 +225,8 @@ int sub_to(cp_handle* h, const double* a, const double* b, double* y, int64_t n,
            hipStream_t st);    // y = a - b
 int cg_direction(cp_handle* h, const double* g, double gamma, double* d, int64_t n,
                  hipStream_t st);   // d = -g + gamma d
+int neg_div_to(cp_handle* h, const double* x, double s, double* y, int64_t n,
+               hipStream_t st);     // y = -x / s
 
 // u[i] = i-th double of the seeded Philox-4x64-10 stream (key (seed, 0),
 // block b from counter b + 1), in [0, 1)

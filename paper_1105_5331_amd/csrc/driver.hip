@@ -59,6 +59,9 @@ namespace {
 
 bool is_f64_acc(int p) { return p == CP_PREC_FP64 || p == CP_PREC_FP32IN_FP64ACC; }
 
+// N-GMRES with either one-step process keeps the window of iterates
+bool uses_window(int method) { return method == CP_METHOD_NGMRES || method == CP_METHOD_NGMRES_SD; }
+
 int check_prec(cp_handle* h, const cp_tensor* T, int p) {
   if (p < 0 || p > 3) return fail(h, CP_EINVAL, "unknown precision %d", p);
   if ((p == CP_PREC_FP32 || p == CP_PREC_BF16X3) && T->dtype != CP_F32)
@@ -300,21 +303,27 @@ enum { LS_CONVERGED = 0, LS_MAXFEV = 1, LS_XTOL = 2, LS_STPMAX = 3, LS_STPMIN = 
 
 enum { PHASE_STEP12 = 0, PHASE_EVAL = 1 };
 
-// The device work of Steps I and II: u_bar = M(u_i), f and g at u_bar, the
-// accelerated u_hat over the window, d = u_hat - u_bar and the slope
-// g(u_bar)^T d (scal[0], scal[1]).
-int enqueue_step12(cp_handle* h, cp_ngmres_state* S) {
-  CP_HIP(h, hipMemcpyAsync(S->dpar, S->hpar, sizeof(StepPar), hipMemcpyHostToDevice, S->st));
-  CP_HIP(h, hipMemcpyAsync(S->ubar, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
-  CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0));
-  CP_TRY(objective_grad_impl(h, S->T, S->s, S->ubar, S->R, S->prec, S->scal, S->gbar, S->st,
-                             S->opt.mttkrp_tree != 0));
+// The device work of Step II from u_bar and g_bar: the accelerated u_hat
+// over the window (normalised), d = u_hat - u_bar and the slope g(u_bar)^T d
+// (scal[1]).  Expects the window size and oldest slot in S->dpar.
+int enqueue_step2(cp_handle* h, cp_ngmres_state* S) {
   CP_TRY(step2(h, S->L, S->winU, S->winG, S->wcap, S->dpar, S->ubar, S->gbar, S->opt.eps,
                S->uhat, S->scal + 8, S->st));
   if (S->opt.normalize_accel) CP_TRY(normalize(h, S->s, S->uhat, S->R, nullptr, S->st));
   CP_TRY(sub_to(h, S->uhat, S->ubar, S->d, S->L, S->st));
   CP_TRY(dot(h, S->gbar, S->d, S->L, S->scal + 1, S->st));
   return CP_OK;
+}
+
+// The device work of Steps I and II with ALS as the one-step process: u_bar =
+// M(u_i), f and g at u_bar (scal[0]), then Step II (scal[1]).
+int enqueue_step12(cp_handle* h, cp_ngmres_state* S) {
+  CP_HIP(h, hipMemcpyAsync(S->dpar, S->hpar, sizeof(StepPar), hipMemcpyHostToDevice, S->st));
+  CP_HIP(h, hipMemcpyAsync(S->ubar, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
+  CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0));
+  CP_TRY(objective_grad_impl(h, S->T, S->s, S->ubar, S->R, S->prec, S->scal, S->gbar, S->st,
+                             S->opt.mttkrp_tree != 0));
+  return enqueue_step2(h, S);
 }
 
 // The device work of one line-search trial: u_t = u_bar + beta d, f and g
@@ -594,6 +603,49 @@ int ncg_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* rec, int* rc_out) {
   S->rho = std::sqrt(std::max(0.0, v[2])) / S->normT;
   if (!std::isfinite(S->f) || !std::isfinite(S->rho))
     return fail(h, CP_ENOTFINITE, "objective or gradient not finite");
+  return CP_OK;
+}
+
+// Step I with steepest descent as the one-step process (CP_METHOD_NGMRES_SD):
+// d = -g/||g||_2 from u_i, the Moré–Thuente search of Step III along it from
+// S->ubar = u_i, u_bar = u_i + beta d (the last trial point itself when it
+// was accepted), normalised with the accepted gradient carried over (Section
+// 2.3 end).  A zero gradient leaves u_bar = u_i, g_bar = g_i.  On return
+// S->ubar, S->gbar hold u_bar, g(u_bar) and *fbar is f(u_bar).
+int sd_step1(cp_handle* h, cp_ngmres_state* S, double* fbar, int* nfev_out) {
+  const int64_t L = S->L;
+  const size_t bytes = sizeof(double) * L;
+  *nfev_out = 0;
+  *fbar = S->f;
+  CP_TRY(dot(h, S->g, S->g, L, S->scal + 4, S->st));
+  double gg;
+  CP_TRY(readback(h, S->scal + 4, 1, &gg, S->st));
+  const double gn = std::sqrt(std::max(0.0, gg));
+  CP_HIP(h, hipMemcpyAsync(S->ubar, S->u, bytes, hipMemcpyDeviceToDevice, S->st));
+  if (!(gn > 0.0)) {
+    CP_HIP(h, hipMemcpyAsync(S->gbar, S->g, bytes, hipMemcpyDeviceToDevice, S->st));
+    return CP_OK;
+  }
+  CP_TRY(neg_div_to(h, S->g, gn, S->d, L, S->st));
+  double slope;
+  CP_TRY(dot(h, S->g, S->d, L, S->scal + 4, S->st));
+  CP_TRY(readback(h, S->scal + 4, 1, &slope, S->st));
+  double beta = 0.0, fnew = S->f;
+  int status = 0;
+  const double* gacc = nullptr;
+  CP_TRY(more_thuente(h, S, S->f, slope, &beta, &fnew, &gacc, nfev_out, &status));
+  if (!gacc) {
+    beta = 0.0;
+    fnew = S->f;
+  }
+  const double* gnew = gacc ? gacc : S->g;
+  if (beta != 0.0) {
+    if (gnew == S->gt) CP_HIP(h, hipMemcpyAsync(S->ubar, S->ut, bytes, hipMemcpyDeviceToDevice, S->st));
+    else CP_TRY(axpy_to(h, S->u, beta, S->d, S->ubar, L, S->st));
+  }
+  CP_HIP(h, hipMemcpyAsync(S->gbar, gnew, bytes, hipMemcpyDeviceToDevice, S->st));
+  CP_TRY(normalize(h, S->s, S->ubar, S->R, S->gbar, S->st));
+  *fbar = fnew;
   return CP_OK;
 }
 
@@ -955,7 +1007,8 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
   if (opt) o = *opt;
   else cp_options_default(&o);
   if (o.window < 1 || o.window > 64) return fail(h, CP_EINVAL, "window must be in 1..64");
-  if (o.method != CP_METHOD_NGMRES && o.method != CP_METHOD_ALS && o.method != CP_METHOD_NCG)
+  if (o.method != CP_METHOD_NGMRES && o.method != CP_METHOD_ALS && o.method != CP_METHOD_NCG &&
+      o.method != CP_METHOD_NGMRES_SD)
     return fail(h, CP_EINVAL, "unknown method %d", o.method);
   if (o.ls_maxfev < 1 || !(o.ls_stp0 > 0.0)) return fail(h, CP_EINVAL, "bad line-search options");
   if (o.init != CP_INIT_GIVEN && o.init != CP_INIT_SEEDED)
@@ -972,7 +1025,7 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
   S->st = st;
   S->prec = o.precision;
   S->normT = std::sqrt(T->norm_sq);
-  S->wcap = o.method == CP_METHOD_NGMRES ? o.window : 1;
+  S->wcap = uses_window(o.method) ? o.window : 1;
   const size_t nvec = 9 + 2 * (size_t)S->wcap;
   if (hipMalloc(&S->mem, sizeof(double) * (nvec * S->L + 80)) != hipSuccess) {
     delete S;
@@ -1044,7 +1097,7 @@ int cp_ngmres_save(cp_handle* h, cp_ngmres_state* S, double* U_out, double* G_ou
   if (!h || !S) return CP_EINVAL;
   CP_HIP(h, hipSetDevice(h->device));
   const size_t bytes = sizeof(double) * S->L;
-  const int m = S->opt.method == CP_METHOD_NGMRES ? S->wcount : 0;
+  const int m = uses_window(S->opt.method) ? S->wcount : 0;
   for (int j = 0; j < m; ++j) {
     if (U_out) CP_HIP(h, hipMemcpyAsync(U_out + (size_t)j * S->L, win_u(S, j), bytes, hipMemcpyDeviceToDevice, S->st));
     if (G_out) CP_HIP(h, hipMemcpyAsync(G_out + (size_t)j * S->L, win_g(S, j), bytes, hipMemcpyDeviceToDevice, S->st));
@@ -1073,7 +1126,7 @@ int cp_ngmres_load(cp_handle* h, cp_ngmres_state* S, const double* U, const doub
                    const double* u, const double* g, const double* d, const cp_ngmres_meta* meta) {
   if (!h || !S || !meta || !u || !g) return fail(h, CP_EINVAL, "null state, iterate or meta");
   CP_HIP(h, hipSetDevice(h->device));
-  const bool ngm = S->opt.method == CP_METHOD_NGMRES;
+  const bool ngm = uses_window(S->opt.method);
   if (ngm && (meta->m < 1 || meta->m > S->wcap || !U || !G))
     return fail(h, CP_EINVAL, "window of %d entries (capacity %d) needs U and G", meta->m, S->wcap);
   if (S->opt.method == CP_METHOD_NCG && !meta->cg_fresh && !d)
@@ -1108,7 +1161,7 @@ int cp_ngmres_load(cp_handle* h, cp_ngmres_state* S, const double* U, const doub
 int cp_ngmres_last_step(cp_handle* h, cp_ngmres_state* S, double* u_bar, double* g_bar,
                         double* u_hat, double* d, double* f_bar, double* slope) {
   if (!h || !S) return CP_EINVAL;
-  if (!S->have_last || S->opt.method != CP_METHOD_NGMRES)
+  if (!S->have_last || !uses_window(S->opt.method))
     return fail(h, CP_EINVAL, "no N-GMRES iteration taken yet");
   CP_HIP(h, hipSetDevice(h->device));
   const size_t bytes = sizeof(double) * S->L;
@@ -1132,7 +1185,7 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
   rec.rho = S->rho;
   rec.beta = NAN;
   rec.ls_status = -1;
-  rec.m = S->opt.method == CP_METHOD_NGMRES ? S->wcount : 0;
+  rec.m = uses_window(S->opt.method) ? S->wcount : 0;
   rec.precision = S->prec;
   const int64_t passes0 = h->t_passes;
   int rc = CP_OK;
@@ -1145,11 +1198,20 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
     // Steps I and II: u_bar = M(u_i); f, g at u_bar; u_hat over the window
     S->hpar->m = S->wcount;
     S->hpar->whead = S->whead;
-    CP_TRY(run_phase(h, S, PHASE_STEP12));
-    S->n_fg++;
-    double fs[2];   // f(u_bar) and the slope g(u_bar)^T d in one readback
-    CP_TRY(readback(h, S->scal, 2, fs, S->st));
-    const double fbar = fs[0], slope = fs[1];
+    double fbar, slope;
+    if (S->opt.method == CP_METHOD_NGMRES_SD) {
+      CP_TRY(sd_step1(h, S, &fbar, &rec.nfev_pre));
+      CP_HIP(h, hipMemcpyAsync(S->dpar, S->hpar, sizeof(StepPar), hipMemcpyHostToDevice, S->st));
+      CP_TRY(enqueue_step2(h, S));
+      CP_TRY(readback(h, S->scal + 1, 1, &slope, S->st));
+    } else {
+      CP_TRY(run_phase(h, S, PHASE_STEP12));
+      S->n_fg++;
+      double fs[2];   // f(u_bar) and the slope g(u_bar)^T d in one readback
+      CP_TRY(readback(h, S->scal, 2, fs, S->st));
+      fbar = fs[0];
+      slope = fs[1];
+    }
     S->have_last = true;
     S->last_fbar = fbar;
     S->last_slope = slope;
@@ -1251,7 +1313,7 @@ int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const 
       if (o.trace && ntr < o.trace_cap) {
         cp_iter_info r{};
         r.it = S->it; r.f = S->f; r.rho = S->rho; r.beta = NAN; r.ls_status = -1;
-        r.m = o.method == CP_METHOD_NGMRES ? S->wcount : 0;
+        r.m = uses_window(o.method) ? S->wcount : 0;
         r.precision = S->prec;
         o.trace[ntr++] = r;
       }

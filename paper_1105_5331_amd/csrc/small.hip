@@ -1035,6 +1035,13 @@ __global__ void axpy_kernel(const double* __restrict__ x, double a, const double
   if (e < n) y[e] = fma(a, d[e], x[e]);
 }
 
+// y = -x / s
+__global__ void neg_div_kernel(const double* __restrict__ x, double s, double* __restrict__ y,
+                               int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = -x[e] / s;
+}
+
 // d = -g + gamma d (d = -g exactly when gamma = 0)
 __global__ void cg_direction_kernel(const double* __restrict__ g, double gamma,
                                     double* __restrict__ d, int64_t n) {
@@ -1458,6 +1465,13 @@ int copy2(cp_handle* h, const double* x1, double* y1, const double* x2, double* 
           hipStream_t st) {
   if (n == 0) return CP_OK;
   hipLaunchKernelGGL(copy2_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, x1, y1, x2, y2, n);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
+int neg_div_to(cp_handle* h, const double* x, double s, double* y, int64_t n, hipStream_t st) {
+  if (n == 0) return CP_OK;
+  hipLaunchKernelGGL(neg_div_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, x, s, y, n);
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }

@@ -44,12 +44,12 @@ RHO_ABS = 1e-9    # ... + this absolute floor
 BETA_REL = 1e-2   # |beta_gpu - beta_oracle| / max(1, |beta_oracle|)
 
 
-def compare_trajectory(trace, ref_trace, half, what):
+def compare_trajectory(trace, ref_trace, half, what, f_tol=F_TOL):
     """Compare GPU trace records (dicts) with the oracle's IterRecords until
     the first discrete divergence; returns the number of iterates compared."""
     n = 0
     for a, b in zip(trace, ref_trace):
-        assert abs(a["f"] - b.f) <= F_TOL * half, f"{what} it {b.it}: f {a['f']} vs {b.f}"
+        assert abs(a["f"] - b.f) <= f_tol * half, f"{what} it {b.it}: f {a['f']} vs {b.f}"
         assert abs(a["rho"] - b.rho) <= RHO_REL * b.rho + RHO_ABS, \
             f"{what} it {b.it}: rho {a['rho']} vs {b.rho}"
         n += 1

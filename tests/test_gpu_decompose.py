@@ -316,3 +316,72 @@ def test_ncg_trajectory_dense_fp64(h, seed):
     n = _compare(out["trace"], ref.trace, half, f"ncg seed {seed}")
     assert n >= min(len(ref.trace), 10)
     assert out["converged"] == ref.converged
+
+
+# Steepest descent as the one-step process is more sensitive to rounding than
+# ALS: the oracle against itself with u0 perturbed by 1e-15 relative moves f
+# by up to 1.0e-9 of 1/2 ||T||^2 (seed 1, a slow run still at rho ~ 0.1 after
+# 55 iterations; 9e-13 on seed 0) before any discrete divergence, so the
+# objective is compared at ten times that.
+F_TOL_SD = 1e-8
+
+
+def _sd_agree(trace, rec):
+    """Index of the first iteration whose Step I line search took a different
+    number of evaluations on the two sides (a discrete divergence of the
+    steepest-descent process), or the end of the shorter run."""
+    for k, (a, r) in enumerate(zip(trace, rec)):
+        if a["nfev_pre"] != r["nfev_pre"]:
+            return k
+    return min(len(trace), len(rec))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ngmres_sd_trajectory_small_dense_fp64(h, seed):
+    """N-GMRES with steepest descent as the one-step process (CP_METHOD_NGMRES_SD)
+    against the oracle's ngmres(precond="sd"): dense 20x20x20, R = 3, FP64,
+    compared iterate by iterate (f, rho, restart, window, Step III trials and
+    beta) until the first discrete divergence; the Step I line search takes as
+    many evaluations on both sides while they agree."""
+    import paper_1105_5331_amd as cpng
+    dims, R, tol = (20, 20, 20), 3, 1e-8
+    print(f"case ngmres-sd trajectory seed={seed}", flush=True)
+    p = test_problem_1(dims, R, 0.5, 1, 1, seed=seed)
+    u0 = initial_guess(dims, R, seed=seed + 10000)
+    rec = []
+    ref = ngmres(CPProblem(ocp.DenseTensor(p.T), R), u0, tol=tol, max_iter=150, precond="sd",
+                 record=rec)
+    Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
+    cpng.cp_tensor_prepare(h, Tg)
+    u = _dev(u0)
+    out = cpng.cp_decompose(h, Tg, R, tol, u, trace_cap=200, max_iter=150, method="ngmres_sd")
+    half = 0.5 * np.sum(p.T ** 2)
+    k = _sd_agree(out["trace"], rec)
+    n = _compare(out["trace"][:k + 1], ref.trace[:k + 1], half, f"sd seed {seed}", F_TOL_SD)
+    assert n >= min(len(ref.trace), 5)
+    assert all(t["nfev_pre"] >= 1 for t in out["trace"][:-1])
+    # both runs decrease f well below its start; the GPU's objective sequence is monotone
+    fs = [t["f"] for t in out["trace"]]
+    assert all(b <= a + 1e-13 * half for a, b in zip(fs, fs[1:]))
+    assert fs[-1] < 0.5 * fs[0]
+
+
+def test_ngmres_sd_trajectory_sparse(h):
+    """The same on the paper's sparse Test Problem II (d = 2, s = 4: order 4,
+    COO), FP64."""
+    import paper_1105_5331_amd as cpng
+    print("case ngmres-sd trajectory sparse", flush=True)
+    tp = test_problem_2(2, 4)
+    R, tol = 3, 1e-8
+    u0 = initial_guess(tp.dims, R, seed=20001)
+    rec = []
+    ref = ngmres(CPProblem(ocp.CooTensor(tp.dims, tp.coords, tp.values), R), u0, tol=tol,
+                 max_iter=100, precond="sd", record=rec)
+    Tg = cpng.Tensor(tp.dims, _dev(tp.values), coords=_dev(tp.coords))
+    cpng.cp_tensor_prepare(h, Tg)
+    u = _dev(u0)
+    out = cpng.cp_decompose(h, Tg, R, tol, u, trace_cap=200, max_iter=100, method="ngmres_sd")
+    half = 0.5 * float(np.sum(tp.values ** 2))
+    k = _sd_agree(out["trace"], rec)
+    n = _compare(out["trace"][:k + 1], ref.trace[:k + 1], half, "sd sparse", F_TOL_SD)
+    assert n >= min(len(ref.trace), 5)
