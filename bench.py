@@ -389,7 +389,7 @@ def _accuracy_row(runs, row):
     return row
 
 
-def paper_tables(h, cpng, torch, max_iter=2000):
+def paper_tables(h, cpng, torch, max_iter=2000, parts=("tp1", "tp2")):
     """The paper's dense (Test Problem I, Tables 1-3) and sparse (Test Problem
     II, Tables 4-6) comparisons at the paper's sizes: ALS, N-GMRES and N-CG on
     the GPU, iterations and seconds until |h(u_i) - h*| <= 1e-3, 1e-6, 1e-10.
@@ -397,7 +397,7 @@ def paper_tables(h, cpng, torch, max_iter=2000):
     exact counts are not."""
     from workloads import initial_guess, test_problem_1, test_problem_2
     out = {"tp1": [], "tp2": []}
-    for k, (sz, c, R, l1, l2) in enumerate(TP1_CASES):
+    for k, (sz, c, R, l1, l2) in enumerate(TP1_CASES if "tp1" in parts else []):
         dims = (sz, sz, sz)
         p = test_problem_1(dims, R, c, l1, l2, seed=k)
         Tg = cpng.Tensor(dims, torch.from_numpy(p.T).cuda().reshape(-1))
@@ -408,7 +408,7 @@ def paper_tables(h, cpng, torch, max_iter=2000):
         log("tp1 case %d: " % (k + 1) + ", ".join(f"{m} it(1e-10)={row[m + '_it_1e-10']}"
                                                  for m in runs))
         out["tp1"].append(row)
-    for N, sz, R in TP2_CASES:
+    for N, sz, R in (TP2_CASES if "tp2" in parts else []):
         tp = test_problem_2(N // 2, sz)
         Tg = cpng.Tensor(tp.dims, torch.from_numpy(tp.values).cuda(),
                          coords=torch.from_numpy(tp.coords).cuda())
@@ -813,6 +813,9 @@ def main():
         res["extra"]["sparse_mttkrp_20000cubed_R16"] = sparse_mttkrp(h, cpng, torch)
         log("serving stream (32 requests)")
         res["extra"]["serving"] = serving(cpng, torch, n=32)
+        log("paper Tables 4-6: Test Problem II at the paper's sizes (ALS, N-GMRES, N-CG)")
+        res["extra"]["paper_tables_tp2"] = paper_tables(h, cpng, torch, max_iter=1000,
+                                                        parts=("tp2",))["tp2"]
         log("small dense 20^3 (GPU vs oracle)")
         res["extra"]["small_dense_20cubed_R3"] = small_dense(h, cpng, torch)
         if not args.skip_cpu:

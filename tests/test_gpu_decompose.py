@@ -385,3 +385,29 @@ def test_ngmres_sd_trajectory_sparse(h):
     k = _sd_agree(out["trace"], rec)
     n = _compare(out["trace"][:k + 1], ref.trace[:k + 1], half, "sd sparse", F_TOL_SD)
     assert n >= min(len(ref.trace), 5)
+
+
+# Test Problem II at the paper's sizes (Section 4, Tables 4-6): order N = 2d,
+# grid size s, rank R, nnz = s^d + 2 d s^(d-1) (s - 1).
+TP2_PAPER = [(4, 8, 6), (4, 16, 3), (6, 4, 2), (6, 8, 5), (8, 4, 2)]
+
+
+@pytest.mark.parametrize("N,s,R", TP2_PAPER, ids=lambda v: str(v))
+def test_ngmres_trajectory_tp2_paper_sizes(h, N, s, R):
+    """N-GMRES on the sparse Laplacian tensors of the paper's Tables 4-6, FP64,
+    GPU against the oracle from the same initial guess, iterate by iterate
+    until the first discrete divergence (at most 60 iterations)."""
+    import paper_1105_5331_amd as cpng
+    print(f"case tp2 paper size N={N} s={s} R={R}", flush=True)
+    tp = test_problem_2(N // 2, s)
+    assert tp.values.size == s ** (N // 2) + N * s ** (N // 2 - 1) * (s - 1)
+    u0 = initial_guess(tp.dims, R, seed=20000)
+    ref = ngmres(CPProblem(ocp.CooTensor(tp.dims, tp.coords, tp.values), R), u0, tol=1e-8,
+                 max_iter=60)
+    Tg = cpng.Tensor(tp.dims, _dev(tp.values), coords=_dev(tp.coords))
+    cpng.cp_tensor_prepare(h, Tg)
+    u = _dev(u0)
+    out = cpng.cp_decompose(h, Tg, R, 1e-8, u, trace_cap=80, max_iter=60)
+    half = 0.5 * float(np.sum(tp.values ** 2))
+    n = _compare(out["trace"], ref.trace, half, f"tp2 N={N} s={s}")
+    assert n >= min(len(ref.trace), 5)
