@@ -213,13 +213,26 @@ def sparse_mttkrp(h, cpng, torch, nnz_draw=20_000_000, R=16, reps=10):
         nl, ms = cpng.cp_profile_read(h, cpng.CP_KERNEL_SPARSE_MTTKRP)
         cpng.cp_profile(h, False)
         us = ms / nl * 1e3
+        # the same mode's factor-row gathers alone (measurement reference)
+        for _ in range(2):
+            cpng.cp_sparse_gather_read(h, Tg, u, R, n)
+        torch.cuda.synchronize()
+        cpng.cp_profile(h, True)
+        for _ in range(reps):
+            cpng.cp_sparse_gather_read(h, Tg, u, R, n)
+        torch.cuda.synchronize()
+        ngl, gms = cpng.cp_profile_read(h, cpng.CP_KERNEL_SPARSE_GATHER)
+        cpng.cp_profile(h, False)
+        gus = gms / ngl * 1e3
         # sorted copy read once (row index, other two coordinates, value:
         # 16 B per nonzero), the two other factors (float32) once, the output
         # (float64) written once
         alg = nnz * 16 + 2 * dims[0] * R * 4 + dims[n] * R * 8
         per_mode.append({"mode": n, "kernel_us": round(us, 1),
                          "GBs": round(alg / (us * 1e-6) / 1e9, 1),
-                         "frac": round(alg / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)})
+                         "frac": round(alg / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                         "gather_reference_us": round(gus, 1),
+                         "frac_of_gather_reference": round(gus / us, 4)})
         log(f"sparse mode {n}: {per_mode[-1]}")
     cpng.cp_tensor_release(h, Tg)
     return {"nnz": int(nnz), "rank": R, "prepare_s": round(prep, 3), "modes": per_mode}
@@ -726,7 +739,7 @@ def main():
         if n_l:
             kern[kid] = (n_l, ms_l)
     cpng.cp_profile(h, False)
-    cpng.cp_profile_select(h, 0x1F)
+    cpng.cp_profile_select(h, 0x3F)
     elem = 8 if args.precision == "fp64" else 4
     value = passes * nT * elem / dt / 1e9
     # the achievable streaming read of the same buffer (our reference kernel)

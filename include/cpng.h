@@ -439,14 +439,15 @@ int cp_server_destroy(cp_server* s);
                                        MTTKRP from its group's partial contraction */
 #define CP_KERNEL_DENSE_MTTKRP_F64 4 /* main dense MTTKRP kernel, float64-accumulating
                                        precisions (CP_PREC_FP64, CP_PREC_FP32IN_FP64ACC) */
+#define CP_KERNEL_SPARSE_GATHER 5   /* cp_sparse_gather_read */
 
 /* Enable (1) or disable (0) HIP-event timing of the main MTTKRP kernels on
  * the stream each is launched on; enabling clears the counters. */
 int cp_profile(cp_handle* h, int32_t enable);
 /* Which kernel ids cp_profile times: bit k of kernel_mask selects id k
- * (default 0x1F, all five).  Each timed launch adds two event records to its
+ * (default 0x3F, all six).  Each timed launch adds two event records to its
  * stream, so timing only the kernel being measured keeps the others' launch
- * gaps out of a timed run.  CP_EINVAL for bits above 4. */
+ * gaps out of a timed run.  CP_EINVAL for bits above 5. */
 int cp_profile_select(cp_handle* h, uint32_t kernel_mask);
 /* Synchronise the recorded events and return, for kernel id `kernel`, the
  * number of timed launches and their summed duration in milliseconds
@@ -461,6 +462,19 @@ int cp_profile_read(cp_handle* h, int32_t kernel, int64_t* launches, double* tot
  * is on: the achievable streaming-read bandwidth that the MTTKRP rooflines
  * are also compared with. */
 int cp_stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t stream);
+
+/* Measurement reference (not part of the method): the factor-row gathers of
+ * the sparse FP32 MTTKRP of `mode` alone.  For every nonzero of the prepared
+ * tensor's mode-sorted copy it reads the other modes' coordinates and the
+ * corresponding rows of the padded float32 factor copy, with the MTTKRP
+ * kernel's waves, lane groups and 16-byte loads, and keeps one value per
+ * wave in library workspace: no values, row indices, products with the
+ * tensor or segmented reduction.  Timed under CP_KERNEL_SPARSE_GATHER while
+ * profiling is on: the achievable gather rate that the sparse MTTKRP is
+ * compared with.  Errors: CP_EINVAL (dense or unprepared tensor, R outside
+ * 1..64, mode out of range). */
+int cp_sparse_gather_read(cp_handle* h, const cp_tensor* T, const double* u, int32_t R,
+                          int32_t mode, hipStream_t stream);
 
 #ifdef __cplusplus
 }

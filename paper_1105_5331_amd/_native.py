@@ -134,6 +134,7 @@ def lib():
             "cp_profile_select": (C.c_int, [vp, C.c_uint32]),
             "cp_profile_read": (C.c_int, [vp, i32, C.POINTER(i64), C.POINTER(dp)]),
             "cp_stream_read": (C.c_int, [vp, vp, C.c_size_t, vp]),
+            "cp_sparse_gather_read": (C.c_int, [vp, C.POINTER(cp_tensor), vp, i32, i32, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -459,13 +460,20 @@ class NGMRESState:
 
 
 CP_KERNEL_DENSE_MTTKRP, CP_KERNEL_SPARSE_MTTKRP, CP_KERNEL_STREAM_READ, CP_KERNEL_GROUP_MTTKRP = 0, 1, 2, 3
-CP_KERNEL_DENSE_MTTKRP_F64 = 4
+CP_KERNEL_DENSE_MTTKRP_F64, CP_KERNEL_SPARSE_GATHER = 4, 5
 
 
 def cp_stream_read(h: Handle, buf):
     """Streaming-read reference kernel over a device tensor (measurement only)."""
     nbytes = buf.numel() * buf.element_size()
     h.check(lib().cp_stream_read(h._h, buf.data_ptr(), nbytes, _stream()))
+
+
+def cp_sparse_gather_read(h: Handle, T: Tensor, u, R: int, mode: int):
+    """The sparse FP32 MTTKRP's factor-row gathers alone (measurement only)."""
+    h.check(lib().cp_sparse_gather_read(h._h, C.byref(T.c),
+                                        _ptr(u, torch.float64, iterate_length(T.dims, R), "u"),
+                                        int(R), int(mode), _stream()))
 
 
 def cp_profile(h: Handle, enable: bool):

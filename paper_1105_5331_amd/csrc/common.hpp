@@ -55,11 +55,11 @@ struct cp_handle {
   int* flags = nullptr;       // device status word (ALS solve fallbacks)
   // optional event timing of the main MTTKRP kernels
   bool prof = false;
-  static constexpr int kKernelIds = 5;
-  uint32_t prof_mask = 0x1Fu;   // kernel ids timed while prof is on
+  static constexpr int kKernelIds = 6;
+  uint32_t prof_mask = 0x3Fu;   // kernel ids timed while prof is on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[kKernelIds];
-  int64_t prof_launches[kKernelIds] = {0, 0, 0, 0, 0};
-  double prof_ms[kKernelIds] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t prof_launches[kKernelIds] = {};
+  double prof_ms[kKernelIds] = {};
   // passes over a tensor's values made by MTTKRP launches (always counted)
   int64_t t_passes = 0;
   // Allocation-free calls (cp_mttkrp_noalloc): while `arena` is set, ensure()
@@ -170,6 +170,8 @@ int sparse_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double
                   int mode, int prec, double* M, hipStream_t st);
 int sparse_prepare(cp_handle* h, cp_tensor* T, const Shape& s, hipStream_t st);
 int sparse_release(cp_handle* h, cp_tensor* T);
+int sparse_gather_ref(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
+                      int mode, hipStream_t st);
 int stage_factors_f32(cp_handle* h, const double* u, int64_t L, float** out, hipStream_t st);
 int dense_fast_bf16x3(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
                       int mode, double* M, hipStream_t st);

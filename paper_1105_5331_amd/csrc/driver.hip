@@ -795,8 +795,21 @@ int cp_stream_read(cp_handle* h, const void* buf, size_t bytes, hipStream_t stre
   return stream_read(h, buf, bytes, stream);
 }
 
+int cp_sparse_gather_read(cp_handle* h, const cp_tensor* T, const double* u, int32_t R,
+                          int32_t mode, hipStream_t st) {
+  if (!h) return CP_EINVAL;
+  CP_HIP(h, hipSetDevice(h->device));
+  Shape s;
+  CP_TRY(check_tensor(h, T, &s));
+  if (!T->sparse) return fail(h, CP_EINVAL, "cp_sparse_gather_read needs a sparse tensor");
+  if (R < 1 || R > 64) return fail(h, CP_EINVAL, "rank %d outside 1..64", R);
+  if (mode < 0 || mode >= s.N) return fail(h, CP_EINVAL, "mode %d outside 0..%d", mode, s.N - 1);
+  if (!u) return fail(h, CP_EINVAL, "null factor pointer");
+  return sparse_gather_ref(h, T, s, u, R, mode, st);
+}
+
 int cp_profile_select(cp_handle* h, uint32_t kernel_mask) {
-  if (!h || (kernel_mask & ~0x1Fu) != 0) return CP_EINVAL;
+  if (!h || (kernel_mask & ~0x3Fu) != 0) return CP_EINVAL;
   h->prof_mask = kernel_mask;
   return CP_OK;
 }

@@ -269,6 +269,81 @@ __global__ __launch_bounds__(256) void sparse_wave_kernel(const TT* __restrict__
   group_flush<CT, VW, L>(acc, p.R, cur, nflush, true, lane, wid, M, crow, cval);
 }
 
+// Measurement reference: the factor-row gathers of sparse_wave_kernel alone.
+// The same waves, ranges, lane groups, coordinate stream (non-temporal, one
+// nonzero per lane, handed out by shuffles) and 16-byte row loads; the rows of
+// a nonzero are multiplied into a running per-lane product (so every load is
+// used) instead of being weighted by the value and reduced by row.  Each wave
+// writes one float.  What it measures is the rate at which these random
+// factor-row reads can be served, the bound the MTTKRP cannot beat.
+template <typename CT, int L, int KM>
+__global__ __launch_bounds__(256) void sparse_gather_ref_kernel(const CT* __restrict__ fac,
+                                                                SparseParams p,
+                                                                float* __restrict__ out) {
+  constexpr int VW = VecOf<CT>::n;
+  constexpr int G = 64 / L;
+  constexpr int J = L < 8 ? L : 8;
+  constexpr int S = G * J;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / L;
+  const int c = lane % L;
+  const bool lane_ok = c * VW < p.Rp;
+  const int cc = lane_ok ? c * VW : 0;
+  const int km = KM < CP_MAX_ORDER - 1 ? KM : p.N - 1;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t z0 = wid * p.wave_nnz;
+  if (z0 >= p.nnz) return;
+  const int64_t z1 = min<int64_t>(p.nnz, z0 + p.wave_nnz);
+  CT acc = CT(0);
+  for (int64_t zb = z0; zb < z1; zb += S) {
+    const int nstep = (int)min<int64_t>(S, z1 - zb);
+    const bool mine = lane < nstep;
+    const int64_t zm = mine ? zb + lane : z0;
+    int32_t my_c[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+      my_c[k] = k < km ? __builtin_nontemporal_load(p.coords + (int64_t)k * p.nnz + zm) : 0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int src = g * J + j;
+      CT prod[VW];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) prod[v] = CT(1);
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (k < km) {
+          const int32_t ck = __shfl(my_c[k], src);
+          CT f[VW];
+          load_vec<CT, VW>(fac + p.foff[k] + (int64_t)ck * p.Rp + cc, f);
+#pragma unroll
+          for (int v = 0; v < VW; ++v) prod[v] *= f[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < VW; ++v) acc += src < nstep ? prod[v] : CT(0);
+    }
+  }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) acc += __shfl_xor(acc, m);
+  if (lane == 0) out[wid] = (float)acc;
+}
+
+template <typename CT, int L>
+int launch_gather_ref(cp_handle* h, const CT* fac, const SparseParams& p, hipStream_t st) {
+  const int64_t nwaves = (p.nnz + p.wave_nnz - 1) / p.wave_nnz;
+  CP_TRY(ensure(h, h->carry, sizeof(float) * (size_t)std::max<int64_t>(1, nwaves), st));
+  float* out = static_cast<float*>(h->carry.ptr);
+  KernelTimer timer(h, CP_KERNEL_SPARSE_GATHER, st);
+  if (p.N == 3)
+    CP_TIMED_LAUNCH(timer, (sparse_gather_ref_kernel<CT, L, 2>), dim3(nblk(nwaves * 64, 256)), dim3(256), 0, st, fac, p, out);
+  else if (p.N == 4)
+    CP_TIMED_LAUNCH(timer, (sparse_gather_ref_kernel<CT, L, 3>), dim3(nblk(nwaves * 64, 256)), dim3(256), 0, st, fac, p, out);
+  else
+    CP_TIMED_LAUNCH(timer, (sparse_gather_ref_kernel<CT, L, CP_MAX_ORDER - 1>), dim3(nblk(nwaves * 64, 256)), dim3(256), 0, st, fac, p, out);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
 // For each run of equal rows among the carry slots, the first slot of the run
 // sums the run in slot order and writes the row.
 __global__ void carry_fixup_kernel(const int64_t* __restrict__ carry_row,
@@ -582,6 +657,34 @@ int sparse_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double
   if (sp->dtype == CP_F32)
     return dispatch_wave<float, double>(h, static_cast<const float*>(vals), rws, fac, p, M, st);
   return dispatch_wave<double, double>(h, static_cast<const double*>(vals), rws, fac, p, M, st);
+}
+
+// The gather reference of sparse_mttkrp(.., mode, CP_PREC_FP32, ..): the same
+// padded float32 factor copy and wave layout, the gathers alone.
+int sparse_gather_ref(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
+                      int mode, hipStream_t st) {
+  auto* sp = static_cast<const SparsePrepared*>(T->prepared);
+  if (!sp) return fail(h, CP_EINVAL, "sparse tensor is not prepared (cp_tensor_prepare)");
+  if (sp->nnz == 0) return CP_OK;
+  SparseParams p{};
+  p.N = s.N;
+  p.mode = mode;
+  p.R = R;
+  p.nnz = sp->nnz;
+  p.wave_nnz = wave_range(sp->nnz);
+  p.I_n = s.dims[mode];
+  p.coords = sp->mode[mode].coords;
+  p.seg = sp->mode[mode].seg;
+  p.Rp = (R + 3) / 4 * 4;
+  set_offsets(s, mode, p);
+  const float* fac = nullptr;
+  CP_TRY(padded_factors<float>(h, u, s.sum_dims(), R, p.Rp, &fac, st));
+  const int lanes = p.Rp / 4;
+  if (lanes <= 1) return launch_gather_ref<float, 1>(h, fac, p, st);
+  if (lanes <= 2) return launch_gather_ref<float, 2>(h, fac, p, st);
+  if (lanes <= 4) return launch_gather_ref<float, 4>(h, fac, p, st);
+  if (lanes <= 8) return launch_gather_ref<float, 8>(h, fac, p, st);
+  return launch_gather_ref<float, 16>(h, fac, p, st);
 }
 
 }  // namespace cpng

@@ -453,7 +453,7 @@ def test_profile_select_times_only_the_chosen_kernels(h):
     nd, msd = cpng.cp_profile_read(h, cpng.CP_KERNEL_DENSE_MTTKRP)
     ng, _ = cpng.cp_profile_read(h, cpng.CP_KERNEL_GROUP_MTTKRP)
     cpng.cp_profile(h, False)
-    cpng.cp_profile_select(h, 0x1F)
+    cpng.cp_profile_select(h, 0x3F)
     assert nd >= 1 and msd > 0 and ng == 0
     cpng.cp_profile(h, True)
     cpng.cp_objective_grad(h, Tg, u, R, "fp32")
@@ -471,7 +471,28 @@ def test_profile_select_times_only_the_chosen_kernels(h):
     cpng.cp_profile(h, False)
     assert n64 == 1 and n32 == 1
     with pytest.raises(cpng.CpError):
-        cpng.cp_profile_select(h, 1 << 5)
+        cpng.cp_profile_select(h, 1 << 6)
+
+
+def test_sparse_gather_reference(h):
+    """The sparse gather measurement kernel runs on a prepared COO tensor in
+    every mode, is timed under its own id, and rejects a dense tensor."""
+    cpng = _cpng()
+    sp = random_coo((300, 40, 50), 9000, seed=2, dtype=np.float32)
+    Tg = cpng.Tensor(sp.dims, _dev(sp.values), _dev(sp.coords))
+    cpng.cp_tensor_prepare(h, Tg)
+    R = 16
+    u = _dev(ocp.join_u(_factors(sp.dims, R, 3)))
+    cpng.cp_profile(h, True)
+    for n in range(3):
+        cpng.cp_sparse_gather_read(h, Tg, u, R, n)
+    torch.cuda.synchronize()
+    nl, ms = cpng.cp_profile_read(h, cpng.CP_KERNEL_SPARSE_GATHER)
+    cpng.cp_profile(h, False)
+    assert nl == 3 and ms > 0
+    Td = cpng.Tensor((4, 5, 6), _dev(np.ones(120, dtype=np.float32)))
+    with pytest.raises(cpng.CpError):
+        cpng.cp_sparse_gather_read(h, Td, _dev(np.ones(15 * R)), R, 0)
 
 
 def test_stream_read_reference(h):
