@@ -379,6 +379,38 @@ int cp_ngmres_last_step(cp_handle* h, cp_ngmres_state* st, double* u_bar, double
 int cp_decompose(cp_handle* h, const cp_tensor* T, int32_t R, double tol, const cp_options* opt,
                  double* u_inout, cp_report* rep_out, hipStream_t stream);
 
+/* ---- batched N-GMRES for small dense requests ---------------------------- */
+
+/* Largest tensor (entries) the batched path takes. */
+#define CP_BATCH_MAX_ELEMS (1 << 20)
+
+typedef struct cp_batch_request {
+  const cp_tensor* T;      /* dense float32, order 3 or 4, at most CP_BATCH_MAX_ELEMS entries,
+                              prepared (cp_tensor_prepare: ||T||^2) */
+  int32_t R;               /* 1..32 */
+  double tol;              /* stop once rho = ||g||_2 / ||T||_F <= tol */
+  double* u_inout;         /* device, L doubles: initial guess in, result out */
+  cp_iter_info* trace;     /* host, nullable: per-iteration records as cp_decompose writes them */
+  int32_t trace_cap;
+  int32_t status;          /* out: CP_OK (converged), CP_MAXITER or an error */
+  cp_report report;        /* out (seconds: the whole batch) */
+} cp_batch_request;
+
+/* Decompose n small dense tensors together by N-GMRES with ALS (Section 2.1,
+ * algorithm box; Section 2.3) in float64 arithmetic on the float32 values,
+ * with one kernel launch per step over all unfinished requests: each launch
+ * advances every request by one device phase (the start; Steps I-II; one
+ * line-search trial; the end of an iteration), one workgroup per request, and
+ * one readback of every request's scalars follows.  Each request's control
+ * (restart test, Moré-Thuente line search with the R13 fallback, window,
+ * stopping test) is its own, and every sum has a fixed order, so a request's
+ * result is bitwise the same alone or in any batch.  opt (nullable):
+ * method must be CP_METHOD_NGMRES, window <= 21; the precision fields are
+ * ignored.  Synchronises the stream.  Errors: CP_EINVAL (a request outside
+ * the batched path's limits), CP_ENOMEM; per-request errors in status. */
+int cp_batch_decompose(cp_handle* h, int32_t n, cp_batch_request* reqs, const cp_options* opt,
+                       hipStream_t stream);
+
 /* ---- serving: continuous batching of decomposition requests ------------- */
 
 typedef struct cp_server cp_server;

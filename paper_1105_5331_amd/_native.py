@@ -73,6 +73,12 @@ class cp_report(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class cp_batch_request(C.Structure):
+    _fields_ = [("T", C.POINTER(cp_tensor)), ("R", C.c_int32), ("tol", C.c_double),
+                ("u_inout", C.c_void_p), ("trace", C.POINTER(cp_iter_info)),
+                ("trace_cap", C.c_int32), ("status", C.c_int32), ("report", cp_report)]
+
+
 class cp_server_opts(C.Structure):
     _fields_ = [("slots", C.c_int32), ("hbm_budget", C.c_size_t), ("decompose", cp_options)]
 
@@ -123,6 +129,8 @@ def lib():
             "cp_ngmres_destroy": (C.c_int, [vp, vp]),
             "cp_decompose": (C.c_int, [vp, C.POINTER(cp_tensor), i32, dp, C.POINTER(cp_options),
                                        vp, C.POINTER(cp_report), vp]),
+            "cp_batch_decompose": (C.c_int, [vp, i32, C.POINTER(cp_batch_request),
+                                             C.POINTER(cp_options), vp]),
             "cp_server_create": (C.c_int, [C.c_int, C.POINTER(cp_server_opts), C.POINTER(vp)]),
             "cp_server_submit": (C.c_int, [vp, C.POINTER(cp_tensor), i32, dp, vp, C.c_uint64,
                                            C.POINTER(i64)]),
@@ -520,6 +528,42 @@ def cp_decompose(h: Handle, T: Tensor, R: int, tol: float, u_inout, trace_cap=0,
             "rho": rep.rho, "n_fg": rep.n_fg, "n_restarts": rep.n_restarts,
             "n_ls_fallback": rep.n_ls_fallback, "switch_iter": rep.switch_iter,
             "seconds": rep.seconds, "trace": trace}
+
+
+def _report_dict(rep):
+    return {"iters": rep.iters, "converged": bool(rep.converged), "f": rep.f, "rho": rep.rho,
+            "n_fg": rep.n_fg, "n_restarts": rep.n_restarts, "n_ls_fallback": rep.n_ls_fallback,
+            "switch_iter": rep.switch_iter, "seconds": rep.seconds}
+
+
+def cp_batch_decompose(h: Handle, tensors, ranks, tol, us, trace_cap=0, **opts):
+    """Batched N-GMRES of several small dense requests (one launch per step
+    over all of them); us[k] holds request k's initial guess and receives its
+    result.  Returns one dict per request (status, report, trace)."""
+    n = len(tensors)
+    o = options(**opts)
+    reqs = (cp_batch_request * max(1, n))()
+    bufs = []
+    for k, (T, R, u) in enumerate(zip(tensors, ranks, us)):
+        r = reqs[k]
+        r.T = C.pointer(T.c)
+        r.R = int(R)
+        r.tol = float(tol[k] if isinstance(tol, (list, tuple)) else tol)
+        r.u_inout = _ptr(u, torch.float64, iterate_length(T.dims, R), "u")
+        if trace_cap > 0:
+            buf = (cp_iter_info * trace_cap)()
+            bufs.append(buf)
+            r.trace = C.cast(buf, C.POINTER(cp_iter_info))
+            r.trace_cap = trace_cap
+        else:
+            bufs.append(None)
+    h.check(lib().cp_batch_decompose(h._h, n, reqs, C.byref(o), _stream()))
+    out = []
+    for k in range(n):
+        r = reqs[k]
+        tr = [_info_dict(bufs[k][i]) for i in range(r.report.n_trace)] if bufs[k] is not None else []
+        out.append({"status": r.status, **_report_dict(r.report), "trace": tr})
+    return out
 
 
 class Server:

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpng.so")
 SOURCES = ["dense_mttkrp.hip", "dense_fast.hip", "small.hip", "sparse.hip", "driver.hip",
-           "server.hip", "tree.hip"]
+           "server.hip", "tree.hip", "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

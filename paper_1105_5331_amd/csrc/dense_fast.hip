@@ -127,11 +127,12 @@ struct FlavBF16x3 {
     Sh[r * kpad + k] = h;
     Sh[32 * kpad + r * kpad + k] = (__bf16)(v - (float)h);
   }
-  __device__ static V mma(const Op& a, const Op& b, V c) {
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, c, 0, 0, 0);
-    return c;
+  // the products of one tile, in order: hi*hi, hi*lo, lo*hi
+  static constexpr int kSteps = 3;
+  __device__ static V mma_step(const Op& a, const Op& b, int j, V c) {
+    if (j == 0) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
+    if (j == 1) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, c, 0, 0, 0);
   }
 };
 
@@ -160,10 +161,9 @@ struct FlavF32 {
   __device__ static void put(unsigned char* lds, int kpad, int r, int k, float v) {
     reinterpret_cast<float*>(lds)[r * kpad + k] = v;
   }
-  __device__ static V mma(const Op& a, const Op& b, V c) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[j], b.x[j], c, 0, 0, 0);
-    return c;
+  static constexpr int kSteps = 8;
+  __device__ static V mma_step(const Op& a, const Op& b, int j, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a.x[j], b.x[j], c, 0, 0, 0);
   }
 };
 
@@ -199,10 +199,9 @@ struct FlavF64 {
   __device__ static void put(unsigned char* lds, int kpad, int r, int k, double v) {
     reinterpret_cast<double*>(lds)[r * kpad + k] = v;
   }
-  __device__ static V mma(const Op& a, const Op& b, V c) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[j], b.x[j], c, 0, 0, 0);
-    return c;
+  static constexpr int kSteps = 8;
+  __device__ static V mma_step(const Op& a, const Op& b, int j, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a.x[j], b.x[j], c, 0, 0, 0);
   }
 };
 
@@ -424,11 +423,15 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_mfma(const float* __restrict
       const int k = ks * 32 + kb;
       const Op b0 = F::from_lds(dyn_lds, p.kpad, lr * p.kpad + k);
       const Op b1 = F::from_lds(dyn_lds, p.kpad, (16 + lr) * p.kpad + k);
+      // step j of every tile before step j + 1 of any: independent MFMAs
+      // between dependent ones (each tile's own order is unchanged)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        Y[mt][0] = F::mma(a[mt], b0, Y[mt][0]);
-        Y[mt][1] = F::mma(a[mt], b1, Y[mt][1]);
-      }
+      for (int js = 0; js < F::kSteps; ++js)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          Y[mt][0] = F::mma_step(a[mt], b0, js, Y[mt][0]);
+          Y[mt][1] = F::mma_step(a[mt], b1, js, Y[mt][1]);
+        }
       if (ks + 1 == p.nks) {
         const S P0 = pscale(Pg, p, oc + j, r0 + lr);
         const S P1 = pscale(Pg, p, oc + j, r0 + 16 + lr);
@@ -562,12 +565,16 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_mfma(const float* __restrict
       const int k = ks * 32 + kb;
       const Op a0 = F::from_lds(dyn_lds, p.kpad, lr * p.kpad + k);
       const Op a1 = F::from_lds(dyn_lds, p.kpad, (16 + lr) * p.kpad + k);
+      Op b[NT];
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const Op b = F::from_t(buf[0][nt]);
-        Y[0][nt] = F::mma(a0, b, Y[0][nt]);
-        Y[1][nt] = F::mma(a1, b, Y[1][nt]);
-      }
+      for (int nt = 0; nt < NT; ++nt) b[nt] = F::from_t(buf[0][nt]);
+#pragma unroll
+      for (int js = 0; js < F::kSteps; ++js)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          Y[0][nt] = F::mma_step(a0, b[nt], js, Y[0][nt]);
+          Y[1][nt] = F::mma_step(a1, b[nt], js, Y[1][nt]);
+        }
       if (ks + 1 == p.nks) {
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
@@ -699,12 +706,16 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_mfma(const float* __res
       const int k = ks * 32 + kb;
       const Op b0 = F::from_lds(dyn_lds, p.kpad, lr * p.kpad + k);
       const Op b1 = F::from_lds(dyn_lds, p.kpad, (16 + lr) * p.kpad + k);
+      Op a[TW];
 #pragma unroll
-      for (int t = 0; t < TW; ++t) {
-        const Op a = F::from_t(v[t]);
-        Y[t][0] = F::mma(a, b0, Y[t][0]);
-        Y[t][1] = F::mma(a, b1, Y[t][1]);
-      }
+      for (int t = 0; t < TW; ++t) a[t] = F::from_t(v[t]);
+#pragma unroll
+      for (int js = 0; js < F::kSteps; ++js)
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+          Y[t][0] = F::mma_step(a[t], b0, js, Y[t][0]);
+          Y[t][1] = F::mma_step(a[t], b1, js, Y[t][1]);
+        }
     }
     // D rows are outer indices og + t*16 + drow(lane/16, q); the column is
     // the rank.  og is a multiple of 4 (o_per_block is a multiple of 16), so

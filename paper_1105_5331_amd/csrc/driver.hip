@@ -6,6 +6,7 @@
 // host reads back: rho at the top (1 double), the slope g(u_bar)^T d after
 // Step II (1 double), and (f, phi') for every line-search trial (2 doubles).
 #include "common.hpp"
+#include "linesearch.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -15,6 +16,7 @@
 #include <new>
 
 using namespace cpng;
+using cpng::ls::LS_CONVERGED;
 
 struct cp_ngmres_state {
   const cp_tensor* T = nullptr;
@@ -232,75 +234,6 @@ int readback(cp_handle* h, const double* src, int n, double* dst, hipStream_t st
   return CP_OK;
 }
 
-// ---- Moré–Thuente line search (host control, device evaluations) ----------
-// The method of More & Thuente (ACM TOMS 20(3), 1994): strong-Wolfe search
-// with an interval of uncertainty, the auxiliary function psi in the first
-// stage and safeguarded cubic/quadratic/secant trial steps (four cases).
-struct MTState {
-  double stx, fx, gx, sty, fy, gy;
-  bool brackt;
-};
-
-double cubic_min(double a, double fa, double da, double b, double fb, double db) {
-  const double theta = 3.0 * (fa - fb) / (b - a) + da + db;
-  const double sc = std::max({std::fabs(theta), std::fabs(da), std::fabs(db)});
-  double gamma = sc * std::sqrt((theta / sc) * (theta / sc) - (da / sc) * (db / sc));
-  if (b < a) gamma = -gamma;
-  const double p = (gamma - da) + theta;
-  const double q = ((gamma - da) + gamma) + db;
-  return a + (p / q) * (b - a);
-}
-
-// One trial-step update; returns the new trial step.
-double mt_step(MTState& m, double stp, double fp, double dp, double stmin, double stmax) {
-  const double sgnd = dp * std::copysign(1.0, m.gx);
-  double stpf;
-  if (fp > m.fx) {                                   // case 1
-    const double stpc = cubic_min(m.stx, m.fx, m.gx, stp, fp, dp);
-    const double stpq = m.stx + ((m.gx / ((m.fx - fp) / (stp - m.stx) + m.gx)) / 2.0) * (stp - m.stx);
-    stpf = std::fabs(stpc - m.stx) < std::fabs(stpq - m.stx) ? stpc : stpc + (stpq - stpc) / 2.0;
-    m.brackt = true;
-  } else if (sgnd < 0.0) {                           // case 2
-    const double stpc = cubic_min(stp, fp, dp, m.stx, m.fx, m.gx);
-    const double stpq = stp + (dp / (dp - m.gx)) * (m.stx - stp);
-    stpf = std::fabs(stpc - stp) > std::fabs(stpq - stp) ? stpc : stpq;
-    m.brackt = true;
-  } else if (std::fabs(dp) < std::fabs(m.gx)) {      // case 3
-    const double theta = 3.0 * (m.fx - fp) / (stp - m.stx) + m.gx + dp;
-    const double sc = std::max({std::fabs(theta), std::fabs(m.gx), std::fabs(dp)});
-    double gamma = sc * std::sqrt(std::max(0.0, (theta / sc) * (theta / sc) - (m.gx / sc) * (dp / sc)));
-    if (stp > m.stx) gamma = -gamma;
-    const double p = (gamma - dp) + theta;
-    const double q = (gamma + (m.gx - dp)) + gamma;
-    const double r = p / q;
-    double stpc;
-    if (r < 0.0 && gamma != 0.0) stpc = stp + r * (m.stx - stp);
-    else if (stp > m.stx) stpc = stmax;
-    else stpc = stmin;
-    const double stpq = stp + (dp / (dp - m.gx)) * (m.stx - stp);
-    if (m.brackt) {
-      stpf = std::fabs(stpc - stp) < std::fabs(stpq - stp) ? stpc : stpq;
-      const double lim = stp + 0.66 * (m.sty - stp);
-      stpf = stp > m.stx ? std::min(lim, stpf) : std::max(lim, stpf);
-    } else {
-      stpf = std::fabs(stpc - stp) > std::fabs(stpq - stp) ? stpc : stpq;
-      stpf = std::max(stmin, std::min(stmax, stpf));
-    }
-  } else {                                           // case 4
-    if (m.brackt) stpf = cubic_min(stp, fp, dp, m.sty, m.fy, m.gy);
-    else stpf = stp > m.stx ? stmax : stmin;
-  }
-  if (fp > m.fx) {
-    m.sty = stp; m.fy = fp; m.gy = dp;
-  } else {
-    if (sgnd < 0.0) { m.sty = m.stx; m.fy = m.fx; m.gy = m.gx; }
-    m.stx = stp; m.fx = fp; m.gx = dp;
-  }
-  return stpf;
-}
-
-enum { LS_CONVERGED = 0, LS_MAXFEV = 1, LS_XTOL = 2, LS_STPMAX = 3, LS_STPMIN = 4, LS_ROUNDING = 5 };
-
 enum { PHASE_STEP12 = 0, PHASE_EVAL = 1 };
 
 // The device work of Step II from u_bar and g_bar: the accelerated u_hat
@@ -417,81 +350,27 @@ int ls_eval(cp_handle* h, cp_ngmres_state* S, double beta, double* f, double* dp
 // step and objective and S->gt (converged) or S->gbest (fallback) its gradient.
 int more_thuente(cp_handle* h, cp_ngmres_state* S, double f0, double g0, double* beta,
                  double* f_acc, const double** g_acc, int* nfev_out, int* status_out) {
-  const cp_options& o = S->opt;
-  const double ftol = o.ls_ftol, gtol = o.ls_gtol, xtol = o.ls_xtol;
-  const double stpmin = o.ls_stpmin, stpmax = o.ls_stpmax;
-  double stp = o.ls_stp0;
-  MTState m{0.0, f0, g0, 0.0, f0, g0, false};
-  int stage = 1;
-  const double gtest = ftol * g0;
-  double width = stpmax - stpmin, width1 = 2.0 * width;
-  double stmin = 0.0, stmax = stp + 4.0 * stp;
-  double best_f = INFINITY, best_stp = 0.0;
-  int nfev = 0;
+  ls::MoreThuente mt;
+  double stp = mt.start(S->opt, f0, g0);
   for (;;) {
     double f, g;
     CP_TRY(ls_eval(h, S, stp, &f, &g));
-    ++nfev;
-    const bool better = f < best_f;
-    if (better) {
-      best_f = f;
-      best_stp = stp;
-    }
-    const double ftest = f0 + stp * gtest;
-    if (stage == 1 && f <= ftest && g >= 0.0) stage = 2;
-    int status = -1;
-    if (f <= ftest && std::fabs(g) <= gtol * (-g0)) status = LS_CONVERGED;
-    else if (stp == stpmin && (f > ftest || g >= gtest)) status = LS_STPMIN;
-    else if (stp == stpmax && f <= ftest && g <= gtest) status = LS_STPMAX;
-    else if (m.brackt && stmax - stmin <= xtol * stmax) status = LS_XTOL;
-    else if (m.brackt && (stp <= stmin || stp >= stmax)) status = LS_ROUNDING;
-    else if (nfev >= o.ls_maxfev) status = LS_MAXFEV;
+    bool keep = false;
+    const int status = mt.feed(f, g, &keep);
     // the trial's gradient is kept for a fallback only while the search goes
     // on (a final trial's gradient is still in S->gt)
-    if (better && status < 0)
+    if (keep)
       CP_HIP(h, hipMemcpyAsync(S->gbest, S->gt, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
     if (status >= 0) {
-      *nfev_out = nfev;
+      *nfev_out = mt.nfev;
       *status_out = status;
-      if (status == LS_CONVERGED) {
-        *beta = stp;
-        *f_acc = f;
-        *g_acc = S->gt;
-      } else if (best_f < f0) {
-        *beta = best_stp;
-        *f_acc = best_f;
-        *g_acc = better ? S->gt : S->gbest;
-      } else {
-        *beta = 0.0;
-        *f_acc = f0;
-        *g_acc = nullptr;
-      }
+      *beta = mt.acc_beta;
+      *f_acc = mt.acc_f;
+      *g_acc = mt.acc_grad == ls::MoreThuente::ACC_LAST ? S->gt
+             : mt.acc_grad == ls::MoreThuente::ACC_BEST ? S->gbest : nullptr;
       return CP_OK;
     }
-    if (stage == 1 && f <= m.fx && f > ftest) {
-      MTState mm{m.stx, m.fx - m.stx * gtest, m.gx - gtest, m.sty, m.fy - m.sty * gtest,
-                 m.gy - gtest, m.brackt};
-      stp = mt_step(mm, stp, f - stp * gtest, g - gtest, stmin, stmax);
-      m.stx = mm.stx; m.sty = mm.sty; m.brackt = mm.brackt;
-      m.fx = mm.fx + mm.stx * gtest;
-      m.fy = mm.fy + mm.sty * gtest;
-      m.gx = mm.gx + gtest;
-      m.gy = mm.gy + gtest;
-    } else {
-      stp = mt_step(m, stp, f, g, stmin, stmax);
-    }
-    if (m.brackt) {
-      if (std::fabs(m.sty - m.stx) >= 0.66 * width1) stp = m.stx + 0.5 * (m.sty - m.stx);
-      width1 = width;
-      width = std::fabs(m.sty - m.stx);
-      stmin = std::min(m.stx, m.sty);
-      stmax = std::max(m.stx, m.sty);
-    } else {
-      stmin = stp + 1.1 * (stp - m.stx);
-      stmax = stp + 4.0 * (stp - m.stx);
-    }
-    stp = std::min(std::max(stp, stpmin), stpmax);
-    if (m.brackt && (stp <= stmin || stp >= stmax || stmax - stmin <= xtol * stmax)) stp = m.stx;
+    stp = mt.stp;
   }
 }
 
