@@ -419,6 +419,14 @@ typedef struct cp_server_opts {
   int32_t slots;          /* decompositions running at once, each on its own stream (4; max 16) */
   size_t hbm_budget;      /* bytes the running requests may occupy (0: 80% of free memory) */
   cp_options decompose;   /* method options of every request (trace ignored) */
+  int64_t batch_elems;    /* > 0 (and decompose.method = CP_METHOD_NGMRES, window <= 21):
+                             dense float32 requests of order 3 or 4 with 1 <= R <= 32 and at
+                             most this many entries (capped at CP_BATCH_MAX_ELEMS) run on the
+                             batched path of cp_batch_decompose, admitted continuously into
+                             one batch that a thread of its own advances, one launch per step
+                             for all of them, in float64 arithmetic (precision fields ignored);
+                             0: every request takes a slot (0) */
+  int32_t batch_capacity; /* requests in the batch at once (256) */
 } cp_server_opts;
 
 typedef struct cp_result {
@@ -429,7 +437,7 @@ typedef struct cp_result {
   int32_t converged;
   int32_t n_fg;
   int32_t switch_iter;
-  int32_t slot;           /* slot that ran it */
+  int32_t slot;           /* slot that ran it; -1: the batched path */
   double f;
   double rho;
   double t_submit;        /* seconds since cp_server_create */
@@ -438,10 +446,11 @@ typedef struct cp_result {
 } cp_result;
 
 /* Start a server on `device` with `slots` worker threads, each owning a
- * handle and a HIP stream (default priority).  Requests are admitted in
- * arrival order when a slot is free and their footprint (tensor, N-GMRES
- * window and state, workspace estimate) fits in hbm_budget beside the running
- * ones.  o nullable (defaults). */
+ * handle and a HIP stream (default priority), and, with batch_elems > 0, a
+ * batch thread with its own handle and stream.  Requests are admitted in
+ * arrival order (per path) when a slot (or batch place) is free and their
+ * footprint (tensor, N-GMRES window and state, workspace estimate) fits in
+ * hbm_budget beside the running ones.  o nullable (defaults). */
 int cp_server_create(int device, const cp_server_opts* o, cp_server** s);
 /* Queue a decomposition of T (device arrays; prepared by the server) to
  * rho <= tol from the initial guess in u_inout (device, L doubles), which

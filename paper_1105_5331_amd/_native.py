@@ -80,7 +80,8 @@ class cp_batch_request(C.Structure):
 
 
 class cp_server_opts(C.Structure):
-    _fields_ = [("slots", C.c_int32), ("hbm_budget", C.c_size_t), ("decompose", cp_options)]
+    _fields_ = [("slots", C.c_int32), ("hbm_budget", C.c_size_t), ("decompose", cp_options),
+                ("batch_elems", C.c_int64), ("batch_capacity", C.c_int32)]
 
 
 class cp_result(C.Structure):
@@ -572,11 +573,14 @@ class Server:
     submit() hands a device tensor and initial guess to the native scheduler;
     the caller's objects are kept alive here until their result is polled."""
 
-    def __init__(self, device=0, slots=4, hbm_budget=0, **opts):
+    def __init__(self, device=0, slots=4, hbm_budget=0, batch_elems=0, batch_capacity=256,
+                 **opts):
         o = cp_server_opts()
         o.slots = int(slots)
         o.hbm_budget = int(hbm_budget)
         o.decompose = options(**opts)
+        o.batch_elems = int(batch_elems)
+        o.batch_capacity = int(batch_capacity)
         self._s = C.c_void_p()
         rc = lib().cp_server_create(int(device), C.byref(o), C.byref(self._s))
         if rc != CP_OK:

@@ -811,6 +811,32 @@ int batch_engine_add(BatchEngine* e, const cp_tensor* T, int R, double tol, cons
 int batch_engine_tick(BatchEngine* e, std::vector<BatchItem*>* finished) { return e->tick(finished); }
 int batch_engine_active(const BatchEngine* e) { return (int)e->items.size(); }
 
+void batch_engine_drain(BatchEngine* e, std::vector<BatchItem*>* out) {
+  (void)hipStreamSynchronize(e->st);
+  for (BatchItem* it : e->items) {
+    if (it->status == CP_OK) it->status = CP_EDEVICE;
+    out->push_back(it);
+  }
+  e->items.clear();
+}
+
+void batch_item_delete(BatchItem* it) {
+  batch_item_free(it);
+  delete it;
+}
+
+// Device bytes of a request on the batched path: the tensor, 10 + 2 w
+// iterate-length vectors and the Grams, Gammabars and factor.
+int64_t batch_footprint(const cp_tensor* T, int R, int window) {
+  int64_t total = 1, sum = 0;
+  for (int k = 0; k < T->order; ++k) {
+    total *= T->dims[k];
+    sum += T->dims[k];
+  }
+  const int64_t w = std::max(1, std::min(window, kBatchMaxWindow));
+  return total * 4 + 8 * sum * R * (10 + 2 * w) + 8 * (int64_t)R * R * (2 * T->order + 1);
+}
+
 void batch_item_report(const BatchItem* it, cp_report* rep, int* status, uint64_t* tag) {
   if (rep) {
     *rep = cp_report{};

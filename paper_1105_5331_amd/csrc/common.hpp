@@ -198,6 +198,24 @@ int tree_all_modes(cp_handle* h, const Shape& s, int split, const double* XL, co
 int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, const double* u, int R,
               int mode, double* M, hipStream_t st);
 
+// batched N-GMRES engine for small dense requests (batch.hip)
+struct BatchEngine;
+struct BatchItem;
+bool batch_eligible(const cp_tensor* T, int R, int64_t max_elems);
+BatchEngine* batch_engine_create(cp_handle* h, hipStream_t st, const cp_options& o, int capacity);
+void batch_engine_destroy(BatchEngine* e);
+int batch_engine_add(BatchEngine* e, const cp_tensor* T, int R, double tol, const double* u0,
+                     double* u_out, uint64_t tag, cp_iter_info* trace, int trace_cap,
+                     BatchItem** out);
+// one launch over every active request; finished ones are appended to *finished
+int batch_engine_tick(BatchEngine* e, std::vector<BatchItem*>* finished);
+int batch_engine_active(const BatchEngine* e);
+// moves every active request to *out (after a failed tick)
+void batch_engine_drain(BatchEngine* e, std::vector<BatchItem*>* out);
+void batch_item_report(const BatchItem* it, cp_report* rep, int* status, uint64_t* tag);
+void batch_item_delete(BatchItem* it);   // frees its device memory too
+int64_t batch_footprint(const cp_tensor* T, int R, int window);
+
 // small kernels
 // With factor_mode >= 0 also factorises Gammabar^(factor_mode) for the next
 // mode_solve(..., Gbar = nullptr, ...).  With only_mode >= 0 only that mode's

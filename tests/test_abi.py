@@ -52,6 +52,12 @@ int main() {
   printf("cp_options %zu\n", sizeof(cp_options));
   printf("cp_iter_info %zu\n", sizeof(cp_iter_info));
   printf("cp_report %zu\n", sizeof(cp_report));
+  printf("cp_server_opts %zu\n", sizeof(cp_server_opts));
+  printf("cp_batch_request %zu\n", sizeof(cp_batch_request));
+  printf("cp_result %zu\n", sizeof(cp_result));
+  P(cp_server_opts, decompose) P(cp_server_opts, batch_elems) P(cp_server_opts, batch_capacity)
+  P(cp_batch_request, tol) P(cp_batch_request, trace_cap) P(cp_batch_request, status)
+  P(cp_batch_request, report) P(cp_iter_info, nfev_pre)
   P(cp_tensor, values) P(cp_tensor, nnz) P(cp_tensor, norm_sq)
   P(cp_options, trace) P(cp_options, trace_cap) P(cp_options, switch_rho)
   P(cp_iter_info, beta) P(cp_iter_info, precision)
@@ -71,7 +77,9 @@ int main() {
         out = subprocess.run([exe], capture_output=True, text=True).stdout.split("\n")
     got = dict(line.split() for line in out if line.strip())
     S = {"cp_tensor": nat.cp_tensor, "cp_options": nat.cp_options,
-         "cp_iter_info": nat.cp_iter_info, "cp_report": nat.cp_report}
+         "cp_iter_info": nat.cp_iter_info, "cp_report": nat.cp_report,
+         "cp_server_opts": nat.cp_server_opts, "cp_batch_request": nat.cp_batch_request,
+         "cp_result": nat.cp_result}
     for k, v in got.items():
         if "." in k:
             s, f = k.split(".")

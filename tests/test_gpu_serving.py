@@ -68,6 +68,29 @@ def test_isolation_50_requests_one_at_a_time_vs_mix():
         assert np.array_equal(a_u, m_u), f"request {r.rid} differs one at a time vs in the mix"
 
 
+def test_isolation_with_the_batched_path_50_requests():
+    """50 requests of the serving mix with the batched path on for tensors of
+    at most 2^17 entries: run with one slot and a batch of one place (every
+    batched request alone in its batch) and as a 4-slot mix with a full batch,
+    every result is the same bits; both paths are used."""
+    print("case serving isolation with the batched path", flush=True)
+    reqs = _requests(50, seed=13)
+    serial = _run(reqs, slots=1, batch_elems=1 << 17, batch_capacity=1)
+    mix = _run(reqs, slots=4, batch_elems=1 << 17)
+    assert len(serial) == len(mix) == 50
+    n_batched = sum(1 for g, _ in mix.values() if g["slot"] == -1)
+    assert 0 < n_batched < 50
+    for r, _, _ in reqs:
+        a_res, a_u = serial[r.rid]
+        m_res, m_u = mix[r.rid]
+        assert a_res["slot"] == -1 if m_res["slot"] == -1 else a_res["slot"] >= 0
+        assert a_res["status"] == m_res["status"] and a_res["iters"] == m_res["iters"], r.rid
+        assert a_res["rho"] == m_res["rho"], r.rid
+        assert np.array_equal(a_u, m_u), f"request {r.rid} differs alone vs in the mix"
+        if m_res["slot"] == -1:
+            assert m_res["status"] in (0, 1) and np.all(np.isfinite(m_u))
+
+
 def test_every_request_terminates_and_mixed_precision_certifies():
     reqs = _requests(10, seed=5)
     res = _run(reqs, slots=3, precision="bf16x3", final_precision="fp32in_fp64acc",
