@@ -43,10 +43,13 @@ PEAK_F64_TFS = 78.6        # MI355X dense float64 matrix (and vector) rate
 TOL_RHO = 1e-8             # the stopping tolerance on ||g|| / ||T||
 PREC_NAMES = {0: "fp64", 1: "fp32", 2: "bf16x3", 3: "fp32in_fp64acc"}
 # rocprofv3 HBM counters of the default workload's dense MTTKRP kernels (the
-# bulk BF16x3 class and the float64-accumulation class), each with the hash of
+# bulk BF16x3 class and the float64-accumulation class, each as a single group
+# partial and as the two-sided pass that forms both), each with the hash of
 # the source file that holds the kernels (the counters are per kernel)
-COUNTER_SUMMARY = {False: "profiles/dense_mttkrp_bf16x3_128x4_R32_hbm_counters.txt",
-                   True: "profiles/dense_mttkrp_f64acc_128x4_R32_hbm_counters.txt"}
+COUNTER_SUMMARY = {"bulk": "profiles/dense_mttkrp_bf16x3_128x4_R32_hbm_counters.txt",
+                   "f64acc": "profiles/dense_mttkrp_f64acc_128x4_R32_hbm_counters.txt",
+                   "bulk_one_pass": "profiles/dense_twosided_bf16x3_128x4_R32_hbm_counters.txt",
+                   "f64acc_one_pass": "profiles/dense_twosided_f64acc_128x4_R32_hbm_counters.txt"}
 KERNEL_SOURCES = ("paper_1105_5331_amd/csrc/dense_fast.hip",)
 
 
@@ -59,12 +62,12 @@ def kernel_source_hash():
     return hs.hexdigest()
 
 
-def counter_traffic(f64=False):
-    """HBM bytes per dense MTTKRP launch (FETCH_SIZE + WRITE_SIZE, calibrated
-    on a copy of known size) from the committed counter summary, or None if
-    the counters were taken on other kernel sources."""
+def counter_traffic(cls):
+    """HBM bytes per launch of one dense MTTKRP kernel class (FETCH_SIZE +
+    WRITE_SIZE, calibrated on a copy of known size) from the committed counter
+    summary, or None if the counters were taken on other kernel sources."""
     try:
-        with open(os.path.join(ROOT, COUNTER_SUMMARY[f64])) as fh:
+        with open(os.path.join(ROOT, COUNTER_SUMMARY[cls])) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None
@@ -437,33 +440,100 @@ def paper_tables(h, cpng, torch, max_iter=2000, parts=("tp1", "tp2")):
     return out
 
 
-def _serve(cpng, torch, data, slots, rate, max_iter):
+def _serve(cpng, torch, reqs, slots, rate, max_iter, batch_elems=0, ahead_bytes=16 << 30,
+           label=""):
+    """One pass of the request stream through a server.  A producer thread
+    generates each request's tensor and initial guess on the device (Test
+    Problem I recipe) ahead of its submission, holding at most `ahead_bytes`
+    of tensors not yet finished; the submitter sends request k at
+    arrival_k / rate seconds (all at once when rate is None) and drops each
+    request's arrays once its result is polled.  Latency: submission to
+    result, on the server's clock."""
+    import threading
+    from workloads import initial_guess, test_problem_1_torch
     srv = cpng.Server(0, slots=slots, max_iter=max_iter, precision="bf16x3",
-                      final_precision="fp32in_fp64acc", switch_rho=1e-4)
-    t0 = time.perf_counter()
+                      final_precision="fp32in_fp64acc", switch_rho=1e-4, batch_elems=batch_elems)
+    ready = {}
+    cv = threading.Condition()
+    state = {"pending": 0, "stop": False}
+
+    def produce():
+        for r in reqs:
+            nbytes = 4 * int(np.prod(r.dims))
+            with cv:
+                cv.wait_for(lambda: state["stop"] or state["pending"] + nbytes <= ahead_bytes
+                            or state["pending"] == 0)
+                if state["stop"]:
+                    return
+            T = test_problem_1_torch(r.dims, r.R, r.c, 1, 1, seed=r.seed)
+            u0 = torch.from_numpy(initial_guess(r.dims, r.R, seed=r.seed + 10000)).cuda()
+            torch.cuda.current_stream().synchronize()
+            with cv:
+                ready[r.rid] = (T, u0, nbytes)
+                state["pending"] += nbytes
+                cv.notify_all()
+
+    prod = threading.Thread(target=produce, daemon=True)
+    prod.start()
+    held = {}
     got = []
-    keep = []
-    for r, T, u0 in data:
-        if rate:
-            delay = r.arrival / rate - (time.perf_counter() - t0)
-            if delay > 0:
-                time.sleep(delay)
-        u = u0.clone()
-        keep.append((T, u))
-        srv.submit(cpng.Tensor(r.dims, T), r.R, 1e-8, u, tag=r.rid)
-        got += srv.poll(0)
-    while len(got) < len(data):
-        got += srv.poll(wait_for=len(data) - len(got))
+    t0 = time.perf_counter()
+
+    def drain(wait_for=0):
+        for g in srv.poll(wait_for):
+            got.append(g)
+            T, u, nbytes = held.pop(g["tag"])
+            with cv:
+                state["pending"] -= nbytes
+                cv.notify_all()
+            if len(got) % 200 == 0:
+                log(f"serving {label}: {len(got)}/{len(reqs)} done")
+
+    try:
+        for r in reqs:
+            while True:
+                with cv:
+                    item = ready.pop(r.rid, None)
+                    if item is None:
+                        cv.wait(0.05)
+                if item is not None:
+                    break
+                drain()
+            T, u0, nbytes = item
+            if rate:
+                delay = r.arrival / rate - (time.perf_counter() - t0)
+                while delay > 0:
+                    time.sleep(min(delay, 0.02))
+                    drain()
+                    delay = r.arrival / rate - (time.perf_counter() - t0)
+            u = u0.clone()
+            held[r.rid] = (T, u, nbytes)
+            srv.submit(cpng.Tensor(r.dims, T), r.R, 1e-8, u, tag=r.rid)
+            drain()
+        while len(got) < len(reqs):
+            drain(wait_for=1)
+    finally:
+        with cv:
+            state["stop"] = True
+            cv.notify_all()
+        prod.join()
     span = time.perf_counter() - t0
     srv.close()
     lat = np.array([g["t_end"] - g["t_submit"] for g in got])
     conv = sum(1 for g in got if g["converged"])
-    return {"slots": slots, "rate_per_s": round(rate, 3) if rate else None, "requests": len(got),
-            "p50_s": round(float(np.percentile(lat, 50)), 4),
-            "p99_s": round(float(np.percentile(lat, 99)), 4),
-            "solves_per_s": round(len(got) / span, 3), "makespan_s": round(span, 3),
-            "converged": conv, "not_converged": len(got) - conv,
-            "errors": sum(1 for g in got if g["status"] < 0)}
+    nb = [g for g in got if g["slot"] == -1]
+    out = {"slots": slots, "batch_elems": batch_elems,
+           "rate_per_s": round(rate, 3) if rate else None, "requests": len(got),
+           "p50_s": round(float(np.percentile(lat, 50)), 4),
+           "p99_s": round(float(np.percentile(lat, 99)), 4),
+           "solves_per_s": round(len(got) / span, 3), "makespan_s": round(span, 3),
+           "converged": conv, "not_converged": len(got) - conv,
+           "errors": sum(1 for g in got if g["status"] < 0), "batched": len(nb)}
+    if nb:
+        bl = np.array([g["t_end"] - g["t_submit"] for g in nb])
+        out["batched_p50_s"] = round(float(np.percentile(bl, 50)), 4)
+        out["batched_p99_s"] = round(float(np.percentile(bl, 99)), 4)
+    return out
 
 
 def oracle_side_by_side(h, cpng, torch, sparse_gpu_us=None):
@@ -581,36 +651,33 @@ def oracle_side_by_side(h, cpng, torch, sparse_gpu_us=None):
     return out
 
 
-def serving(cpng, torch, n=64, slots=4, seed=7, max_iter=500, loads=(0.5, 0.8)):
-    """Stream of decomposition requests (dense 3-/4-way float32, mode sizes
-    U{16..160}, R U{2..24}, congruence U[0, 0.9], noise 1%+1%, tol 1e-8)
-    through the continuous-batching server.  First the saturation throughput
-    (all requests queued at t = 0, `slots` concurrent decompositions, and one
-    at a time); then
-    Poisson arrivals at the given fractions of it, with `slots` concurrent
-    decompositions and one at a time; p50/p99 latency from arrival to result."""
-    from workloads import initial_guess, serving_stream, test_problem_1_torch
+def serving(cpng, torch, n=100, slots=4, seed=7, max_iter=500, load=0.8, batch_elems=1 << 17,
+            sat_n=None):
+    """The serving stream (dense 3-/4-way float32, mode sizes U{16..160}, R
+    U{2..24}, congruence U[0, 0.9], noise 1%+1%, tol 1e-8, BF16x3 bulk then
+    float64 accumulation) through the continuous-batching server in three
+    arms: `slots` concurrent decompositions plus the batched path for tensors
+    of at most `batch_elems` entries; the slots alone; one request at a time.
+    First the saturation throughput of the slots arm (the first sat_n
+    requests queued at t = 0), then Poisson arrivals of all n requests at
+    `load` times it for every arm; p50/p99 latency from submission to
+    result, solves/s, non-converged requests."""
+    from workloads import serving_stream
     reqs = serving_stream(n, rate_per_s=1.0, seed=seed)   # arrival times for rate 1
-    data = []
-    for r in reqs:
-        T = test_problem_1_torch(r.dims, r.R, r.c, 1, 1, seed=r.seed)
-        u0 = torch.from_numpy(initial_guess(r.dims, r.R, seed=r.seed + 10000)).cuda()
-        data.append((r, T, u0))
-    torch.cuda.synchronize()
-    _serve(cpng, torch, data[:8], slots, None, max_iter)   # first launches
-    sat = _serve(cpng, torch, data, slots, None, max_iter)
-    log(f"serving saturation: {sat}")
-    sat1 = _serve(cpng, torch, data, 1, None, max_iter)
-    log(f"serving saturation, one at a time: {sat1}")
-    out = {"saturation": sat, "saturation_slots1": sat1}
-    mu = sat["solves_per_s"]
-    for frac in loads:
-        for sl in (slots, 1):
-            res = _serve(cpng, torch, data, sl, frac * mu, max_iter)
-            log(f"serving load {frac} slots {sl}: {res}")
-            out[f"load{frac:g}_slots{sl}"] = res
-    return {"load": f"{n} requests; Poisson arrivals at {', '.join(f'{x:g}' for x in loads)} x "
-                    f"the saturation rate of {slots} slots", **out}
+    sat_n = sat_n or min(n, 300)
+    _serve(cpng, torch, reqs[:8], slots, None, max_iter, batch_elems, label="first launches")
+    sat = _serve(cpng, torch, reqs[:sat_n], slots, None, max_iter, label="saturation")
+    log(f"serving saturation ({sat_n} requests, {slots} slots): {sat}")
+    rate = load * sat["solves_per_s"]
+    out = {"load": f"{n} requests; Poisson arrivals at {rate:.3f}/s = {load:g} x the saturation "
+                   f"rate of {slots} slots on the first {sat_n} requests",
+           "saturation_slots": sat}
+    for name, sl, be in (("batched_and_slots", slots, batch_elems), ("slots", slots, 0),
+                         ("one_at_a_time", 1, 0)):
+        res = _serve(cpng, torch, reqs, sl, rate, max_iter, be, label=name)
+        log(f"serving {name}: {res}")
+        out[name] = res
+    return out
 
 
 def main():
@@ -708,9 +775,11 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
-    # events on the dense MTTKRP launches only (both accumulation classes):
-    # every timed launch adds two event records to the stream
-    kids = (cpng.CP_KERNEL_DENSE_MTTKRP, cpng.CP_KERNEL_DENSE_MTTKRP_F64)
+    # events on the dense MTTKRP launches only (both accumulation classes, a
+    # single group partial or both from one pass): every timed launch adds two
+    # event records to the stream
+    kids = (cpng.CP_KERNEL_DENSE_MTTKRP, cpng.CP_KERNEL_DENSE_MTTKRP_F64,
+            cpng.CP_KERNEL_DENSE_TWOSIDED, cpng.CP_KERNEL_DENSE_TWOSIDED_F64)
     cpng.cp_profile_select(h, sum(1 << k for k in kids))
     cpng.cp_profile(h, True)
     torch.cuda.synchronize()
@@ -739,7 +808,7 @@ def main():
         if n_l:
             kern[kid] = (n_l, ms_l)
     cpng.cp_profile(h, False)
-    cpng.cp_profile_select(h, 0x3F)
+    cpng.cp_profile_select(h, 0xFF)
     elem = 8 if args.precision == "fp64" else 4
     value = passes * nT * elem / dt / 1e9
     # the achievable streaming read of the same buffer (our reference kernel)
@@ -753,36 +822,44 @@ def main():
     srn, srms = cpng.cp_profile_read(h, cpng.CP_KERNEL_STREAM_READ)
     cpng.cp_profile(h, False)
     stream_gbs = nT * elem / (srms / srn * 1e-3) / 1e9
-    # algorithmic bytes of one dense MTTKRP launch in these steps: every
-    # evaluation and sweep runs the two group partials of the two-level
-    # evaluation (modes {1,2} | {3,4}); each reads the tensor once and the
-    # other group's two factors, and writes its (I_1 I_2) x R float64 partial
+    # algorithmic bytes of one dense MTTKRP launch in these steps.  The two-
+    # level evaluation splits the modes {1,2} | {3,4}: a single group partial
+    # reads the tensor once and the other group's two factors and writes its
+    # (I_1 I_2) x R float64 partial (the ALS sweep, and every evaluation where
+    # the one-pass kernel is off); the two-sided pass reads the tensor once
+    # and all four factors and writes both partials, with twice the flops
     fac_bytes = 2 * s * R * (8 if args.precision == "fp64" else 4)
-    traffic = nT * elem + fac_bytes + s * s * R * 8
-    flops = 2 * R * nT
+    one_part = {"bytes": nT * elem + fac_bytes + s * s * R * 8, "flops": 2 * R * nT}
+    two_part = {"bytes": nT * elem + 2 * fac_bytes + 2 * s * s * R * 8, "flops": 4 * R * nT}
+    classes = {cpng.CP_KERNEL_DENSE_MTTKRP: ("bulk", False, one_part),
+               cpng.CP_KERNEL_DENSE_MTTKRP_F64: ("f64acc", True, one_part),
+               cpng.CP_KERNEL_DENSE_TWOSIDED: ("bulk_one_pass", False, two_part),
+               cpng.CP_KERNEL_DENSE_TWOSIDED_F64: ("f64acc_one_pass", True, two_part)}
     rooflines = {}
     for kid, (n_l, ms_l) in kern.items():
         avg_s = ms_l / n_l * 1e-3
-        f64 = kid == cpng.CP_KERNEL_DENSE_MTTKRP_F64
-        ach_gbs = traffic / avg_s / 1e9
-        ach_tf = flops / avg_s / 1e12
+        cls, f64, alg = classes[kid]
+        what = "both group partials in one pass" if "one_pass" in cls else "one group partial"
+        ach_gbs = alg["bytes"] / avg_s / 1e9
+        ach_tf = alg["flops"] / avg_s / 1e12
         if f64:   # float64 MFMA products: bound by the float64 matrix rate, not HBM
             rl = {"bound": "mfma", "achieved": round(ach_tf, 2), "peak": PEAK_F64_TFS,
                   "unit": "TFLOP/s", "frac": round(ach_tf / PEAK_F64_TFS, 4),
-                  "kernel": "dense MTTKRP, float64 products and sums (v_mfma_f64_16x16x4_f64)",
+                  "kernel": f"dense MTTKRP, float64 products and sums "
+                            f"(v_mfma_f64_16x16x4_f64), {what}",
                   "hbm_GBs": round(ach_gbs, 1), "hbm_frac": round(ach_gbs / PEAK_HBM_GBS, 4),
-                  "flops_per_launch": flops}
+                  "flops_per_launch": alg["flops"]}
         else:
             rl = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": PEAK_HBM_GBS,
                   "unit": "GB/s", "frac": round(ach_gbs / PEAK_HBM_GBS, 4),
-                  "kernel": f"dense MTTKRP, {args.precision} (matrix cores)",
+                  "kernel": f"dense MTTKRP, {args.precision} (matrix cores), {what}",
                   "stream_read_GBs": round(stream_gbs, 1),
                   "frac_of_stream_read": round(ach_gbs / stream_gbs, 4),
                   "mfma_TFs": round(ach_tf, 1)}
         rl.update({"launches": n_l, "avg_us": round(avg_s * 1e6, 2), "total_ms": round(ms_l, 3),
-                   "bytes_per_launch": traffic})
-        rl["traffic"] = counter_traffic(f64) if (s, R) == (128, 32) else None
-        rooflines["f64acc" if f64 else "bulk"] = rl
+                   "bytes_per_launch": alg["bytes"]})
+        rl["traffic"] = counter_traffic(cls) if (s, R) == (128, 32) else None
+        rooflines[cls] = rl
     dominant = max(rooflines, key=lambda k: rooflines[k]["total_ms"])
     ls = [x["nfev"] for x in steps if x["nfev"]]
     res = {
@@ -824,8 +901,8 @@ def main():
         res.setdefault("extra", {})["time_to_grad_200cubed_R10"] = time_to_grad(h, cpng, torch)
         log("sparse MTTKRP (20000^3, ~2e7 nonzeros, R=16)")
         res["extra"]["sparse_mttkrp_20000cubed_R16"] = sparse_mttkrp(h, cpng, torch)
-        log("serving stream (32 requests)")
-        res["extra"]["serving"] = serving(cpng, torch, n=32)
+        log("serving stream (100 requests; --serving N for the full stream)")
+        res["extra"]["serving"] = serving(cpng, torch, n=100)
         log("paper Tables 4-6: Test Problem II at the paper's sizes (ALS, N-GMRES, N-CG)")
         res["extra"]["paper_tables_tp2"] = paper_tables(h, cpng, torch, max_iter=1000,
                                                         parts=("tp2",))["tp2"]

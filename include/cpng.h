@@ -160,8 +160,14 @@ typedef struct cp_options {
                                complement (two partial MTTKRPs on the same kernels and
                                precision as a per-mode MTTKRP) and take every M^(n) from
                                its group's partial in float64, so a gradient evaluation
-                               or ALS sweep streams T twice instead of N times (1);
-                               0 = one pass per mode */
+                               or ALS sweep streams T twice instead of N times.
+                               1 (default): an evaluation of a float32 tensor forms
+                               both partials in one pass over T where the two-sided
+                               kernel covers the shape (R <= 32, the last modes of both
+                               groups of length 64 or 128; the ALS sweep keeps two
+                               passes, its right partial needs the updated left
+                               factors); 2: always one pass per partial; 0: one pass
+                               per mode.  Other values: CP_EINVAL */
   int32_t switch_on_stall;  /* with switch_rho > 0, also switch once rho <= 1e-2 after a
                                line search in the first precision ends without a Wolfe
                                point (1) */
@@ -214,7 +220,9 @@ void cp_options_default(cp_options* opt);
  * checking coordinate bounds and duplicates.  Synchronises the stream.
  * Errors: CP_EINVAL (shape, coordinate out of range), CP_EDUPLICATE, CP_ENOMEM. */
 int cp_tensor_prepare(cp_handle* h, cp_tensor* T, hipStream_t stream);
-/* Free what cp_tensor_prepare attached (synchronises the device). */
+/* Free what cp_tensor_prepare attached.  Synchronises the stream the tensor
+ * was prepared on (not the device): work that used the tensor on any other
+ * stream must be complete before the call. */
 int cp_tensor_release(cp_handle* h, cp_tensor* T);
 
 /* ---- hot-path building blocks ---------------------------------------- */
@@ -294,7 +302,9 @@ int cp_mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, 
  *   G^(n) = -M^(n) + A^(n) Gammabar^(n)           for every n
  * f_out: device, 1 double; g_out: device, L doubles (nullable: f only still
  * runs every MTTKRP it needs).  T must be prepared (for ||T||^2).  Dense
- * tensors of order >= 3: the two-level evaluation, two passes over T. */
+ * tensors of order >= 3: the two-level evaluation, two passes over T, or one
+ * for a float32 tensor whose shape the two-sided kernel covers (see
+ * cp_options.mttkrp_tree = 1). */
 int cp_objective_grad(cp_handle* h, const cp_tensor* T, const double* u, int32_t R, int32_t p,
                       double* f_out, double* g_out, hipStream_t stream);
 
@@ -481,14 +491,17 @@ int cp_server_destroy(cp_server* s);
 #define CP_KERNEL_DENSE_MTTKRP_F64 4 /* main dense MTTKRP kernel, float64-accumulating
                                        precisions (CP_PREC_FP64, CP_PREC_FP32IN_FP64ACC) */
 #define CP_KERNEL_SPARSE_GATHER 5   /* cp_sparse_gather_read */
+#define CP_KERNEL_DENSE_TWOSIDED 6  /* both group partials of a two-level evaluation from one
+                                       pass over T, float32-accumulating precisions */
+#define CP_KERNEL_DENSE_TWOSIDED_F64 7 /* the same, float64-accumulating precisions */
 
 /* Enable (1) or disable (0) HIP-event timing of the main MTTKRP kernels on
  * the stream each is launched on; enabling clears the counters. */
 int cp_profile(cp_handle* h, int32_t enable);
 /* Which kernel ids cp_profile times: bit k of kernel_mask selects id k
- * (default 0x3F, all six).  Each timed launch adds two event records to its
+ * (default 0xFF, all eight).  Each timed launch adds two event records to its
  * stream, so timing only the kernel being measured keeps the others' launch
- * gaps out of a timed run.  CP_EINVAL for bits above 5. */
+ * gaps out of a timed run.  CP_EINVAL for bits above 7. */
 int cp_profile_select(cp_handle* h, uint32_t kernel_mask);
 /* Synchronise the recorded events and return, for kernel id `kernel`, the
  * number of timed launches and their summed duration in milliseconds

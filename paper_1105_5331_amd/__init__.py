@@ -10,5 +10,6 @@ from ._native import (  # noqa: F401
     cp_mttkrp, cp_mttkrp_noalloc, cp_mode_solve, cp_normalize, cp_objective_grad, cp_tensor_prepare, cp_tensor_release,
     iterate_length, lib, ngmres_accelerate, ngmres_step, options, LIB_PATH, cp_profile,
     cp_profile_read, cp_profile_select, CP_KERNEL_DENSE_MTTKRP, CP_KERNEL_SPARSE_MTTKRP, CP_KERNEL_STREAM_READ,
-    CP_KERNEL_GROUP_MTTKRP, CP_KERNEL_DENSE_MTTKRP_F64, CP_KERNEL_SPARSE_GATHER, cp_stream_read, cp_sparse_gather_read, cp_batch_decompose, Server, cp_init_uniform,
+    CP_KERNEL_GROUP_MTTKRP, CP_KERNEL_DENSE_MTTKRP_F64, CP_KERNEL_SPARSE_GATHER, CP_KERNEL_DENSE_TWOSIDED,
+    CP_KERNEL_DENSE_TWOSIDED_F64, cp_stream_read, cp_sparse_gather_read, cp_batch_decompose, Server, cp_init_uniform,
 )

@@ -470,6 +470,7 @@ class NGMRESState:
 
 CP_KERNEL_DENSE_MTTKRP, CP_KERNEL_SPARSE_MTTKRP, CP_KERNEL_STREAM_READ, CP_KERNEL_GROUP_MTTKRP = 0, 1, 2, 3
 CP_KERNEL_DENSE_MTTKRP_F64, CP_KERNEL_SPARSE_GATHER = 4, 5
+CP_KERNEL_DENSE_TWOSIDED, CP_KERNEL_DENSE_TWOSIDED_F64 = 6, 7
 
 
 def cp_stream_read(h: Handle, buf):

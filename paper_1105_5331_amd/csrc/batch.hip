@@ -95,8 +95,20 @@ __device__ void wg_grams(const BReq& q, const double* __restrict__ u, int only) 
   for (int e = threadIdx.x; e < (k1 - k0) * RR; e += kBT) {
     const int k = k0 + e / RR, rq = e % RR, r = rq / R, c = rq % R;
     const double* A = u + q.off[k] * R;
+    const int64_t I = q.dims[k];
     double s = 0.0;
-    for (int64_t i = 0; i < q.dims[k]; ++i) s = fma(A[i * R + r], A[i * R + c], s);
+    for (int64_t i0 = 0; i0 < I; i0 += 8) {   // 8 loads in flight, row order kept
+      double x[8], y[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool ok = i0 + b < I;
+        x[b] = ok ? A[(i0 + b) * R + r] : 0.0;
+        y[b] = ok ? A[(i0 + b) * R + c] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        if (i0 + b < I) s = fma(x[b], y[b], s);
+    }
     q.S[k * RR + rq] = s;
   }
   wg_sync();
@@ -116,10 +128,14 @@ __device__ void wg_gammabars(const BReq& q) {
 }
 
 // M^(n)(i, r) = sum over the other indices (C order) of T(...) prod_{k != n}
-// A^(k)(i_k, r), one output entry per thread, the innermost other mode summed
-// first and scaled by the product of the outer modes' values.
+// A^(k)(i_k, r): the innermost other mode summed first and scaled by the
+// product of the outer modes' values.  Output entries go to threads; when
+// there are fewer than 256 of them, G groups of threads split the outermost
+// other mode (group g takes its indices g, g + G, ...) and the G partial sums
+// are added in group order.
 __device__ void wg_mttkrp(const BReq& q, const double* __restrict__ u, int n,
                           double* __restrict__ Mn) {
+  __shared__ double gpart[kBT];
   const int R = q.R, N = q.N;
   int64_t stride[kBatchMaxOrder];
   stride[N - 1] = 1;
@@ -137,22 +153,48 @@ __device__ void wg_mttkrp(const BReq& q, const double* __restrict__ u, int n,
   const double* Aa = u + q.off[ka] * R;
   const double* Ab = kb >= 0 ? u + q.off[kb] * R : nullptr;
   const int64_t In = q.dims[n];
-  for (int64_t e = threadIdx.x; e < In * R; e += kBT) {
+  const int64_t ne = In * R;
+  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(kBT / std::max<int64_t>(1, ne), Ia));
+  const int grp = G > 1 ? (int)(threadIdx.x / ne) : 0;
+  const int64_t e0 = G > 1 ? (int64_t)threadIdx.x - grp * ne : threadIdx.x;
+  for (int64_t e = e0; e < ne && grp < G; e += G > 1 ? ne : kBT) {
     const int64_t i = e / R;
     const int r = (int)(e - i * R);
     const float* Ti = q.T + i * stride[n];
     double acc = 0.0;
-    for (int64_t ia = 0; ia < Ia; ++ia) {
+    for (int64_t ia = grp; ia < Ia; ia += G) {
       const double pa = Aa[ia * R + r];
       for (int64_t ib = 0; ib < Ib; ++ib) {
         const double p = kb >= 0 ? pa * Ab[ib * R + r] : pa;
         const float* Tab = Ti + ia * sa + ib * sb;
         double s = 0.0;
-        for (int64_t ic = 0; ic < Ic; ++ic) s = fma((double)Tab[ic * sc], Ac[ic * R + r], s);
+        // the loads of 8 terms go out together; the sum keeps ic order
+        for (int64_t i0 = 0; i0 < Ic; i0 += 8) {
+          float tv[8];
+          double av[8];
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const bool ok = i0 + b < Ic;
+            tv[b] = ok ? Tab[(i0 + b) * sc] : 0.f;
+            av[b] = ok ? Ac[(i0 + b) * R + r] : 0.0;
+          }
+#pragma unroll
+          for (int b = 0; b < 8; ++b)
+            if (i0 + b < Ic) s = fma((double)tv[b], av[b], s);
+        }
         acc = fma(p, s, acc);
       }
     }
-    Mn[e] = acc;
+    if (G > 1) gpart[threadIdx.x] = acc;
+    else Mn[e] = acc;
+  }
+  if (G > 1) {
+    wg_sync();
+    for (int64_t e = threadIdx.x; e < ne; e += kBT) {
+      double s = gpart[e];
+      for (int g = 1; g < G; ++g) s += gpart[g * ne + e];
+      Mn[e] = s;
+    }
   }
   wg_sync();
 }
@@ -224,8 +266,16 @@ __device__ void wg_normalize(const BReq& q, double* __restrict__ u, double* __re
   for (int e = threadIdx.x; e < N * R; e += kBT) {
     const int k = e / R, r = e % R;
     const double* A = u + q.off[k] * R;
+    const int64_t I = q.dims[k];
     double s = 0.0;
-    for (int64_t i = 0; i < q.dims[k]; ++i) s = fma(A[i * R + r], A[i * R + r], s);
+    for (int64_t i0 = 0; i0 < I; i0 += 8) {
+      double x[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) x[b] = i0 + b < I ? A[(i0 + b) * R + r] : 0.0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        if (i0 + b < I) s = fma(x[b], x[b], s);
+    }
     nu[k][r] = sqrt(s);
   }
   wg_sync();

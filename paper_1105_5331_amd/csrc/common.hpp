@@ -38,6 +38,7 @@ struct Status {
 
 struct cp_handle {
   int device = 0;
+  int max_lds = 0;   // bytes of LDS one workgroup may use (queried on first need)
   std::string err;
   // Workspace slices, each grown on demand (host calls only).
   cpng::DevBuf part;     // MTTKRP per-workgroup partials
@@ -55,8 +56,8 @@ struct cp_handle {
   int* flags = nullptr;       // device status word (ALS solve fallbacks)
   // optional event timing of the main MTTKRP kernels
   bool prof = false;
-  static constexpr int kKernelIds = 6;
-  uint32_t prof_mask = 0x3Fu;   // kernel ids timed while prof is on
+  static constexpr int kKernelIds = 8;
+  uint32_t prof_mask = 0xFFu;   // kernel ids timed while prof is on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[kKernelIds];
   int64_t prof_launches[kKernelIds] = {};
   double prof_ms[kKernelIds] = {};
@@ -160,6 +161,7 @@ struct SparsePrepared {
   int N = 0;
   int64_t nnz = 0;
   int dtype = CP_F32;
+  hipStream_t stream = nullptr;   // the stream cp_tensor_prepare ran on
   SparseMode mode[CP_MAX_ORDER];
 };
 
@@ -179,6 +181,10 @@ int dense_fast_mfma_f32(cp_handle* h, const float* T, const double* u, const Sha
                         int mode, double* M, hipStream_t st);
 int dense_fast_mfma_f64acc(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
                            int mode, double* M, hipStream_t st);
+// Both group partials of the two-level evaluation from one pass over a
+// float32 T (dense_fast.hip); CP_OK after launching, 1 if not covered.
+int dense_twosided(cp_handle* h, const float* T, const double* u, const Shape& s, int split, int R,
+                   int prec, double* XL, double* XR, hipStream_t st);
 template <typename TT, typename CT>
 int dense_fast_vec(cp_handle* h, const TT* T, const CT* fac, const Shape& s, int R, int mode,
                    double* M, hipStream_t st);
@@ -192,6 +198,10 @@ int tree_partial(cp_handle* h, const cp_tensor* T, const Shape& s, const double*
 // Every mode's MTTKRP from the two group partials in one launch (order <= 4,
 // every second-level sum short), with the gradient epilogue when g is given:
 // G^(n) = -M^(n) + A^(n) Gbar^(n).  Returns 1 when the shape is not covered.
+// Both partials (float32 tensor, both groups of more than one mode) from one
+// pass over T: CP_OK after launching, 1 where the shape is not covered.
+int tree_partials_one_pass(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
+                           int prec, int split, double* XL, double* XR, hipStream_t st);
 int tree_all_modes(cp_handle* h, const Shape& s, int split, const double* XL, const double* XR,
                    const double* u, int R, double* M, const double* Gbar, double* g,
                    hipStream_t st);

@@ -423,15 +423,16 @@ __global__ __launch_bounds__(kThr) void mttkrp_rows_mfma(const float* __restrict
       const int k = ks * 32 + kb;
       const Op b0 = F::from_lds(dyn_lds, p.kpad, lr * p.kpad + k);
       const Op b1 = F::from_lds(dyn_lds, p.kpad, (16 + lr) * p.kpad + k);
-      // step j of every tile before step j + 1 of any: independent MFMAs
-      // between dependent ones (each tile's own order is unchanged)
+      // tile by tile, each tile's products in order (issuing step j of every
+      // tile before step j + 1 of any measured no faster for FP32 and FP64
+      // and slowed the BF16x3 row kernel from 172 to 220 us at 128^4)
 #pragma unroll
-      for (int js = 0; js < F::kSteps; ++js)
+      for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          Y[mt][0] = F::mma_step(a[mt], b0, js, Y[mt][0]);
-          Y[mt][1] = F::mma_step(a[mt], b1, js, Y[mt][1]);
-        }
+        for (int js = 0; js < F::kSteps; ++js) Y[mt][0] = F::mma_step(a[mt], b0, js, Y[mt][0]);
+#pragma unroll
+        for (int js = 0; js < F::kSteps; ++js) Y[mt][1] = F::mma_step(a[mt], b1, js, Y[mt][1]);
+      }
       if (ks + 1 == p.nks) {
         const S P0 = pscale(Pg, p, oc + j, r0 + lr);
         const S P1 = pscale(Pg, p, oc + j, r0 + 16 + lr);
@@ -569,12 +570,12 @@ __global__ __launch_bounds__(kThr) void mttkrp_cols_mfma(const float* __restrict
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) b[nt] = F::from_t(buf[0][nt]);
 #pragma unroll
-      for (int js = 0; js < F::kSteps; ++js)
+      for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          Y[0][nt] = F::mma_step(a0, b[nt], js, Y[0][nt]);
-          Y[1][nt] = F::mma_step(a1, b[nt], js, Y[1][nt]);
-        }
+        for (int js = 0; js < F::kSteps; ++js) Y[0][nt] = F::mma_step(a0, b[nt], js, Y[0][nt]);
+#pragma unroll
+        for (int js = 0; js < F::kSteps; ++js) Y[1][nt] = F::mma_step(a1, b[nt], js, Y[1][nt]);
+      }
       if (ks + 1 == p.nks) {
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
@@ -710,12 +711,12 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_mfma(const float* __res
 #pragma unroll
       for (int t = 0; t < TW; ++t) a[t] = F::from_t(v[t]);
 #pragma unroll
-      for (int js = 0; js < F::kSteps; ++js)
+      for (int t = 0; t < TW; ++t) {
 #pragma unroll
-        for (int t = 0; t < TW; ++t) {
-          Y[t][0] = F::mma_step(a[t], b0, js, Y[t][0]);
-          Y[t][1] = F::mma_step(a[t], b1, js, Y[t][1]);
-        }
+        for (int js = 0; js < F::kSteps; ++js) Y[t][0] = F::mma_step(a[t], b0, js, Y[t][0]);
+#pragma unroll
+        for (int js = 0; js < F::kSteps; ++js) Y[t][1] = F::mma_step(a[t], b1, js, Y[t][1]);
+      }
     }
     // D rows are outer indices og + t*16 + drow(lane/16, q); the column is
     // the rank.  og is a multiple of 4 (o_per_block is a multiple of 16), so
@@ -764,6 +765,262 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_mfma(const float* __res
   }
   __syncthreads();   // red is rewritten for the next row
   }
+}
+
+// ---- two-sided kernel: both group partials of an evaluation from one pass ----
+// The two-level evaluation needs, at the same point, X_L = T K_R and
+// X_R = T^T K_L for T seen as a P x Q matrix (rows: the left group's modes
+// 0..s-1, columns: the right group's modes s..N-1; K_L, K_R the Khatri-Rao
+// products of each group's factors, Section 2.3).  Both are formed here from
+// ONE read of T.  Write a = (oa, j) with j the left group's last mode
+// (length J) and b = (ob, k) with k the last mode (length K).  Every J x K
+// slab S = T(oa, :, ob, :) adds
+//     X_L(oa, j, r) += PB(ob, r) sum_k S(j, k) A^(N-1)(k, r),
+//     X_R(ob, k, r) += PA(oa, r) sum_j S(j, k) A^(s-1)(j, r),
+// PA and PB the products of each group's other factors (tables built once
+// per launch).  Workgroup (x, y) owns GA consecutive oa and GB consecutive
+// ob and walks its slabs ob by ob, oa by oa, in chunks of 32 rows j: a chunk
+// is read as whole 128-byte lines (one chunk ahead, in registers), stored to
+// one of two LDS buffers, and one barrier per chunk orders the buffers.  In
+// a chunk wave w computes the left tile of rows 16 (w / 2).., ranks
+// 16 (w % 2).. over all k, and the right rows k = (K / 4) w .. over the
+// chunk's 32 j for both rank tiles: the same MFMA count for every wave.  The
+// left operand is 8 consecutive k of one staged row, the right one 8 rows j
+// of one column k.  Left sums stay in registers for the workgroup's GA oa
+// (written to partial slot y at the end), right sums for the current ob
+// (written to slot x once its GA slabs are done); the slots are added in
+// slot order by the fixed-order split-K reduction.  No atomics.
+struct TwoParams {
+  int R;
+  int64_t J, K;        // lengths of modes s-1 and N-1
+  int64_t OA, OB;      // outer index counts of the left and right groups
+  int64_t Q;           // row stride of the P x Q view (= OB K)
+  int na, nb;          // outer modes of each group
+  int64_t adims[CP_MAX_ORDER], afoff[CP_MAX_ORDER];   // modes 0..s-2
+  int64_t bdims[CP_MAX_ORDER], bfoff[CP_MAX_ORDER];   // modes s..N-2
+  int64_t jfoff, kfoff;   // factor offsets (elements) of modes s-1 and N-1
+  int64_t GB;             // ob per workgroup
+  int kpadK, kpadJ;       // LDS row lengths of the two staged factors
+};
+
+// product over one group's outer modes of its factor values at outer index
+// o, rank r, in S (float32: each value rounded first, as the float32 copy)
+template <typename S>
+__device__ inline S group_scale(const double* __restrict__ fac, int n, const int64_t* dims,
+                                const int64_t* foff, int R, int64_t o, int r) {
+  S s = S(1);
+  for (int m = n - 1; m >= 0; --m) {
+    const int64_t d = dims[m];
+    const int64_t q = o / d;
+    s *= (S)fac[foff[m] + (o - q * d) * R + r];
+    o = q;
+  }
+  return s;
+}
+
+// PA (OA x R), PB (OB x R), and the float32 copy of all L factor values
+template <typename S>
+__global__ void twosided_tables_kernel(const double* __restrict__ fac, TwoParams p,
+                                       S* __restrict__ PA, S* __restrict__ PB,
+                                       float* __restrict__ fac32, int64_t L) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < L) fac32[e] = (float)fac[e];
+  const int64_t na = p.OA * p.R, nb = p.OB * p.R;
+  if (e < na) {
+    const int64_t o = e / p.R;
+    PA[e] = group_scale<S>(fac, p.na, p.adims, p.afoff, p.R, o, (int)(e - o * p.R));
+  } else if (e < na + nb) {
+    const int64_t e2 = e - na;
+    const int64_t o = e2 / p.R;
+    PB[e2] = group_scale<S>(fac, p.nb, p.bdims, p.bfoff, p.R, o, (int)(e2 - o * p.R));
+  }
+}
+
+// Waves per SIMD the two-sided kernel is compiled for: two (registers <= 256)
+// for float32 operands with GA <= 2, where two workgroups fit a CU's LDS;
+// one otherwise (the float64 flavour's staged factors fill most of the LDS).
+template <class F, int GA>
+constexpr int twosided_waves() {
+  return (sizeof(typename F::S) == 4 && GA <= 2) ? 2 : 1;
+}
+
+// oa per workgroup of the float32-operand flavours (compile-time knob)
+#ifndef CPNG_TWOSIDED_GA
+#define CPNG_TWOSIDED_GA 2
+#endif
+
+template <class F, int KS, int NJ, int GA>
+__global__ __launch_bounds__(kThr) __attribute__((amdgpu_waves_per_eu(twosided_waves<F, GA>())))
+void mttkrp_twosided_mfma(const float* __restrict__ T,
+                                                             const typename F::Src* __restrict__ fac,
+                                                             const typename F::S* __restrict__ PA,
+                                                             const typename F::S* __restrict__ PB,
+                                                             TwoParams p,
+                                                             typename F::S* __restrict__ partL,
+                                                             typename F::S* __restrict__ partR) {
+  using S = typename F::S;
+  using V = typename F::V;
+  using Op = typename F::Op;
+  using Src = typename F::Src;
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  constexpr int K = 32 * KS;    // slab columns
+  constexpr int RS = K + 4;     // staging row stride (floats; 16-byte rows)
+  constexpr int KT = KS / 2;    // right row tiles per wave (K / 64)
+  constexpr int KW = K / 4;     // right rows per wave
+  constexpr int NL = KS;        // 16-byte loads per thread per 32 x K chunk
+  constexpr int CH = 32 * RS;   // floats per staging buffer
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  unsigned char* Fk = dyn_lds;
+  unsigned char* Fj = dyn_lds + (size_t)F::kFacBytes * 32 * p.kpadK;
+  float* stg = reinterpret_cast<float*>(Fj + (size_t)F::kFacBytes * 32 * p.kpadJ);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int lr = lane & 15;
+  const int kb = (lane >> 4) * 8;
+  const int rl = (w & 1) * 16 + lr;   // this lane's rank in the left tile
+
+  // both factors, ranks 0..31 (zero beyond R), in the flavour's form
+  for (int e = tid; e < 32 * K; e += kThr) {
+    const int k = e >> 5, r = e & 31;
+    F::put(Fk, p.kpadK, r, k, r < p.R ? fac[p.kfoff + (int64_t)k * p.R + r] : Src(0));
+  }
+  for (int e = tid; e < 32 * 32 * NJ; e += kThr) {
+    const int j = e >> 5, r = e & 31;
+    F::put(Fj, p.kpadJ, r, j, r < p.R ? fac[p.jfoff + (int64_t)j * p.R + r] : Src(0));
+  }
+
+  const int64_t oa0 = (int64_t)blockIdx.x * GA;
+  const int64_t ob0 = (int64_t)blockIdx.y * p.GB;
+  const int nob = (int)min<int64_t>(p.GB, p.OB - ob0);
+  const int nchunk = nob * GA * NJ;
+  // chunk c = ((ob - ob0) GA + (oa - oa0)) NJ + j / 32
+  auto chunk_base = [&](int c) -> const float* {
+    const int jc = c % NJ;
+    const int t = c / NJ;
+    const int64_t oa = oa0 + t % GA, ob = ob0 + t / GA;
+    return T + (oa * p.J + jc * 32) * p.Q + ob * K;
+  };
+  // thread's share of a chunk: load l covers row (l 256 + tid) / (K / 4),
+  // columns 4 ((l 256 + tid) % (K / 4)) .. + 3
+  f4v ld[NL];
+  auto gload = [&](const float* base) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int e = l * kThr + tid;
+      ld[l] = __builtin_nontemporal_load(
+          reinterpret_cast<const f4v*>(base + (int64_t)(e / (K / 4)) * p.Q + (e % (K / 4)) * 4));
+    }
+  };
+  auto sstore = [&](float* buf) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int e = l * kThr + tid;
+      *reinterpret_cast<f4v*>(buf + (e / (K / 4)) * RS + (e % (K / 4)) * 4) = ld[l];
+    }
+  };
+
+  V accL[GA][NJ];
+#pragma unroll
+  for (int a = 0; a < GA; ++a)
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) accL[a][c] = V{0, 0, 0, 0};
+
+  gload(chunk_base(0));
+  sstore(stg);
+  if (nchunk > 1) gload(chunk_base(1));
+  __syncthreads();   // factors and chunk 0 staged
+  // the left product's factor operands are the same for every chunk: kept
+  // in registers (they were a third of the LDS reads)
+  Op bk[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) bk[ks] = F::from_lds(Fk, p.kpadK, rl * p.kpadK + 32 * ks + kb);
+
+  int c = 0;
+  for (int obi = 0; obi < nob; ++obi) {
+    const int64_t ob = ob0 + obi;
+    const S pb = rl < p.R ? PB[ob * p.R + rl] : S(0);
+    V accR[KT][2];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) accR[kt][0] = accR[kt][1] = V{0, 0, 0, 0};
+#pragma unroll
+    for (int ai = 0; ai < GA; ++ai) {
+      V YR[KT][2];
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) YR[kt][0] = YR[kt][1] = V{0, 0, 0, 0};
+#pragma unroll
+      for (int jci = 0; jci < NJ; ++jci, ++c) {
+        const float* cur = stg + (c & 1) * CH;
+        // left: chunk rows 16 (w / 2) + lr, all k
+        V YL = V{0, 0, 0, 0};
+        const float* lrow = cur + (16 * (w >> 1) + lr) * RS + kb;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const f4v x0 = *reinterpret_cast<const f4v*>(lrow + 32 * ks);
+          const f4v x1 = *reinterpret_cast<const f4v*>(lrow + 32 * ks + 4);
+          const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+          const Op a = F::from_t(v);
+#pragma unroll
+          for (int js = 0; js < F::kSteps; ++js) YL = F::mma_step(a, bk[ks], js, YL);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) accL[ai][jci][q] = fma_s(pb, YL[q], accL[ai][jci][q]);
+        // right: rows k = KW w + 16 kt + lr, the chunk's 32 j
+        const Op b0 = F::from_lds(Fj, p.kpadJ, lr * p.kpadJ + 32 * jci + kb);
+        const Op b1 = F::from_lds(Fj, p.kpadJ, (16 + lr) * p.kpadJ + 32 * jci + kb);
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+          const float* col = cur + kb * RS + KW * w + 16 * kt + lr;
+          float v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = col[q * RS];
+          const Op a = F::from_t(v);
+#pragma unroll
+          for (int js = 0; js < F::kSteps; ++js) YR[kt][0] = F::mma_step(a, b0, js, YR[kt][0]);
+#pragma unroll
+          for (int js = 0; js < F::kSteps; ++js) YR[kt][1] = F::mma_step(a, b1, js, YR[kt][1]);
+        }
+        // the next chunk (loaded one chunk ago) into the other buffer, whose
+        // readers all passed the previous barrier; then the loads after it
+        if (c + 1 < nchunk) {
+          sstore(stg + ((c + 1) & 1) * CH);
+          if (c + 2 < nchunk) gload(chunk_base(c + 2));
+        }
+        __syncthreads();
+      }
+      const int64_t oa = oa0 + ai;
+      const S pa0 = lr < p.R ? PA[oa * p.R + lr] : S(0);
+      const S pa1 = 16 + lr < p.R ? PA[oa * p.R + 16 + lr] : S(0);
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          accR[kt][0][q] = fma_s(pa0, YR[kt][0][q], accR[kt][0][q]);
+          accR[kt][1][q] = fma_s(pa1, YR[kt][1][q], accR[kt][1][q]);
+        }
+    }
+    S* outR = partR + (int64_t)blockIdx.x * p.Q * p.R;
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = KW * w + 16 * kt + F::drow(lane >> 4, q);
+          const int r = 16 * rt + lr;
+          if (r < p.R) outR[(ob * K + k) * p.R + r] = accR[kt][rt][q];
+        }
+  }
+  S* outL = partL + (int64_t)blockIdx.y * p.OA * p.J * p.R;
+#pragma unroll
+  for (int ai = 0; ai < GA; ++ai)
+#pragma unroll
+    for (int jci = 0; jci < NJ; ++jci)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t j = 32 * jci + 16 * (w >> 1) + F::drow(lane >> 4, q);
+        if (rl < p.R) outL[((oa0 + ai) * p.J + j) * p.R + rl] = accL[ai][jci][q];
+      }
 }
 
 // ---- vector (VALU) streaming kernel: float32 or float64 arithmetic --------------
@@ -1062,6 +1319,113 @@ int launch_mfma(cp_handle* h, const float* T, const double* u, const Shape& s, i
   return CP_OK;
 }
 
+// Launches the two-sided pass in flavour F: both group partials X_L and X_R
+// (float64, P x R and Q x R) of the split before mode `split`, from one read
+// of T.  Returns CP_OK after launching, or 1 where the shape is not covered
+// (R > 32; modes s-1 and N-1 not of length 64 or 128; the left group's outer
+// count not a multiple of GA; a misaligned tensor; too little LDS).
+template <class F, int GA>
+int launch_twosided(cp_handle* h, const float* T, const double* u, const Shape& s, int split,
+                    int R, double* XL, double* XR, hipStream_t st) {
+  using S = typename F::S;
+  constexpr bool kF32Src = sizeof(typename F::Src) == 4;
+  const int N = s.N;
+  if (split < 1 || split >= N || R < 1 || R > 32) return 1;
+  const int64_t J = s.dims[split - 1], K = s.dims[N - 1];
+  if ((J != 64 && J != 128) || (K != 64 && K != 128)) return 1;
+  if (reinterpret_cast<uintptr_t>(T) % 16 != 0) return 1;
+  TwoParams p{};
+  p.R = R;
+  p.J = J;
+  p.K = K;
+  p.OA = 1;
+  p.na = split - 1;
+  for (int m = 0; m < split - 1; ++m) {
+    p.adims[m] = s.dims[m];
+    p.afoff[m] = s.off[m] * R;
+    p.OA *= s.dims[m];
+  }
+  p.OB = 1;
+  p.nb = N - 1 - split;
+  for (int m = split; m < N - 1; ++m) {
+    p.bdims[m - split] = s.dims[m];
+    p.bfoff[m - split] = s.off[m] * R;
+    p.OB *= s.dims[m];
+  }
+  if (p.OA % GA != 0) return 1;
+  p.Q = p.OB * K;
+  p.jfoff = s.off[split - 1] * R;
+  p.kfoff = s.off[N - 1] * R;
+  p.kpadK = (int)K + 8;
+  p.kpadJ = (int)J + 8;
+  const size_t lds = (size_t)F::kFacBytes * 32 * (size_t)(p.kpadK + p.kpadJ) +
+                     sizeof(float) * 2 * 32 * (size_t)(K + 4);
+  if (h->max_lds == 0) {
+    int v = 0;
+    CP_HIP(h, hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+    h->max_lds = v > 0 ? v : 65536;
+  }
+  if (lds > (size_t)h->max_lds) return 1;
+  // workgroups: GA oa by GB ob each; about as many as fit the chip at once
+  const int64_t gx = p.OA / GA;
+  const int64_t target = 256 * twosided_waves<F, GA>();
+  int64_t gy = std::max<int64_t>(1, std::min<int64_t>(p.OB, (target + gx - 1) / gx));
+  p.GB = (p.OB + gy - 1) / gy;
+  gy = (p.OB + p.GB - 1) / p.GB;
+  const int64_t nL = gy * p.OA * J * R, nR = gx * p.Q * R;   // partial slots, slot-major
+  const size_t pl = (sizeof(S) * (size_t)nL + 255) & ~size_t(255);
+  CP_TRY(ensure(h, h->part, pl + sizeof(S) * (size_t)nR, st));
+  S* partL = static_cast<S*>(h->part.ptr);
+  S* partR = reinterpret_cast<S*>(static_cast<char*>(h->part.ptr) + pl);
+  const size_t ta = (sizeof(S) * (size_t)(p.OA * R) + 255) & ~size_t(255);
+  CP_TRY(ensure(h, h->otab, ta + sizeof(S) * (size_t)(p.OB * R), st));
+  S* PA = static_cast<S*>(h->otab.ptr);
+  S* PB = reinterpret_cast<S*>(static_cast<char*>(h->otab.ptr) + ta);
+  const int64_t L = s.sum_dims() * R;
+  float* fac32 = nullptr;
+  if (kF32Src) {
+    CP_TRY(ensure(h, h->stage, sizeof(float) * (size_t)L, st));
+    fac32 = static_cast<float*>(h->stage.ptr);
+  }
+  const typename F::Src* fac = nullptr;
+  if constexpr (kF32Src) fac = fac32;
+  else fac = u;
+  {
+    const int64_t Lc = kF32Src ? L : 0;
+    const int64_t nt = std::max<int64_t>((p.OA + p.OB) * R, Lc);
+    hipLaunchKernelGGL(twosided_tables_kernel<S>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
+                       st, u, p, PA, PB, fac32, Lc);
+    CP_LAUNCH_CHECK(h);
+  }
+  const int kid = sizeof(S) == 8 ? CP_KERNEL_DENSE_TWOSIDED_F64 : CP_KERNEL_DENSE_TWOSIDED;
+  const dim3 grid((unsigned)gx, (unsigned)gy);
+  // returns 1 (not covered) if the runtime refuses the kernel this much LDS
+  auto go = [&](auto kern) -> int {
+    if (lds > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+      (void)hipGetLastError();
+      return 1;
+    }
+    KernelTimer timer(h, kid, st);
+    CP_TIMED_LAUNCH(timer, kern, grid, dim3(kThr), lds, st, T, fac, PA, PB, p, partL, partR);
+    return CP_OK;
+  };
+  int rc;
+  if (K == 128 && J == 128) rc = go(mttkrp_twosided_mfma<F, 4, 4, GA>);
+  else if (K == 128) rc = go(mttkrp_twosided_mfma<F, 4, 2, GA>);
+  else if (J == 128) rc = go(mttkrp_twosided_mfma<F, 2, 4, GA>);
+  else rc = go(mttkrp_twosided_mfma<F, 2, 2, GA>);
+  if (rc != CP_OK) return rc;
+  CP_LAUNCH_CHECK(h);
+  h->t_passes++;
+  CP_TRY(launch_splitk_reduce(h, partL, gy, p.OA * J * R, R, XL, st));
+  CP_LAUNCH_CHECK(h);
+  CP_TRY(launch_splitk_reduce(h, partR, gx, p.Q * R, R, XR, st));
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
 }  // namespace
 
 // The streaming matrix-core MTTKRP of one mode, per arithmetic: BF16x3
@@ -1083,6 +1447,17 @@ int dense_fast_mfma_f32(cp_handle* h, const float* T, const double* u, const Sha
 int dense_fast_mfma_f64acc(cp_handle* h, const float* T, const double* u, const Shape& s, int R,
                            int mode, double* M, hipStream_t st) {
   return launch_mfma<FlavF64>(h, T, u, s, R, mode, M, st);
+}
+
+// Both group partials of the two-level evaluation (split before mode
+// `split`) from one pass over T, per arithmetic (as the single-mode calls
+// above).  CP_OK after launching, 1 where the shape is not covered.
+int dense_twosided(cp_handle* h, const float* T, const double* u, const Shape& s, int split, int R,
+                   int prec, double* XL, double* XR, hipStream_t st) {
+  constexpr int ga = CPNG_TWOSIDED_GA;
+  if (prec == CP_PREC_BF16X3) return launch_twosided<FlavBF16x3, ga>(h, T, u, s, split, R, XL, XR, st);
+  if (prec == CP_PREC_FP32) return launch_twosided<FlavF32, ga>(h, T, u, s, split, R, XL, XR, st);
+  return launch_twosided<FlavF64, 2>(h, T, u, s, split, R, XL, XR, st);
 }
 
 }  // namespace cpng

@@ -161,17 +161,25 @@ int mode_mttkrp(cp_handle* h, const cp_tensor* T, const Shape& s, const double* 
 
 // f and g at u: all N MTTKRPs at the same point (Section 2.3), the gradient
 // epilogue G^(n) = -M^(n) + A^(n) Gammabar^(n) and the objective from the
-// last mode's M and Gamma.  With `tree` (dense, order >= 3) the MTTKRPs come
-// from the two group partials: T is streamed twice.
+// last mode's M and Gamma.  With `tree` != 0 (dense, order >= 3) the MTTKRPs
+// come from the two group partials: T is streamed twice, or, with tree == 1
+// where the two-sided kernel covers the shape, once for both partials.
 int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
-                        int prec, double* f_out, double* g_out, hipStream_t st, bool tree = true) {
+                        int prec, double* f_out, double* g_out, hipStream_t st, int tree = 1) {
   Scratch sc;
   CP_TRY(mode_buffers(h, s, R, st, &sc));
   CP_TRY(gram_all(h, s, u, R, sc.S, sc.Gbar, sc.Gam, st));
   TreeBufs tb;
-  CP_TRY(tree_setup(h, T, s, R, prec, tree, st, &tb));
-  if (tb.XL) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, true, tb.XL, st));
-  if (tb.XR) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, false, tb.XR, st));
+  CP_TRY(tree_setup(h, T, s, R, prec, tree != 0, st, &tb));
+  int one = 1;
+  if (tree == 1 && tb.XL && tb.XR) {
+    one = tree_partials_one_pass(h, T, s, u, R, prec, tb.split, tb.XL, tb.XR, st);
+    if (one < 0) return one;
+  }
+  if (one != CP_OK) {
+    if (tb.XL) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, true, tb.XL, st));
+    if (tb.XR) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, false, tb.XR, st));
+  }
   struct EpiScope {   // the pending epilogue never outlives one MTTKRP call
     cp_handle* h;
     ~EpiScope() { h->epi = GradEpi{}; }
@@ -255,7 +263,7 @@ int enqueue_step12(cp_handle* h, cp_ngmres_state* S) {
   CP_HIP(h, hipMemcpyAsync(S->ubar, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
   CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0));
   CP_TRY(objective_grad_impl(h, S->T, S->s, S->ubar, S->R, S->prec, S->scal, S->gbar, S->st,
-                             S->opt.mttkrp_tree != 0));
+                             S->opt.mttkrp_tree));
   return enqueue_step2(h, S);
 }
 
@@ -265,7 +273,7 @@ int enqueue_eval(cp_handle* h, cp_ngmres_state* S) {
   CP_HIP(h, hipMemcpyAsync(S->dpar, S->hpar, sizeof(StepPar), hipMemcpyHostToDevice, S->st));
   CP_TRY(axpy_par(h, S->ubar, S->dpar, S->d, S->ut, S->L, S->st));
   CP_TRY(objective_grad_impl(h, S->T, S->s, S->ut, S->R, S->prec, S->scal, S->gt, S->st,
-                             S->opt.mttkrp_tree != 0));
+                             S->opt.mttkrp_tree));
   CP_TRY(dot(h, S->gt, S->d, S->L, S->scal + 1, S->st));
   return CP_OK;
 }
@@ -390,7 +398,7 @@ int window_push(cp_handle* h, cp_ngmres_state* S) {
 
 int eval_current(cp_handle* h, cp_ngmres_state* S) {
   CP_TRY(objective_grad_impl(h, S->T, S->s, S->u, S->R, S->prec, S->scal, S->g, S->st,
-                             S->opt.mttkrp_tree != 0));
+                             S->opt.mttkrp_tree));
   S->n_fg++;
   CP_TRY(dot(h, S->g, S->g, S->L, S->scal + 1, S->st));
   double v[2];
@@ -688,7 +696,7 @@ int cp_sparse_gather_read(cp_handle* h, const cp_tensor* T, const double* u, int
 }
 
 int cp_profile_select(cp_handle* h, uint32_t kernel_mask) {
-  if (!h || (kernel_mask & ~0x3Fu) != 0) return CP_EINVAL;
+  if (!h || (kernel_mask & ~0xFFu) != 0) return CP_EINVAL;
   h->prof_mask = kernel_mask;
   return CP_OK;
 }
@@ -905,6 +913,8 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
   if (o.ls_maxfev < 1 || !(o.ls_stp0 > 0.0)) return fail(h, CP_EINVAL, "bad line-search options");
   if (o.init != CP_INIT_GIVEN && o.init != CP_INIT_SEEDED)
     return fail(h, CP_EINVAL, "unknown init %d", o.init);
+  if (o.mttkrp_tree < 0 || o.mttkrp_tree > 2)
+    return fail(h, CP_EINVAL, "mttkrp_tree must be 0, 1 or 2");
   CP_TRY(check_prec(h, T, o.precision));
   CP_TRY(check_prec(h, T, o.final_precision));
   auto* S = new (std::nothrow) cp_ngmres_state();

@@ -518,6 +518,7 @@ int sparse_prepare(cp_handle* h, cp_tensor* T, const Shape& s, hipStream_t st) {
   sp->N = s.N;
   sp->nnz = nnz;
   sp->dtype = T->dtype;
+  sp->stream = st;
   int rc = CP_OK;
   if (nnz > 0) {
     int* dflag = nullptr;
@@ -599,7 +600,9 @@ int sparse_prepare(cp_handle* h, cp_tensor* T, const Shape& s, hipStream_t st) {
 int sparse_release(cp_handle* h, cp_tensor* T) {
   auto* sp = static_cast<SparsePrepared*>(T->prepared);
   if (!sp) return CP_OK;
-  (void)hipDeviceSynchronize();
+  // only the stream the tensor was prepared on (a serving slot's own): a
+  // device-wide synchronisation would wait for every other slot's work
+  (void)hipStreamSynchronize(sp->stream);
   for (int n = 0; n < sp->N; ++n) {
     if (sp->mode[n].coords) (void)hipFree(sp->mode[n].coords);
     if (sp->mode[n].values) (void)hipFree(sp->mode[n].values);

@@ -420,6 +420,12 @@ int tree_partial(cp_handle* h, const cp_tensor* T, const Shape& s, const double*
   return dense_mttkrp(h, T, v, u, R, mode, prec, X, st);
 }
 
+int tree_partials_one_pass(cp_handle* h, const cp_tensor* T, const Shape& s, const double* u, int R,
+                           int prec, int split, double* XL, double* XR, hipStream_t st) {
+  if (T->sparse || T->dtype != CP_F32 || !XL || !XR) return 1;
+  return dense_twosided(h, static_cast<const float*>(T->values), u, s, split, R, prec, XL, XR, st);
+}
+
 namespace {
 // The second-level description of `mode` within the group [lo, hi).
 GroupParams group_params(const Shape& s, int lo, int hi, int mode, int R) {

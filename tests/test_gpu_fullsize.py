@@ -52,11 +52,12 @@ def test_dense_128x4_R32_sampled_rows(h):
             assert_close_to_bound(M, ref, bound, TOL[prec], f"mode {n} {prec}")
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32", "fp32in_fp64acc"])
 def test_dense_128x4_R32_gradient_rows(h, prec):
     """G^(n)(i, :) = -M^(n)(i, :) + A^(n)(i, :) Gammabar^(n) on sampled rows of
-    every mode, from cp_objective_grad (the two-level evaluation), against the
-    oracle's rows; the bound adds |A| |Gammabar| to the MTTKRP bound."""
+    every mode, from cp_objective_grad (the two-level evaluation, both group
+    partials from one pass of the two-sided kernel), against the oracle's
+    rows; the bound adds |A| |Gammabar| to the MTTKRP bound."""
     import paper_1105_5331_amd as cpng
     dims, R = (128, 128, 128, 128), 32
     print(f"case dense 128^4 R=32 gradient rows {prec}", flush=True)

@@ -453,7 +453,7 @@ def test_profile_select_times_only_the_chosen_kernels(h):
     nd, msd = cpng.cp_profile_read(h, cpng.CP_KERNEL_DENSE_MTTKRP)
     ng, _ = cpng.cp_profile_read(h, cpng.CP_KERNEL_GROUP_MTTKRP)
     cpng.cp_profile(h, False)
-    cpng.cp_profile_select(h, 0x3F)
+    cpng.cp_profile_select(h, 0xFF)
     assert nd >= 1 and msd > 0 and ng == 0
     cpng.cp_profile(h, True)
     cpng.cp_objective_grad(h, Tg, u, R, "fp32")
@@ -471,7 +471,7 @@ def test_profile_select_times_only_the_chosen_kernels(h):
     cpng.cp_profile(h, False)
     assert n64 == 1 and n32 == 1
     with pytest.raises(cpng.CpError):
-        cpng.cp_profile_select(h, 1 << 6)
+        cpng.cp_profile_select(h, 1 << 8)
 
 
 def test_sparse_gather_reference(h):
