@@ -9,16 +9,20 @@ seed 10000.  One "step" is one N-GMRES iteration through the C ABI
 line search in it stalls (rho <= 1e-2) or rho <= 1e-4, then float32 values
 with float64 accumulation to rho <= 1e-8; a converged solve starts again from
 the initial guess.  Each iteration: Step I (ALS sweep), Step II (gradient at
-u_bar, the window's normal equations), Step III (line search); every sweep
-and evaluation streams the tensor twice (two group partials).
+u_bar, the window's normal equations), Step III (line search); a sweep
+streams the tensor twice (two group partials), an objective/gradient
+evaluation once (both partials from the two-sided kernel).
 
 value  = tensor bytes streamed by all MTTKRPs of the timed steps / wall time
-         (GB/s, whole-job throughput, inputs resident in HBM).
-roofline = the dense MTTKRP kernel class with the larger share of the timed
+         (GB/s, whole-job throughput, inputs resident in HBM).  Fewer passes
+         per iteration lower this figure while the iteration gets faster:
+         ms_per_step and ms_per_eval are the work-rate figures.
+roofline = the dense MTTKRP kernel class with the largest share of the timed
          steps' kernel time: algorithmic bytes (or flops) per launch over its
          mean duration, timed with HIP events on the stream it runs on,
          against 8 TB/s (BF16x3 bulk) or the 78.6 TFLOP/s float64 matrix rate
-         (float64 accumulation); both classes are listed in extra.rooflines.
+         (float64 accumulation); every class (single group partial or both
+         partials in one pass, per precision) is listed in extra.rooflines.
 cpu_baseline = the FP64 oracle's MTTKRP (all four modes) on a slab of the
          same tensor, on the host cores.
 extra.time_to_grad = dense 200^3 float32, R = 10, congruence 0.9: wall time of
@@ -683,8 +687,8 @@ def serving(cpng, torch, n=100, slots=4, seed=7, max_iter=500, load=0.8, batch_e
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--size", type=int, default=128)

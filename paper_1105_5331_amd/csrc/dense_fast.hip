@@ -841,7 +841,11 @@ __global__ void twosided_tables_kernel(const double* __restrict__ fac, TwoParams
 // one otherwise (the float64 flavour's staged factors fill most of the LDS).
 template <class F, int GA>
 constexpr int twosided_waves() {
+#ifdef CPNG_TWOSIDED_WAVES
+  return CPNG_TWOSIDED_WAVES;
+#else
   return (sizeof(typename F::S) == 4 && GA <= 2) ? 2 : 1;
+#endif
 }
 
 // oa per workgroup of the float32-operand flavours (compile-time knob)
@@ -868,7 +872,11 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
   constexpr int KT = KS / 2;    // right row tiles per wave (K / 64)
   constexpr int KW = K / 4;     // right rows per wave
   constexpr int NL = KS;        // 16-byte loads per thread per 32 x K chunk
-  constexpr int CH = 32 * RS;   // floats per staging buffer
+  // staged row j starts at j RS + 16 (j / 16) floats: the 16 rows of a
+  // left tile then start in 16 different 16-byte bank groups, and the four
+  // lane groups of a right operand read (rows 8g + q, 16 consecutive
+  // columns) in four disjoint quarters of the banks
+  constexpr int CH = 32 * RS + 16;   // floats per staging buffer
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   unsigned char* Fk = dyn_lds;
   unsigned char* Fj = dyn_lds + (size_t)F::kFacBytes * 32 * p.kpadK;
@@ -901,22 +909,25 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
     const int64_t oa = oa0 + t % GA, ob = ob0 + t / GA;
     return T + (oa * p.J + jc * 32) * p.Q + ob * K;
   };
-  // thread's share of a chunk: load l covers row (l 256 + tid) / (K / 4),
-  // columns 4 ((l 256 + tid) % (K / 4)) .. + 3
-  f4v ld[NL];
-  auto gload = [&](const float* base) {
+  // thread's share of a chunk: load l covers row l RL + tid / (K / 4),
+  // columns 4 (tid % (K / 4)) .. + 3 (32 Q < 2^31: 32-bit offsets)
+  constexpr int RL = kThr / (K / 4);   // rows per load instruction
+  const int trow = tid / (K / 4), tcol = (tid % (K / 4)) * 4;
+  const int toff = trow * (int)p.Q + tcol;
+  // two chunks in flight ahead of the one being multiplied: register sets
+  // ld[0], ld[1] alternate (chunk c's data in set c % 2)
+  f4v ld[2][NL];
+  auto gload = [&](int set, const float* base) {
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      const int e = l * kThr + tid;
-      ld[l] = __builtin_nontemporal_load(
-          reinterpret_cast<const f4v*>(base + (int64_t)(e / (K / 4)) * p.Q + (e % (K / 4)) * 4));
-    }
+    for (int l = 0; l < NL; ++l)
+      ld[set][l] = __builtin_nontemporal_load(
+          reinterpret_cast<const f4v*>(base + (int64_t)l * RL * p.Q + toff));
   };
-  auto sstore = [&](float* buf) {
+  auto sstore = [&](int set, float* buf) {
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-      const int e = l * kThr + tid;
-      *reinterpret_cast<f4v*>(buf + (e / (K / 4)) * RS + (e % (K / 4)) * 4) = ld[l];
+      const int row = l * RL + trow;
+      *reinterpret_cast<f4v*>(buf + row * RS + 16 * (row >> 4) + tcol) = ld[set][l];
     }
   };
 
@@ -926,9 +937,16 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
 #pragma unroll
     for (int c = 0; c < NJ; ++c) accL[a][c] = V{0, 0, 0, 0};
 
-  gload(chunk_base(0));
-  sstore(stg);
-  if (nchunk > 1) gload(chunk_base(1));
+  // Loads and stores are issued without branches (chunk indices past the
+  // end are clamped to the last chunk, whose lines are then still in the
+  // caches), so that the compiler's wait before staging a register set
+  // counts only that set's loads and leaves the newer set in flight.
+  static_assert((GA * NJ) % 2 == 0, "chunk parity is static within an ob");
+  const int last = nchunk - 1;
+  gload(0, chunk_base(0));
+  gload(1, chunk_base(min(1, last)));
+  sstore(0, stg);
+  gload(0, chunk_base(min(2, last)));
   __syncthreads();   // factors and chunk 0 staged
   // the left product's factor operands are the same for every chunk: kept
   // in registers (they were a third of the LDS reads)
@@ -953,7 +971,7 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
         const float* cur = stg + (c & 1) * CH;
         // left: chunk rows 16 (w / 2) + lr, all k
         V YL = V{0, 0, 0, 0};
-        const float* lrow = cur + (16 * (w >> 1) + lr) * RS + kb;
+        const float* lrow = cur + (16 * (w >> 1) + lr) * RS + 16 * (w >> 1) + kb;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
           const f4v x0 = *reinterpret_cast<const f4v*>(lrow + 32 * ks);
@@ -970,7 +988,7 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
         const Op b1 = F::from_lds(Fj, p.kpadJ, (16 + lr) * p.kpadJ + 32 * jci + kb);
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
-          const float* col = cur + kb * RS + KW * w + 16 * kt + lr;
+          const float* col = cur + kb * RS + 16 * (kb >> 4) + KW * w + 16 * kt + lr;
           float v[8];
 #pragma unroll
           for (int q = 0; q < 8; ++q) v[q] = col[q * RS];
@@ -980,11 +998,15 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
 #pragma unroll
           for (int js = 0; js < F::kSteps; ++js) YR[kt][1] = F::mma_step(a, b1, js, YR[kt][1]);
         }
-        // the next chunk (loaded one chunk ago) into the other buffer, whose
-        // readers all passed the previous barrier; then the loads after it
-        if (c + 1 < nchunk) {
-          sstore(stg + ((c + 1) & 1) * CH);
-          if (c + 2 < nchunk) gload(chunk_base(c + 2));
+        // the next chunk (loaded two chunks ago) into the other buffer, whose
+        // readers all passed the previous barrier (past the last chunk this
+        // stages a copy nobody reads); then the loads of chunk c + 3 into the
+        // register set it freed (c is even here exactly when ai NJ + jci is:
+        // GA NJ is even)
+        {
+          const int set = ((ai * NJ + jci) + 1) & 1;
+          sstore(set, stg + ((c + 1) & 1) * CH);
+          gload(set, chunk_base(min(c + 3, last)));
         }
         __syncthreads();
       }
@@ -1354,12 +1376,13 @@ int launch_twosided(cp_handle* h, const float* T, const double* u, const Shape& 
   }
   if (p.OA % GA != 0) return 1;
   p.Q = p.OB * K;
+  if (p.Q >= (int64_t(1) << 26)) return 1;   // in-chunk offsets stay 32-bit
   p.jfoff = s.off[split - 1] * R;
   p.kfoff = s.off[N - 1] * R;
   p.kpadK = (int)K + 8;
   p.kpadJ = (int)J + 8;
   const size_t lds = (size_t)F::kFacBytes * 32 * (size_t)(p.kpadK + p.kpadJ) +
-                     sizeof(float) * 2 * 32 * (size_t)(K + 4);
+                     sizeof(float) * 2 * (32 * (size_t)(K + 4) + 16);
   if (h->max_lds == 0) {
     int v = 0;
     CP_HIP(h, hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));

@@ -3,11 +3,13 @@
 //     M(e) = sum over contiguous slot ranges, in range order, of the
 //            in-order sum of that range,
 // so the result depends only on nsplit and n, never on timing.  Up to 16
-// slots, one thread per output adds all slots in order (256 consecutive
-// outputs per block, every slot's load in flight at once).  Up to 256, a
-// block covers 16 consecutive outputs with 16 threads per output; each
-// thread issues its range's loads 8 at a time before adding.  Many slots go
-// through a first stage over groups of 64 slots (see launch_splitk_reduce).
+// slots, and up to 256 when there are at least 2^16 outputs, one thread per
+// output adds all slots in order (256 consecutive outputs per block, 16
+// slots' loads in flight at a time; a wave reads 256 contiguous bytes of a
+// slot).  Otherwise up to 256 slots, a block covers 16 consecutive outputs
+// with 16 threads per output; each thread issues its range's loads 8 at a
+// time before adding.  Many slots go through a first stage over groups of
+// 64 slots (see launch_splitk_reduce).
 // With a pending gradient epilogue on the handle (M is an I x R MTTKRP) the
 // same kernel also writes G(i, r) = -M(i, r) + sum_q A(i, q) Gbar(q, r), with
 // the sum in q order.
@@ -65,8 +67,8 @@ __global__ __launch_bounds__(kSplitThreads) void splitk_reduce_kernel(
   }
 }
 
-// Few slots: thread e adds slots 0..nsplit-1 of output e in order.  With the
-// epilogue, Gbar (R x R) is staged in LDS (dynamic, R * R doubles).
+// Thread e adds slots 0..nsplit-1 of output e in order, 16 loads at a time.
+// With the epilogue, Gbar (R x R) is staged in LDS (dynamic, R * R doubles).
 template <typename PT>
 __global__ __launch_bounds__(kSplitThreads) void splitk_flat_kernel(
     const PT* __restrict__ part, int nsplit, int64_t n, double* __restrict__ M,
@@ -79,12 +81,14 @@ __global__ __launch_bounds__(kSplitThreads) void splitk_flat_kernel(
     __syncthreads();
   }
   if (e >= n) return;
-  PT v[16];
-#pragma unroll
-  for (int b = 0; b < 16; ++b) v[b] = b < nsplit ? part[(int64_t)b * n + e] : PT(0);
   double t = 0.0;
+  for (int q0 = 0; q0 < nsplit; q0 += 16) {
+    PT v[16];
 #pragma unroll
-  for (int b = 0; b < 16; ++b) t += (double)v[b];
+    for (int b = 0; b < 16; ++b) v[b] = q0 + b < nsplit ? part[(int64_t)(q0 + b) * n + e] : PT(0);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) t += (double)v[b];
+  }
   M[e] = t;
   if (eG) {
     const int64_t i = e / eR;
@@ -134,7 +138,7 @@ inline int launch_splitk_reduce(cp_handle* h, const PT* part, int64_t nsplit, in
   const double* eA = epi ? ep.A : nullptr;
   const double* eGb = epi ? ep.Gbar : nullptr;
   double* eG = epi ? ep.G : nullptr;
-  if (nsplit <= 16) {
+  if (nsplit <= 16 || (nsplit <= 256 && n >= (int64_t(1) << 16))) {
     const size_t lds = epi ? sizeof(double) * (size_t)R * R : 0;
     hipLaunchKernelGGL((splitk_flat_kernel<PT>), dim3((unsigned)((n + kSplitThreads - 1) / kSplitThreads)),
                        dim3(kSplitThreads), lds, st, part, (int)nsplit, n, M, eA, eGb, eG, R);
