@@ -31,12 +31,14 @@
 #include "splitk.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace cpng {
 
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThr = 256;
@@ -102,6 +104,9 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 struct FlavBF16x3 {
   using S = float;     // outer scales, accumulators, per-workgroup partial sums
+  // the two-sided kernel stages its tensor chunks already split into bf16
+  // hi and lo planes (each value split once instead of once per operand)
+  static constexpr bool kPreSplit = true;
   using V = floatx4;   // one MFMA tile: 4 values per lane
   using Src = float;   // factor values staged (the float32 copy)
   static constexpr int kMaxK = 512;
@@ -138,6 +143,7 @@ struct FlavBF16x3 {
 
 struct FlavF32 {
   using S = float;
+  static constexpr bool kPreSplit = false;
   using V = floatx4;
   using Src = float;
   static constexpr int kMaxK = 512;
@@ -169,6 +175,7 @@ struct FlavF32 {
 
 struct FlavF64 {
   using S = double;
+  static constexpr bool kPreSplit = false;
   using V = doublex4;
   using Src = double;   // the float64 factors themselves
   static constexpr int kMaxK = 256;
@@ -853,6 +860,24 @@ constexpr int twosided_waves() {
 #define CPNG_TWOSIDED_GA 2
 #endif
 
+// Staging geometry of one 32 x K chunk: float32 rows of K + 4 values, or
+// (pre-split flavours) a bf16 hi plane and a lo plane with rows of K + 8
+// values; row j starts at j RS + RO (j / 16), RO = 16 words, so the 16 rows
+// of a left tile start in 16 different 16-byte bank groups and the four lane
+// groups of a right operand read (rows 8g + q, 16 consecutive columns) fall
+// in four disjoint quarters of the banks.
+template <class F, int K>
+struct TwoStage {
+  static constexpr bool PS = F::kPreSplit;
+  using E = typename std::conditional<PS, __bf16, float>::type;
+  static constexpr int RS = PS ? K + 8 : K + 4;
+  static constexpr int RO = PS ? 32 : 16;
+  static constexpr int PL = 32 * RS + RO;        // one plane, elements
+  static constexpr int CH = PS ? 2 * PL : PL;    // one staging buffer, elements
+  static constexpr size_t kBufBytes = sizeof(E) * (size_t)CH;
+  __device__ static int radd(int j) { return j * RS + RO * (j >> 4); }
+};
+
 template <class F, int KS, int NJ, int GA>
 __global__ __launch_bounds__(kThr) __attribute__((amdgpu_waves_per_eu(twosided_waves<F, GA>())))
 void mttkrp_twosided_mfma(const float* __restrict__ T,
@@ -868,19 +893,17 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
   using Src = typename F::Src;
   typedef float f4v __attribute__((ext_vector_type(4)));
   constexpr int K = 32 * KS;    // slab columns
-  constexpr int RS = K + 4;     // staging row stride (floats; 16-byte rows)
   constexpr int KT = KS / 2;    // right row tiles per wave (K / 64)
   constexpr int KW = K / 4;     // right rows per wave
   constexpr int NL = KS;        // 16-byte loads per thread per 32 x K chunk
-  // staged row j starts at j RS + 16 (j / 16) floats: the 16 rows of a
-  // left tile then start in 16 different 16-byte bank groups, and the four
-  // lane groups of a right operand read (rows 8g + q, 16 consecutive
-  // columns) in four disjoint quarters of the banks
-  constexpr int CH = 32 * RS + 16;   // floats per staging buffer
+  using St = TwoStage<F, K>;
+  using E = typename St::E;
+  constexpr bool PS = St::PS;
+  constexpr int PL = St::PL, CH = St::CH;
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   unsigned char* Fk = dyn_lds;
   unsigned char* Fj = dyn_lds + (size_t)F::kFacBytes * 32 * p.kpadK;
-  float* stg = reinterpret_cast<float*>(Fj + (size_t)F::kFacBytes * 32 * p.kpadJ);
+  E* stg = reinterpret_cast<E*>(Fj + (size_t)F::kFacBytes * 32 * p.kpadJ);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
@@ -923,11 +946,22 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
       ld[set][l] = __builtin_nontemporal_load(
           reinterpret_cast<const f4v*>(base + (int64_t)l * RL * p.Q + toff));
   };
-  auto sstore = [&](int set, float* buf) {
+  auto sstore = [&](int set, E* buf) {
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-      const int row = l * RL + trow;
-      *reinterpret_cast<f4v*>(buf + row * RS + 16 * (row >> 4) + tcol) = ld[set][l];
+      const int off = St::radd(l * RL + trow) + tcol;
+      if constexpr (PS) {
+        bf16x4 h, lo;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          h[i] = (__bf16)ld[set][l][i];
+          lo[i] = (__bf16)(ld[set][l][i] - (float)h[i]);   // exact residual
+        }
+        *reinterpret_cast<bf16x4*>(buf + off) = h;
+        *reinterpret_cast<bf16x4*>(buf + PL + off) = lo;
+      } else {
+        *reinterpret_cast<f4v*>(buf + off) = ld[set][l];
+      }
     }
   };
 
@@ -968,16 +1002,22 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
       for (int kt = 0; kt < KT; ++kt) YR[kt][0] = YR[kt][1] = V{0, 0, 0, 0};
 #pragma unroll
       for (int jci = 0; jci < NJ; ++jci, ++c) {
-        const float* cur = stg + (c & 1) * CH;
+        const E* cur = stg + (c & 1) * CH;
         // left: chunk rows 16 (w / 2) + lr, all k
         V YL = V{0, 0, 0, 0};
-        const float* lrow = cur + (16 * (w >> 1) + lr) * RS + 16 * (w >> 1) + kb;
+        const E* lrow = cur + St::radd(16 * (w >> 1) + lr) + kb;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-          const f4v x0 = *reinterpret_cast<const f4v*>(lrow + 32 * ks);
-          const f4v x1 = *reinterpret_cast<const f4v*>(lrow + 32 * ks + 4);
-          const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-          const Op a = F::from_t(v);
+          Op a;
+          if constexpr (PS) {
+            a.h = *reinterpret_cast<const bf16x8*>(lrow + 32 * ks);
+            a.l = *reinterpret_cast<const bf16x8*>(lrow + PL + 32 * ks);
+          } else {
+            const f4v x0 = *reinterpret_cast<const f4v*>(lrow + 32 * ks);
+            const f4v x1 = *reinterpret_cast<const f4v*>(lrow + 32 * ks + 4);
+            const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            a = F::from_t(v);
+          }
 #pragma unroll
           for (int js = 0; js < F::kSteps; ++js) YL = F::mma_step(a, bk[ks], js, YL);
         }
@@ -988,11 +1028,21 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
         const Op b1 = F::from_lds(Fj, p.kpadJ, (16 + lr) * p.kpadJ + 32 * jci + kb);
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
-          const float* col = cur + kb * RS + 16 * (kb >> 4) + KW * w + 16 * kt + lr;
-          float v[8];
+          // rows kb .. kb + 7 lie in one 16-row half: radd(kb + q) = radd(kb) + q RS
+          const E* col = cur + St::radd(kb) + KW * w + 16 * kt + lr;
+          Op a;
+          if constexpr (PS) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) v[q] = col[q * RS];
-          const Op a = F::from_t(v);
+            for (int q = 0; q < 8; ++q) {
+              a.h[q] = col[q * St::RS];
+              a.l[q] = col[PL + q * St::RS];
+            }
+          } else {
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = col[q * St::RS];
+            a = F::from_t(v);
+          }
 #pragma unroll
           for (int js = 0; js < F::kSteps; ++js) YR[kt][0] = F::mma_step(a, b0, js, YR[kt][0]);
 #pragma unroll
@@ -1382,7 +1432,7 @@ int launch_twosided(cp_handle* h, const float* T, const double* u, const Shape& 
   p.kpadK = (int)K + 8;
   p.kpadJ = (int)J + 8;
   const size_t lds = (size_t)F::kFacBytes * 32 * (size_t)(p.kpadK + p.kpadJ) +
-                     sizeof(float) * 2 * (32 * (size_t)(K + 4) + 16);
+                     2 * (K == 128 ? TwoStage<F, 128>::kBufBytes : TwoStage<F, 64>::kBufBytes);
   if (h->max_lds == 0) {
     int v = 0;
     CP_HIP(h, hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
