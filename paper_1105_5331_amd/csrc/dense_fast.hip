@@ -855,9 +855,13 @@ constexpr int twosided_waves() {
 #endif
 }
 
-// oa per workgroup of the float32-operand flavours (compile-time knob)
+// oa per workgroup of the float32-operand flavours and of the float64
+// flavour (compile-time knobs)
 #ifndef CPNG_TWOSIDED_GA
 #define CPNG_TWOSIDED_GA 2
+#endif
+#ifndef CPNG_TWOSIDED_GA64
+#define CPNG_TWOSIDED_GA64 2
 #endif
 
 // Staging geometry of one 32 x K chunk: float32 rows of K + 4 values, or
@@ -904,6 +908,8 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
   unsigned char* Fk = dyn_lds;
   unsigned char* Fj = dyn_lds + (size_t)F::kFacBytes * 32 * p.kpadK;
   E* stg = reinterpret_cast<E*>(Fj + (size_t)F::kFacBytes * 32 * p.kpadJ);
+  // outer scales of the workgroup: PA of its GA oa, then PB of its ob range
+  S* psc = reinterpret_cast<S*>(stg + 2 * CH);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
@@ -924,6 +930,15 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
   const int64_t oa0 = (int64_t)blockIdx.x * GA;
   const int64_t ob0 = (int64_t)blockIdx.y * p.GB;
   const int nob = (int)min<int64_t>(p.GB, p.OB - ob0);
+  // The outer scales go through LDS: a global load of one inside the chunk
+  // loop would sit in the same in-order memory counter as the chunk loads,
+  // and waiting for it would also wait for chunk loads issued before it.
+  for (int e = tid; e < (GA + nob) * 32; e += kThr) {
+    const int t = e >> 5, r = e & 31;
+    S v = S(0);
+    if (r < p.R) v = t < GA ? PA[(oa0 + t) * p.R + r] : PB[(ob0 + t - GA) * p.R + r];
+    psc[e] = v;
+  }
   const int nchunk = nob * GA * NJ;
   // chunk c = ((ob - ob0) GA + (oa - oa0)) NJ + j / 32
   auto chunk_base = [&](int c) -> const float* {
@@ -991,7 +1006,7 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
   int c = 0;
   for (int obi = 0; obi < nob; ++obi) {
     const int64_t ob = ob0 + obi;
-    const S pb = rl < p.R ? PB[ob * p.R + rl] : S(0);
+    const S pb = psc[(GA + obi) * 32 + rl];
     V accR[KT][2];
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) accR[kt][0] = accR[kt][1] = V{0, 0, 0, 0};
@@ -1060,9 +1075,7 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
         }
         __syncthreads();
       }
-      const int64_t oa = oa0 + ai;
-      const S pa0 = lr < p.R ? PA[oa * p.R + lr] : S(0);
-      const S pa1 = 16 + lr < p.R ? PA[oa * p.R + 16 + lr] : S(0);
+      const S pa0 = psc[ai * 32 + lr], pa1 = psc[ai * 32 + 16 + lr];
 #pragma unroll
       for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
@@ -1071,28 +1084,24 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
           accR[kt][1][q] = fma_s(pa1, YR[kt][1][q], accR[kt][1][q]);
         }
     }
-    S* outR = partR + (int64_t)blockIdx.x * p.Q * p.R;
+    // partial slots in fragment order (16 x 16 tiles of 64 lanes x 4
+    // values, see splitk_frag_kernel): one 16-byte store per lane and tile
+    // instead of 4-byte stores into half lines
+    S* outR = partR + (int64_t)blockIdx.x * p.Q * 32;
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k = KW * w + 16 * kt + F::drow(lane >> 4, q);
-          const int r = 16 * rt + lr;
-          if (r < p.R) outR[(ob * K + k) * p.R + r] = accR[kt][rt][q];
-        }
+        *reinterpret_cast<V*>(outR + (((ob * K + KW * w + 16 * kt) / 16) * 2 + rt) * 256 + lane * 4) =
+            accR[kt][rt];
   }
-  S* outL = partL + (int64_t)blockIdx.y * p.OA * p.J * p.R;
+  S* outL = partL + (int64_t)blockIdx.y * p.OA * p.J * 32;
 #pragma unroll
   for (int ai = 0; ai < GA; ++ai)
 #pragma unroll
     for (int jci = 0; jci < NJ; ++jci)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t j = 32 * jci + 16 * (w >> 1) + F::drow(lane >> 4, q);
-        if (rl < p.R) outL[((oa0 + ai) * p.J + j) * p.R + rl] = accL[ai][jci][q];
-      }
+      *reinterpret_cast<V*>(outL + ((((oa0 + ai) * p.J + 32 * jci + 16 * (w >> 1)) / 16) * 2 + (w & 1)) * 256 +
+                            lane * 4) = accL[ai][jci];
 }
 
 // ---- vector (VALU) streaming kernel: float32 or float64 arithmetic --------------
@@ -1431,8 +1440,9 @@ int launch_twosided(cp_handle* h, const float* T, const double* u, const Shape& 
   p.kfoff = s.off[N - 1] * R;
   p.kpadK = (int)K + 8;
   p.kpadJ = (int)J + 8;
-  const size_t lds = (size_t)F::kFacBytes * 32 * (size_t)(p.kpadK + p.kpadJ) +
-                     2 * (K == 128 ? TwoStage<F, 128>::kBufBytes : TwoStage<F, 64>::kBufBytes);
+  // (the scales' part, (GA + GB) x 32 values, is added once GB is known)
+  size_t lds = (size_t)F::kFacBytes * 32 * (size_t)(p.kpadK + p.kpadJ) +
+               2 * (K == 128 ? TwoStage<F, 128>::kBufBytes : TwoStage<F, 64>::kBufBytes);
   if (h->max_lds == 0) {
     int v = 0;
     CP_HIP(h, hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
@@ -1445,7 +1455,10 @@ int launch_twosided(cp_handle* h, const float* T, const double* u, const Shape& 
   int64_t gy = std::max<int64_t>(1, std::min<int64_t>(p.OB, (target + gx - 1) / gx));
   p.GB = (p.OB + gy - 1) / gy;
   gy = (p.OB + p.GB - 1) / p.GB;
-  const int64_t nL = gy * p.OA * J * R, nR = gx * p.Q * R;   // partial slots, slot-major
+  lds += sizeof(S) * 32 * (size_t)(GA + p.GB);
+  if (lds > (size_t)h->max_lds) return 1;
+  // partial slots, slot-major, in fragment order: 32 rank columns per row
+  const int64_t nL = gy * p.OA * J * 32, nR = gx * p.Q * 32;
   const size_t pl = (sizeof(S) * (size_t)nL + 255) & ~size_t(255);
   CP_TRY(ensure(h, h->part, pl + sizeof(S) * (size_t)nR, st));
   S* partL = static_cast<S*>(h->part.ptr);
@@ -1492,9 +1505,9 @@ int launch_twosided(cp_handle* h, const float* T, const double* u, const Shape& 
   if (rc != CP_OK) return rc;
   CP_LAUNCH_CHECK(h);
   h->t_passes++;
-  CP_TRY(launch_splitk_reduce(h, partL, gy, p.OA * J * R, R, XL, st));
+  CP_TRY(launch_splitk_frag(h, partL, gy, p.OA * J, R, sizeof(S) == 8, XL, st));
   CP_LAUNCH_CHECK(h);
-  CP_TRY(launch_splitk_reduce(h, partR, gx, p.Q * R, R, XR, st));
+  CP_TRY(launch_splitk_frag(h, partR, gx, p.Q, R, sizeof(S) == 8, XR, st));
   CP_LAUNCH_CHECK(h);
   return CP_OK;
 }
@@ -1530,7 +1543,7 @@ int dense_twosided(cp_handle* h, const float* T, const double* u, const Shape& s
   constexpr int ga = CPNG_TWOSIDED_GA;
   if (prec == CP_PREC_BF16X3) return launch_twosided<FlavBF16x3, ga>(h, T, u, s, split, R, XL, XR, st);
   if (prec == CP_PREC_FP32) return launch_twosided<FlavF32, ga>(h, T, u, s, split, R, XL, XR, st);
-  return launch_twosided<FlavF64, 2>(h, T, u, s, split, R, XL, XR, st);
+  return launch_twosided<FlavF64, CPNG_TWOSIDED_GA64>(h, T, u, s, split, R, XL, XR, st);
 }
 
 }  // namespace cpng

@@ -126,6 +126,51 @@ __global__ __launch_bounds__(kSplitThreads) void splitk_group_kernel(const PT* _
   if (ty == 0 && e < n) part2[(int64_t)blockIdx.y * n + e] = (sh[0][tx] + sh[1][tx]) + (sh[2][tx] + sh[3][tx]);
 }
 
+// Slots in MFMA fragment order (the two-sided kernel's partials): slot s
+// holds nrows / 16 row tiles by 2 rank tiles of 16 x 16, tile t = 2 (row
+// tile) + (rank tile) at t * 256, value q of lane l at 4 l + q, which is row
+// 16 (row tile) + drow(l / 16, q) (4 (l / 16) + q, or l / 16 + 4 q for
+// float64 MFMA results) and rank 16 (rank tile) + l % 16.  Thread e adds
+// value e of every slot in slot order (16 loads in flight) and writes
+// M(row, rank) for rank < R.
+template <typename PT, bool F64ROWS>
+__global__ __launch_bounds__(kSplitThreads) void splitk_frag_kernel(const PT* __restrict__ part,
+                                                                    int nsplit, int64_t nfrag,
+                                                                    int64_t nrows, int R,
+                                                                    double* __restrict__ M) {
+  const int64_t e = (int64_t)blockIdx.x * kSplitThreads + threadIdx.x;
+  if (e >= nfrag) return;
+  double t = 0.0;
+  for (int q0 = 0; q0 < nsplit; q0 += 16) {
+    PT v[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = q0 + b < nsplit ? part[(int64_t)(q0 + b) * nfrag + e] : PT(0);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) t += (double)v[b];
+  }
+  const int64_t tile = e >> 8;
+  const int lane = (int)(e >> 2) & 63, q = (int)(e & 3), g = lane >> 4;
+  const int64_t row = (tile >> 1) * 16 + (F64ROWS ? g + 4 * q : 4 * g + q);
+  const int col = (int)(tile & 1) * 16 + (lane & 15);
+  if (col < R && row < nrows) M[row * R + col] = t;
+}
+
+// nrows x R output from nsplit fragment-order slots of nrows x 32 values
+template <typename PT>
+inline int launch_splitk_frag(cp_handle* h, const PT* part, int64_t nsplit, int64_t nrows, int R,
+                              bool f64rows, double* M, hipStream_t st) {
+  (void)h;
+  const int64_t nfrag = nrows * 32;
+  const dim3 grid((unsigned)((nfrag + kSplitThreads - 1) / kSplitThreads));
+  if (f64rows)
+    hipLaunchKernelGGL((splitk_frag_kernel<PT, true>), grid, dim3(kSplitThreads), 0, st, part,
+                       (int)nsplit, nfrag, nrows, R, M);
+  else
+    hipLaunchKernelGGL((splitk_frag_kernel<PT, false>), grid, dim3(kSplitThreads), 0, st, part,
+                       (int)nsplit, nfrag, nrows, R, M);
+  return CP_OK;
+}
+
 // R: columns of M (for the epilogue).  Up to 256 slots: one pass with 16
 // ranges per output.  More: groups of 64 slots first (coalesced), then the
 // group sums.  The shape depends only on nsplit and n, so the order of the
