@@ -111,6 +111,9 @@ struct FlavBF16x3 {
   using Src = float;   // factor values staged (the float32 copy)
   static constexpr int kMaxK = 512;
   static constexpr int kFacBytes = 2 * sizeof(__bf16);   // LDS bytes per staged value
+  // padding (values) of a staged factor row: rows of an odd number of 16-byte
+  // bank groups, so the 16 rows one operand read touches meet 16 groups
+  static constexpr int kPad = 8;
   // row of the 16x16 tile held by result value q of lane group g (lane / 16)
   __device__ static int drow(int g, int q) { return 4 * g + q; }
   struct Op {
@@ -148,6 +151,7 @@ struct FlavF32 {
   using Src = float;
   static constexpr int kMaxK = 512;
   static constexpr int kFacBytes = sizeof(float);
+  static constexpr int kPad = 4;
   __device__ static int drow(int g, int q) { return 4 * g + q; }
   struct Op {
     float x[8];
@@ -180,6 +184,7 @@ struct FlavF64 {
   using Src = double;   // the float64 factors themselves
   static constexpr int kMaxK = 256;
   static constexpr int kFacBytes = sizeof(double);
+  static constexpr int kPad = 2;
   // the float64 16x16 result interleaves its rows: value q of group g is row g + 4q
   __device__ static int drow(int g, int q) { return g + 4 * q; }
   struct Op {
@@ -1330,7 +1335,7 @@ int launch_mfma(cp_handle* h, const float* T, const double* u, const Shape& s, i
   p.istride = stride[mode];
   p.kstride = stride[q];
   p.nks = (int)((K + 31) / 32);
-  p.kpad = p.nks * 32 + 8;
+  p.kpad = p.nks * 32 + F::kPad;
   // rows of mode n < N-2 are runs of I_right = J' * K >= 16 K contiguous
   // elements per (left index, i): stream them one output row per workgroup.
   const bool stream_rows = rows && mode < N - 2 && (stride[mode] / K) >= 16;
@@ -1438,8 +1443,8 @@ int launch_twosided(cp_handle* h, const float* T, const double* u, const Shape& 
   if (p.Q >= (int64_t(1) << 26)) return 1;   // in-chunk offsets stay 32-bit
   p.jfoff = s.off[split - 1] * R;
   p.kfoff = s.off[N - 1] * R;
-  p.kpadK = (int)K + 8;
-  p.kpadJ = (int)J + 8;
+  p.kpadK = (int)K + F::kPad;
+  p.kpadJ = (int)J + F::kPad;
   // (the scales' part, (GA + GB) x 32 values, is added once GB is known)
   size_t lds = (size_t)F::kFacBytes * 32 * (size_t)(p.kpadK + p.kpadJ) +
                2 * (K == 128 ? TwoStage<F, 128>::kBufBytes : TwoStage<F, 64>::kBufBytes);
