@@ -1043,6 +1043,17 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) accL[ai][jci][q] = fma_s(pb, YL[q], accL[ai][jci][q]);
+        // between the two products (so that the matrix cores still work on
+        // the left tile meanwhile): the next chunk (loaded two chunks ago)
+        // into the other buffer, whose readers all passed the previous
+        // barrier (past the last chunk this stages a copy nobody reads); then
+        // the loads of chunk c + 3 into the register set it freed (c is even
+        // here exactly when ai NJ + jci is: GA NJ is even)
+        {
+          const int set = ((ai * NJ + jci) + 1) & 1;
+          sstore(set, stg + ((c + 1) & 1) * CH);
+          gload(set, chunk_base(min(c + 3, last)));
+        }
         // right: rows k = KW w + 16 kt + lr, the chunk's 32 j
         const Op b0 = F::from_lds(Fj, p.kpadJ, lr * p.kpadJ + 32 * jci + kb);
         const Op b1 = F::from_lds(Fj, p.kpadJ, (16 + lr) * p.kpadJ + 32 * jci + kb);
@@ -1067,16 +1078,6 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
           for (int js = 0; js < F::kSteps; ++js) YR[kt][0] = F::mma_step(a, b0, js, YR[kt][0]);
 #pragma unroll
           for (int js = 0; js < F::kSteps; ++js) YR[kt][1] = F::mma_step(a, b1, js, YR[kt][1]);
-        }
-        // the next chunk (loaded two chunks ago) into the other buffer, whose
-        // readers all passed the previous barrier (past the last chunk this
-        // stages a copy nobody reads); then the loads of chunk c + 3 into the
-        // register set it freed (c is even here exactly when ai NJ + jci is:
-        // GA NJ is even)
-        {
-          const int set = ((ai * NJ + jci) + 1) & 1;
-          sstore(set, stg + ((c + 1) & 1) * CH);
-          gload(set, chunk_base(min(c + 3, last)));
         }
         __syncthreads();
       }
