@@ -703,7 +703,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
+              "(sharding over several GPUs is a design only, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
