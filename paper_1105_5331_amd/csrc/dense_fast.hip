@@ -39,6 +39,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef bf16x4 __attribute__((address_space(3)))* lds_bf16x4_p;
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThr = 256;
@@ -921,6 +922,11 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
   const int lr = lane & 15;
   const int kb = (lane >> 4) * 8;
   const int rl = (w & 1) * 16 + lr;   // this lane's rank in the left tile
+  // transpose-read address of the right operand (pre-split flavours): lane
+  // 4e + h of lane group g points at row 8 g + e, columns 4 h .. (the
+  // group's 8 rows lie in one 16-row half, so radd adds RO (g / 2))
+  const int troff = (8 * (lane >> 4) + ((lane & 15) >> 2)) * TwoStage<F, 32 * KS>::RS +
+                    TwoStage<F, 32 * KS>::RO * (lane >> 5) + 4 * (lane & 3);
 
   // both factors, ranks 0..31 (zero beyond R), in the flavour's form
   for (int e = tid; e < 32 * K; e += kThr) {
@@ -1059,16 +1065,23 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
         const Op b1 = F::from_lds(Fj, p.kpadJ, (16 + lr) * p.kpadJ + 32 * jci + kb);
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
-          // rows kb .. kb + 7 lie in one 16-row half: radd(kb + q) = radd(kb) + q RS
-          const E* col = cur + St::radd(kb) + KW * w + 16 * kt + lr;
           Op a;
           if constexpr (PS) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              a.h[q] = col[q * St::RS];
-              a.l[q] = col[PL + q * St::RS];
-            }
+            // the operand (8 rows j of one column k) with transpose reads:
+            // in each 16-lane group the read hands lane t column t of the
+            // 4 x 16 block whose row e the lanes 4e .. 4e + 3 point at (4
+            // values each), so lane 4e + h points at row kb + e, columns
+            // 4h .. 4h + 3 of the tile; a second read covers rows kb + 4 ..
+            const E* col = cur + troff + KW * w + 16 * kt;
+            const bf16x4 h0 = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4_p)(col));
+            const bf16x4 h1 = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4_p)(col + 4 * St::RS));
+            const bf16x4 l0 = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4_p)(col + PL));
+            const bf16x4 l1 = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4_p)(col + PL + 4 * St::RS));
+            a.h = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
+            a.l = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
           } else {
+            // rows kb .. kb + 7 lie in one 16-row half: radd(kb + q) = radd(kb) + q RS
+            const E* col = cur + St::radd(kb) + KW * w + 16 * kt + lr;
             float v[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) v[q] = col[q * St::RS];
