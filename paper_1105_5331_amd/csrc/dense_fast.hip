@@ -39,6 +39,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef bf16x4 __attribute__((address_space(3)))* lds_bf16x4_p;
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -977,14 +978,26 @@ void mttkrp_twosided_mfma(const float* __restrict__ T,
     for (int l = 0; l < NL; ++l) {
       const int off = St::radd(l * RL + trow) + tcol;
       if constexpr (PS) {
-        bf16x4 h, lo;
+        // hi = bf16(x) two at a time; the hi values back in float32 from
+        // the packed word (low half shifted up, high half masked), then
+        // lo = bf16(x - hi) (x - hi is exact)
+        typedef unsigned u2v __attribute__((ext_vector_type(2)));
+        u2v h, lo;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          h[i] = (__bf16)ld[set][l][i];
-          lo[i] = (__bf16)(ld[set][l][i] - (float)h[i]);   // exact residual
+        for (int i = 0; i < 2; ++i) {
+          const float x0 = ld[set][l][2 * i], x1 = ld[set][l][2 * i + 1];
+          const bf16x2 hp = {(__bf16)x0, (__bf16)x1};
+          unsigned hb = __builtin_bit_cast(unsigned, hp);
+          // (opaque to the optimiser, which would otherwise redo the low
+          // half's conversion on its own instead of shifting the word)
+          asm("" : "+v"(hb));
+          const bf16x2 lp = {(__bf16)(x0 - __uint_as_float(hb << 16)),
+                             (__bf16)(x1 - __uint_as_float(hb & 0xffff0000u))};
+          h[i] = hb;
+          lo[i] = __builtin_bit_cast(unsigned, lp);
         }
-        *reinterpret_cast<bf16x4*>(buf + off) = h;
-        *reinterpret_cast<bf16x4*>(buf + PL + off) = lo;
+        *reinterpret_cast<u2v*>(buf + off) = h;
+        *reinterpret_cast<u2v*>(buf + PL + off) = lo;
       } else {
         *reinterpret_cast<f4v*>(buf + off) = ld[set][l];
       }
