@@ -851,24 +851,28 @@ __global__ void twosided_tables_kernel(const double* __restrict__ fac, TwoParams
 }
 
 // Waves per SIMD the two-sided kernel is compiled for: two (registers <= 256)
-// for float32 operands with GA <= 2, where two workgroups fit a CU's LDS;
+// for float32 operands with GA <= 4, where two workgroups fit a CU's LDS;
 // one otherwise (the float64 flavour's staged factors fill most of the LDS).
 template <class F, int GA>
 constexpr int twosided_waves() {
 #ifdef CPNG_TWOSIDED_WAVES
   return CPNG_TWOSIDED_WAVES;
 #else
-  return (sizeof(typename F::S) == 4 && GA <= 2) ? 2 : 1;
+  return (sizeof(typename F::S) == 4 && GA <= 4) ? 2 : 1;
 #endif
 }
 
 // oa per workgroup of the float32-operand flavours and of the float64
-// flavour (compile-time knobs)
+// flavour (compile-time knobs; outer counts the value does not divide run
+// with 2).  The partial slots written per pass are (OA / GA + OB / GB) rows
+// of P or Q: with GA = 4 at 128^4 that is 101 MB instead of 151 MB (GA = 2)
+// for float32 slots, and the writes cost the streaming pass more than
+// their share of the bytes.
 #ifndef CPNG_TWOSIDED_GA
-#define CPNG_TWOSIDED_GA 2
+#define CPNG_TWOSIDED_GA 4
 #endif
 #ifndef CPNG_TWOSIDED_GA64
-#define CPNG_TWOSIDED_GA64 2
+#define CPNG_TWOSIDED_GA64 4
 #endif
 
 // Staging geometry of one 32 x K chunk: float32 rows of K + 4 values, or
@@ -1572,10 +1576,21 @@ int dense_fast_mfma_f64acc(cp_handle* h, const float* T, const double* u, const 
 // above).  CP_OK after launching, 1 where the shape is not covered.
 int dense_twosided(cp_handle* h, const float* T, const double* u, const Shape& s, int split, int R,
                    int prec, double* XL, double* XR, hipStream_t st) {
-  constexpr int ga = CPNG_TWOSIDED_GA;
-  if (prec == CP_PREC_BF16X3) return launch_twosided<FlavBF16x3, ga>(h, T, u, s, split, R, XL, XR, st);
-  if (prec == CP_PREC_FP32) return launch_twosided<FlavF32, ga>(h, T, u, s, split, R, XL, XR, st);
-  return launch_twosided<FlavF64, CPNG_TWOSIDED_GA64>(h, T, u, s, split, R, XL, XR, st);
+  // (launch_twosided returns 1 before launching anything where GA does not
+  // divide the left outer count; those shapes run with GA = 2)
+  constexpr int ga = CPNG_TWOSIDED_GA, ga64 = CPNG_TWOSIDED_GA64;
+  int rc = 1;
+  if (prec == CP_PREC_BF16X3) {
+    rc = launch_twosided<FlavBF16x3, ga>(h, T, u, s, split, R, XL, XR, st);
+    if (rc == 1 && ga != 2) rc = launch_twosided<FlavBF16x3, 2>(h, T, u, s, split, R, XL, XR, st);
+  } else if (prec == CP_PREC_FP32) {
+    rc = launch_twosided<FlavF32, ga>(h, T, u, s, split, R, XL, XR, st);
+    if (rc == 1 && ga != 2) rc = launch_twosided<FlavF32, 2>(h, T, u, s, split, R, XL, XR, st);
+  } else {
+    rc = launch_twosided<FlavF64, ga64>(h, T, u, s, split, R, XL, XR, st);
+    if (rc == 1 && ga64 != 2) rc = launch_twosided<FlavF64, 2>(h, T, u, s, split, R, XL, XR, st);
+  }
+  return rc;
 }
 
 }  // namespace cpng

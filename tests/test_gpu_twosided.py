@@ -7,8 +7,9 @@ Covered shapes: float32 tensor, order >= 4 with both mode groups of more than
 one mode, the last mode of each group of length 64 or 128, R <= 32.  The
 cases span one and several 32-row chunks per slab, both slab widths, outer
 groups of one and of two modes (order 5), R = 1, R = 32 and ranks that leave
-part of a 16-wide rank tile empty, and outer counts that leave the last
-workgroup with fewer outer indices than the others."""
+part of a 16-wide rank tile empty, outer counts that leave the last
+workgroup with fewer outer indices than the others, and left outer counts
+that 4 divides (four outer indices per workgroup) and that it does not (two)."""
 import numpy as np
 import pytest
 
@@ -34,11 +35,13 @@ def _dev(x):
 
 
 # (dims, R): split before mode 2 for the order-4 shapes, before mode 3 for the order-5 one
-# (2, 64, 515, 64): one outer index on the left, 515 on the right, more than
-# the workgroups take one each, so the last workgroup gets fewer than the rest
+# (2, 64, 515, 64): two outer indices on the left, 515 on the right, more
+# than the workgroups take one each, so the last workgroup gets fewer than
+# the rest; left outer counts 8, 4, 12 and (order 5) 4 x 2 run four per
+# workgroup, the others two
 CASES = [((8, 64, 6, 128), 5), ((4, 128, 3, 64), 32), ((2, 3, 64, 4, 128), 7),
          ((6, 128, 5, 128), 17), ((2, 64, 3, 64), 1), ((10, 64, 9, 128), 16),
-         ((2, 64, 515, 64), 9)]
+         ((2, 64, 515, 64), 9), ((12, 64, 5, 128), 32), ((4, 2, 64, 7, 64), 11)]
 PRECS = ["bf16x3", "fp32", "fp32in_fp64acc", "fp64"]
 
 
