@@ -94,9 +94,11 @@ def test_one_pass_objective_grad(h, dims, R, prec):
 
 def test_uncovered_shapes_take_two_passes(h):
     """Shapes the two-sided kernel does not cover (a group's last mode of
-    another length, R above 32) run the two single-partial passes."""
+    another length, R above 32, an odd left outer count) run the two
+    single-partial passes."""
     import paper_1105_5331_amd as cpng
-    for dims, R in [((4, 96, 3, 64), 5), ((4, 64, 3, 128), 33), ((4, 64, 3, 40), 3)]:
+    for dims, R in [((4, 96, 3, 64), 5), ((4, 64, 3, 128), 33), ((4, 64, 3, 40), 3),
+                    ((3, 64, 4, 64), 5)]:
         print(f"case two-pass fallback dims={dims} R={R}", flush=True)
         p = test_problem_1(dims, min(R, 8), 0.5, 1, 1, seed=2, dtype=np.float32)
         Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
