@@ -164,10 +164,13 @@ typedef struct cp_options {
                                1 (default): an evaluation of a float32 tensor forms
                                both partials in one pass over T where the two-sided
                                kernel covers the shape (R <= 32, the last modes of both
-                               groups of length 64 or 128; the ALS sweep keeps two
-                               passes, its right partial needs the updated left
-                               factors); 2: always one pass per partial; 0: one pass
-                               per mode.  Other values: CP_EINVAL */
+                               groups of length 64 or 128); the ALS sweep of an N-GMRES
+                               step takes its left partial from the last evaluation
+                               when that was at the sweep's starting point (rescaled
+                               for the normalisation) and then makes one pass, for its
+                               right partial (which needs the updated left factors);
+                               2: always one pass per partial; 0: one pass per mode.
+                               Other values: CP_EINVAL */
   int32_t switch_on_stall;  /* with switch_rho > 0, also switch once rho <= 1e-2 after a
                                line search in the first precision ends without a Wolfe
                                point (1) */

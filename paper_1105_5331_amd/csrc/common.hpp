@@ -51,6 +51,7 @@ struct cp_handle {
   cpng::DevBuf otab;     // per-launch outer-index tables of the streaming MTTKRP
   cpng::DevBuf ybuf;     // mode-group partials of the two-level evaluation (float64)
   uint64_t gen = 0;           // bumped whenever a workspace slice is reallocated
+  uint64_t ywrites = 0;       // bumped by every evaluation or sweep that writes ybuf
   cpng::GradEpi epi;          // pending gradient epilogue for the next dense MTTKRP
   double* pinned = nullptr;   // host pinned readback area (64 doubles)
   int* flags = nullptr;       // device status word (ALS solve fallbacks)
@@ -205,6 +206,9 @@ int tree_partials_one_pass(cp_handle* h, const cp_tensor* T, const Shape& s, con
 int tree_all_modes(cp_handle* h, const Shape& s, int split, const double* XL, const double* XR,
                    const double* u, int R, double* M, const double* Gbar, double* g,
                    hipStream_t st);
+// X_L at the iterate renormalised by the plan (scales, perm) of normalize()
+int tree_rescale_left(cp_handle* h, const Shape& s, int split, int R, double* XL,
+                      const double* scales, const int* perm, hipStream_t st);
 int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, const double* u, int R,
               int mode, double* M, hipStream_t st);
 
@@ -232,7 +236,8 @@ int64_t batch_footprint(const cp_tensor* T, int R, int window);
 // Gram is recomputed; S must hold the other modes' Grams of the same factors.
 int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, double* Gbar,
              double* Gam, hipStream_t st, int factor_mode = -1, int only_mode = -1);
-int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStream_t st);
+int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStream_t st,
+              const double** scales_out = nullptr, const int** perm_out = nullptr);
 // A = M Gbar^-1 (Gbar nullptr: use the factor gram_all formed).
 int mode_solve(cp_handle* h, const double* M, const double* Gbar, int64_t I, int R, double* A,
                hipStream_t st);

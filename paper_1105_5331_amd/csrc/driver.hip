@@ -32,6 +32,14 @@ struct cp_ngmres_state {
   int n_fg = 0, n_restarts = 0, n_fallback = 0, switch_iter = -1;
   bool stalled = false;   // a line search in reduced precision ended without a Wolfe point
   bool cg_fresh = true;   // N-CG: the next direction is -g (start, switch, failed search)
+  // The left partial X_L in the handle's ybuf is the one at u (the last
+  // evaluation was at u_{i+1}, rescaled for its normalisation) while xl_ok
+  // and no call has written ybuf since (ywrites, ybuf's address): the next
+  // ALS sweep then skips its left pass (mttkrp_tree = 1, N-GMRES).
+  bool xl_ok = false;
+  uint64_t xl_token = 0;
+  void* xl_ptr = nullptr;
+  bool reuse_xl = false;   // the Steps I-II being enqueued take X_L from ybuf
   // f(u_bar) and the slope g(u_bar)^T d of the last N-GMRES iteration (Steps I-II)
   bool have_last = false;
   double last_fbar = 0.0, last_slope = 0.0;
@@ -54,7 +62,8 @@ struct cp_ngmres_state {
     bool warm = false;     // ran once eagerly at the current precision
     bool failed = false;   // capture not possible: stay eager
     int64_t passes = 0;    // passes over T per replay
-  } cap[2];
+    uint64_t ywrites = 0;  // writes of the handle's ybuf per replay
+  } cap[3];
 };
 
 namespace {
@@ -145,10 +154,26 @@ int tree_setup(cp_handle* h, const cp_tensor* T, const Shape& s, int R, int prec
   const size_t nr = tree_partial_elems(s, split, R, false);
   CP_TRY(ensure(h, h->ybuf, sizeof(double) * (nl + nr), st));
   double* b = static_cast<double*>(h->ybuf.ptr);
+  h->ywrites++;   // the caller writes (at least one of) the partials
   tb->split = split;
   if (nl) tb->XL = b;
   if (nr) tb->XR = b + nl;
   return CP_OK;
+}
+
+// The left partial of the two-level evaluation of S's tensor in the handle's
+// ybuf, where that evaluation has one (dense, order >= 3, left group of two
+// or more modes) and ybuf is large enough to hold it.
+bool tree_left_buffer(cp_handle* h, const cp_tensor* T, const Shape& s, int R, int prec, int* split,
+                      double** XL) {
+  const int sp = tree_split(T, s, prec);
+  if (!sp) return false;
+  const size_t nl = tree_partial_elems(s, sp, R, true);
+  const size_t nr = tree_partial_elems(s, sp, R, false);
+  if (!nl || !h->ybuf.ptr || h->ybuf.bytes < sizeof(double) * (nl + nr)) return false;
+  *split = sp;
+  *XL = static_cast<double*>(h->ybuf.ptr);
+  return true;
 }
 
 // M^(n) from its group's partial (formed beforehand), or by its own pass over T.
@@ -215,13 +240,15 @@ int objective_grad_impl(cp_handle* h, const cp_tensor* T, const Shape& s, const 
 // with the factors updated so far.  With `tree`, the left group's partial is
 // formed first (the right factors are untouched until the split) and the
 // right group's once the left modes are updated.
+// With xl_ready the left partial at u is already in the handle's ybuf (the
+// caller's last evaluation was at u) and is not formed again.
 int als_sweep_impl(cp_handle* h, const cp_tensor* T, const Shape& s, double* u, int R, int prec,
-                   int normalize_after, hipStream_t st, bool tree = true) {
+                   int normalize_after, hipStream_t st, bool tree = true, bool xl_ready = false) {
   Scratch sc;
   CP_TRY(mode_buffers(h, s, R, st, &sc));
   TreeBufs tb;
   CP_TRY(tree_setup(h, T, s, R, prec, tree, st, &tb));
-  if (tb.XL) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, true, tb.XL, st));
+  if (tb.XL && !xl_ready) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, true, tb.XL, st));
   for (int n = 0; n < s.N; ++n) {
     if (tb.XR && n == tb.split) CP_TRY(tree_partial(h, T, s, u, R, prec, tb.split, false, tb.XR, st));
     // Grams (after mode 0 only the mode updated last changed) and the factor of Gbar^(n)
@@ -242,7 +269,7 @@ int readback(cp_handle* h, const double* src, int n, double* dst, hipStream_t st
   return CP_OK;
 }
 
-enum { PHASE_STEP12 = 0, PHASE_EVAL = 1 };
+enum { PHASE_STEP12 = 0, PHASE_EVAL = 1, PHASE_STEP12_XL = 2 };
 
 // The device work of Step II from u_bar and g_bar: the accelerated u_hat
 // over the window (normalised), d = u_hat - u_bar and the slope g(u_bar)^T d
@@ -261,7 +288,8 @@ int enqueue_step2(cp_handle* h, cp_ngmres_state* S) {
 int enqueue_step12(cp_handle* h, cp_ngmres_state* S) {
   CP_HIP(h, hipMemcpyAsync(S->dpar, S->hpar, sizeof(StepPar), hipMemcpyHostToDevice, S->st));
   CP_HIP(h, hipMemcpyAsync(S->ubar, S->u, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
-  CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0));
+  CP_TRY(als_sweep_impl(h, S->T, S->s, S->ubar, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0,
+                        S->reuse_xl));
   CP_TRY(objective_grad_impl(h, S->T, S->s, S->ubar, S->R, S->prec, S->scal, S->gbar, S->st,
                              S->opt.mttkrp_tree));
   return enqueue_step2(h, S);
@@ -290,13 +318,15 @@ void drop_captured(cp_ngmres_state::Captured& c) {
 // The host values in S->hpar are copied to the device inside the phase, so
 // a replay uses the current ones.
 int run_phase(cp_handle* h, cp_ngmres_state* S, int ph) {
-  auto enqueue = [&]() { return ph == PHASE_STEP12 ? enqueue_step12(h, S) : enqueue_eval(h, S); };
+  S->reuse_xl = ph == PHASE_STEP12_XL;
+  auto enqueue = [&]() { return ph == PHASE_EVAL ? enqueue_eval(h, S) : enqueue_step12(h, S); };
   cp_ngmres_state::Captured& c = S->cap[ph];
   if (!S->st || h->prof || c.failed) return enqueue();
   if (c.h != h || c.gen != h->gen || c.prec != S->prec) drop_captured(c);
   if (c.exec) {
     CP_HIP(h, hipGraphLaunch(c.exec, S->st));
     h->t_passes += c.passes;
+    h->ywrites += c.ywrites;
     return CP_OK;
   }
   if (!c.warm) {
@@ -309,6 +339,7 @@ int run_phase(cp_handle* h, cp_ngmres_state* S, int ph) {
   }
   const uint64_t gen0 = h->gen;
   const int64_t passes0 = h->t_passes;
+  const uint64_t ywrites0 = h->ywrites;
   if (hipStreamBeginCapture(S->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
     c.failed = true;
@@ -329,6 +360,7 @@ int run_phase(cp_handle* h, cp_ngmres_state* S, int ph) {
   if (!ok) {   // nothing of the capture ran: do the phase eagerly
     c.failed = true;
     h->t_passes = passes0;
+    h->ywrites = ywrites0;
     return enqueue();
   }
   c.exec = exec;
@@ -336,6 +368,7 @@ int run_phase(cp_handle* h, cp_ngmres_state* S, int ph) {
   c.gen = h->gen;
   c.prec = S->prec;
   c.passes = h->t_passes - passes0;   // counted while recording, run by the launch below
+  c.ywrites = h->ywrites - ywrites0;
   CP_HIP(h, hipGraphLaunch(c.exec, S->st));
   return CP_OK;
 }
@@ -961,6 +994,15 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
     rc = fail(h, CP_EDEVICE, "copy of the initial guess failed");
   if (rc == CP_OK) rc = normalize(h, s, S->u, R, nullptr, st);
   if (rc == CP_OK) rc = eval_current(h, S);
+  if (rc == CP_OK && o.method == CP_METHOD_NGMRES && o.mttkrp_tree == 1) {
+    int split = 0;
+    double* XL = nullptr;
+    if (tree_left_buffer(h, T, s, R, S->prec, &split, &XL)) {   // evaluated at the normalised u0
+      S->xl_ok = true;
+      S->xl_token = h->ywrites;
+      S->xl_ptr = h->ybuf.ptr;
+    }
+  }
   if (rc == CP_OK) rc = window_push(h, S);
   if (rc < 0) {
     cp_ngmres_destroy(h, S);
@@ -1053,6 +1095,7 @@ int cp_ngmres_load(cp_handle* h, cp_ngmres_state* S, const double* U, const doub
   S->n_fallback = meta->n_ls_fallback;
   S->switch_iter = meta->switch_iter;
   S->have_last = false;
+  S->xl_ok = false;
   CP_TRY(dot(h, S->g, S->g, S->L, S->scal + 3, S->st));
   double gg;
   CP_TRY(readback(h, S->scal + 3, 1, &gg, S->st));
@@ -1090,6 +1133,9 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
   rec.m = uses_window(S->opt.method) ? S->wcount : 0;
   rec.precision = S->prec;
   const int64_t passes0 = h->t_passes;
+  // X_L at u kept by the previous step, unless anything has written ybuf since
+  const bool xl_in = S->xl_ok && S->xl_token == h->ywrites && S->xl_ptr == h->ybuf.ptr;
+  S->xl_ok = false;
   int rc = CP_OK;
   if (S->opt.method == CP_METHOD_ALS) {
     CP_TRY(als_sweep_impl(h, S->T, S->s, S->u, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0));
@@ -1107,7 +1153,7 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
       CP_TRY(enqueue_step2(h, S));
       CP_TRY(readback(h, S->scal + 1, 1, &slope, S->st));
     } else {
-      CP_TRY(run_phase(h, S, PHASE_STEP12));
+      CP_TRY(run_phase(h, S, xl_in ? PHASE_STEP12_XL : PHASE_STEP12));
       S->n_fg++;
       double fs[2];   // f(u_bar) and the slope g(u_bar)^T d in one readback
       CP_TRY(readback(h, S->scal, 2, fs, S->st));
@@ -1120,7 +1166,8 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
     const double* gnew = S->gbar;
     double fnew = fbar;
     double beta = 0.0;
-    if (!(slope < 0.0)) {
+    const bool restart = !(slope < 0.0);
+    if (restart) {
       // restart: u_{i+1} = u_bar, window back to one iterate
       rec.restart = 1;
       S->n_restarts++;
@@ -1149,7 +1196,27 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
       CP_TRY(axpy_to(h, S->ubar, beta, S->d, S->u, S->L, S->st));
       CP_HIP(h, hipMemcpyAsync(S->g, gnew, sizeof(double) * S->L, hipMemcpyDeviceToDevice, S->st));
     }
-    CP_TRY(normalize(h, S->s, S->u, S->R, S->g, S->st));
+    // The last evaluation was at u_{i+1} on a restart (u_bar) and when the
+    // accepted point is the last trial: then the next sweep's left partial
+    // is that evaluation's, carried through the normalisation
+    // (tree_rescale_left) instead of a pass over T.
+    int split = 0;
+    double* XL = nullptr;
+    const bool keep = S->opt.method == CP_METHOD_NGMRES && S->opt.mttkrp_tree == 1 &&
+                      (restart || (beta != 0.0 && gnew == S->gt)) &&
+                      tree_left_buffer(h, S->T, S->s, S->R, S->prec, &split, &XL);
+    const double* nsc = nullptr;
+    const int* nperm = nullptr;
+    CP_TRY(normalize(h, S->s, S->u, S->R, S->g, S->st, keep ? &nsc : nullptr, keep ? &nperm : nullptr));
+    if (keep) {
+      const int rr = tree_rescale_left(h, S->s, split, S->R, XL, nsc, nperm, S->st);
+      if (rr < 0) return rr;
+      if (rr == CP_OK) {
+        S->xl_ok = true;
+        S->xl_token = h->ywrites;
+        S->xl_ptr = h->ybuf.ptr;
+      }
+    }
     S->f = fnew;
     CP_TRY(dot(h, S->g, S->g, S->L, S->scal + 3, S->st));
     CP_TRY(window_push(h, S));   // queued before the readback below waits

@@ -682,7 +682,9 @@ __global__ __launch_bounds__(256) void objective_small_kernel(const double* __re
 // place through an LDS tile.
 __global__ __launch_bounds__(256) void normalize_small_kernel(double* __restrict__ u,
                                                               double* __restrict__ g,
-                                                              ModeTable t) {
+                                                              ModeTable t,
+                                                              double* __restrict__ scales_out,
+                                                              int* __restrict__ perm_out) {
   constexpr int kTile = 4096;
   __shared__ double nu[CP_MAX_ORDER][kMaxR];
   __shared__ double scl[CP_MAX_ORDER][kMaxR];
@@ -735,6 +737,11 @@ __global__ __launch_bounds__(256) void normalize_small_kernel(double* __restrict
     perm[pos] = r;   // perm[new position] = old term index
   }
   __syncthreads();
+  if (scales_out && (int)threadIdx.x < R) {   // the plan, for callers that rescale other data
+    const int r = threadIdx.x;
+    for (int k = 0; k < t.N; ++k) scales_out[k * R + r] = scl[k][r];
+    perm_out[r] = perm[r];
+  }
   const int64_t rows = t.off[t.N];
   const int64_t tr = kTile / R;   // rows per tile
   constexpr int kPer = kTile / 256;   // tile entries per thread
@@ -1145,11 +1152,24 @@ int gram_all(cp_handle* h, const Shape& s, const double* u, int R, double* S, do
   return CP_OK;
 }
 
-int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStream_t st) {
+// With scales_out / perm_out the plan (scales[k R + r] of old term r in mode
+// k, perm[new position] = old term) is left in the handle's small slice for
+// the caller to apply to other data before its next call on this handle.
+int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStream_t st,
+              const double** scales_out, const int** perm_out) {
   if (R < 1 || R > kMaxR) return fail(h, CP_EINVAL, "rank %d outside 1..%d", R, kMaxR);
   ModeTable t = table(s, R);
   if (s.sum_dims() * R <= kSmallNorm) {
-    hipLaunchKernelGGL(normalize_small_kernel, dim3(1), dim3(256), 0, st, u, g, t);
+    double* sc = nullptr;
+    int* pm = nullptr;
+    if (scales_out) {
+      CP_TRY(ensure(h, h->small, small_layout(s.N, R) + 4096, st));
+      sc = static_cast<double*>(h->small.ptr);
+      pm = reinterpret_cast<int*>(sc + s.N * R);
+      *scales_out = sc;
+      *perm_out = pm;
+    }
+    hipLaunchKernelGGL(normalize_small_kernel, dim3(1), dim3(256), 0, st, u, g, t, sc, pm);
     CP_LAUNCH_CHECK(h);
     return CP_OK;
   }
@@ -1159,6 +1179,10 @@ int normalize(cp_handle* h, const Shape& s, double* u, int R, double* g, hipStre
   double* part = static_cast<double*>(h->red.ptr);
   double* scales = static_cast<double*>(h->small.ptr);
   int* perm = reinterpret_cast<int*>(scales + s.N * R);
+  if (scales_out) {
+    *scales_out = scales;
+    *perm_out = perm;
+  }
   hipLaunchKernelGGL(colsq_partial_kernel, dim3((unsigned)nch), dim3(256), 0, st, u, t, part);
   CP_LAUNCH_CHECK(h);
   hipLaunchKernelGGL(norm_plan_kernel, dim3(1), dim3(64), 0, st, part, t, scales, perm);

@@ -517,4 +517,38 @@ int tree_mode(cp_handle* h, const Shape& s, int lo, int hi, const double* X, con
   return CP_OK;
 }
 
+// The left partial at a renormalised iterate.  Normalising moves term
+// perm[j] to position j and scales its factor column in mode k by
+// scales[k R + perm[j]]; K_R's column of a term is the Khatri-Rao product of
+// the right group's factor columns, so X_L = T K_R becomes
+//     X_L'(p, j) = X_L(p, perm[j]) prod_{k >= split} scales[k R + perm[j]].
+// In place, 64 / R rows per wave: a row's lanes all read (one load
+// instruction, whose results every store waits for) before any lane stores.
+__global__ __launch_bounds__(256) void rescale_left_kernel(double* __restrict__ X, int64_t P, int R,
+                                                           int split, int N,
+                                                           const double* __restrict__ scales,
+                                                           const int* __restrict__ perm) {
+  const int lane = threadIdx.x & 63;
+  const int rpw = 64 / R;
+  const int j = lane % R, sub = lane / R;
+  const int64_t p = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * rpw + sub;
+  if (sub >= rpw || p >= P) return;
+  const int pj = perm[j];
+  double fac = 1.0;
+  for (int k = split; k < N; ++k) fac *= scales[k * R + pj];
+  const double v = X[p * R + pj];
+  X[p * R + j] = v * fac;
+}
+
+int tree_rescale_left(cp_handle* h, const Shape& s, int split, int R, double* XL,
+                      const double* scales, const int* perm, hipStream_t st) {
+  const int64_t P = group_size(s, 0, split);
+  if (P <= 0 || R < 1 || R > 64) return 1;
+  const int64_t waves = (P + 64 / R - 1) / (64 / R);
+  hipLaunchKernelGGL(rescale_left_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, XL, P,
+                     R, split, s.N, scales, perm);
+  CP_LAUNCH_CHECK(h);
+  return CP_OK;
+}
+
 }  // namespace cpng
