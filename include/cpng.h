@@ -165,7 +165,7 @@ typedef struct cp_options {
                                both partials in one pass over T where the two-sided
                                kernel covers the shape (R <= 32, the last modes of both
                                groups of length 64 or 128); the ALS sweep of an N-GMRES
-                               step takes its left partial from the last evaluation
+                               or ALS step takes its left partial from the last evaluation
                                when that was at the sweep's starting point (rescaled
                                for the normalisation) and then makes one pass, for its
                                right partial (which needs the updated left factors);

@@ -994,7 +994,8 @@ int cp_ngmres_create(cp_handle* h, const cp_tensor* T, int32_t R, const cp_optio
     rc = fail(h, CP_EDEVICE, "copy of the initial guess failed");
   if (rc == CP_OK) rc = normalize(h, s, S->u, R, nullptr, st);
   if (rc == CP_OK) rc = eval_current(h, S);
-  if (rc == CP_OK && o.method == CP_METHOD_NGMRES && o.mttkrp_tree == 1) {
+  if (rc == CP_OK && (o.method == CP_METHOD_NGMRES || o.method == CP_METHOD_ALS) &&
+      o.mttkrp_tree == 1) {
     int split = 0;
     double* XL = nullptr;
     if (tree_left_buffer(h, T, s, R, S->prec, &split, &XL)) {   // evaluated at the normalised u0
@@ -1138,8 +1139,18 @@ int ngmres_step(cp_handle* h, cp_ngmres_state* S, cp_iter_info* info) {
   S->xl_ok = false;
   int rc = CP_OK;
   if (S->opt.method == CP_METHOD_ALS) {
-    CP_TRY(als_sweep_impl(h, S->T, S->s, S->u, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0));
+    // the sweep starts from the point of the last evaluation (of the
+    // normalised iterate): its left partial is that evaluation's
+    CP_TRY(als_sweep_impl(h, S->T, S->s, S->u, S->R, S->prec, 1, S->st, S->opt.mttkrp_tree != 0,
+                          xl_in));
     CP_TRY(eval_current(h, S));
+    int split = 0;
+    double* XL = nullptr;
+    if (S->opt.mttkrp_tree == 1 && tree_left_buffer(h, S->T, S->s, S->R, S->prec, &split, &XL)) {
+      S->xl_ok = true;
+      S->xl_token = h->ywrites;
+      S->xl_ptr = h->ybuf.ptr;
+    }
   } else if (S->opt.method == CP_METHOD_NCG) {
     CP_TRY(ncg_step(h, S, &rec, &rc));
   } else {
