@@ -794,7 +794,7 @@ __global__ __launch_bounds__(kThr) void mttkrp_rowstream_mfma(const float* __res
 // PA and PB the products of each group's other factors (tables built once
 // per launch).  Workgroup (x, y) owns GA consecutive oa and GB consecutive
 // ob and walks its slabs ob by ob, oa by oa, in chunks of 32 rows j: a chunk
-// is read as whole 128-byte lines (one chunk ahead, in registers), stored to
+// is read as whole 128-byte lines (loaded two chunks ahead, in registers), stored to
 // one of two LDS buffers, and one barrier per chunk orders the buffers.  In
 // a chunk wave w computes the left tile of rows 16 (w / 2).., ranks
 // 16 (w % 2).. over all k, and the right rows k = (K / 4) w .. over the

@@ -33,9 +33,10 @@ struct cp_ngmres_state {
   bool stalled = false;   // a line search in reduced precision ended without a Wolfe point
   bool cg_fresh = true;   // N-CG: the next direction is -g (start, switch, failed search)
   // The left partial X_L in the handle's ybuf is the one at u (the last
-  // evaluation was at u_{i+1}, rescaled for its normalisation) while xl_ok
-  // and no call has written ybuf since (ywrites, ybuf's address): the next
-  // ALS sweep then skips its left pass (mttkrp_tree = 1, N-GMRES).
+  // evaluation was at u, in N-GMRES rescaled for u's normalisation) while
+  // xl_ok and no call has written ybuf since (ywrites, ybuf's address): the
+  // next ALS sweep then skips its left pass (mttkrp_tree = 1; N-GMRES with
+  // ALS as the one-step process, and ALS).
   bool xl_ok = false;
   uint64_t xl_token = 0;
   void* xl_ptr = nullptr;
