@@ -133,8 +133,12 @@ def test_one_pass_is_reproducible(h, prec):
     assert torch.equal(g1, g2)
 
 
+# (64, 128, 40, 128), R = 32: the iterate is long enough for the multi-kernel
+# normalisation (the reused left partial is rescaled from its plan in global
+# memory); (8, 64, 6, 128): the one-workgroup normalisation
+@pytest.mark.parametrize("dims,R", [((8, 64, 6, 128), 6), ((64, 128, 40, 128), 32)])
 @pytest.mark.parametrize("prec", ["fp32in_fp64acc", "bf16x3"])
-def test_trajectory_one_pass_vs_two_passes(h, prec):
+def test_trajectory_one_pass_vs_two_passes(h, prec, dims, R):
     """N-GMRES with the one-pass evaluation (mttkrp_tree = 1) against the same
     run with a pass per partial (mttkrp_tree = 2): the per-iterate objective
     agrees to the evaluation's rounding over the first iterations, and each
@@ -143,8 +147,7 @@ def test_trajectory_one_pass_vs_two_passes(h, prec):
     at the sweep's starting point: the first step, after a restart or a line
     search converged on its last trial), two otherwise."""
     import paper_1105_5331_amd as cpng
-    dims, R = (8, 64, 6, 128), 6
-    print(f"case one-pass trajectory {prec}", flush=True)
+    print(f"case one-pass trajectory {prec} dims={dims} R={R}", flush=True)
     p = test_problem_1(dims, R, 0.5, 1, 1, seed=1, dtype=np.float32)
     Tg = cpng.Tensor(dims, _dev(p.T).reshape(-1))
     cpng.cp_tensor_prepare(h, Tg)
