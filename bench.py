@@ -9,9 +9,10 @@ seed 10000.  One "step" is one N-GMRES iteration through the C ABI
 line search in it stalls (rho <= 1e-2) or rho <= 1e-4, then float32 values
 with float64 accumulation to rho <= 1e-8; a converged solve starts again from
 the initial guess.  Each iteration: Step I (ALS sweep), Step II (gradient at
-u_bar, the window's normal equations), Step III (line search); a sweep
-streams the tensor twice (two group partials), an objective/gradient
-evaluation once (both partials from the two-sided kernel).
+u_bar, the window's normal equations), Step III (line search); an
+objective/gradient evaluation streams the tensor once (both group partials
+from the two-sided kernel), a sweep once where it takes its left partial
+from the evaluation at its starting point and twice otherwise.
 
 value  = tensor bytes streamed by all MTTKRPs of the timed steps / wall time
          (GB/s, whole-job throughput, inputs resident in HBM).  Fewer passes
